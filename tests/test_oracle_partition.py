@@ -1,0 +1,153 @@
+"""Pins of the oracle's partitioner and partition-quality measures.
+
+P9:  cutsize(Pi) = sum_{k<m} ip_km = half the sum of |c_ij| over off-block
+     entries (Section 2.2), and the paper's interIP arithmetic.
+P10: on tiny graphs the greedy cut is never below the brute-force optimum.
+Closed forms: K equal disjoint cliques are separated with zero cut; on a
+path the parts are contiguous segments.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import workloads
+from workloads import Csr
+from oracle import (rip_graph, greedy_partition, cutsize, int_cut, ip_matrix, imbalance,
+                    brute_force_min_cut, part_max_weight)
+from oracle.ripgraph import RipGraph
+
+
+def graph_from_dense(W):
+    W = np.asarray(W, dtype=np.int64)
+    n = W.shape[0]
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    cols, wg = [], []
+    for i in range(n):
+        nz = np.flatnonzero(W[i])
+        nz = nz[nz != i]
+        cols.extend(nz.tolist())
+        wg.extend(W[i, nz].tolist())
+        rowptr[i + 1] = len(cols)
+    wg = np.array(wg, dtype=np.int64)
+    return RipGraph(n, rowptr, np.array(cols, dtype=np.int32), wg.astype(np.float64), wg)
+
+
+def test_interip_arithmetic(golden):
+    gv = golden["interIP_sample"]
+    assert sum(gv["straightforward_ip"]) == gv["straightforward_total"]
+    assert sum(gv["good_ip"]) == gv["good_total"]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_cutsize_equals_interip(seed):
+    rng = np.random.default_rng(seed)
+    n, K = 50, 4
+    M = sp.random(n, n, density=0.08, random_state=rng,
+                  data_rvs=lambda k: rng.integers(1, 6, k).astype(float)).tocsr() + sp.eye(n)
+    A = Csr.from_scipy(M)
+    g = rip_graph(A, prescale=False, sparsify=False)
+    part = rng.integers(0, K, n)
+    IP = ip_matrix(g, part, K)
+    assert np.allclose(IP, IP.T)
+    upper = sum(IP[k, m] for k in range(K) for m in range(k + 1, K))
+    D = A.to_scipy().toarray()
+    C = np.abs(D @ D.T)
+    off = part[:, None] != part[None, :]
+    assert cutsize(g, part) == pytest.approx(upper, rel=1e-14)
+    assert cutsize(g, part) == pytest.approx(0.5 * C[off].sum(), rel=1e-14)
+    assert int_cut(g, part) == int(round(0.5 * C[off].sum())) * 2 ** 20
+
+
+@pytest.mark.parametrize("seed,n,K", [(0, 8, 2), (1, 9, 3), (2, 10, 2), (3, 9, 3)])
+def test_greedy_not_below_brute_force(seed, n, K):
+    rng = np.random.default_rng(seed)
+    W = np.triu(rng.integers(0, 4, (n, n)) * (rng.random((n, n)) < 0.5), 1)
+    W = W + W.T
+    g = graph_from_dense(W)
+    part = greedy_partition(g, K)
+    assert set(part.tolist()) == set(range(K))
+    assert np.bincount(part, minlength=K).max() <= part_max_weight(n, K)
+    best = brute_force_min_cut(g, K)
+    assert int_cut(g, part) >= best
+
+
+def test_disjoint_cliques_zero_cut():
+    K, s = 4, 5
+    W = np.zeros((K * s, K * s), dtype=np.int64)
+    rng = np.random.default_rng(5)
+    perm = rng.permutation(K * s)
+    for k in range(K):
+        idx = perm[k * s:(k + 1) * s]
+        W[np.ix_(idx, idx)] = 3
+    np.fill_diagonal(W, 0)
+    g = graph_from_dense(W)
+    part = greedy_partition(g, K)
+    assert int_cut(g, part) == 0
+    assert np.all(np.bincount(part) == s)
+
+
+def test_path_gives_contiguous_segments():
+    n, K = 20, 4
+    W = np.zeros((n, n), dtype=np.int64)
+    for i in range(n - 1):
+        W[i, i + 1] = W[i + 1, i] = 1
+    part = greedy_partition(graph_from_dense(W), K)
+    assert np.array_equal(part, np.repeat(np.arange(K), 5))
+
+
+def test_greedy_on_stencil_graph_is_balanced_and_beats_contiguous():
+    p = workloads.small_config2(N=10, K=4)
+    g = rip_graph(p.A)
+    part = greedy_partition(g, p.K)
+    assert imbalance(part, p.K) <= 0.1 + 1e-12
+    assert set(part.tolist()) == set(range(p.K))
+    contiguous = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, p.K))
+    assert cutsize(g, part) <= cutsize(g, contiguous) * 1.05
+    assert np.array_equal(part, greedy_partition(g, p.K))  # deterministic
+
+
+def _path(n):
+    W = np.zeros((n, n), dtype=np.int64)
+    for i in range(n - 1):
+        W[i, i + 1] = W[i + 1, i] = 1
+    return graph_from_dense(W)
+
+
+def test_hand_computed_partitions():
+    # path of 10, K = 4: growth sizes ceil(10/4)=3, ceil(7/3)=3, ceil(4/2)=2, rest 2;
+    # every boundary move has gain 0, so refinement keeps the segments
+    assert greedy_partition(_path(10), 4).tolist() == [0, 0, 0, 1, 1, 1, 2, 2, 3, 3]
+    # path of 9, K = 2: vertex 4 has gain 0 towards part 1 (which has room): no move
+    assert greedy_partition(_path(9), 2).tolist() == [0] * 5 + [1] * 4
+    # 3x3 grid graph, unit weights, K = 3: ties go to the lowest index, so parts are rows
+    W = np.zeros((9, 9), dtype=np.int64)
+    for r in range(3):
+        for c in range(3):
+            v = 3 * r + c
+            if c < 2:
+                W[v, v + 1] = W[v + 1, v] = 1
+            if r < 2:
+                W[v, v + 3] = W[v + 3, v] = 1
+    assert greedy_partition(graph_from_dense(W), 3).tolist() == [0, 0, 0, 1, 1, 1, 2, 2, 2]
+
+
+def test_refinement_moves_positive_gain():
+    """Hand-traced: growth (K = 3, caps ceil(10/3) = 4, then 3, rest 3) gives
+    part 0 = {0, 9, 1, 4} (9 has weight 4 to 0; 1 then has 8; 4 and 6 tie at 6
+    and 4 wins), part 1 = {2, 3, 8} (2 touches nothing unassigned, 3 is the
+    lowest unassigned, then 8), part 2 = {5, 6, 7}.  Refinement (W_max = 4):
+    vertex 2 would gain 3 towards part 0 but part 0 is full; vertex 5 gains 5
+    towards part 1 and moves; vertex 6 would gain 5 towards part 0 (full)."""
+    W = np.array([[0, 3, 0, 1, 1, 0, 0, 0, 1, 4],
+                  [3, 0, 3, 0, 5, 0, 3, 0, 0, 5],
+                  [0, 3, 0, 0, 0, 0, 0, 0, 0, 0],
+                  [1, 0, 0, 0, 0, 0, 0, 0, 2, 0],
+                  [1, 5, 0, 0, 0, 0, 3, 0, 0, 0],
+                  [0, 0, 0, 0, 0, 0, 0, 0, 5, 0],
+                  [0, 3, 0, 0, 3, 0, 0, 4, 0, 3],
+                  [0, 0, 0, 0, 0, 0, 4, 0, 3, 2],
+                  [1, 0, 0, 2, 0, 5, 0, 3, 0, 0],
+                  [4, 5, 0, 0, 0, 0, 3, 2, 0, 0]])
+    g = graph_from_dense(W)
+    assert greedy_partition(g, 3, passes=0).tolist() == [0, 0, 1, 1, 0, 2, 2, 2, 1, 0]
+    assert greedy_partition(g, 3).tolist() == [0, 0, 1, 1, 0, 1, 2, 2, 1, 0]
