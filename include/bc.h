@@ -1,0 +1,210 @@
+/*
+ * bc.h - C ABI of the MI355X (gfx950) block Cimmino library.
+ *
+ * The library solves a square, nonsingular, nonsymmetric sparse system
+ * A x = f with the CG-accelerated block Cimmino method: the rows of A are split
+ * into K blocks A_1..A_K (Section 1, eq. (blockCimmino)), and classical CG is
+ * run on H x = xi with
+ *
+ *     H  = sum_i A_i^T (A_i A_i^T)^{-1} A_i        (eq. (H)),
+ *     xi = sum_i A_i^T (A_i A_i^T)^{-1} f_i        (eq. (cg)),
+ *
+ * which is Algorithm 2 of the paper.  Each block projection solves the
+ * normal equations (A_i A_i^T) y_i = u_i on the GPU, either with a dense FP64
+ * Cholesky factor (blocks of at most `dense_max_m` rows) or with a
+ * matrix-free inner CG; the sum over blocks is one transposed sparse
+ * product A^T y.  It also builds the row inner-product graph of Section 2.1
+ * (edge costs |r_i r_j^T| of C = A A^T, Section 2.3) and partitions it.
+ *
+ * Conventions shared by every entry point:
+ *  - Matrices are CSR with int32 row pointers (rowptr[0] == 0,
+ *    nondecreasing, rowptr[n] == nnz), int32 column indices sorted strictly
+ *    ascending within each row and lying in [0, n), and finite float64 values.
+ *  - Setup-time inputs (matrices, partitions) are HOST pointers, borrowed for
+ *    the duration of the call only; the library copies what it keeps.
+ *  - Solve-time vectors (f, x0, x, v, Hv) are DEVICE pointers to float64
+ *    arrays of length n (for a batched context: the systems' vectors
+ *    concatenated in system order, total length sum_s n_s).  Vectors indexed
+ *    by rows (f) use the caller's original row order; the internal block
+ *    permutation is invisible.
+ *  - Work is enqueued on a library-owned stream that is ordered after the
+ *    caller's stream (bc_opts.stream, NULL = the null stream) on entry, and
+ *    the caller's stream is ordered after it on exit; entry points return
+ *    once the results are final on the device.
+ *  - Negative status codes mean that no output was written.  The text of the
+ *    last error of the calling thread is returned by bc_last_error().
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef BC_H
+#define BC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bc_ctx bc_ctx; /* opaque; owns its device memory */
+
+typedef enum {
+  BC_OK = 0,
+  BC_NOT_CONVERGED = 1,      /* maxit reached; x holds the last iterate ("F" in Table itertable) */
+  BC_ERR_INVALID = -1,       /* malformed input (see the entry point) */
+  BC_ERR_SINGULAR_BLOCK = -2,/* a block A_i has no full row rank: A is singular */
+  BC_ERR_BREAKDOWN = -3,     /* p^T H p not a positive finite number in the CG of Algorithm 2 */
+  BC_ERR_DEVICE = -4,        /* a HIP runtime call failed, or no gfx950 device */
+  BC_ERR_NOMEM = -5          /* device or host allocation failed */
+} bc_status;
+
+enum { BC_FP64 = 0, BC_MIXED = 1 };
+enum { BC_PROJ_AUTO = 0, BC_PROJ_DENSE_CHOL = 1, BC_PROJ_INNER_CG = 2 };
+enum { BC_STOP_REL2 = 0, BC_STOP_BACKWARD_ERR = 1 };
+
+typedef struct {
+  int32_t precision;      /* BC_FP64 (default) or BC_MIXED: FP32 products and
+                             projections, FP64 outer CG scalars, x, residuals */
+  int32_t projection;     /* BC_PROJ_AUTO (default): dense Cholesky when the
+                             block has at most dense_max_m rows, else inner CG */
+  int32_t dense_max_m;    /* default 4096 */
+  double inner_tol;       /* inner CG stops when ||u_i - G_i y_i|| <= inner_tol ||u_i||; default 1e-12 */
+  int32_t inner_maxit;    /* default 20000 */
+  int32_t inner_groups;   /* workgroups cooperating on one inner-CG block; 0 = choose */
+  int32_t replace_every;  /* FP64 true-residual replacement period (BC_MIXED); 0 = never; default 20 */
+  int32_t stop_rule;      /* BC_STOP_REL2 (default): ||f - A x||_2 <= tol ||f||_2;
+                             BC_STOP_BACKWARD_ERR: gamma < tol, eq. (stopping) */
+  int32_t check_every;    /* outer iterations between host convergence checks; default 8 */
+  int32_t spmv_lanes;     /* lanes per row in the sparse products; 0 = choose */
+  void* stream;           /* caller's hipStream_t; NULL = null stream */
+} bc_opts;
+
+typedef struct {
+  int32_t iterations;     /* outer CG iterations (applications of H in the loop) */
+  int32_t status;         /* bc_status of this system */
+  double rel_residual;    /* ||f - A x||_2 / ||f||_2, recomputed in FP64 from x */
+  double backward_err;    /* gamma of eq. (stopping) */
+  double t_solve_ms;      /* wall time of the solve call */
+  double t_proj_ms;       /* GPU time in the block-projection kernels (HIP events) */
+  int32_t proj_launches;  /* number of projection kernel launches timed in t_proj_ms */
+  int32_t replacements;   /* true-residual replacements performed */
+  int64_t inner_iterations; /* sum over outer iterations and inner-CG blocks */
+} bc_stats;
+
+/* Fills *opts with the defaults listed above. */
+void bc_opts_default(bc_opts* opts);
+
+/* Builds a context for one system: validates A and the partition, permutes
+ * the rows into block order (blocks in part-id order, rows ascending inside
+ * a block; Section 2.2: the order inside a block does not change H), builds
+ * A^T, and factors every dense block's A_i A_i^T in FP64.
+ *   n              : order of A (n >= 1)
+ *   rowptr/colidx/vals : host CSR of A (see conventions)
+ *   K              : number of blocks, 1 <= K <= n
+ *   part           : host int32[n], part[r] in [0, K) = block of row r; every block nonempty
+ *   opts           : NULL = defaults
+ * Errors: BC_ERR_INVALID (malformed CSR, non-finite value, bad partition,
+ * empty block), BC_ERR_SINGULAR_BLOCK (non-positive pivot in a dense block's
+ * Cholesky), BC_ERR_DEVICE, BC_ERR_NOMEM.  On error *ctx is NULL. */
+bc_status bc_setup(bc_ctx** ctx, int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                   const double* vals, int32_t K, const int32_t* part, const bc_opts* opts);
+
+/* Same for nsys independent systems solved together (block-diagonal batch).
+ * n[s], K[s] and the per-system host arrays rowptr[s], colidx[s], vals[s],
+ * part[s] describe system s exactly as in bc_setup. */
+bc_status bc_setup_batched(bc_ctx** ctx, int32_t nsys, const int32_t* n,
+                           const int32_t* const* rowptr, const int32_t* const* colidx,
+                           const double* const* vals, const int32_t* K,
+                           const int32_t* const* part, const bc_opts* opts);
+
+/* Hv = H v = sum_i A_i^+ A_i v (eq. (H)): one block-projection sweep.
+ * v, Hv: device float64[n_total].  Uses the context's precision. */
+bc_status bc_project(bc_ctx* ctx, const double* v, double* Hv);
+
+/* Algorithm 2 from x0 (device float64[n], or NULL for zero) until the stop
+ * rule holds with threshold tol, or maxit iterations.  x: device float64[n]
+ * output.  stats: host, may be NULL.  Returns BC_OK, BC_NOT_CONVERGED (x is
+ * the last iterate), BC_ERR_BREAKDOWN (x is the last iterate before the
+ * breakdown), or an error.  tol = 0 runs exactly maxit iterations. */
+bc_status bc_solve(bc_ctx* ctx, const double* f, const double* x0, double tol,
+                   int32_t maxit, double* x, bc_stats* stats);
+
+/* Batched form of bc_solve: f, x0, x are concatenated device vectors; stats
+ * (host, may be NULL) has nsys entries.  Each system stops on its own; the
+ * call returns the worst status over the systems. */
+bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, double tol,
+                           int32_t maxit, double* x, bc_stats* stats);
+
+/* Sizes of a context: total order, number of systems and of blocks, and the
+ * number of blocks using the dense Cholesky projection.  Any pointer may be NULL. */
+bc_status bc_info(const bc_ctx* ctx, int64_t* n_total, int32_t* nsys, int32_t* nblocks,
+                  int32_t* ndense);
+
+/* Releases the context and all its device memory.  NULL is allowed. */
+void bc_destroy(bc_ctx* ctx);
+
+/* ---- row inner-product graph (Sections 2.1 and 2.3) ---- */
+
+typedef struct {
+  int32_t n;        /* vertices = rows of A */
+  int64_t nnz;      /* directed edge entries (each undirected edge twice) */
+  int64_t* rowptr;  /* int64[n+1] */
+  int32_t* col;     /* int32[nnz], ascending within a row, no diagonal */
+  double* cost;     /* float64[nnz], |c_ij| of C = A~ A~^T */
+  int64_t* wgt;     /* int64[nnz], ceil(alpha * cost) */
+} rip_graph_t;
+
+typedef struct {
+  int32_t prescale;  /* 1 (default): rows scaled to unit 2-norm first (Section 2.1) */
+  int32_t sparsify;  /* 1 (default): each column with more than isqrt(n) entries
+                        keeps its isqrt(n) largest |a| (ties: lower row; Section 2.3) */
+  int64_t alpha;     /* weight scale, default 2^20 (Section 2.3: wgt = ceil(alpha*cost)) */
+  void* stream;      /* caller's hipStream_t; NULL = null stream */
+} rip_opts;
+
+void rip_opts_default(rip_opts* opts);
+
+/* Builds G_RIP(A) on the GPU with a row-wise sparse product C = A~ A~^T.
+ * Row norms are accumulated in ascending column order; c_ij accumulates its
+ * products in ascending shared-column order, each product rounded before the
+ * add (no fused multiply-add); the diagonal and exact zeros are not edges.
+ * A: host CSR as in bc_setup.  out: filled with HOST arrays allocated by the
+ * library; release with rip_graph_free.
+ * Errors: BC_ERR_INVALID (malformed CSR, a zero row with prescale on, or a
+ * weight that would reach 2^62), BC_ERR_DEVICE, BC_ERR_NOMEM. */
+bc_status rip_graph(int32_t n, const int32_t* rowptr, const int32_t* colidx, const double* vals,
+                    const rip_opts* opts, rip_graph_t* out);
+
+void rip_graph_free(rip_graph_t* g);
+
+/* GPU time of the sparse product kernels (both passes, HIP events) and wall
+ * time of the last rip_graph call made by the calling thread, in ms. */
+bc_status rip_graph_timing(double* spgemm_ms, double* total_ms);
+
+/* Deterministic greedy K-way partition of a graph with integer edge weights
+ * (the project's replacement for METIS on G_RIP, Sections 2.3 and 3.1; unit
+ * vertex weights, balance cap W_max = max(floor(1.1 n / K), ceil(n / K)) of
+ * eq. (partbal)).  Growth: parts 0..K-2 are grown in turn to
+ * ceil(remaining / parts left) vertices from the lowest-index unassigned
+ * vertex, always adding the unassigned vertex with the largest total weight
+ * into the part (ties: lower index; none touching: lowest unassigned); the
+ * last part takes the rest.  Refinement: `passes` sweeps in ascending vertex
+ * order move a vertex to the part with the largest positive gain that stays
+ * within W_max, keeping its source part nonempty (ties: lower part id).
+ * Host arrays: rowptr int64[n+1], col int32[nnz] (symmetric, no diagonal),
+ * wgt int64[nnz] >= 1; part int32[n] output.  Errors: BC_ERR_INVALID. */
+bc_status bc_partition_greedy(int32_t n, const int64_t* rowptr, const int32_t* col,
+                              const int64_t* wgt, int32_t K, int32_t passes, int32_t* part);
+
+/* Cutsize of a partition: sum of cost over cut edges, each undirected edge
+ * once (eq. (partcut)), and the same sum over the integer weights.  Host arrays. */
+bc_status bc_partition_cut(int32_t n, const int64_t* rowptr, const int32_t* col,
+                           const double* cost, const int64_t* wgt, const int32_t* part,
+                           double* cutsize, int64_t* int_cut);
+
+const char* bc_status_str(bc_status s);
+const char* bc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BC_H */

@@ -1,0 +1,1249 @@
+// C-ABI entry points: setup (validation, block permutation, transposes,
+// per-block metadata, dense factorisation), projection and solve drivers,
+// and the row inner-product graph builder.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_last_error;
+void bc_set_error(const std::string& msg) { g_last_error = msg; }
+
+extern "C" const char* bc_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* bc_status_str(bc_status s) {
+  switch (s) {
+    case BC_OK: return "ok";
+    case BC_NOT_CONVERGED: return "not converged";
+    case BC_ERR_INVALID: return "invalid argument";
+    case BC_ERR_SINGULAR_BLOCK: return "singular block";
+    case BC_ERR_BREAKDOWN: return "CG breakdown";
+    case BC_ERR_DEVICE: return "device error";
+    case BC_ERR_NOMEM: return "out of memory";
+  }
+  return "unknown status";
+}
+
+extern "C" void bc_opts_default(bc_opts* o) {
+  if (!o) return;
+  o->precision = BC_FP64;
+  o->projection = BC_PROJ_AUTO;
+  o->dense_max_m = 4096;
+  o->inner_tol = 1e-12;
+  o->inner_maxit = 20000;
+  o->inner_groups = 0;
+  o->replace_every = 20;
+  o->stop_rule = BC_STOP_REL2;
+  o->check_every = 8;
+  o->spmv_lanes = 0;
+  o->stream = nullptr;
+}
+
+extern "C" void rip_opts_default(rip_opts* o) {
+  if (!o) return;
+  o->prescale = 1;
+  o->sparsify = 1;
+  o->alpha = (int64_t)1 << 20;
+  o->stream = nullptr;
+}
+
+// launchers defined in the other translation units
+hipError_t launch_gram(hipStream_t st, const DenseBlocks& D, const int4* tiles, int ntiles,
+                       const int* rowptr, const int* col, const double* val, const int* tptr,
+                       const int* trow, const double* tval);
+int inner_max_resident_groups(bool mixed);
+int* inner_err_flag();
+hipError_t rip_launch_prescale(hipStream_t st, int n, long long nnz, const int* rowptr,
+                               double* aval, const int* trow, double* tval, double* nrm,
+                               int* zero_row);
+hipError_t rip_launch_sparsify(hipStream_t st, const int* dense_cols, int ndense, int t,
+                               const int* tptr, const int* trow, double* tval,
+                               const long long* tpos, double* aval);
+hipError_t rip_launch_col_nonzeros(hipStream_t st, int n, const int* tptr, const double* tval,
+                                   int* cnt);
+hipError_t rip_launch_compact(hipStream_t st, int n, const int* tptr, const int* trow,
+                              const double* tval, const int* cptr, int* crow, double* cval);
+hipError_t rip_launch_row_products(hipStream_t st, int n, const int* rowptr, const int* col,
+                                   const double* aval, const int* cptr, long long* ub);
+hipError_t rip_launch_short(hipStream_t st, bool emit, const int* rows, int nrows,
+                            const int* rowptr, const int* col, const double* aval,
+                            const int* cptr, const int* crow, const double* cval, int* cnt,
+                            const long long* optr, int* ocol, double* ocost, long long* owgt,
+                            double alpha, int* overflow);
+hipError_t rip_launch_long(hipStream_t st, bool emit, const int* rows, int nrows,
+                           const long long* toff, const int* tsize, const int* rowptr,
+                           const int* col, const double* aval, const int* cptr, const int* crow,
+                           const double* cval, int* gkeys, double* gvals, int* cnt,
+                           const long long* optr, int* ocol, double* ocost, long long* owgt,
+                           double alpha, int* overflow);
+int rip_short_max();
+
+// ------------------------------------------------------------- helpers
+
+namespace {
+
+// Device allocations of one owner, released together.
+struct Arena {
+  std::vector<void*> ptrs;
+  ~Arena() { release(); }
+  void release() {
+    for (void* p : ptrs) (void)hipFree(p);
+    ptrs.clear();
+  }
+  template <typename T>
+  bc_status alloc(T** out, size_t count) {
+    *out = nullptr;
+    if (count == 0) count = 1;
+    void* p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+      (void)hipGetLastError();
+      bc_set_error("hipMalloc of " + std::to_string(count * sizeof(T)) + " bytes failed");
+      return BC_ERR_NOMEM;
+    }
+    ptrs.push_back(p);
+    *out = (T*)p;
+    return BC_OK;
+  }
+  template <typename T>
+  bc_status upload(T** out, const std::vector<T>& v, hipStream_t st) {
+    bc_status s = alloc(out, v.size());
+    if (s != BC_OK) return s;
+    if (!v.empty() &&
+        hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st) != hipSuccess) {
+      bc_set_error("host-to-device copy failed");
+      return BC_ERR_DEVICE;
+    }
+    return BC_OK;
+  }
+};
+
+#define BC_TRY(expr)             \
+  do {                           \
+    bc_status s_ = (expr);       \
+    if (s_ != BC_OK) return s_;  \
+  } while (0)
+
+bool is_gfx950_device() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+  return std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+}
+
+bc_status check_device() {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    bc_set_error("no HIP device available");
+    return BC_ERR_DEVICE;
+  }
+  if (!is_gfx950_device()) {
+    bc_set_error("this library is built for gfx950 (MI355X) only");
+    return BC_ERR_DEVICE;
+  }
+  return BC_OK;
+}
+
+bc_status validate_csr(int32_t n, const int32_t* rowptr, const int32_t* colidx, const double* vals,
+                       const char* who) {
+  if (n < 1 || !rowptr) {
+    bc_set_error(std::string(who) + ": n must be >= 1 and rowptr non-null");
+    return BC_ERR_INVALID;
+  }
+  if (rowptr[0] != 0) {
+    bc_set_error(std::string(who) + ": rowptr[0] != 0");
+    return BC_ERR_INVALID;
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    if (rowptr[i + 1] < rowptr[i]) {
+      bc_set_error(std::string(who) + ": rowptr decreases at row " + std::to_string(i));
+      return BC_ERR_INVALID;
+    }
+  }
+  const int64_t nnz = rowptr[n];
+  if (nnz > 0 && (!colidx || !vals)) {
+    bc_set_error(std::string(who) + ": null colidx/vals");
+    return BC_ERR_INVALID;
+  }
+  for (int32_t i = 0; i < n; ++i) {
+    for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      const int32_t c = colidx[e];
+      if (c < 0 || c >= n) {
+        bc_set_error(std::string(who) + ": column index out of range in row " + std::to_string(i));
+        return BC_ERR_INVALID;
+      }
+      if (e > rowptr[i] && colidx[e - 1] >= c) {
+        bc_set_error(std::string(who) + ": columns not strictly ascending in row " + std::to_string(i));
+        return BC_ERR_INVALID;
+      }
+      if (!std::isfinite(vals[e])) {
+        bc_set_error(std::string(who) + ": non-finite value in row " + std::to_string(i));
+        return BC_ERR_INVALID;
+      }
+    }
+  }
+  return BC_OK;
+}
+
+int choose_lanes(int64_t nnz, int64_t rows) {
+  const double avg = rows ? (double)nnz / (double)rows : 1.0;
+  int l = 1;
+  while (l < 64 && l * 2 <= avg) l <<= 1;
+  return std::max(1, std::min(64, l));
+}
+
+struct SysIn {
+  int32_t n;
+  const int32_t* rowptr;
+  const int32_t* col;
+  const double* val;
+  int32_t K;
+  const int32_t* part;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+
+struct bc_ctx {
+  Arena arena;
+  bc_opts opts;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev_sync = nullptr;
+  std::vector<hipEvent_t> ev_proj;  // pairs around projection launches
+  bool mixed = false;
+  int nsys = 0;
+  int n_total = 0;
+  long long nnz_total = 0;
+  int lanes = 4;
+  std::vector<int> sys_off;        // nsys + 1
+  std::vector<double> normA_inf;   // per system
+  // permuted A and A^T
+  int* d_perm = nullptr;           // permuted row -> original (global) row
+  int* d_rowptr = nullptr;
+  int* d_col = nullptr;
+  double* d_val = nullptr;
+  float* d_val32 = nullptr;
+  int* d_tptr = nullptr;
+  int* d_trow = nullptr;
+  double* d_tval = nullptr;
+  float* d_tval32 = nullptr;
+  // tiles
+  int ntiles = 0;
+  int* d_tile_start = nullptr;
+  int* d_tile_sys = nullptr;
+  int* d_sys_tile = nullptr;
+  // per-system state
+  int* d_done = nullptr;
+  int* d_zero_flags = nullptr;
+  int* d_iters = nullptr;
+  int* d_status = nullptr;
+  int* d_pending = nullptr;
+  int* d_mask = nullptr;
+  double* d_thr = nullptr;
+  double* d_rr = nullptr;
+  double* d_hist = nullptr;
+  double *d_part_a = nullptr, *d_part_b = nullptr, *d_part_c = nullptr, *d_part_f = nullptr;
+  double *d_part_d = nullptr, *d_part_e = nullptr, *d_part_g = nullptr;
+  double* d_normA = nullptr;
+  double* d_finf = nullptr;
+  // vectors
+  double *d_r = nullptr, *d_p = nullptr, *d_psi = nullptr;
+  double *d_s = nullptr, *d_u = nullptr, *d_y = nullptr, *d_f = nullptr;
+  // blocks
+  int nblk = 0;
+  InnerBlocks inner{};
+  DenseBlocks dense{};
+  unsigned long long* d_inner_total = nullptr;
+  std::vector<int> blk_m;
+  std::vector<int> blk_dense;
+
+  ~bc_ctx() {
+    for (hipEvent_t e : ev_proj) (void)hipEventDestroy(e);
+    if (ev_sync) (void)hipEventDestroy(ev_sync);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
+
+  OuterState outer(int maxit, int use_backward) const {
+    OuterState S;
+    S.nsys = nsys;
+    S.ntiles = ntiles;
+    S.tile_start = d_tile_start;
+    S.tile_sys = d_tile_sys;
+    S.sys_tile = d_sys_tile;
+    S.done = d_done;
+    S.iters = d_iters;
+    S.status = d_status;
+    S.thr = d_thr;
+    S.maxit = maxit;
+    S.part_a = d_part_a;
+    S.part_b = d_part_b;
+    S.part_c = d_part_c;
+    S.rr = d_rr;
+    S.hist = d_hist;
+    S.pending = d_pending;
+    S.use_backward = use_backward;
+    S.tol_bw = 0.0;
+    S.part_d = d_part_d;
+    S.part_e = d_part_e;
+    S.part_g = d_part_g;
+    S.normA = d_normA;
+    S.finf = d_finf;
+    return S;
+  }
+};
+
+namespace {
+
+// Enter/leave the library stream in the order of the caller's stream.
+bc_status enter(bc_ctx* c, void* user_stream) {
+  BC_HIP(hipEventRecord(c->ev_sync, (hipStream_t)user_stream));
+  BC_HIP(hipStreamWaitEvent(c->stream, c->ev_sync, 0));
+  return BC_OK;
+}
+bc_status leave(bc_ctx* c, void* user_stream) {
+  BC_HIP(hipEventRecord(c->ev_sync, c->stream));
+  BC_HIP(hipStreamWaitEvent((hipStream_t)user_stream, c->ev_sync, 0));
+  BC_HIP(hipStreamSynchronize(c->stream));
+  return BC_OK;
+}
+
+bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
+  const bc_opts& o = c->opts;
+  c->mixed = o.precision == BC_MIXED;
+  c->nsys = (int)sys.size();
+  // ---- sizes
+  c->sys_off.assign(c->nsys + 1, 0);
+  long long ntot = 0, nnz = 0;
+  for (int s = 0; s < c->nsys; ++s) {
+    ntot += sys[s].n;
+    nnz += sys[s].rowptr[sys[s].n];
+    c->sys_off[s + 1] = (int)std::min<long long>(ntot, INT32_MAX);
+  }
+  if (ntot > INT32_MAX / 2 || nnz > INT32_MAX) {
+    bc_set_error("problem too large for 32-bit indices");
+    return BC_ERR_INVALID;
+  }
+  c->n_total = (int)ntot;
+  c->nnz_total = nnz;
+  const int n = c->n_total;
+  // ---- permutation and blocks
+  std::vector<int> perm(n);
+  std::vector<int> blk_row0, blk_m, blk_sys;
+  for (int s = 0; s < c->nsys; ++s) {
+    const SysIn& S = sys[s];
+    std::vector<int> cnt(S.K + 1, 0);
+    for (int r = 0; r < S.n; ++r) cnt[S.part[r] + 1]++;
+    for (int k = 0; k < S.K; ++k) {
+      if (cnt[k + 1] == 0) {
+        bc_set_error("empty block " + std::to_string(k) + " in system " + std::to_string(s));
+        return BC_ERR_INVALID;
+      }
+    }
+    std::vector<int> start(S.K + 1, 0);
+    for (int k = 0; k < S.K; ++k) start[k + 1] = start[k] + cnt[k + 1];
+    for (int k = 0; k < S.K; ++k) {
+      blk_row0.push_back(c->sys_off[s] + start[k]);
+      blk_m.push_back(cnt[k + 1]);
+      blk_sys.push_back(s);
+    }
+    std::vector<int> cur(start.begin(), start.end() - 1);
+    for (int r = 0; r < S.n; ++r) perm[c->sys_off[s] + cur[S.part[r]]++] = c->sys_off[s] + r;
+  }
+  c->nblk = (int)blk_m.size();
+  c->blk_m = blk_m;
+  // ---- permuted CSR (global columns)
+  std::vector<int> rowptr(n + 1, 0), col(nnz);
+  std::vector<double> val(nnz);
+  std::vector<int> row_sys(n);
+  c->normA_inf.assign(c->nsys, 0.0);
+  {
+    int e = 0;
+    for (int i = 0; i < n; ++i) {
+      const int g = perm[i];
+      const int s = (int)(std::upper_bound(c->sys_off.begin(), c->sys_off.end(), g) - c->sys_off.begin()) - 1;
+      row_sys[i] = s;
+      const int r = g - c->sys_off[s];
+      const SysIn& S = sys[s];
+      double rs = 0.0;
+      for (int q = S.rowptr[r]; q < S.rowptr[r + 1]; ++q) {
+        col[e] = S.col[q] + c->sys_off[s];
+        val[e] = S.val[q];
+        rs += std::fabs(S.val[q]);
+        ++e;
+      }
+      c->normA_inf[s] = std::max(c->normA_inf[s], rs);
+      rowptr[i + 1] = e;
+    }
+  }
+  // ---- A^T: per column, permuted rows ascending
+  std::vector<int> tptr(n + 1, 0), trow(nnz);
+  std::vector<double> tval(nnz);
+  for (long long e = 0; e < nnz; ++e) tptr[col[e] + 1]++;
+  for (int j = 0; j < n; ++j) tptr[j + 1] += tptr[j];
+  {
+    std::vector<int> cur(tptr.begin(), tptr.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int q = cur[col[e]]++;
+        trow[q] = i;
+        tval[q] = val[e];
+      }
+  }
+  // ---- tiles
+  std::vector<int> tile_start, tile_sys, sys_tile(c->nsys + 1, 0);
+  for (int s = 0; s < c->nsys; ++s) {
+    for (int a = c->sys_off[s]; a < c->sys_off[s + 1]; a += TILE) {
+      tile_start.push_back(a);
+      tile_sys.push_back(s);
+    }
+    sys_tile[s + 1] = (int)tile_start.size();
+  }
+  c->ntiles = (int)tile_start.size();
+  tile_start.push_back(n);
+  c->lanes = o.spmv_lanes > 0 ? o.spmv_lanes : choose_lanes(nnz, n);
+  // ---- block kinds
+  const int dmax = std::min(o.dense_max_m, 4096);
+  std::vector<int> is_dense(c->nblk, 0);
+  for (int b = 0; b < c->nblk; ++b) {
+    if (o.projection == BC_PROJ_DENSE_CHOL) {
+      if (blk_m[b] > 4096) {
+        bc_set_error("dense Cholesky projection needs blocks of at most 4096 rows");
+        return BC_ERR_INVALID;
+      }
+      is_dense[b] = 1;
+    } else if (o.projection == BC_PROJ_AUTO) {
+      is_dense[b] = blk_m[b] <= dmax;
+    }
+  }
+  c->blk_dense = is_dense;
+  // ---- inner-CG block data
+  std::vector<int> in_row0, in_m, in_sup0, in_nsup, in_sys;
+  std::vector<int> loc(nnz, 0), btptr(1, 0), btrow;
+  std::vector<double> btval;
+  {
+    std::vector<int> mark(n, -1);
+    int sup_total = 0;
+    for (int b = 0; b < c->nblk; ++b) {
+      if (is_dense[b]) continue;
+      const int r0 = blk_row0[b], m = blk_m[b];
+      std::vector<int> sup;
+      for (int i = r0; i < r0 + m; ++i)
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) sup.push_back(col[e]);
+      std::sort(sup.begin(), sup.end());
+      sup.erase(std::unique(sup.begin(), sup.end()), sup.end());
+      for (size_t q = 0; q < sup.size(); ++q) mark[sup[q]] = (int)q;
+      for (int i = r0; i < r0 + m; ++i)
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) loc[e] = mark[col[e]];
+      // transposed block CSR: support columns ascending, rows ascending
+      std::vector<int> cnt(sup.size() + 1, 0);
+      for (int i = r0; i < r0 + m; ++i)
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) cnt[mark[col[e]] + 1]++;
+      for (size_t q = 0; q < sup.size(); ++q) cnt[q + 1] += cnt[q];
+      const int base = (int)btrow.size();
+      btrow.resize(base + cnt[sup.size()]);
+      btval.resize(base + cnt[sup.size()]);
+      std::vector<int> cur(cnt.begin(), cnt.end() - 1);
+      for (int i = r0; i < r0 + m; ++i)
+        for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+          const int q = base + cur[mark[col[e]]]++;
+          btrow[q] = i - r0;
+          btval[q] = val[e];
+        }
+      for (size_t q = 0; q < sup.size(); ++q) btptr.push_back(base + cnt[q + 1]);
+      for (int cc : sup) mark[cc] = -1;
+      in_row0.push_back(r0);
+      in_m.push_back(m);
+      in_sup0.push_back(sup_total);
+      in_nsup.push_back((int)sup.size());
+      in_sys.push_back(blk_sys[b]);
+      sup_total += (int)sup.size();
+    }
+  }
+  // ---- dense block data
+  std::vector<int> dn_row0, dn_m, dn_nt, dn_sys;
+  std::vector<long long> dn_loff, dn_doff;
+  std::vector<int4> gram_tiles;
+  long long ltot = 0, dtot = 0;
+  for (int b = 0; b < c->nblk; ++b) {
+    if (!is_dense[b]) continue;
+    const int m = blk_m[b], nt = (m + DT - 1) / DT;
+    const int db = (int)dn_m.size();
+    dn_row0.push_back(blk_row0[b]);
+    dn_m.push_back(m);
+    dn_nt.push_back(nt);
+    dn_sys.push_back(blk_sys[b]);
+    dn_loff.push_back(ltot);
+    dn_doff.push_back(dtot);
+    ltot += (long long)nt * (nt + 1) / 2 * DT * DT;
+    dtot += 2LL * nt * DT * DT;
+    for (int i = 0; i < nt; ++i)
+      for (int j = 0; j <= i; ++j) gram_tiles.push_back(make_int4(db, i, j, 0));
+  }
+  // ---- device state
+  hipStream_t st = c->stream;
+  Arena& A = c->arena;
+  BC_TRY(A.upload(&c->d_perm, perm, st));
+  BC_TRY(A.upload(&c->d_rowptr, rowptr, st));
+  BC_TRY(A.upload(&c->d_col, col, st));
+  BC_TRY(A.upload(&c->d_val, val, st));
+  BC_TRY(A.upload(&c->d_tptr, tptr, st));
+  BC_TRY(A.upload(&c->d_trow, trow, st));
+  BC_TRY(A.upload(&c->d_tval, tval, st));
+  if (c->mixed) {
+    std::vector<float> v32(val.begin(), val.end()), t32(tval.begin(), tval.end());
+    BC_TRY(A.upload(&c->d_val32, v32, st));
+    BC_TRY(A.upload(&c->d_tval32, t32, st));
+  }
+  BC_TRY(A.upload(&c->d_tile_start, tile_start, st));
+  BC_TRY(A.upload(&c->d_tile_sys, tile_sys, st));
+  BC_TRY(A.upload(&c->d_sys_tile, sys_tile, st));
+  const int ns = c->nsys;
+  std::vector<int> zeros_ns(ns, 0);
+  BC_TRY(A.upload(&c->d_done, zeros_ns, st));
+  BC_TRY(A.upload(&c->d_zero_flags, zeros_ns, st));
+  BC_TRY(A.upload(&c->d_iters, zeros_ns, st));
+  BC_TRY(A.upload(&c->d_status, zeros_ns, st));
+  BC_TRY(A.upload(&c->d_pending, zeros_ns, st));
+  BC_TRY(A.upload(&c->d_mask, zeros_ns, st));
+  BC_TRY(A.alloc(&c->d_thr, ns));
+  BC_TRY(A.alloc(&c->d_rr, 2 * ns));
+  BC_TRY(A.alloc(&c->d_hist, ns));
+  BC_TRY(A.alloc(&c->d_part_a, c->ntiles));
+  BC_TRY(A.alloc(&c->d_part_b, c->ntiles));
+  BC_TRY(A.alloc(&c->d_part_c, c->ntiles));
+  BC_TRY(A.alloc(&c->d_part_f, c->ntiles));
+  BC_TRY(A.alloc(&c->d_part_d, c->ntiles));
+  BC_TRY(A.alloc(&c->d_part_e, c->ntiles));
+  BC_TRY(A.alloc(&c->d_part_g, c->ntiles));
+  BC_TRY(A.upload(&c->d_normA, c->normA_inf, st));
+  BC_TRY(A.alloc(&c->d_finf, ns));
+  BC_TRY(A.alloc(&c->d_r, n));
+  BC_TRY(A.alloc(&c->d_p, n));
+  BC_TRY(A.alloc(&c->d_psi, n));
+  BC_TRY(A.alloc(&c->d_s, n));
+  BC_TRY(A.alloc(&c->d_u, n));
+  BC_TRY(A.alloc(&c->d_y, n));
+  BC_TRY(A.alloc(&c->d_f, n));
+  BC_TRY(A.alloc(&c->d_inner_total, 1));
+  // inner blocks
+  InnerBlocks& B = c->inner;
+  B = InnerBlocks{};
+  B.nblk = (int)in_m.size();
+  if (B.nblk > 0) {
+    int *p0, *p1, *p2, *p3, *p4, *ploc, *pbp, *pbr;
+    double* pbv;
+    BC_TRY(A.upload(&p0, in_row0, st));
+    BC_TRY(A.upload(&p1, in_m, st));
+    BC_TRY(A.upload(&p2, in_sup0, st));
+    BC_TRY(A.upload(&p3, in_nsup, st));
+    BC_TRY(A.upload(&p4, in_sys, st));
+    BC_TRY(A.upload(&ploc, loc, st));
+    BC_TRY(A.upload(&pbp, btptr, st));
+    BC_TRY(A.upload(&pbr, btrow, st));
+    BC_TRY(A.upload(&pbv, btval, st));
+    B.row0 = p0; B.m = p1; B.sup0 = p2; B.nsup = p3; B.sys = p4;
+    B.rowptr = c->d_rowptr; B.loc = ploc; B.val = c->d_val; B.val32 = c->d_val32;
+    B.btptr = pbp; B.btrow = pbr; B.btval = pbv;
+    const int sup_total = (int)btptr.size() - 1;
+    if (c->mixed) {
+      std::vector<float> b32(btval.begin(), btval.end());
+      float* pb32;
+      BC_TRY(A.upload(&pb32, b32, st));
+      B.btval32 = pb32;
+      BC_TRY(A.alloc(&B.q32, n));
+      BC_TRY(A.alloc(&B.z32, n));
+      BC_TRY(A.alloc(&B.ri32, n));
+      BC_TRY(A.alloc(&B.t32, sup_total));
+    } else {
+      BC_TRY(A.alloc(&B.q, n));
+      BC_TRY(A.alloc(&B.z, n));
+      BC_TRY(A.alloc(&B.ri, n));
+      BC_TRY(A.alloc(&B.t, sup_total));
+    }
+    // workgroups per block: fill the chip once, at least 512 rows each
+    int G = o.inner_groups;
+    if (G <= 0) {
+      G = std::max(1, 256 / std::max(1, B.nblk));
+      const int minm = *std::min_element(in_m.begin(), in_m.end());
+      G = std::max(1, std::min(G, minm / 512));
+      G = std::min(G, 16);
+    }
+    if (G > 1) {
+      const int per_xcd = (B.nblk + 7) / 8;
+      const int cap = inner_max_resident_groups(c->mixed);
+      while (G > 1 && per_xcd * G * 8 > cap) --G;
+    }
+    B.groups = G;
+    BC_TRY(A.alloc(&B.red, (size_t)B.nblk * 2 * G));
+    std::vector<unsigned> bz(2 * B.nblk, 0u);
+    unsigned* pbar;
+    BC_TRY(A.upload(&pbar, bz, st));
+    B.bar = pbar;
+    std::vector<int> iz(B.nblk, 0);
+    int* pit;
+    BC_TRY(A.upload(&pit, iz, st));
+    B.iters = pit;
+    B.total = c->d_inner_total;
+    B.tol = (c->mixed && o.inner_tol < 1e-5) ? 1e-5 : o.inner_tol;
+    B.maxit = o.inner_maxit;
+  }
+  // dense blocks
+  DenseBlocks& D = c->dense;
+  D = DenseBlocks{};
+  D.nblk = (int)dn_m.size();
+  if (D.nblk > 0) {
+    int *p0, *p1, *p2, *p3, *pinfo;
+    long long *pl, *pd;
+    int4* ptiles;
+    BC_TRY(A.upload(&p0, dn_row0, st));
+    BC_TRY(A.upload(&p1, dn_m, st));
+    BC_TRY(A.upload(&p2, dn_nt, st));
+    BC_TRY(A.upload(&p3, dn_sys, st));
+    BC_TRY(A.upload(&pl, dn_loff, st));
+    BC_TRY(A.upload(&pd, dn_doff, st));
+    BC_TRY(A.upload(&ptiles, gram_tiles, st));
+    std::vector<int> iz(D.nblk, 0);
+    BC_TRY(A.upload(&pinfo, iz, st));
+    D.row0 = p0; D.m = p1; D.nt = p2; D.sys = p3; D.loff = pl; D.doff = pd; D.info = pinfo;
+    BC_TRY(A.alloc(&D.gdiag, n));
+    BC_TRY(A.alloc(&D.L, ltot));
+    BC_TRY(A.alloc(&D.LT, ltot));
+    BC_TRY(A.alloc(&D.Dinv, dtot));
+    if (c->mixed) {
+      BC_TRY(A.alloc(&D.L32, ltot));
+      BC_TRY(A.alloc(&D.LT32, ltot));
+      BC_TRY(A.alloc(&D.Dinv32, dtot));
+    }
+    BC_HIP(launch_gram(st, D, ptiles, (int)gram_tiles.size(), c->d_rowptr, c->d_col, c->d_val,
+                       c->d_tptr, c->d_trow, c->d_tval));
+    BC_HIP(launch_cholesky(st, D));
+    BC_HIP(launch_dense_finish(st, D, c->mixed));
+    std::vector<int> info(D.nblk);
+    BC_HIP(hipMemcpyAsync(info.data(), pinfo, D.nblk * sizeof(int), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < D.nblk; ++b)
+      if (info[b] != 0) {
+        bc_set_error("block " + std::to_string(b) + " of the dense projections has a non-positive "
+                     "pivot at row " + std::to_string(info[b] - 1) + ": A_i A_i^T is numerically singular");
+        return BC_ERR_SINGULAR_BLOCK;
+      }
+  }
+  BC_HIP(hipStreamSynchronize(st));
+  return BC_OK;
+}
+
+bc_status new_ctx(bc_ctx** out, const bc_opts* opts) {
+  *out = nullptr;
+  BC_TRY(check_device());
+  bc_ctx* c = new (std::nothrow) bc_ctx();
+  if (!c) {
+    bc_set_error("host allocation failed");
+    return BC_ERR_NOMEM;
+  }
+  if (opts) c->opts = *opts; else bc_opts_default(&c->opts);
+  if (c->opts.check_every < 1) c->opts.check_every = 1;
+  if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&c->ev_sync, hipEventDisableTiming) != hipSuccess) {
+    delete c;
+    bc_set_error("stream/event creation failed");
+    return BC_ERR_DEVICE;
+  }
+  *out = c;
+  return BC_OK;
+}
+
+}  // namespace
+
+extern "C" bc_status bc_setup_batched(bc_ctx** ctx, int32_t nsys, const int32_t* n,
+                                      const int32_t* const* rowptr, const int32_t* const* colidx,
+                                      const double* const* vals, const int32_t* K,
+                                      const int32_t* const* part, const bc_opts* opts) {
+  if (!ctx) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  *ctx = nullptr;
+  if (nsys < 1 || !n || !rowptr || !colidx || !vals || !K || !part) {
+    bc_set_error("bc_setup_batched: null argument or nsys < 1");
+    return BC_ERR_INVALID;
+  }
+  if (opts && (opts->precision != BC_FP64 && opts->precision != BC_MIXED)) {
+    bc_set_error("unknown precision");
+    return BC_ERR_INVALID;
+  }
+  if (opts && (opts->projection < BC_PROJ_AUTO || opts->projection > BC_PROJ_INNER_CG ||
+               opts->inner_tol < 0.0 || opts->inner_maxit < 1 || opts->dense_max_m < 0 ||
+               opts->stop_rule < 0 || opts->stop_rule > 1 || opts->spmv_lanes < 0 ||
+               (opts->spmv_lanes & (opts->spmv_lanes - 1)) || opts->spmv_lanes > 64)) {
+    bc_set_error("invalid option value");
+    return BC_ERR_INVALID;
+  }
+  std::vector<SysIn> sys(nsys);
+  for (int s = 0; s < nsys; ++s) {
+    BC_TRY(validate_csr(n[s], rowptr[s], colidx[s], vals[s], "bc_setup"));
+    if (K[s] < 1 || K[s] > n[s] || !part[s]) {
+      bc_set_error("K must satisfy 1 <= K <= n and part must be non-null");
+      return BC_ERR_INVALID;
+    }
+    std::vector<int> used(K[s], 0);
+    for (int r = 0; r < n[s]; ++r) {
+      if (part[s][r] < 0 || part[s][r] >= K[s]) {
+        bc_set_error("part[" + std::to_string(r) + "] outside [0, K)");
+        return BC_ERR_INVALID;
+      }
+      used[part[s][r]] = 1;
+    }
+    for (int k = 0; k < K[s]; ++k)
+      if (!used[k]) {
+        bc_set_error("empty block " + std::to_string(k) + " in system " + std::to_string(s));
+        return BC_ERR_INVALID;
+      }
+    sys[s] = SysIn{n[s], rowptr[s], colidx[s], vals[s], K[s], part[s]};
+  }
+  bc_ctx* c = nullptr;
+  BC_TRY(new_ctx(&c, opts));
+  bc_status st = setup_impl(c, sys);
+  if (st != BC_OK) {
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+    return st;
+  }
+  *ctx = c;
+  return BC_OK;
+}
+
+extern "C" bc_status bc_setup(bc_ctx** ctx, int32_t n, const int32_t* rowptr,
+                              const int32_t* colidx, const double* vals, int32_t K,
+                              const int32_t* part, const bc_opts* opts) {
+  return bc_setup_batched(ctx, 1, &n, &rowptr, &colidx, &vals, &K, &part, opts);
+}
+
+extern "C" void bc_destroy(bc_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+extern "C" bc_status bc_info(const bc_ctx* c, int64_t* n_total, int32_t* nsys, int32_t* nblocks,
+                             int32_t* ndense) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  if (n_total) *n_total = c->n_total;
+  if (nsys) *nsys = c->nsys;
+  if (nblocks) *nblocks = c->nblk;
+  if (ndense) *ndense = c->dense.nblk;
+  return BC_OK;
+}
+
+// ------------------------------------------------------------- projections
+
+namespace {
+
+// y = D^{-1} u block by block (dense sweeps and inner CG).
+bc_status block_solves(bc_ctx* c, const double* u, double* y, const int* done) {
+  hipStream_t st = c->stream;
+  BC_HIP(launch_dense_apply(st, c->dense, c->mixed, u, y, done));
+  BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u, y, done));
+  return BC_OK;
+}
+
+
+}  // namespace
+
+extern "C" bc_status bc_project(bc_ctx* c, const double* v, double* Hv) {
+  if (!c || !v || !Hv) {
+    bc_set_error("bc_project: null argument");
+    return BC_ERR_INVALID;
+  }
+  BC_TRY(enter(c, c->opts.stream));
+  OuterState S = c->outer(0, 0);
+  S.done = c->d_zero_flags;
+  hipStream_t st = c->stream;
+  BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->mixed, v,
+                     c->d_u, S, false));
+  BC_TRY(block_solves(c, c->d_u, c->d_y, nullptr));
+  BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->mixed,
+                          c->d_y, Hv, v, S));
+  BC_TRY(leave(c, c->opts.stream));
+  int* err = inner_err_flag();
+  int h = 0;
+  BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
+  if (h) {
+    bc_set_error("inner CG workgroups timed out waiting for each other");
+    return BC_ERR_DEVICE;
+  }
+  return BC_OK;
+}
+
+// ------------------------------------------------------------------- solve
+
+namespace {
+
+bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, int maxit,
+                     double* x, bc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!f || !x || !(tol >= 0.0) || maxit < 0) {
+    bc_set_error("bc_solve: null f/x, negative tol or maxit");
+    return BC_ERR_INVALID;
+  }
+  const bc_opts& o = c->opts;
+  hipStream_t st = c->stream;
+  const int n = c->n_total, ns = c->nsys;
+  const bool backward = o.stop_rule == BC_STOP_BACKWARD_ERR;
+  BC_TRY(enter(c, o.stream));
+  OuterState S = c->outer(maxit, backward ? 1 : 0);
+  S.tol_bw = tol;
+  // f in block order, x = x0 (or 0), s = f - A x
+  BC_HIP(launch_gather(st, f, c->d_perm, c->d_f, n));
+  if (x0) BC_HIP(launch_copy(st, x0, x, n)); else BC_HIP(launch_zero(st, x, n));
+  BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s, S,
+                         nullptr));
+  BC_HIP(launch_init_norms(st, c->d_f, c->d_s, x, c->d_part_f, S));
+  BC_HIP(launch_set_thresholds(st, c->d_part_f, backward ? 0.0 : tol, S));
+  BC_HIP(hipMemsetAsync(c->d_inner_total, 0, sizeof(unsigned long long), st));
+  // r = sum_i A_i^+ (f_i - A_i x0) = A^T D^{-1} s ; p = r
+  BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
+  BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->mixed,
+                          c->d_y, c->d_r, c->d_p, S));
+  BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S));
+
+  // projection timing events
+  const int R = o.check_every;
+  if ((int)c->ev_proj.size() < 2 * R) {
+    for (int q = (int)c->ev_proj.size(); q < 2 * R; ++q) {
+      hipEvent_t e;
+      BC_HIP(hipEventCreate(&e));
+      c->ev_proj.push_back(e);
+    }
+  }
+  std::vector<int> done(ns, 0), status(ns, 0), iters(ns, 0);
+  std::vector<int> verified(ns, 0), replacements(ns, 0);
+  double t_proj = 0.0;
+  int proj_launches = 0;
+  int it = 0;
+  BC_HIP(hipMemcpyAsync(done.data(), c->d_done, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  BC_HIP(hipStreamSynchronize(st));
+  bool all_done = std::all_of(done.begin(), done.end(), [](int d) { return d != 0; });
+  while (!all_done && it < maxit) {
+    int nrec = 0;
+    for (int q = 0; q < R && it < maxit; ++q) {
+      ++it;
+      BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->mixed,
+                         c->d_p, c->d_u, S, true));
+      BC_HIP(hipEventRecord(c->ev_proj[2 * nrec], st));
+      BC_TRY(block_solves(c, c->d_u, c->d_y, c->d_done));
+      BC_HIP(hipEventRecord(c->ev_proj[2 * nrec + 1], st));
+      ++nrec;
+      BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
+                              c->mixed, c->d_y, c->d_psi, c->d_p, S));
+      BC_HIP(launch_update_xrs(st, x, c->d_r, c->d_s, c->d_p, c->d_psi, c->d_u, S, it));
+      BC_HIP(launch_update_p(st, c->d_p, c->d_r, S, it));
+      if (c->mixed && o.replace_every > 0 && it % o.replace_every == 0) {
+        // FP64 true residual s = f - A x, then r = A^T D^{-1} s through the
+        // working-precision projection; p is kept
+        BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s,
+                               S, nullptr));
+        BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
+        BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
+                                c->mixed, c->d_y, c->d_r, c->d_p, S));
+        BC_HIP(launch_sqnorm_tiles(st, c->d_r, c->d_part_b, S));
+        BC_HIP(launch_rr_from_partials(st, S, it & 1));
+        for (int s2 = 0; s2 < ns; ++s2) replacements[s2]++;
+      }
+    }
+    BC_HIP(hipMemcpyAsync(done.data(), c->d_done, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipMemcpyAsync(status.data(), c->d_status, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+    for (int q = 0; q < nrec; ++q) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, c->ev_proj[2 * q], c->ev_proj[2 * q + 1]) == hipSuccess) {
+        t_proj += ms;
+        ++proj_launches;
+      }
+    }
+    // verify newly converged systems on the true residual; resume those that fail
+    std::vector<int> mask(ns, 0);
+    bool any = false;
+    for (int s2 = 0; s2 < ns; ++s2)
+      if (done[s2] && status[s2] == BC_OK && !verified[s2] && !backward) {
+        mask[s2] = 1;
+        any = true;
+      }
+    if (any) {
+      BC_HIP(hipMemcpyAsync(c->d_mask, mask.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+      BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s, S,
+                             c->d_mask));
+      std::vector<double> pc(c->ntiles), thr(ns);
+      std::vector<int> st_h(c->ntiles + 1);
+      BC_HIP(hipMemcpyAsync(pc.data(), c->d_part_c, c->ntiles * sizeof(double), hipMemcpyDeviceToHost, st));
+      BC_HIP(hipMemcpyAsync(thr.data(), c->d_thr, ns * sizeof(double), hipMemcpyDeviceToHost, st));
+      BC_HIP(hipStreamSynchronize(st));
+      std::vector<int> sys_tile(ns + 1);
+      BC_HIP(hipMemcpy(sys_tile.data(), c->d_sys_tile, (ns + 1) * sizeof(int), hipMemcpyDeviceToHost));
+      bool resume = false;
+      for (int s2 = 0; s2 < ns; ++s2) {
+        if (!mask[s2]) continue;
+        double ss = 0.0;
+        for (int tt = sys_tile[s2]; tt < sys_tile[s2 + 1]; ++tt) ss += pc[tt];
+        if (ss <= thr[s2]) {
+          verified[s2] = 1;
+        } else {
+          done[s2] = 0;
+          resume = true;
+          replacements[s2]++;
+        }
+      }
+      if (resume) {
+        BC_HIP(hipMemcpyAsync(c->d_done, done.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+        BC_HIP(hipStreamSynchronize(st));
+      }
+    }
+    all_done = std::all_of(done.begin(), done.end(), [](int d) { return d != 0; });
+  }
+  // final bookkeeping
+  BC_HIP(hipMemcpyAsync(iters.data(), c->d_iters, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  BC_HIP(hipMemcpyAsync(status.data(), c->d_status, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  unsigned long long inner_total = 0;
+  BC_HIP(hipMemcpyAsync(&inner_total, c->d_inner_total, sizeof(inner_total), hipMemcpyDeviceToHost, st));
+  BC_HIP(hipStreamSynchronize(st));
+  for (int s2 = 0; s2 < ns; ++s2)
+    if (!done[s2]) status[s2] = BC_NOT_CONVERGED;
+  {
+    int* err = inner_err_flag();
+    int h = 0;
+    BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
+    if (h) {
+      bc_set_error("inner CG workgroups timed out waiting for each other");
+      return BC_ERR_DEVICE;
+    }
+  }
+  const double t_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) {
+    // true residuals and backward errors in FP64 from x
+    std::vector<double> xh(n), sh(n), fh(n);
+    BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s, S,
+                           nullptr));
+    BC_HIP(hipMemcpyAsync(xh.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipMemcpyAsync(sh.data(), c->d_s, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipMemcpyAsync(fh.data(), c->d_f, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+    for (int s2 = 0; s2 < ns; ++s2) {
+      double ss = 0, ff = 0, smax = 0, fmax = 0, x1 = 0;
+      for (int i = c->sys_off[s2]; i < c->sys_off[s2 + 1]; ++i) {
+        ss += sh[i] * sh[i];
+        ff += fh[i] * fh[i];
+        smax = std::max(smax, std::fabs(sh[i]));
+        fmax = std::max(fmax, std::fabs(fh[i]));
+        x1 += std::fabs(xh[i]);
+      }
+      bc_stats& q = stats[s2];
+      q.iterations = iters[s2];
+      q.status = status[s2];
+      q.rel_residual = ff > 0 ? std::sqrt(ss / ff) : 0.0;
+      const double den = c->normA_inf[s2] * x1 + fmax;
+      q.backward_err = den > 0 ? smax / den : 0.0;
+      q.t_solve_ms = t_ms;
+      q.t_proj_ms = t_proj;
+      q.proj_launches = proj_launches;
+      q.replacements = replacements[s2];
+      q.inner_iterations = (int64_t)inner_total;
+    }
+  }
+  BC_TRY(leave(c, o.stream));
+  int worst = BC_OK;
+  for (int s2 = 0; s2 < ns; ++s2) {
+    const int v = status[s2];
+    if (v < 0 && (worst >= 0 || v < worst)) worst = v;
+    else if (v > 0 && worst == BC_OK) worst = v;
+  }
+  return (bc_status)worst;
+}
+
+}  // namespace
+
+extern "C" bc_status bc_solve(bc_ctx* c, const double* f, const double* x0, double tol,
+                              int32_t maxit, double* x, bc_stats* stats) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  if (c->nsys != 1) {
+    bc_set_error("bc_solve on a batched context: use bc_solve_batched");
+    return BC_ERR_INVALID;
+  }
+  return solve_impl(c, f, x0, tol, maxit, x, stats);
+}
+
+extern "C" bc_status bc_solve_batched(bc_ctx* c, const double* f, const double* x0, double tol,
+                                      int32_t maxit, double* x, bc_stats* stats) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  return solve_impl(c, f, x0, tol, maxit, x, stats);
+}
+
+// ------------------------------------------------------- row inner-product graph
+
+namespace {
+thread_local double g_rip_spgemm_ms = 0.0, g_rip_total_ms = 0.0;
+
+template <typename T>
+bc_status d2h(std::vector<T>& h, const T* d, size_t count, hipStream_t st) {
+  h.resize(count);
+  if (count) BC_HIP(hipMemcpyAsync(h.data(), d, count * sizeof(T), hipMemcpyDeviceToHost, st));
+  return BC_OK;
+}
+
+bc_status rip_impl(int32_t n, const int32_t* rowptr, const int32_t* colidx, const double* vals,
+                   const rip_opts& o, rip_graph_t* out, hipStream_t st, Arena& A) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const long long nnz = rowptr[n];
+  // A^T on the host: per column, rows ascending, with the position in A
+  std::vector<int> tptr(n + 1, 0), trow(nnz);
+  std::vector<long long> tpos(nnz);
+  std::vector<double> tval(nnz);
+  for (long long e = 0; e < nnz; ++e) tptr[colidx[e] + 1]++;
+  for (int j = 0; j < n; ++j) tptr[j + 1] += tptr[j];
+  {
+    std::vector<int> cur(tptr.begin(), tptr.end() - 1);
+    for (int i = 0; i < n; ++i)
+      for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int q = cur[colidx[e]]++;
+        trow[q] = i;
+        tpos[q] = e;
+        tval[q] = vals[e];
+      }
+  }
+  std::vector<int> hrow(rowptr, rowptr + n + 1), hcol(colidx, colidx + nnz);
+  std::vector<double> hval(vals, vals + nnz);
+  int *d_rowptr, *d_col, *d_tptr, *d_trow, *d_flag;
+  double *d_aval, *d_tval, *d_nrm;
+  long long* d_tpos;
+  BC_TRY(A.upload(&d_rowptr, hrow, st));
+  BC_TRY(A.upload(&d_col, hcol, st));
+  BC_TRY(A.upload(&d_aval, hval, st));
+  BC_TRY(A.upload(&d_tptr, tptr, st));
+  BC_TRY(A.upload(&d_trow, trow, st));
+  BC_TRY(A.upload(&d_tval, tval, st));
+  BC_TRY(A.upload(&d_tpos, tpos, st));
+  std::vector<int> flags(2, 0);
+  BC_TRY(A.upload(&d_flag, flags, st));  // [0] zero row, [1] weight overflow
+  BC_TRY(A.alloc(&d_nrm, n));
+  if (o.prescale) {
+    BC_HIP(rip_launch_prescale(st, n, nnz, d_rowptr, d_aval, d_trow, d_tval, d_nrm, d_flag));
+  }
+  if (o.sparsify) {
+    int t = (int)std::sqrt((double)n);
+    while ((long long)(t + 1) * (t + 1) <= n) ++t;
+    while ((long long)t * t > n) --t;
+    std::vector<int> dense;
+    for (int j = 0; j < n; ++j)
+      if (tptr[j + 1] - tptr[j] > t) dense.push_back(j);
+    if (!dense.empty()) {
+      int* d_dense;
+      BC_TRY(A.upload(&d_dense, dense, st));
+      BC_HIP(rip_launch_sparsify(st, d_dense, (int)dense.size(), t, d_tptr, d_trow, d_tval, d_tpos,
+                                 d_aval));
+    }
+  }
+  // compact the column lists (drop zero entries)
+  int *d_ccnt, *d_cptr, *d_crow;
+  double* d_cval;
+  BC_TRY(A.alloc(&d_ccnt, n));
+  BC_HIP(rip_launch_col_nonzeros(st, n, d_tptr, d_tval, d_ccnt));
+  std::vector<int> ccnt;
+  BC_TRY(d2h(ccnt, d_ccnt, n, st));
+  BC_HIP(hipStreamSynchronize(st));
+  std::vector<int> cptr(n + 1, 0);
+  for (int j = 0; j < n; ++j) cptr[j + 1] = cptr[j] + ccnt[j];
+  BC_TRY(A.upload(&d_cptr, cptr, st));
+  BC_TRY(A.alloc(&d_crow, cptr[n]));
+  BC_TRY(A.alloc(&d_cval, cptr[n]));
+  BC_HIP(rip_launch_compact(st, n, d_tptr, d_trow, d_tval, d_cptr, d_crow, d_cval));
+  // products per row -> short (LDS table) and long (global table) rows
+  long long* d_ub;
+  BC_TRY(A.alloc(&d_ub, n));
+  BC_HIP(rip_launch_row_products(st, n, d_rowptr, d_col, d_aval, d_cptr, d_ub));
+  std::vector<long long> ub;
+  BC_TRY(d2h(ub, d_ub, n, st));
+  std::vector<int> flags_h(2);
+  BC_HIP(hipMemcpyAsync(flags_h.data(), d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  BC_HIP(hipStreamSynchronize(st));
+  if (flags_h[0]) {
+    bc_set_error("rip_graph: a row of A is zero, cannot prescale");
+    return BC_ERR_INVALID;
+  }
+  std::vector<int> short_rows, long_rows, tsize;
+  std::vector<long long> toff;
+  long long ttot = 0;
+  for (int i = 0; i < n; ++i) {
+    if (ub[i] <= rip_short_max()) {
+      short_rows.push_back(i);
+    } else {
+      long long s = 64;
+      while (s < 2 * ub[i]) s <<= 1;
+      if (s > (1LL << 30)) {
+        bc_set_error("rip_graph: row " + std::to_string(i) + " has too many products");
+        return BC_ERR_INVALID;
+      }
+      long_rows.push_back(i);
+      tsize.push_back((int)s);
+      toff.push_back(ttot);
+      ttot += s;
+    }
+  }
+  int *d_srows = nullptr, *d_lrows = nullptr, *d_tsize = nullptr, *d_gkeys = nullptr, *d_cnt;
+  long long* d_toff = nullptr;
+  double* d_gvals = nullptr;
+  BC_TRY(A.upload(&d_srows, short_rows, st));
+  BC_TRY(A.upload(&d_lrows, long_rows, st));
+  BC_TRY(A.upload(&d_tsize, tsize, st));
+  BC_TRY(A.upload(&d_toff, toff, st));
+  BC_TRY(A.alloc(&d_gkeys, ttot));
+  BC_TRY(A.alloc(&d_gvals, ttot));
+  BC_TRY(A.alloc(&d_cnt, n));
+  hipEvent_t e0, e1, e2, e3;
+  BC_HIP(hipEventCreate(&e0));
+  BC_HIP(hipEventCreate(&e1));
+  BC_HIP(hipEventCreate(&e2));
+  BC_HIP(hipEventCreate(&e3));
+  const double alpha = (double)o.alpha;
+  BC_HIP(hipEventRecord(e0, st));
+  BC_HIP(rip_launch_short(st, false, d_srows, (int)short_rows.size(), d_rowptr, d_col, d_aval,
+                          d_cptr, d_crow, d_cval, d_cnt, nullptr, nullptr, nullptr, nullptr, alpha,
+                          d_flag + 1));
+  BC_HIP(rip_launch_long(st, false, d_lrows, (int)long_rows.size(), d_toff, d_tsize, d_rowptr,
+                         d_col, d_aval, d_cptr, d_crow, d_cval, d_gkeys, d_gvals, d_cnt, nullptr,
+                         nullptr, nullptr, nullptr, alpha, d_flag + 1));
+  BC_HIP(hipEventRecord(e1, st));
+  std::vector<int> cnt;
+  BC_TRY(d2h(cnt, d_cnt, n, st));
+  BC_HIP(hipStreamSynchronize(st));
+  std::vector<long long> optr(n + 1, 0);
+  for (int i = 0; i < n; ++i) optr[i + 1] = optr[i] + cnt[i];
+  const long long ne = optr[n];
+  long long* d_optr;
+  int* d_ocol;
+  double* d_ocost;
+  long long* d_owgt;
+  BC_TRY(A.upload(&d_optr, optr, st));
+  BC_TRY(A.alloc(&d_ocol, ne));
+  BC_TRY(A.alloc(&d_ocost, ne));
+  BC_TRY(A.alloc(&d_owgt, ne));
+  BC_HIP(hipEventRecord(e2, st));
+  BC_HIP(rip_launch_short(st, true, d_srows, (int)short_rows.size(), d_rowptr, d_col, d_aval,
+                          d_cptr, d_crow, d_cval, nullptr, d_optr, d_ocol, d_ocost, d_owgt, alpha,
+                          d_flag + 1));
+  BC_HIP(rip_launch_long(st, true, d_lrows, (int)long_rows.size(), d_toff, d_tsize, d_rowptr,
+                         d_col, d_aval, d_cptr, d_crow, d_cval, d_gkeys, d_gvals, nullptr, d_optr,
+                         d_ocol, d_ocost, d_owgt, alpha, d_flag + 1));
+  BC_HIP(hipEventRecord(e3, st));
+  out->n = n;
+  out->nnz = ne;
+  out->rowptr = (int64_t*)std::malloc((n + 1) * sizeof(int64_t));
+  out->col = (int32_t*)std::malloc(std::max<long long>(ne, 1) * sizeof(int32_t));
+  out->cost = (double*)std::malloc(std::max<long long>(ne, 1) * sizeof(double));
+  out->wgt = (int64_t*)std::malloc(std::max<long long>(ne, 1) * sizeof(int64_t));
+  if (!out->rowptr || !out->col || !out->cost || !out->wgt) {
+    BC_HIP(hipStreamSynchronize(st));
+    bc_set_error("rip_graph: host allocation failed");
+    return BC_ERR_NOMEM;
+  }
+  std::memcpy(out->rowptr, optr.data(), (n + 1) * sizeof(int64_t));
+  if (ne) {
+    BC_HIP(hipMemcpyAsync(out->col, d_ocol, ne * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipMemcpyAsync(out->cost, d_ocost, ne * sizeof(double), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipMemcpyAsync(out->wgt, d_owgt, ne * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  }
+  BC_HIP(hipMemcpyAsync(flags_h.data(), d_flag, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+  BC_HIP(hipStreamSynchronize(st));
+  float ms1 = 0.f, ms2 = 0.f;
+  (void)hipEventElapsedTime(&ms1, e0, e1);
+  (void)hipEventElapsedTime(&ms2, e2, e3);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  (void)hipEventDestroy(e3);
+  g_rip_spgemm_ms = (double)ms1 + (double)ms2;
+  g_rip_total_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (flags_h[1]) {
+    bc_set_error("rip_graph: alpha * cost does not fit below 2^62");
+    return BC_ERR_INVALID;
+  }
+  return BC_OK;
+}
+
+}  // namespace
+
+extern "C" void rip_graph_free(rip_graph_t* g) {
+  if (!g) return;
+  std::free(g->rowptr);
+  std::free(g->col);
+  std::free(g->cost);
+  std::free(g->wgt);
+  g->rowptr = nullptr;
+  g->col = nullptr;
+  g->cost = nullptr;
+  g->wgt = nullptr;
+  g->n = 0;
+  g->nnz = 0;
+}
+
+extern "C" bc_status rip_graph(int32_t n, const int32_t* rowptr, const int32_t* colidx,
+                               const double* vals, const rip_opts* opts, rip_graph_t* out) {
+  if (!out) {
+    bc_set_error("rip_graph: out is null");
+    return BC_ERR_INVALID;
+  }
+  std::memset(out, 0, sizeof(*out));
+  BC_TRY(validate_csr(n, rowptr, colidx, vals, "rip_graph"));
+  rip_opts o;
+  if (opts) o = *opts; else rip_opts_default(&o);
+  if (o.alpha < 1) {
+    bc_set_error("rip_graph: alpha must be >= 1");
+    return BC_ERR_INVALID;
+  }
+  BC_TRY(check_device());
+  hipStream_t st = nullptr;
+  hipEvent_t ev = nullptr;
+  BC_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(ev, (hipStream_t)o.stream) != hipSuccess ||
+      hipStreamWaitEvent(st, ev, 0) != hipSuccess) {
+    (void)hipStreamDestroy(st);
+    bc_set_error("rip_graph: stream ordering failed");
+    return BC_ERR_DEVICE;
+  }
+  bc_status s;
+  {
+    Arena A;
+    s = rip_impl(n, rowptr, colidx, vals, o, out, st, A);
+    (void)hipStreamSynchronize(st);
+  }
+  (void)hipEventDestroy(ev);
+  (void)hipStreamDestroy(st);
+  if (s != BC_OK) rip_graph_free(out);
+  return s;
+}
+
+extern "C" bc_status rip_graph_timing(double* spgemm_ms, double* total_ms) {
+  if (spgemm_ms) *spgemm_ms = g_rip_spgemm_ms;
+  if (total_ms) *total_ms = g_rip_total_ms;
+  return BC_OK;
+}

@@ -1,0 +1,203 @@
+// Internal declarations shared by the library's HIP sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bc.h"
+
+// ------------------------------------------------------------------ errors
+
+void bc_set_error(const std::string& msg);
+
+#define BC_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      bc_set_error(std::string(#call " failed: ") + hipGetErrorString(e_));            \
+      return BC_ERR_DEVICE;                                                            \
+    }                                                                                  \
+  } while (0)
+
+// ------------------------------------------------------------ device memory
+
+// Owning device buffer; released with the context.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+// ------------------------------------------------------------------ layout
+// Elements per reduction tile of the vector kernels.  A tile never straddles
+// two systems of a batch, so per-system sums are sums over a tile range.
+constexpr int TILE = 1024;
+constexpr int VEC_THREADS = 256;
+// Dense projection tile edge (tiles of the packed lower-triangular factor).
+constexpr int DT = 64;
+
+// Per-solve device state shared by the outer-iteration kernels.
+struct OuterState {
+  int nsys;
+  int ntiles;
+  const int* tile_start;   // ntiles + 1 row/column offsets
+  const int* tile_sys;     // system of each tile
+  const int* sys_tile;     // nsys + 1 tile offsets
+  int* done;               // per system: 1 once finished (converged, maxit, breakdown)
+  int* iters;              // per system: outer iterations done
+  int* status;             // per system: bc_status
+  double* thr;             // per system: stop threshold on ||s||^2 (tol^2 ||f||^2)
+  int maxit;
+  double* part_a;          // ntiles partial sums (p.psi)
+  double* part_b;          // ntiles partial sums (r.r)
+  double* part_c;          // ntiles partial sums (s.s)
+  double* rr;              // per system r.r of the current iterate
+  double* hist;            // per system ||s||^2 of the last iteration (may be null)
+  int* pending;            // per system stop decision of the last k_update_p (1 conv, 2 maxit)
+  int use_backward;        // 1: stop when gamma < tol_bw (eq. (stopping)) instead of ||s||^2 <= thr
+  double tol_bw;
+  double* part_d;          // ntiles partial max |s|
+  double* part_e;          // ntiles partial sum |x|
+  double* part_g;          // ntiles partial max |f|
+  const double* normA;     // per system ||A||_inf
+  double* finf;            // per system ||f||_inf
+};
+
+// ---------------------------------------------------------- device helpers
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+
+__device__ __forceinline__ double wave_sum_lane0(double v) {
+  // Butterfly over the 64 lanes; lane 0's association order is the same in
+  // every wavefront, so taking lane 0 makes the result deterministic.
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return __shfl(v, 0, 64);
+}
+
+// Sum of the partials of one system, in a fixed order, computed by one
+// wavefront (every lane returns the same value).
+__device__ __forceinline__ double sys_sum_wave(const double* part, int t0, int t1) {
+  const int lane = threadIdx.x & 63;
+  double acc = 0.0;
+  for (int t = t0 + lane; t < t1; t += 64) acc += part[t];
+  return wave_sum_lane0(acc);
+}
+
+// Serial fixed-order sum / max of a system's partials (one thread).
+__device__ __forceinline__ double sys_sum_serial(const double* part, int t0, int t1) {
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) a += part[t];
+  return a;
+}
+__device__ __forceinline__ double sys_max_serial(const double* part, int t0, int t1) {
+  double a = 0.0;
+  for (int t = t0; t < t1; ++t) a = fmax(a, part[t]);
+  return a;
+}
+
+// Workgroup max of non-negative values; all threads get the result.
+__device__ __forceinline__ double block_max(double v, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t = fmax(t, sh[i]);
+  return t;
+}
+
+// Workgroup sum (blockDim.x a multiple of 64, at most 1024); all threads get
+// the result.  `sh` must hold blockDim.x/64 doubles.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  v = wave_sum_lane0(v);
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int i = 0; i < nw; ++i) t += sh[i];
+  return t;
+}
+
+#endif
+
+// ------------------------------------------------------- kernel launchers
+// (defined in the .hip files; all return hipError_t of the launch)
+
+hipError_t launch_spmv(int lanes, hipStream_t st, const int* rowptr, const int* col,
+                       const double* val, const float* val32, bool mixed, const double* x,
+                       double* y, const OuterState& S, bool skip_done);
+hipError_t launch_spmvT_dot(int lanes, hipStream_t st, const int* tptr, const int* trow,
+                            const double* tval, const float* tval32, bool mixed, const double* y,
+                            double* psi, const double* p, const OuterState& S);
+hipError_t launch_residual(int lanes, hipStream_t st, const int* rowptr, const int* col,
+                           const double* val, const double* x, const double* fperm, double* s,
+                           const OuterState& S, const int* mask);
+hipError_t launch_update_xrs(hipStream_t st, double* x, double* r, double* s, const double* p,
+                             const double* psi, const double* u, const OuterState& S, int it);
+hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const OuterState& S,
+                           int it);
+hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S);
+hipError_t launch_rr_from_partials(hipStream_t st, const OuterState& S, int slot);
+hipError_t launch_init_norms(hipStream_t st, const double* f, const double* s, const double* x,
+                             double* part_f, const OuterState& S);
+hipError_t launch_gather(hipStream_t st, const double* src, const int* idx, double* dst, int n);
+hipError_t launch_sqnorm_tiles(hipStream_t st, const double* v, double* part, const OuterState& S);
+hipError_t launch_set_thresholds(hipStream_t st, const double* part_f, double tol, const OuterState& S);
+hipError_t launch_copy(hipStream_t st, const double* src, double* dst, int n);
+hipError_t launch_zero(hipStream_t st, double* dst, int n);
+
+// Inner CG on the normal equations of the inner-CG blocks.
+struct InnerBlocks {
+  int nblk;                // number of inner-CG blocks
+  const int* row0;         // first permuted row
+  const int* m;            // rows
+  const int* sup0;         // first support position
+  const int* nsup;         // support size
+  const int* sys;          // system of the block
+  const int* rowptr;       // CSR of the permuted A (global)
+  const int* loc;          // support position of each entry (relative to sup0)
+  const double* val;
+  const float* val32;
+  const int* btptr;        // transposed block CSR: per support position
+  const int* btrow;        // local row
+  const double* btval;
+  const float* btval32;
+  double* q; double* z; double* ri; double* t;   // scratch (rows / support)
+  float* q32; float* z32; float* ri32; float* t32;
+  double* red;             // per block 2 * groups partial slots
+  unsigned* bar;           // per block 2 barrier words (count, generation)
+  int* iters;              // per block inner iterations of the last call
+  unsigned long long* total; // running sum of inner iterations over blocks and calls
+  double tol;
+  int maxit;
+  int groups;              // workgroups per block
+};
+hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, const double* u,
+                           double* y, const int* done);
+
+// Dense blocks: packed lower-triangular tiles of L (column-major 64x64 tiles)
+struct DenseBlocks {
+  int nblk;
+  const int* row0;
+  const int* m;
+  const int* nt;           // tiles per side
+  const long long* loff;   // offset (elements) of the block's packed L tiles
+  const long long* doff;   // offset (elements) of the block's inverted diagonal tiles
+  const int* sys;
+  double* L;               // packed lower tiles, tile (i,j), i>=j, at loff + (i(i+1)/2+j)*DT*DT
+  double* LT;              // packed transposed copy for the backward sweep: tile (i,j), j>=i
+                           // holds (L_ji)^T at loff + (i*nt - i(i-1)/2 + (j-i))*DT*DT
+  double* Dinv;            // inverted diagonal tiles L_kk^{-1}
+  float* L32; float* LT32; float* Dinv32;
+  int* info;               // per block: 0 ok, j+1 = first pivot at or below m*eps*G_jj
+  double* gdiag;           // diagonal of every block's Gram matrix (permuted row index)
+};
+hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
+hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);
+hipError_t launch_dense_apply(hipStream_t st, const DenseBlocks& D, bool mixed, const double* u,
+                              double* y, const int* done);

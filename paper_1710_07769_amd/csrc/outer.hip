@@ -1,0 +1,474 @@
+// Outer-iteration kernels of the CG-accelerated block Cimmino method
+// (Algorithm 2 of the paper): the sparse products u = A p and psi = A^T y,
+// and the fused vector updates with deterministic per-system reductions.
+//
+// Layout: all vectors are float64 over the concatenated index range of the
+// (batched) system.  Row-space vectors (u, s, y, f) are in the block-permuted
+// row order; column-space vectors (x, r, p, psi) in the original column
+// order.  Both ranges are cut into the same tiles of TILE entries that never
+// straddle a system; one workgroup handles one tile and writes one partial
+// sum per reduced quantity, and every consumer re-adds a system's partials
+// in the same fixed order, so all reductions are bitwise reproducible.
+#include "common.h"
+
+#include <cmath>
+
+namespace {
+
+__device__ __forceinline__ int tile_of_block() { return blockIdx.x; }
+
+// Sum over the `lanes`-wide lane group of x (lanes a power of two <= 64); the
+// group's first lane holds the result.
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_down(v, o, L);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ float group_sumf(float v) {
+#pragma unroll
+  for (int o = L / 2; o > 0; o >>= 1) v += __shfl_down(v, o, L);
+  return v;
+}
+
+// y[i] = sum_e val[e] * x[col[e]] for the rows of this tile (row-space tile).
+template <int L, bool MIXED>
+__global__ void __launch_bounds__(VEC_THREADS)
+k_spmv(const int* __restrict__ rowptr, const int* __restrict__ col,
+       const double* __restrict__ val, const float* __restrict__ val32,
+       const double* __restrict__ x, double* __restrict__ y, OuterState S, int skip_done) {
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (skip_done && S.done[sys]) return;
+  const int r0 = S.tile_start[t], r1 = S.tile_start[t + 1];
+  const int g = threadIdx.x / L, l = threadIdx.x % L;
+  constexpr int RPP = VEC_THREADS / L;  // rows per pass
+  for (int i = r0 + g; i < r1; i += RPP) {
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    if constexpr (MIXED) {
+      float acc = 0.f;
+      for (int e = e0 + l; e < e1; e += L) acc += val32[e] * (float)x[col[e]];
+      acc = group_sumf<L>(acc);
+      if (l == 0) y[i] = (double)acc;
+    } else {
+      double acc = 0.0;
+      for (int e = e0 + l; e < e1; e += L) acc += val[e] * x[col[e]];
+      acc = group_sum<L>(acc);
+      if (l == 0) y[i] = acc;
+    }
+  }
+}
+
+// psi[j] = sum over column j of A of a_ij * y[i] (stored A^T), plus the
+// tile's partial of p . psi.
+template <int L, bool MIXED>
+__global__ void __launch_bounds__(VEC_THREADS)
+k_spmvT_dot(const int* __restrict__ tptr, const int* __restrict__ trow,
+            const double* __restrict__ tval, const float* __restrict__ tval32,
+            const double* __restrict__ y, double* __restrict__ psi,
+            const double* __restrict__ p, OuterState S) {
+  __shared__ double sh[VEC_THREADS / 64];
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (S.done[sys]) return;
+  const int c0 = S.tile_start[t], c1 = S.tile_start[t + 1];
+  const int g = threadIdx.x / L, l = threadIdx.x % L;
+  constexpr int RPP = VEC_THREADS / L;
+  double dot = 0.0;
+  for (int j = c0 + g; j < c1; j += RPP) {
+    const int e0 = tptr[j], e1 = tptr[j + 1];
+    double acc;
+    if constexpr (MIXED) {
+      float a = 0.f;
+      for (int e = e0 + l; e < e1; e += L) a += tval32[e] * (float)y[trow[e]];
+      acc = (double)group_sumf<L>(a);
+    } else {
+      double a = 0.0;
+      for (int e = e0 + l; e < e1; e += L) a += tval[e] * y[trow[e]];
+      acc = group_sum<L>(a);
+    }
+    if (l == 0) {
+      psi[j] = acc;
+      dot += p[j] * acc;
+    }
+  }
+  dot = block_sum(dot, sh);
+  if (threadIdx.x == 0) S.part_a[t] = dot;
+}
+
+// s[i] = f[i] - (A x)[i] in FP64 for the systems with mask[sys] != 0 (all
+// systems if mask is null); tile partial of s.s into part_c.
+template <int L>
+__global__ void __launch_bounds__(VEC_THREADS)
+k_residual(const int* __restrict__ rowptr, const int* __restrict__ col,
+           const double* __restrict__ val, const double* __restrict__ x,
+           const double* __restrict__ f, double* __restrict__ s, OuterState S,
+           const int* __restrict__ mask) {
+  __shared__ double sh[VEC_THREADS / 64];
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (mask && !mask[sys]) return;
+  const int r0 = S.tile_start[t], r1 = S.tile_start[t + 1];
+  const int g = threadIdx.x / L, l = threadIdx.x % L;
+  constexpr int RPP = VEC_THREADS / L;
+  double ss = 0.0;
+  for (int i = r0 + g; i < r1; i += RPP) {
+    const int e0 = rowptr[i], e1 = rowptr[i + 1];
+    double acc = 0.0;
+    for (int e = e0 + l; e < e1; e += L) acc += val[e] * x[col[e]];
+    acc = group_sum<L>(acc);
+    if (l == 0) {
+      const double v = f[i] - acc;
+      s[i] = v;
+      ss += v * v;
+    }
+  }
+  ss = block_sum(ss, sh);
+  if (threadIdx.x == 0) S.part_c[t] = ss;
+}
+
+// alpha = rr / (p.psi); x += alpha p; r -= alpha psi; s -= alpha u (the true
+// residual f - A x moves by -alpha A p, and A p = u is already at hand);
+// tile partials of r.r (part_b) and s.s (part_c).
+__global__ void __launch_bounds__(VEC_THREADS)
+k_update_xrs(double* __restrict__ x, double* __restrict__ r, double* __restrict__ s,
+             const double* __restrict__ p, const double* __restrict__ psi,
+             const double* __restrict__ u, OuterState S, int it) {
+  __shared__ double sh[VEC_THREADS / 64];
+  __shared__ double alpha_sh;
+  __shared__ int bad_sh;
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (S.done[sys]) return;
+  if (threadIdx.x < 64) {
+    const double ppsi = sys_sum_wave(S.part_a, S.sys_tile[sys], S.sys_tile[sys + 1]);
+    if (threadIdx.x == 0) {
+      const double rr = S.rr[2 * sys + ((it - 1) & 1)];
+      const bool bad = !(ppsi > 0.0) || !isfinite(ppsi) || !isfinite(rr);
+      bad_sh = bad;
+      alpha_sh = bad ? 0.0 : rr / ppsi;
+    }
+  }
+  __syncthreads();
+  if (bad_sh) {
+    if (t == S.sys_tile[sys] && threadIdx.x == 0) {
+      S.status[sys] = BC_ERR_BREAKDOWN;
+      S.iters[sys] = it - 1;
+      S.done[sys] = 1;
+    }
+    return;
+  }
+  const double alpha = alpha_sh;
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  double rr = 0.0, ss = 0.0, smax = 0.0, xsum = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
+    const double xi = x[i] + alpha * p[i];
+    x[i] = xi;
+    xsum += fabs(xi);
+    const double ri = r[i] - alpha * psi[i];
+    r[i] = ri;
+    rr += ri * ri;
+    const double si = s[i] - alpha * u[i];
+    s[i] = si;
+    ss += si * si;
+    smax = fmax(smax, fabs(si));
+  }
+  rr = block_sum(rr, sh);
+  ss = block_sum(ss, sh);
+  if (S.use_backward) {
+    xsum = block_sum(xsum, sh);
+    smax = block_max(smax, sh);
+  }
+  if (threadIdx.x == 0) {
+    S.part_b[t] = rr;
+    S.part_c[t] = ss;
+    if (S.use_backward) {
+      S.part_d[t] = smax;
+      S.part_e[t] = xsum;
+    }
+  }
+}
+
+// Stop test on ||s||^2 for iteration `it`, then beta = rr_new / rr and
+// p = r + beta p.  The first tile of a system records rr, the iteration count
+// and the stop decision in `pending`; `done` itself is only changed by
+// k_book after this kernel, so every tile of a system sees the same flags.
+__global__ void __launch_bounds__(VEC_THREADS)
+k_update_p(double* __restrict__ p, const double* __restrict__ r, OuterState S, int it) {
+  __shared__ double beta_sh;
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (S.done[sys]) return;
+  if (threadIdx.x < 64) {
+    const int a = S.sys_tile[sys], b = S.sys_tile[sys + 1];
+    const double rrn = sys_sum_wave(S.part_b, a, b);
+    const double ss = sys_sum_wave(S.part_c, a, b);
+    if (threadIdx.x == 0) {
+      const double rro = S.rr[2 * sys + ((it - 1) & 1)];
+      beta_sh = rrn / rro;
+      if (t == a) {
+        S.rr[2 * sys + (it & 1)] = rrn;
+        S.iters[sys] = it;
+        if (S.hist) S.hist[sys] = ss;
+        bool conv;
+        if (S.use_backward) {
+          const double smax = sys_max_serial(S.part_d, a, b);
+          const double xsum = sys_sum_serial(S.part_e, a, b);
+          const double den = S.normA[sys] * xsum + S.finf[sys];
+          conv = den > 0.0 ? (smax / den < S.tol_bw) : true;
+        } else {
+          conv = ss <= S.thr[sys];
+        }
+        S.pending[sys] = conv ? 1 : (it >= S.maxit ? 2 : 0);
+      }
+    }
+  }
+  __syncthreads();
+  const double beta = beta_sh;
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) p[i] = r[i] + beta * p[i];
+}
+
+// Per-system bookkeeping after k_update_p: apply the stop decision.
+__global__ void k_book(OuterState S) {
+  const int sys = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sys >= S.nsys || S.done[sys]) return;
+  const int pend = S.pending[sys];
+  if (pend) {
+    S.status[sys] = pend == 1 ? BC_OK : BC_NOT_CONVERGED;
+    S.done[sys] = 1;
+  }
+}
+
+// p = r and the tile partial of r.r (CG start).
+__global__ void __launch_bounds__(VEC_THREADS)
+k_init_cg(double* __restrict__ p, const double* __restrict__ r, OuterState S) {
+  __shared__ double sh[VEC_THREADS / 64];
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (S.done[sys]) return;
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  double rr = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
+    const double v = r[i];
+    p[i] = v;
+    rr += v * v;
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) S.part_b[t] = rr;
+}
+
+// Per system: rr slot `slot` from the partials in part_b.
+__global__ void k_rr_from_partials(OuterState S, int slot) {
+  const int sys = blockIdx.x;
+  const double rr = sys_sum_wave(S.part_b, S.sys_tile[sys], S.sys_tile[sys + 1]);
+  if (threadIdx.x == 0 && !S.done[sys]) S.rr[2 * sys + slot] = rr;
+}
+
+// Tile partials at the start of a solve: f.f (part_f), max|f| (part_g),
+// max|s| (part_d) and sum|x| (part_e).
+__global__ void __launch_bounds__(VEC_THREADS)
+k_init_norms(const double* __restrict__ f, const double* __restrict__ s,
+             const double* __restrict__ x, double* __restrict__ part_f, OuterState S) {
+  __shared__ double sh[VEC_THREADS / 64];
+  const int t = tile_of_block();
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  double ff = 0.0, fm = 0.0, sm = 0.0, xs = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
+    ff += f[i] * f[i];
+    fm = fmax(fm, fabs(f[i]));
+    sm = fmax(sm, fabs(s[i]));
+    xs += fabs(x[i]);
+  }
+  ff = block_sum(ff, sh);
+  fm = block_max(fm, sh);
+  sm = block_max(sm, sh);
+  xs = block_sum(xs, sh);
+  if (threadIdx.x == 0) {
+    part_f[t] = ff;
+    S.part_g[t] = fm;
+    S.part_d[t] = sm;
+    S.part_e[t] = xs;
+  }
+}
+
+// Tile partials of v.v (into part).
+__global__ void __launch_bounds__(VEC_THREADS)
+k_sqnorm_tiles(const double* __restrict__ v, double* __restrict__ part, OuterState S) {
+  __shared__ double sh[VEC_THREADS / 64];
+  const int t = tile_of_block();
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  double a = 0.0;
+  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) a += v[i] * v[i];
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) part[t] = a;
+}
+
+// Per system: thr = tol^2 ||f||^2 from the partials of f.f and ||f||_inf; a
+// system whose initial residual already meets the stop rule, or with f = 0,
+// is done at iteration 0.
+__global__ void k_set_thresholds(const double* __restrict__ part_f, double tol2, OuterState S) {
+  const int sys = blockIdx.x;
+  const int a = S.sys_tile[sys], b = S.sys_tile[sys + 1];
+  const double ff = sys_sum_wave(part_f, a, b);
+  const double ss = sys_sum_wave(S.part_c, a, b);
+  if (threadIdx.x == 0) {
+    const double thr = tol2 * ff;
+    const double fm = sys_max_serial(S.part_g, a, b);
+    S.finf[sys] = fm;
+    S.thr[sys] = thr;
+    S.iters[sys] = 0;
+    S.status[sys] = BC_NOT_CONVERGED;
+    S.done[sys] = 0;
+    S.pending[sys] = 0;
+    bool conv = ss <= thr;
+    if (S.use_backward) {
+      const double den = S.normA[sys] * sys_sum_serial(S.part_e, a, b) + fm;
+      conv = den > 0.0 ? (sys_max_serial(S.part_d, a, b) / den < S.tol_bw) : true;
+    }
+    if (ff == 0.0 || conv) {
+      S.done[sys] = 1;
+      S.status[sys] = BC_OK;
+    }
+  }
+}
+
+__global__ void k_gather(const double* __restrict__ src, const int* __restrict__ idx,
+                         double* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_zero(double* __restrict__ dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = 0.0;
+}
+
+}  // namespace
+
+#define LANE_SWITCH(lanes, MACRO) \
+  switch (lanes) {                \
+    case 1: MACRO(1); break;      \
+    case 2: MACRO(2); break;      \
+    case 4: MACRO(4); break;      \
+    case 8: MACRO(8); break;      \
+    case 16: MACRO(16); break;    \
+    case 32: MACRO(32); break;    \
+    default: MACRO(64); break;    \
+  }
+
+hipError_t launch_spmv(int lanes, hipStream_t st, const int* rowptr, const int* col,
+                       const double* val, const float* val32, bool mixed, const double* x,
+                       double* y, const OuterState& S, bool skip_done) {
+  if (S.ntiles == 0) return hipSuccess;
+#define L_SPMV(L)                                                                          \
+  if (mixed)                                                                               \
+    hipLaunchKernelGGL((k_spmv<L, true>), dim3(S.ntiles), dim3(VEC_THREADS), 0, st, rowptr, \
+                       col, val, val32, x, y, S, (int)skip_done);                          \
+  else                                                                                     \
+    hipLaunchKernelGGL((k_spmv<L, false>), dim3(S.ntiles), dim3(VEC_THREADS), 0, st, rowptr,\
+                       col, val, val32, x, y, S, (int)skip_done);
+  LANE_SWITCH(lanes, L_SPMV)
+#undef L_SPMV
+  return hipGetLastError();
+}
+
+hipError_t launch_spmvT_dot(int lanes, hipStream_t st, const int* tptr, const int* trow,
+                            const double* tval, const float* tval32, bool mixed, const double* y,
+                            double* psi, const double* p, const OuterState& S) {
+  if (S.ntiles == 0) return hipSuccess;
+#define L_SPMVT(L)                                                                           \
+  if (mixed)                                                                                 \
+    hipLaunchKernelGGL((k_spmvT_dot<L, true>), dim3(S.ntiles), dim3(VEC_THREADS), 0, st, tptr,\
+                       trow, tval, tval32, y, psi, p, S);                                    \
+  else                                                                                       \
+    hipLaunchKernelGGL((k_spmvT_dot<L, false>), dim3(S.ntiles), dim3(VEC_THREADS), 0, st,     \
+                       tptr, trow, tval, tval32, y, psi, p, S);
+  LANE_SWITCH(lanes, L_SPMVT)
+#undef L_SPMVT
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(int lanes, hipStream_t st, const int* rowptr, const int* col,
+                           const double* val, const double* x, const double* fperm, double* s,
+                           const OuterState& S, const int* mask) {
+  if (S.ntiles == 0) return hipSuccess;
+#define L_RES(L)                                                                             \
+  hipLaunchKernelGGL((k_residual<L>), dim3(S.ntiles), dim3(VEC_THREADS), 0, st, rowptr, col, \
+                     val, x, fperm, s, S, mask);
+  LANE_SWITCH(lanes, L_RES)
+#undef L_RES
+  return hipGetLastError();
+}
+
+hipError_t launch_update_xrs(hipStream_t st, double* x, double* r, double* s, const double* p,
+                             const double* psi, const double* u, const OuterState& S, int it) {
+  if (S.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update_xrs, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, x, r, s, p, psi, u,
+                     S, it);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const OuterState& S,
+                           int it) {
+  if (S.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_update_p, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, p, r, S, it);
+  hipLaunchKernelGGL(k_book, dim3((S.nsys + 63) / 64), dim3(64), 0, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S) {
+  if (S.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_cg, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, p, r, S);
+  hipLaunchKernelGGL(k_rr_from_partials, dim3(S.nsys), dim3(64), 0, st, S, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_rr_from_partials(hipStream_t st, const OuterState& S, int slot) {
+  hipLaunchKernelGGL(k_rr_from_partials, dim3(S.nsys), dim3(64), 0, st, S, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_norms(hipStream_t st, const double* f, const double* s, const double* x,
+                             double* part_f, const OuterState& S) {
+  if (S.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init_norms, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, f, s, x, part_f, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_sqnorm_tiles(hipStream_t st, const double* v, double* part, const OuterState& S) {
+  if (S.ntiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sqnorm_tiles, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, v, part, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_thresholds(hipStream_t st, const double* part_f, double tol,
+                                 const OuterState& S) {
+  hipLaunchKernelGGL(k_set_thresholds, dim3(S.nsys), dim3(64), 0, st, part_f, tol * tol, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(hipStream_t st, const double* src, const int* idx, double* dst, int n) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gather, dim3((n + 255) / 256), dim3(256), 0, st, src, idx, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(hipStream_t st, const double* src, double* dst, int n) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero(hipStream_t st, double* dst, int n) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, dst, n);
+  return hipGetLastError();
+}
