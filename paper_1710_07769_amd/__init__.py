@@ -18,6 +18,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbcimmino.so")
 
+# torch ships its own HIP runtime under the same soname (libamdhip64.so.7);
+# loading torch first lets this library bind to that one copy instead of
+# bringing a second runtime into the process.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the C ABI itself does not need torch
+    torch = None
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libbcimmino.so is not built; run `python paper_1710_07769_amd/build.py` "
                       "(or __graft_entry__.build()) first")
