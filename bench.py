@@ -1,0 +1,247 @@
+#!/usr/bin/env python
+"""Benchmark of the CG-accelerated block Cimmino path on one MI355X.
+
+One step is one pass of the whole path over the workload:
+row inner-product graph (GPU) -> greedy partition (host C++) -> setup
+(permutation, transposes, dense factors on the GPU) -> solve to a relative
+true residual of 1e-10 (GPU).  The headline `value` is outer CG iterations
+per second of the solve phase (inputs resident in HBM); time-to-tolerance
+and the other phases are reported beside it.
+
+Usage: python bench.py [--steps K] [--warmup W] [--workload cfg2|cfg1|cfg3|cfg4|cfg5|cfg5-rip]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "outer Cimmino iters/s + time-to-1e-10 residual; % HBM roofline; mixed vs FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=20)
+    return ap.parse_args()
+
+
+class Workload:
+    """Host inputs of one bench configuration."""
+
+    def __init__(self, name, precision=None):
+        import workloads as W
+        import paper_1710_07769_amd as bc
+        self.name = name
+        self.batched = False
+        self.opts = {}
+        self.tol = 1e-10
+        if name == "cfg1":
+            p = W.config1()
+            self.problems, self.partition = [p], "contiguous"
+            self.desc = "cd2d-32 n=1024 K=4 contiguous, dense Cholesky, FP64"
+        elif name == "cfg2":
+            p = W.config2()
+            self.problems, self.partition = [p], "greedy-rip"
+            self.opts = {"projection": bc.BC_PROJ_INNER_CG}
+            self.desc = "cd3d-64 n=262144 K=32 greedy-rip, inner CG, FP64"
+        elif name == "cfg3":
+            p = W.config3()
+            self.problems, self.partition = [p], "contiguous"
+            self.opts = {"projection": bc.BC_PROJ_INNER_CG, "precision": bc.BC_MIXED}
+            self.desc = "powerlaw n=500000 K=64 uneven, inner CG, mixed"
+        elif name == "cfg4":
+            self.problems, self.partition = W.config4(), "contiguous"
+            self.batched = True
+            self.opts = {"precision": bc.BC_MIXED}
+            self.desc = "256 x cd2d sides 48..256, K=8 each, batched, mixed"
+        elif name in ("cfg5", "cfg5-rip"):
+            p = W.config5()
+            self.problems = [p]
+            self.partition = "greedy-rip" if name == "cfg5-rip" else "contiguous"
+            self.opts = {"projection": bc.BC_PROJ_DENSE_CHOL}
+            self.desc = "st27-100 n=1e6 K=512 %s, dense Cholesky" % self.partition
+        else:
+            raise SystemExit("unknown workload " + name)
+        if precision == "fp64":
+            self.opts["precision"] = bc.BC_FP64
+        elif precision == "mixed":
+            self.opts["precision"] = bc.BC_MIXED
+        self.mixed = self.opts.get("precision", 0) == bc.BC_MIXED
+        self.n = sum(q.n for q in self.problems)
+        self.nnz = sum(q.A.nnz for q in self.problems)
+
+
+def run_step(wl, f_dev):
+    """One pass of the whole path; returns a dict of phase times and stats."""
+    import torch
+    import paper_1710_07769_amd as bc
+    out = {"rip_ms": 0.0, "rip_spgemm_ms": 0.0, "partition_ms": 0.0}
+    parts = []
+    for q in wl.problems:
+        if wl.partition == "greedy-rip":
+            t0 = time.perf_counter()
+            g = bc.rip_graph(q.n, q.A.rowptr, q.A.col, q.A.val)
+            t1 = time.perf_counter()
+            part = bc.bc_partition_greedy(g, q.K)
+            t2 = time.perf_counter()
+            out["rip_ms"] += (t1 - t0) * 1e3
+            out["rip_spgemm_ms"] += bc.rip_graph_timing()["spgemm_ms"]
+            out["partition_ms"] += (t2 - t1) * 1e3
+            out["rip_edges"] = int(g.col.size)
+        else:
+            part = q.part()
+        parts.append(part)
+    t0 = time.perf_counter()
+    opts = bc.make_opts(**wl.opts)
+    if wl.batched:
+        ctx = bc.bc_setup_batched([(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, pt)
+                                   for q, pt in zip(wl.problems, parts)], opts)
+    else:
+        q = wl.problems[0]
+        ctx = bc.bc_setup(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, parts[0], opts)
+    torch.cuda.synchronize()
+    out["setup_ms"] = (time.perf_counter() - t0) * 1e3
+    try:
+        x = torch.empty_like(f_dev)
+        t0 = time.perf_counter()
+        if wl.batched:
+            sts = bc.bc_solve_batched(ctx, f_dev, None, wl.tol, 10000, x)
+        else:
+            sts = [bc.bc_solve(ctx, f_dev, None, wl.tol, 10000, x)]
+        torch.cuda.synchronize()
+        out["solve_ms"] = (time.perf_counter() - t0) * 1e3
+    finally:
+        bc.bc_destroy(ctx)
+    out["iterations"] = sum(s.iterations for s in sts)
+    out["max_iterations"] = max(s.iterations for s in sts)
+    out["status"] = max(abs(s.status) for s in sts)
+    out["rel_residual"] = max(s.rel_residual for s in sts)
+    out["t_proj_ms"] = sts[0].t_proj_ms
+    out["proj_launches"] = sts[0].proj_launches
+    out["proj_bytes"] = sts[0].proj_bytes
+    out["inner_iterations"] = sts[0].inner_iterations
+    out["x"] = x
+    return out
+
+
+def cpu_baseline(wl, iters):
+    """The oracle timed on the host cores on a bounded sample of the workload:
+    its projection setup for the whole system, then the first `iters` outer
+    iterations of its Algorithm 2 (tol = 0)."""
+    import workloads as W
+    from oracle import BlockProjections, block_cimmino_cg, rip_graph, greedy_partition
+    q = wl.problems[0]
+    if wl.partition == "greedy-rip":
+        part = greedy_partition(rip_graph(q.A), q.K)
+    else:
+        part = q.part()
+    A = q.A.to_scipy()
+    t0 = time.perf_counter()
+    B = BlockProjections(A, part, q.K)
+    t1 = time.perf_counter()
+    block_cimmino_cg(A, q.f, part, q.K, tol=0.0, maxit=iters, proj=B)
+    t2 = time.perf_counter()
+    return {"value": iters / (t2 - t1), "unit": "outer iters/s", "cores": 1, "kind": "oracle",
+            "sample": "%s: oracle projection setup (%.1f s, seminormal equations with SuperLU / "
+                      "LAPACK per block) then its first %d outer CG iterations (%.1f s); "
+                      "single-threaded SciPy; %d host cores visible"
+                      % (q.name, t1 - t0, iters, t2 - t1, len(os.sched_getaffinity(0)))}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1710_07769_amd as bc  # noqa: F401  (fails loudly if the library is missing)
+    dev = torch.device("cuda:0")
+    wl = Workload(args.workload, args.precision)
+    f = torch.from_numpy(np.concatenate([q.f for q in wl.problems])).to(dev)
+    print("[bench] workload %s: %s; n=%d nnz=%d" % (wl.name, wl.desc, wl.n, wl.nnz),
+          file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        r = run_step(wl, f)
+        print("[bench] warmup %d: iters=%d solve=%.1f ms" % (w, r["iterations"], r["solve_ms"]),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T0 = time.perf_counter()
+    runs = []
+    for k in range(args.steps):
+        r = run_step(wl, f)
+        runs.append(r)
+        print("[bench] step %d: iters=%d solve=%.1f ms setup=%.1f ms rip=%.1f ms part=%.1f ms"
+              % (k, r["iterations"], r["solve_ms"], r["setup_ms"], r["rip_ms"],
+                 r["partition_ms"]), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    T1 = time.perf_counter()
+    ms_per_step = (T1 - T0) * 1e3 / max(args.steps, 1)
+    iters = sum(r["iterations"] for r in runs)
+    solve_s = sum(r["solve_ms"] for r in runs) / 1e3
+    value = iters / solve_s if solve_s > 0 else 0.0
+    proj_ms = sum(r["t_proj_ms"] for r in runs)
+    launches = sum(r["proj_launches"] for r in runs)
+    pbytes = sum(r["proj_bytes"] for r in runs)
+    achieved = pbytes / (proj_ms / 1e3) / 1e9 if proj_ms > 0 else 0.0
+    xs = runs[-1]["x"].cpu().numpy()
+    xstar = np.concatenate([q.xstar for q in wl.problems])
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "outer iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if wl.mixed else "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.desc, "n": wl.n, "nnz": wl.nnz,
+                   "K": [q.K for q in wl.problems][0] if not wl.batched else 8,
+                   "systems": len(wl.problems), "partition": wl.partition, "tol": wl.tol},
+        "iterations": runs[-1]["iterations"],
+        "time_to_tol_ms": float(np.mean([r["solve_ms"] for r in runs])),
+        "setup_ms": float(np.mean([r["setup_ms"] for r in runs])),
+        "rip_graph_ms": float(np.mean([r["rip_ms"] for r in runs])),
+        "rip_spgemm_ms": float(np.mean([r["rip_spgemm_ms"] for r in runs])),
+        "partition_ms": float(np.mean([r["partition_ms"] for r in runs])),
+        "rel_residual": max(r["rel_residual"] for r in runs),
+        "rel_error_vs_xstar": float(np.linalg.norm(xs - xstar) / np.linalg.norm(xstar)),
+        "inner_iterations_per_solve": runs[-1]["inner_iterations"],
+        "roofline": {"bound": "hbm", "kernel": "block projections (%s)" %
+                     ("inner CG" if wl.opts.get("projection") == bc.BC_PROJ_INNER_CG
+                      else "dense triangular sweeps"),
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "avg_launch_ms": proj_ms / max(launches, 1),
+                     "bytes_per_launch": pbytes / max(launches, 1),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline and not wl.batched:
+        print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

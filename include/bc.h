@@ -87,6 +87,9 @@ typedef struct {
   int32_t proj_launches;  /* number of projection kernel launches timed in t_proj_ms */
   int32_t replacements;   /* true-residual replacements performed */
   int64_t inner_iterations; /* sum over outer iterations and inner-CG blocks */
+  double proj_bytes;      /* algorithmic bytes of the timed projection launches: per dense
+                             block m(m+1)*w (both sweeps over the packed factor, w = 8 or 4
+                             bytes), per inner-CG iteration (2*(w+4)*nnz_i + 6*w*m_i) */
 } bc_stats;
 
 /* Fills *opts with the defaults listed above. */

@@ -52,7 +52,7 @@ class bc_stats(C.Structure):
                 ("rel_residual", C.c_double), ("backward_err", C.c_double),
                 ("t_solve_ms", C.c_double), ("t_proj_ms", C.c_double),
                 ("proj_launches", C.c_int32), ("replacements", C.c_int32),
-                ("inner_iterations", C.c_int64)]
+                ("inner_iterations", C.c_int64), ("proj_bytes", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -61,6 +61,7 @@ hipError_t launch_gram(hipStream_t st, const DenseBlocks& D, const int4* tiles, 
                        const int* rowptr, const int* col, const double* val, const int* tptr,
                        const int* trow, const double* tval);
 int inner_max_resident_groups(bool mixed);
+int inner_grp_max_resident(bool mixed, int max_m);
 int* inner_err_flag();
 hipError_t rip_launch_prescale(hipStream_t st, int n, long long nnz, const int* rowptr,
                                double* aval, const int* trow, double* tval, double* nrm,
@@ -221,6 +222,10 @@ struct bc_ctx {
   hipStream_t stream = nullptr;
   hipEvent_t ev_sync = nullptr;
   std::vector<hipEvent_t> ev_proj;  // pairs around projection launches
+  int ev_used = 0;                  // pairs recorded since the last harvest
+  double t_proj_ms = 0.0;           // harvested projection time of the current solve
+  int proj_launches = 0;
+  bool timing = false;
   bool mixed = false;
   int nsys = 0;
   int n_total = 0;
@@ -267,6 +272,7 @@ struct bc_ctx {
   unsigned long long* d_inner_total = nullptr;
   std::vector<int> blk_m;
   std::vector<int> blk_dense;
+  std::vector<long long> in_nnz, in_m_h, dn_m_h;  // per inner / dense block sizes
 
   ~bc_ctx() {
     for (hipEvent_t e : ev_proj) (void)hipEventDestroy(e);
@@ -464,6 +470,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       for (int cc : sup) mark[cc] = -1;
       in_row0.push_back(r0);
       in_m.push_back(m);
+      c->in_nnz.push_back(rowptr[r0 + m] - rowptr[r0]);
+      c->in_m_h.push_back(m);
       in_sup0.push_back(sup_total);
       in_nsup.push_back((int)sup.size());
       in_sys.push_back(blk_sys[b]);
@@ -481,6 +489,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     const int db = (int)dn_m.size();
     dn_row0.push_back(blk_row0[b]);
     dn_m.push_back(m);
+    c->dn_m_h.push_back(m);
     dn_nt.push_back(nt);
     dn_sys.push_back(blk_sys[b]);
     dn_loff.push_back(ltot);
@@ -571,22 +580,117 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       BC_TRY(A.alloc(&B.ri, n));
       BC_TRY(A.alloc(&B.t, sup_total));
     }
-    // workgroups per block: fill the chip once, at least 512 rows each
+    B.max_m = *std::max_element(in_m.begin(), in_m.end());
+    B.max_nsup = *std::max_element(in_nsup.begin(), in_nsup.end());
+    // Sliced ELL copies of every inner block (slices of 64 rows and of 64
+    // support columns, widths padded to a multiple of 8).
+    {
+      const bool i16 = B.max_m < 65536 && B.max_nsup < 65536;
+      std::vector<int> a_s0, a_w, t_s0, t_w;
+      std::vector<long long> a_ptr, t_ptr;
+      std::vector<int> a_ix, t_ix;
+      std::vector<double> a_v, t_v;
+      for (int q = 0; q < B.nblk; ++q) {
+        const int r0 = in_row0[q], m = in_m[q], s0 = in_sup0[q], ns2 = in_nsup[q];
+        a_s0.push_back((int)a_w.size());
+        for (int s = 0; s * 64 < m; ++s) {
+          int w = 0;
+          for (int l = 0; l < 64 && s * 64 + l < m; ++l) {
+            const int i = r0 + s * 64 + l;
+            w = std::max(w, rowptr[i + 1] - rowptr[i]);
+          }
+          w = (w + 7) / 8 * 8;
+          const long long base = (long long)a_ix.size();
+          a_ptr.push_back(base);
+          a_w.push_back(w);
+          a_ix.resize(base + (long long)w * 64, 0);
+          a_v.resize(base + (long long)w * 64, 0.0);
+          for (int l = 0; l < 64 && s * 64 + l < m; ++l) {
+            const int i = r0 + s * 64 + l;
+            for (int e = rowptr[i], k = 0; e < rowptr[i + 1]; ++e, ++k) {
+              a_ix[base + (long long)k * 64 + l] = loc[e];
+              a_v[base + (long long)k * 64 + l] = val[e];
+            }
+          }
+        }
+        t_s0.push_back((int)t_w.size());
+        for (int s = 0; s * 64 < ns2; ++s) {
+          int w = 0;
+          for (int l = 0; l < 64 && s * 64 + l < ns2; ++l) {
+            const int cc = s0 + s * 64 + l;
+            w = std::max(w, btptr[cc + 1] - btptr[cc]);
+          }
+          w = (w + 7) / 8 * 8;
+          const long long base = (long long)t_ix.size();
+          t_ptr.push_back(base);
+          t_w.push_back(w);
+          t_ix.resize(base + (long long)w * 64, 0);
+          t_v.resize(base + (long long)w * 64, 0.0);
+          for (int l = 0; l < 64 && s * 64 + l < ns2; ++l) {
+            const int cc = s0 + s * 64 + l;
+            for (int e = btptr[cc], k = 0; e < btptr[cc + 1]; ++e, ++k) {
+              t_ix[base + (long long)k * 64 + l] = btrow[e];
+              t_v[base + (long long)k * 64 + l] = btval[e];
+            }
+          }
+        }
+      }
+      int *pas0, *paw, *pts0, *ptw;
+      long long *pap, *ptp;
+      double *pav, *ptv;
+      BC_TRY(A.upload(&pas0, a_s0, st));
+      BC_TRY(A.upload(&paw, a_w, st));
+      BC_TRY(A.upload(&pap, a_ptr, st));
+      BC_TRY(A.upload(&pts0, t_s0, st));
+      BC_TRY(A.upload(&ptw, t_w, st));
+      BC_TRY(A.upload(&ptp, t_ptr, st));
+      BC_TRY(A.upload(&pav, a_v, st));
+      BC_TRY(A.upload(&ptv, t_v, st));
+      if (i16) {
+        std::vector<uint16_t> a16(a_ix.begin(), a_ix.end()), t16(t_ix.begin(), t_ix.end());
+        uint16_t *pa16, *pt16;
+        BC_TRY(A.upload(&pa16, a16, st));
+        BC_TRY(A.upload(&pt16, t16, st));
+        B.a_idx = pa16;
+        B.t_idx = pt16;
+      } else {
+        int *pa32, *pt32;
+        BC_TRY(A.upload(&pa32, a_ix, st));
+        BC_TRY(A.upload(&pt32, t_ix, st));
+        B.a_idx = pa32;
+        B.t_idx = pt32;
+      }
+      if (c->mixed) {
+        std::vector<float> a32(a_v.begin(), a_v.end()), t32(t_v.begin(), t_v.end());
+        float *pa32f, *pt32f;
+        BC_TRY(A.upload(&pa32f, a32, st));
+        BC_TRY(A.upload(&pt32f, t32, st));
+        B.a_val32 = pa32f;
+        B.t_val32 = pt32f;
+      }
+      B.a_s0 = pas0; B.a_w = paw; B.a_ptr = pap; B.a_val = pav;
+      B.t_s0 = pts0; B.t_w = ptw; B.t_ptr = ptp; B.t_val = ptv;
+      B.idx16 = i16 ? 1 : 0;
+      B.sell = 1;
+      BC_HIP(hipStreamSynchronize(st));  // host staging vectors go out of scope
+    }
+    // workgroups per block: spread the blocks over the CUs (at most 16 per
+    // block, each owning at least 4 row slices), limited by co-residency
     int G = o.inner_groups;
     if (G <= 0) {
       G = std::max(1, 256 / std::max(1, B.nblk));
       const int minm = *std::min_element(in_m.begin(), in_m.end());
-      G = std::max(1, std::min(G, minm / 512));
-      G = std::min(G, 16);
+      G = std::min(G, std::max(1, minm / 256));
     }
+    G = std::min(G, 16);
     if (G > 1) {
       const int per_xcd = (B.nblk + 7) / 8;
-      const int cap = inner_max_resident_groups(c->mixed);
+      const int cap = inner_grp_max_resident(c->mixed, B.max_m);
       while (G > 1 && per_xcd * G * 8 > cap) --G;
     }
     B.groups = G;
-    BC_TRY(A.alloc(&B.red, (size_t)B.nblk * 2 * G));
-    std::vector<unsigned> bz(2 * B.nblk, 0u);
+    BC_TRY(A.alloc(&B.red, (size_t)B.nblk * 2 * std::max(G, 1)));
+    std::vector<unsigned> bz(32 * B.nblk, 0u);
     unsigned* pbar;
     BC_TRY(A.upload(&pbar, bz, st));
     B.bar = pbar;
@@ -595,6 +699,10 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     BC_TRY(A.upload(&pit, iz, st));
     B.iters = pit;
     B.total = c->d_inner_total;
+    unsigned long long* pbt;
+    BC_TRY(A.alloc(&pbt, B.nblk));
+    BC_HIP(hipMemsetAsync(pbt, 0, B.nblk * sizeof(unsigned long long), st));
+    B.blk_total = pbt;
     B.tol = (c->mixed && o.inner_tol < 1e-5) ? 1e-5 : o.inner_tol;
     B.maxit = o.inner_maxit;
   }
@@ -616,6 +724,10 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     std::vector<int> iz(D.nblk, 0);
     BC_TRY(A.upload(&pinfo, iz, st));
     D.row0 = p0; D.m = p1; D.nt = p2; D.sys = p3; D.loff = pl; D.doff = pd; D.info = pinfo;
+    unsigned long long* pap;
+    BC_TRY(A.alloc(&pap, D.nblk));
+    BC_HIP(hipMemsetAsync(pap, 0, D.nblk * sizeof(unsigned long long), st));
+    D.applies = pap;
     BC_TRY(A.alloc(&D.gdiag, n));
     BC_TRY(A.alloc(&D.L, ltot));
     BC_TRY(A.alloc(&D.LT, ltot));
@@ -755,8 +867,68 @@ namespace {
 // y = D^{-1} u block by block (dense sweeps and inner CG).
 bc_status block_solves(bc_ctx* c, const double* u, double* y, const int* done) {
   hipStream_t st = c->stream;
+  if (c->timing) {
+    if (2 * c->ev_used + 2 > (int)c->ev_proj.size()) {
+      for (int q = 0; q < 16; ++q) {
+        hipEvent_t e;
+        BC_HIP(hipEventCreate(&e));
+        c->ev_proj.push_back(e);
+      }
+    }
+    BC_HIP(hipEventRecord(c->ev_proj[2 * c->ev_used], st));
+  }
   BC_HIP(launch_dense_apply(st, c->dense, c->mixed, u, y, done));
   BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u, y, done));
+  if (c->timing) {
+    BC_HIP(hipEventRecord(c->ev_proj[2 * c->ev_used + 1], st));
+    ++c->ev_used;
+  }
+  return BC_OK;
+}
+
+// Adds the elapsed times of the recorded projection event pairs (the stream
+// must have been synchronised).
+void harvest_proj_events(bc_ctx* c) {
+  for (int q = 0; q < c->ev_used; ++q) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_proj[2 * q], c->ev_proj[2 * q + 1]) == hipSuccess) {
+      c->t_proj_ms += ms;
+      ++c->proj_launches;
+    }
+  }
+  c->ev_used = 0;
+}
+
+// Algorithmic bytes of all projection launches counted by the device counters.
+bc_status proj_bytes(bc_ctx* c, double* out) {
+  const double w = c->mixed ? 4.0 : 8.0;
+  double bytes = 0.0;
+  if (c->inner.nblk) {
+    std::vector<unsigned long long> it(c->inner.nblk);
+    BC_HIP(hipMemcpy(it.data(), c->inner.blk_total, it.size() * sizeof(it[0]), hipMemcpyDeviceToHost));
+    for (int b = 0; b < c->inner.nblk; ++b)
+      bytes += (double)it[b] * (2.0 * (w + 4.0) * (double)c->in_nnz[b] + 6.0 * w * (double)c->in_m_h[b]);
+  }
+  if (c->dense.nblk) {
+    std::vector<unsigned long long> ap(c->dense.nblk);
+    BC_HIP(hipMemcpy(ap.data(), c->dense.applies, ap.size() * sizeof(ap[0]), hipMemcpyDeviceToHost));
+    for (int b = 0; b < c->dense.nblk; ++b) {
+      const double m = (double)c->dn_m_h[b];
+      bytes += (double)ap[b] * m * (m + 1.0) * w;
+    }
+  }
+  *out = bytes;
+  return BC_OK;
+}
+
+bc_status reset_proj_counters(bc_ctx* c) {
+  if (c->inner.nblk)
+    BC_HIP(hipMemsetAsync(c->inner.blk_total, 0, c->inner.nblk * sizeof(unsigned long long), c->stream));
+  if (c->dense.nblk)
+    BC_HIP(hipMemsetAsync(c->dense.applies, 0, c->dense.nblk * sizeof(unsigned long long), c->stream));
+  c->ev_used = 0;
+  c->t_proj_ms = 0.0;
+  c->proj_launches = 0;
   return BC_OK;
 }
 
@@ -814,39 +986,27 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   BC_HIP(launch_init_norms(st, c->d_f, c->d_s, x, c->d_part_f, S));
   BC_HIP(launch_set_thresholds(st, c->d_part_f, backward ? 0.0 : tol, S));
   BC_HIP(hipMemsetAsync(c->d_inner_total, 0, sizeof(unsigned long long), st));
+  BC_TRY(reset_proj_counters(c));
+  c->timing = true;
   // r = sum_i A_i^+ (f_i - A_i x0) = A^T D^{-1} s ; p = r
   BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
   BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->mixed,
                           c->d_y, c->d_r, c->d_p, S));
   BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S));
 
-  // projection timing events
   const int R = o.check_every;
-  if ((int)c->ev_proj.size() < 2 * R) {
-    for (int q = (int)c->ev_proj.size(); q < 2 * R; ++q) {
-      hipEvent_t e;
-      BC_HIP(hipEventCreate(&e));
-      c->ev_proj.push_back(e);
-    }
-  }
   std::vector<int> done(ns, 0), status(ns, 0), iters(ns, 0);
   std::vector<int> verified(ns, 0), replacements(ns, 0);
-  double t_proj = 0.0;
-  int proj_launches = 0;
   int it = 0;
   BC_HIP(hipMemcpyAsync(done.data(), c->d_done, ns * sizeof(int), hipMemcpyDeviceToHost, st));
   BC_HIP(hipStreamSynchronize(st));
   bool all_done = std::all_of(done.begin(), done.end(), [](int d) { return d != 0; });
   while (!all_done && it < maxit) {
-    int nrec = 0;
     for (int q = 0; q < R && it < maxit; ++q) {
       ++it;
       BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->mixed,
                          c->d_p, c->d_u, S, true));
-      BC_HIP(hipEventRecord(c->ev_proj[2 * nrec], st));
       BC_TRY(block_solves(c, c->d_u, c->d_y, c->d_done));
-      BC_HIP(hipEventRecord(c->ev_proj[2 * nrec + 1], st));
-      ++nrec;
       BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
                               c->mixed, c->d_y, c->d_psi, c->d_p, S));
       BC_HIP(launch_update_xrs(st, x, c->d_r, c->d_s, c->d_p, c->d_psi, c->d_u, S, it));
@@ -867,13 +1027,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
     BC_HIP(hipMemcpyAsync(done.data(), c->d_done, ns * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipMemcpyAsync(status.data(), c->d_status, ns * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
-    for (int q = 0; q < nrec; ++q) {
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, c->ev_proj[2 * q], c->ev_proj[2 * q + 1]) == hipSuccess) {
-        t_proj += ms;
-        ++proj_launches;
-      }
-    }
+    harvest_proj_events(c);
     // verify newly converged systems on the true residual; resume those that fail
     std::vector<int> mask(ns, 0);
     bool any = false;
@@ -919,6 +1073,10 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   unsigned long long inner_total = 0;
   BC_HIP(hipMemcpyAsync(&inner_total, c->d_inner_total, sizeof(inner_total), hipMemcpyDeviceToHost, st));
   BC_HIP(hipStreamSynchronize(st));
+  harvest_proj_events(c);
+  c->timing = false;
+  double pbytes = 0.0;
+  BC_TRY(proj_bytes(c, &pbytes));
   for (int s2 = 0; s2 < ns; ++s2)
     if (!done[s2]) status[s2] = BC_NOT_CONVERGED;
   {
@@ -957,8 +1115,9 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
       const double den = c->normA_inf[s2] * x1 + fmax;
       q.backward_err = den > 0 ? smax / den : 0.0;
       q.t_solve_ms = t_ms;
-      q.t_proj_ms = t_proj;
-      q.proj_launches = proj_launches;
+      q.t_proj_ms = c->t_proj_ms;
+      q.proj_launches = c->proj_launches;
+      q.proj_bytes = pbytes;
       q.replacements = replacements[s2];
       q.inner_iterations = (int64_t)inner_total;
     }

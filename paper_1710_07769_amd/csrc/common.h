@@ -173,9 +173,28 @@ struct InnerBlocks {
   unsigned* bar;           // per block 2 barrier words (count, generation)
   int* iters;              // per block inner iterations of the last call
   unsigned long long* total; // running sum of inner iterations over blocks and calls
+  unsigned long long* blk_total; // per block running sum of inner iterations
   double tol;
   int maxit;
   int groups;              // workgroups per block
+  int max_m;               // largest block
+  int max_nsup;            // largest support
+  // Sliced ELL copies (slices of 64 rows / 64 support columns; entry k of
+  // lane l of slice s at ptr[s] + 64 k + l; padding has index 0, value 0)
+  int sell;                // 1 if built
+  int idx16;               // indices stored as uint16 (else int32)
+  const int* a_s0;         // per block first row slice
+  const long long* a_ptr;  // per row slice entry offset
+  const int* a_w;          // per row slice width
+  const void* a_idx;       // support position of each entry
+  const double* a_val;
+  const float* a_val32;
+  const int* t_s0;         // per block first column slice
+  const long long* t_ptr;
+  const int* t_w;
+  const void* t_idx;       // local row of each entry
+  const double* t_val;
+  const float* t_val32;
 };
 hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, const double* u,
                            double* y, const int* done);
@@ -196,6 +215,7 @@ struct DenseBlocks {
   float* L32; float* LT32; float* Dinv32;
   int* info;               // per block: 0 ok, j+1 = first pivot at or below m*eps*G_jj
   double* gdiag;           // diagonal of every block's Gram matrix (permuted row index)
+  unsigned long long* applies; // per block running count of applications
 };
 hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);

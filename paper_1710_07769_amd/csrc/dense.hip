@@ -285,6 +285,7 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   constexpr int NW = APPLY_THREADS / 64;
+  if (threadIdx.x == 0) atomicAdd(&D.applies[b], 1ull);
   // forward: z = L^{-1} u
   for (int i = 0; i < nt; ++i) {
     T acc = (T)0;

@@ -129,7 +129,7 @@ k_inner_cg(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   const int* __restrict__ btptr = B.btptr + sup0;
   double* slots_a = B.red + (size_t)b * 2 * G;
   double* slots_b = slots_a + G;
-  GroupCtx gc{B.bar + 2 * b, 0u, G};
+  GroupCtx gc{B.bar + 32 * (size_t)b, 0u, G};
   if (MULTI && threadIdx.x == 0)
     gc.gen = __hip_atomic_load(&gc.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   bool ok = true;
@@ -202,7 +202,644 @@ k_inner_cg(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   if (g == 0 && threadIdx.x == 0) {
     B.iters[b] = ok ? it : -1;
     atomicAdd(B.total, (unsigned long long)it);
+    atomicAdd(&B.blk_total[b], (unsigned long long)it);
   }
+}
+
+// One workgroup per block (no cross-CU synchronisation).  q lives in LDS,
+// t in LDS when the block's column support fits beside it, and the
+// residual, iterate and z of the thread's own rows in registers
+// (row i = tid + k * 1024, k < RPT), so that each iteration reads only the
+// block's matrix from L2.
+constexpr int WG_THREADS = 1024;
+
+template <typename T, int RPT, bool TLDS>
+__global__ void __launch_bounds__(WG_THREADS)
+k_inner_wg(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
+           const int* __restrict__ done, int qcap) {
+  extern __shared__ double lds_d[];
+  __shared__ double sh[WG_THREADS / 64];
+  const int b = blockIdx.x;
+  if (done && done[B.sys[b]]) return;
+  const int row0 = B.row0[b], m = B.m[b];
+  const int sup0 = B.sup0[b], ns = B.nsup[b];
+  T* qs = reinterpret_cast<T*>(lds_d);
+  T* ts = TLDS ? qs + qcap : Vec<T>::t(B) + sup0;
+  const T* __restrict__ av = Vec<T>::v(B);
+  const T* __restrict__ bv = Vec<T>::bv(B);
+  const int* __restrict__ rowptr = B.rowptr + row0;
+  const int* __restrict__ btptr = B.btptr + sup0;
+  const int* __restrict__ btrow = B.btrow;
+  const int* __restrict__ loc = B.loc;
+  const int tid = threadIdx.x;
+
+  T rr[RPT], zz[RPT];
+  double yy[RPT];
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * WG_THREADS;
+    yy[k] = 0.0;
+    zz[k] = (T)0;
+    rr[k] = (T)0;
+    if (i < m) {
+      const T v = (T)u[row0 + i];
+      rr[k] = v;
+      qs[i] = v;
+      part += (double)v * (double)v;
+    }
+  }
+  const double gamma0 = block_sum(part, sh);
+  int it = 0;
+  if (gamma0 > 0.0) {
+    const double thr = B.tol * B.tol * gamma0;
+    double gamma = gamma0;
+    while (it < B.maxit) {
+      ++it;
+      __syncthreads();
+      // t = A_i^T q over the support columns
+      for (int c = tid; c < ns; c += WG_THREADS) {
+        const int e0 = btptr[c], e1 = btptr[c + 1];
+        T acc = (T)0;
+        for (int e = e0; e < e1; ++e) acc += bv[e] * qs[btrow[e]];
+        ts[c] = acc;
+      }
+      __syncthreads();
+      // z = A_i t on the own rows; q.z
+      part = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * WG_THREADS;
+        if (i < m) {
+          const int e0 = rowptr[i], e1 = rowptr[i + 1];
+          T acc = (T)0;
+          for (int e = e0; e < e1; ++e) acc += av[e] * ts[loc[e]];
+          zz[k] = acc;
+          part += (double)qs[i] * (double)acc;
+        }
+      }
+      const double delta = block_sum(part, sh);
+      if (!(delta > 0.0) || !isfinite(delta)) break;
+      const double alpha = gamma / delta;
+      part = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * WG_THREADS;
+        if (i < m) {
+          yy[k] += alpha * (double)qs[i];
+          rr[k] = rr[k] - (T)alpha * zz[k];
+          part += (double)rr[k] * (double)rr[k];
+        }
+      }
+      const double gnew = block_sum(part, sh);
+      if (gnew <= thr) break;
+      const T beta = (T)(gnew / gamma);
+      gamma = gnew;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = tid + k * WG_THREADS;
+        if (i < m) qs[i] = rr[k] + beta * qs[i];
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = tid + k * WG_THREADS;
+    if (i < m) y[row0 + i] = yy[k];
+  }
+  if (tid == 0) {
+    B.iters[b] = it;
+    atomicAdd(B.total, (unsigned long long)it);
+    atomicAdd(&B.blk_total[b], (unsigned long long)it);
+  }
+}
+
+// Same single-workgroup inner CG on the sliced ELL copies: for a slice
+// every load address is known without reading a row pointer, so a wavefront
+// issues the eight index and eight value loads of a chunk at once.
+template <typename T>
+__device__ __forceinline__ const T* sel_val(const double* d, const float* f);
+template <>
+__device__ __forceinline__ const double* sel_val<double>(const double* d, const float*) { return d; }
+template <>
+__device__ __forceinline__ const float* sel_val<float>(const double*, const float* f) { return f; }
+
+template <typename T, typename IX>
+__device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const T* __restrict__ val,
+                                      long long e, int w, const T* __restrict__ x) {
+  T acc = (T)0;
+  for (int k0 = 0; k0 < w; k0 += 8) {
+    IX ix[8];
+    T vv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      ix[k] = idx[e + (long long)(k0 + k) * 64];
+      vv[k] = val[e + (long long)(k0 + k) * 64];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += vv[k] * x[ix[k]];
+  }
+  return acc;
+}
+
+// Two 8-wide slices at once: 32 independent loads per lane in flight.
+template <typename T, typename IX>
+__device__ __forceinline__ void two_slices8(const IX* __restrict__ idx, const T* __restrict__ val,
+                                            long long e1, long long e2, const T* __restrict__ x,
+                                            T& a1, T& a2) {
+  IX i1[8], i2[8];
+  T v1[8], v2[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    i1[k] = idx[e1 + k * 64];
+    v1[k] = val[e1 + k * 64];
+    i2[k] = idx[e2 + k * 64];
+    v2[k] = val[e2 + k * 64];
+  }
+  T s1 = (T)0, s2 = (T)0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    s1 += v1[k] * x[i1[k]];
+    s2 += v2[k] * x[i2[k]];
+  }
+  a1 = s1;
+  a2 = s2;
+}
+
+// LDS layout: q (qcap), t (tcap, if resident), then the slice descriptors
+// (offset of every row slice and column slice, and their widths).
+template <typename T, typename IX, int RPT, bool TLDS>
+__global__ void __launch_bounds__(WG_THREADS)
+k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
+             const int* __restrict__ done, int qcap, int tcap, int dcap) {
+  extern __shared__ double lds_d[];
+  __shared__ double sh[WG_THREADS / 64];
+  const int b = blockIdx.x;
+  if (done && done[B.sys[b]]) return;
+  const int row0 = B.row0[b], m = B.m[b];
+  const int sup0 = B.sup0[b], ns = B.nsup[b];
+  T* qs = reinterpret_cast<T*>(lds_d);
+  T* ts = TLDS ? qs + qcap : Vec<T>::t(B) + sup0;
+  long long* dptr = reinterpret_cast<long long*>(qs + qcap + (TLDS ? tcap : 0));
+  int* dw = reinterpret_cast<int*>(dptr + dcap);
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const IX* __restrict__ aidx = reinterpret_cast<const IX*>(B.a_idx);
+  const IX* __restrict__ tidx = reinterpret_cast<const IX*>(B.t_idx);
+  const T* __restrict__ aval = sel_val<T>(B.a_val, B.a_val32);
+  const T* __restrict__ tval = sel_val<T>(B.t_val, B.t_val32);
+  const int nsa = (m + 63) >> 6, nst = (ns + 63) >> 6;
+  constexpr int NW = WG_THREADS / 64;
+  T* __restrict__ rg = Vec<T>::r(B) + row0;   // residual of the block
+  double* __restrict__ yg = y + row0;          // iterate of the block
+  // slice descriptors: row slices at [0, nsa), column slices at [nsa, nsa + nst)
+  for (int s = threadIdx.x; s < nsa + nst; s += WG_THREADS) {
+    if (s < nsa) {
+      dptr[s] = B.a_ptr[B.a_s0[b] + s];
+      dw[s] = B.a_w[B.a_s0[b] + s];
+    } else {
+      dptr[s] = B.t_ptr[B.t_s0[b] + s - nsa];
+      dw[s] = B.t_w[B.t_s0[b] + s - nsa];
+    }
+  }
+  T zz[RPT];
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int i = (wave + k * NW) * 64 + lane;
+    zz[k] = (T)0;
+    if (i < m) {
+      const T v = (T)u[row0 + i];
+      rg[i] = v;
+      qs[i] = v;
+      yg[i] = 0.0;
+      part += (double)v * (double)v;
+    }
+  }
+  const double gamma0 = block_sum(part, sh);
+  int it = 0;
+  if (gamma0 > 0.0) {
+    const double thr = B.tol * B.tol * gamma0;
+    double gamma = gamma0;
+    while (it < B.maxit) {
+      ++it;
+      __syncthreads();
+      // t = A_i^T q: column slices, two per wavefront round when both are 8 wide
+      for (int s = wave; s < nst; s += 2 * NW) {
+        const int s2 = s + NW;
+        const long long e1 = dptr[nsa + s] + lane;
+        const int w1 = dw[nsa + s];
+        if (s2 < nst && w1 == 8 && dw[nsa + s2] == 8) {
+          T a1, a2;
+          two_slices8<T, IX>(tidx, tval, e1, dptr[nsa + s2] + lane, qs, a1, a2);
+          if (s * 64 + lane < ns) ts[s * 64 + lane] = a1;
+          if (s2 * 64 + lane < ns) ts[s2 * 64 + lane] = a2;
+        } else {
+          const T a1 = sell_row<T, IX>(tidx, tval, e1, w1, qs);
+          if (s * 64 + lane < ns) ts[s * 64 + lane] = a1;
+          if (s2 < nst) {
+            const T a2 = sell_row<T, IX>(tidx, tval, dptr[nsa + s2] + lane, dw[nsa + s2], qs);
+            if (s2 * 64 + lane < ns) ts[s2 * 64 + lane] = a2;
+          }
+        }
+      }
+      __syncthreads();
+      // z = A_i t on the own rows (two row slices per round), and q.z
+      part = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; k += 2) {
+        const int s = wave + k * NW, s2 = s + NW;
+        if (s < nsa) {
+          T a1 = (T)0, a2 = (T)0;
+          if (k + 1 < RPT && s2 < nsa && dw[s] == 8 && dw[s2] == 8) {
+            two_slices8<T, IX>(aidx, aval, dptr[s] + lane, dptr[s2] + lane, ts, a1, a2);
+          } else {
+            a1 = sell_row<T, IX>(aidx, aval, dptr[s] + lane, dw[s], ts);
+            if (k + 1 < RPT && s2 < nsa) a2 = sell_row<T, IX>(aidx, aval, dptr[s2] + lane, dw[s2], ts);
+          }
+          const int i1 = s * 64 + lane, i2 = s2 * 64 + lane;
+          if (i1 < m) {
+            zz[k] = a1;
+            part += (double)qs[i1] * (double)a1;
+          }
+          if (k + 1 < RPT && i2 < m) {
+            zz[k + 1] = a2;
+            part += (double)qs[i2] * (double)a2;
+          }
+        }
+        __asm__ __volatile__("" ::: "memory");
+      }
+      const double delta = block_sum(part, sh);
+      if (!(delta > 0.0) || !isfinite(delta)) break;
+      const double alpha = gamma / delta;
+      part = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = (wave + k * NW) * 64 + lane;
+        if (i < m) {
+          yg[i] += alpha * (double)qs[i];
+          const T rn = rg[i] - (T)alpha * zz[k];
+          rg[i] = rn;
+          part += (double)rn * (double)rn;
+        }
+      }
+      const double gnew = block_sum(part, sh);
+      if (gnew <= thr) break;
+      const T beta = (T)(gnew / gamma);
+      gamma = gnew;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int i = (wave + k * NW) * 64 + lane;
+        if (i < m) qs[i] = rg[i] + beta * qs[i];
+      }
+    }
+  }
+  if (threadIdx.x == 0) {
+    B.iters[b] = it;
+    atomicAdd(B.total, (unsigned long long)it);
+    atomicAdd(&B.blk_total[b], (unsigned long long)it);
+  }
+}
+
+template <typename T, typename IX, int RPT>
+hipError_t launch_sell(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
+                       const int* done, int qcap, int tcap, int dcap, bool tlds, size_t lds) {
+  const void* fn = tlds ? (const void*)k_inner_sell<T, IX, RPT, true>
+                        : (const void*)k_inner_sell<T, IX, RPT, false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (tlds)
+    hipLaunchKernelGGL((k_inner_sell<T, IX, RPT, true>), dim3(B.nblk), dim3(WG_THREADS), lds, st,
+                       B, u, y, done, qcap, tcap, dcap);
+  else
+    hipLaunchKernelGGL((k_inner_sell<T, IX, RPT, false>), dim3(B.nblk), dim3(WG_THREADS), lds, st,
+                       B, u, y, done, qcap, tcap, dcap);
+  return hipGetLastError();
+}
+
+template <typename T, typename IX>
+hipError_t launch_sell_rows(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
+                            const int* done) {
+  const int rpt = (B.max_m + WG_THREADS - 1) / WG_THREADS;
+  // element counts rounded so that the descriptor array stays 8-byte aligned
+  const int qcap = (B.max_m + 1) / 2 * 2;
+  const int tcap = (B.max_nsup + 1) / 2 * 2;
+  const int dcap = (B.max_m + 63) / 64 + (B.max_nsup + 63) / 64;
+  const size_t dbytes = (size_t)dcap * (sizeof(long long) + sizeof(int));
+  const size_t lds_budget = 160 * 1024 - (WG_THREADS / 64) * sizeof(double) - 256;
+  const bool tlds = (size_t)(qcap + tcap) * sizeof(T) + dbytes <= lds_budget;
+  const size_t lds = (size_t)(qcap + (tlds ? tcap : 0)) * sizeof(T) + dbytes;
+  if (rpt <= 4) return launch_sell<T, IX, 4>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
+  if (rpt <= 8) return launch_sell<T, IX, 8>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
+  if (rpt <= 9) return launch_sell<T, IX, 9>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
+  if (rpt <= 10) return launch_sell<T, IX, 10>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
+  if (rpt <= 12) return launch_sell<T, IX, 12>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
+  return launch_sell<T, IX, 16>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
+}
+
+// ------------------------------------------------------------------------
+// Several workgroups per block (`groups`, all on the block's XCD).  Every
+// workgroup keeps the block's whole q and r in LDS (updated redundantly, so q
+// is never exchanged); t and z are exchanged through global memory.  Per
+// inner iteration: t on the own column slices -> barrier -> z on the own row
+// slices (t gathered from global) and q.z -> barrier -> r -= alpha z on all
+// rows (z read from global), y on the own rows, r.r -> barrier -> q = r + beta q.
+//
+// The barrier is a flag array: each workgroup stores its epoch with an
+// agent-scope store after its stores have completed, and polls the block's
+// flags with agent-scope loads; exchanged data is read with agent-scope loads.
+// This relies on the workgroups of a block sharing one L2: the kernel checks
+// the XCC id of every workgroup at entry and, if any is misplaced, the whole
+// group uses full agent-scope fences instead.
+constexpr int GRP_THREADS = 1024;
+
+__device__ __forceinline__ unsigned xcc_id() {
+  return __builtin_amdgcn_s_getreg((15 << 11) | 20) & 0xf;
+}
+
+template <typename T>
+__device__ __forceinline__ T agent_load(const T* p);
+template <>
+__device__ __forceinline__ double agent_load<double>(const double* p) {
+  return __builtin_bit_cast(double, __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p),
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+template <>
+__device__ __forceinline__ float agent_load<float>(const float* p) {
+  return __builtin_bit_cast(float, __hip_atomic_load(reinterpret_cast<const unsigned*>(p),
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+
+struct FlagBar {
+  unsigned* flags;   // this block's `groups` epoch slots
+  unsigned epoch;
+  int g, groups;
+  bool fenced;       // full agent-scope fences (workgroups not on one XCC)
+};
+
+__device__ __forceinline__ bool flag_barrier(FlagBar& fb, int* err) {
+  __shared__ int ok_sh;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  fb.epoch += 1;
+  if (threadIdx.x == 0) {
+    if (fb.fenced) __threadfence();
+    __hip_atomic_store(&fb.flags[fb.g], fb.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  int ok = 1;
+  if (threadIdx.x < 64) {
+    const unsigned long long t0 = wall_clock64();
+    while (true) {
+      const unsigned v = threadIdx.x < fb.groups
+                             ? __hip_atomic_load(&fb.flags[threadIdx.x], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT)
+                             : fb.epoch;
+      if (__all((int)(v - fb.epoch) >= 0)) break;
+      if (wall_clock64() - t0 > WAIT_LIMIT) {
+        ok = 0;
+        if (threadIdx.x == 0) atomicExch(err, 1);
+        break;
+      }
+    }
+    if (fb.fenced) __threadfence();
+  }
+  if (threadIdx.x == 0) ok_sh = ok;
+  __syncthreads();
+  return ok_sh != 0;
+}
+
+template <typename T, typename IX, int RPT>
+__global__ void __launch_bounds__(GRP_THREADS)
+k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
+            const int* __restrict__ done, int rcap, int* err) {
+  extern __shared__ double lds_d[];
+  __shared__ double sh[GRP_THREADS / 64];
+  __shared__ int fenced_sh;
+  const int G = B.groups;
+  const int w = blockIdx.x;
+  const int xcd = w % NXCD, kk = w / NXCD;
+  const int lb = kk / G, g = kk % G;
+  const int b = lb * NXCD + xcd;
+  if (b >= B.nblk) return;
+  if (done && done[B.sys[b]]) return;
+  const int row0 = B.row0[b], m = B.m[b];
+  const int sup0 = B.sup0[b], ns = B.nsup[b];
+  const int nsa = (m + 63) >> 6, nst = (ns + 63) >> 6;
+  // own slices
+  const int sa0 = nsa * g / G, sa1 = nsa * (g + 1) / G;
+  const int st0 = nst * g / G, st1 = nst * (g + 1) / G;
+  T* qs = reinterpret_cast<T*>(lds_d);
+  T* rs = qs + rcap;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  constexpr int NW = GRP_THREADS / 64;
+  const IX* __restrict__ aidx = reinterpret_cast<const IX*>(B.a_idx);
+  const IX* __restrict__ tidx = reinterpret_cast<const IX*>(B.t_idx);
+  const T* __restrict__ aval = sel_val<T>(B.a_val, B.a_val32);
+  const T* __restrict__ tval = sel_val<T>(B.t_val, B.t_val32);
+  const long long* __restrict__ aptr = B.a_ptr + B.a_s0[b];
+  const int* __restrict__ aw = B.a_w + B.a_s0[b];
+  const long long* __restrict__ tptr = B.t_ptr + B.t_s0[b];
+  const int* __restrict__ tw = B.t_w + B.t_s0[b];
+  T* tg = Vec<T>::t(B) + sup0;     // exchanged t of the block
+  T* zg = Vec<T>::z(B) + row0;     // exchanged z of the block
+  double* slots = B.red + (size_t)b * 2 * G;
+  FlagBar fb{B.bar + (size_t)b * 32, 0u, g, G, false};
+  if (threadIdx.x == 0) {
+    fb.epoch = __hip_atomic_load(&fb.flags[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // placement check: publish this workgroup's XCC and whether it matches
+    __hip_atomic_store(&fb.flags[16 + g], (unsigned)(xcc_id() == (unsigned)xcd ? 1 : 2),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+  }
+  fb.epoch = __shfl(fb.epoch, 0, 64);
+  __shared__ unsigned epoch_sh;
+  if (threadIdx.x == 0) epoch_sh = fb.epoch;
+  __syncthreads();
+  fb.epoch = epoch_sh;
+  // first barrier with fences; then every workgroup reads the placement flags
+  fb.fenced = true;
+  bool ok = flag_barrier(fb, err);
+  if (threadIdx.x == 0) {
+    int bad = 0;
+    for (int q = 0; q < G; ++q)
+      bad |= __hip_atomic_load(&fb.flags[16 + q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 1;
+    fenced_sh = bad;
+  }
+  __syncthreads();
+  fb.fenced = fenced_sh != 0;
+
+  // full r = q = u in LDS; y = 0 on the own rows
+  for (int i = threadIdx.x; i < m; i += GRP_THREADS) {
+    const T v = (T)u[row0 + i];
+    qs[i] = v;
+    rs[i] = v;
+  }
+  double yy[RPT];
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    yy[k] = 0.0;
+    const int i = (sa0 + wave + k * NW) * 64 + lane;
+    if (sa0 + wave + k * NW < sa1 && i < m) part += (double)u[row0 + i] * (double)u[row0 + i];
+  }
+  __syncthreads();
+  // gamma0 over the own rows, summed over the group in slot order
+  part = block_sum(part, sh);
+  if (threadIdx.x == 0) slots[g] = part;
+  ok = flag_barrier(fb, err) && ok;
+  double gamma0 = 0.0;
+  for (int q = 0; q < G; ++q) gamma0 += agent_load<double>(&slots[q]);
+  int it = 0;
+  T zz[RPT];
+  if (gamma0 > 0.0 && ok) {
+    const double thr = B.tol * B.tol * gamma0;
+    double gamma = gamma0;
+    while (it < B.maxit) {
+      ++it;
+      // t = A_i^T q on the own column slices (q from LDS)
+      for (int s = st0 + wave; s < st1; s += NW) {
+        const T acc = sell_row<T, IX>(tidx, tval, tptr[s] + lane, tw[s], qs);
+        if (s * 64 + lane < ns) tg[s * 64 + lane] = acc;
+      }
+      if (!flag_barrier(fb, err)) { ok = false; break; }
+      // z = A_i t on the own row slices, t gathered from global
+      part = 0.0;
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int s = sa0 + wave + k * NW;
+        zz[k] = (T)0;
+        if (s < sa1) {
+          const long long e = aptr[s] + lane;
+          const int ww = aw[s];
+          T acc = (T)0;
+          for (int k0 = 0; k0 < ww; k0 += 8) {
+            IX ix[8];
+            T vv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              ix[q] = aidx[e + (long long)(k0 + q) * 64];
+              vv[q] = aval[e + (long long)(k0 + q) * 64];
+            }
+            T tv[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) tv[q] = agent_load<T>(&tg[ix[q]]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc += vv[q] * tv[q];
+          }
+          const int i = s * 64 + lane;
+          if (i < m) {
+            zz[k] = acc;
+            zg[i] = acc;
+            part += (double)qs[i] * (double)acc;
+          }
+        }
+        __asm__ __volatile__("" ::: "memory");
+      }
+      part = block_sum(part, sh);
+      if (threadIdx.x == 0) slots[g] = part;
+      if (!flag_barrier(fb, err)) { ok = false; break; }
+      double delta = 0.0;
+      for (int q = 0; q < G; ++q) delta += agent_load<double>(&slots[q]);
+      if (!(delta > 0.0) || !isfinite(delta)) break;
+      const double alpha = gamma / delta;
+      // y on the own rows (before q changes)
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int s = sa0 + wave + k * NW;
+        const int i = s * 64 + lane;
+        if (s < sa1 && i < m) yy[k] += alpha * (double)qs[i];
+      }
+      // r -= alpha z on all rows (z from global); r.r on the own rows
+      part = 0.0;
+      const int i_lo = sa0 * 64, i_hi = min(m, sa1 * 64);
+      for (int i = threadIdx.x; i < m; i += GRP_THREADS) {
+        const T zi = agent_load<T>(&zg[i]);
+        const T rn = rs[i] - (T)alpha * zi;
+        rs[i] = rn;
+        if (i >= i_lo && i < i_hi) part += (double)rn * (double)rn;
+      }
+      part = block_sum(part, sh);
+      if (threadIdx.x == 0) slots[G + g] = part;
+      if (!flag_barrier(fb, err)) { ok = false; break; }
+      double gnew = 0.0;
+      for (int q = 0; q < G; ++q) gnew += agent_load<double>(&slots[G + q]);
+      if (gnew <= thr) break;
+      const T beta = (T)(gnew / gamma);
+      gamma = gnew;
+      for (int i = threadIdx.x; i < m; i += GRP_THREADS) qs[i] = rs[i] + beta * qs[i];
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int s = sa0 + wave + k * NW;
+    const int i = s * 64 + lane;
+    if (s < sa1 && i < m) y[row0 + i] = yy[k];
+  }
+  if (g == 0 && threadIdx.x == 0) {
+    B.iters[b] = ok ? it : -1;
+    atomicAdd(B.total, (unsigned long long)it);
+    atomicAdd(&B.blk_total[b], (unsigned long long)it);
+  }
+}
+
+template <typename T, typename IX, int RPT>
+hipError_t launch_grp_t(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
+                        const int* done, int* err) {
+  const int rcap = (B.max_m + 1) / 2 * 2;
+  const size_t lds = (size_t)2 * rcap * sizeof(T);
+  const void* fn = (const void*)k_inner_grp<T, IX, RPT>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int per_xcd = (B.nblk + NXCD - 1) / NXCD;
+  const int grid = per_xcd * B.groups * NXCD;
+  InnerBlocks Bc = B;
+  int rc = rcap;
+  void* args[] = {&Bc, (void*)&u, (void*)&y, (void*)&done, &rc, &err};
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GRP_THREADS), args, lds, st);
+}
+
+template <typename T, typename IX>
+hipError_t launch_grp(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
+                      const int* done, int* err) {
+  // own row slices per workgroup, spread over the 16 wavefronts
+  const int nsa_max = (B.max_m + 63) / 64;
+  const int own = (nsa_max + B.groups - 1) / B.groups;
+  const int rpt = (own + 15) / 16;
+  if (rpt <= 1) return launch_grp_t<T, IX, 1>(st, B, u, y, done, err);
+  if (rpt <= 2) return launch_grp_t<T, IX, 2>(st, B, u, y, done, err);
+  if (rpt <= 4) return launch_grp_t<T, IX, 4>(st, B, u, y, done, err);
+  return launch_grp_t<T, IX, 8>(st, B, u, y, done, err);
+}
+
+template <typename T, int RPT>
+hipError_t launch_wg(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
+                     const int* done, int qcap, bool tlds, size_t lds) {
+  const void* fn = tlds ? (const void*)k_inner_wg<T, RPT, true> : (const void*)k_inner_wg<T, RPT, false>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (tlds)
+    hipLaunchKernelGGL((k_inner_wg<T, RPT, true>), dim3(B.nblk), dim3(WG_THREADS), lds, st, B, u, y,
+                       done, qcap);
+  else
+    hipLaunchKernelGGL((k_inner_wg<T, RPT, false>), dim3(B.nblk), dim3(WG_THREADS), lds, st, B, u,
+                       y, done, qcap);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_wg_rows(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
+                          const int* done) {
+  const int rpt = (B.max_m + WG_THREADS - 1) / WG_THREADS;
+  const int qcap = ((B.max_m + 1) / 2) * 2;
+  const size_t lds_budget = 160 * 1024 - (WG_THREADS / 64) * sizeof(double) - 256;
+  const bool tlds = (size_t)(qcap + B.max_nsup) * sizeof(T) <= lds_budget;
+  const size_t lds = (size_t)(qcap + (tlds ? B.max_nsup : 0)) * sizeof(T);
+  if (rpt <= 4) return launch_wg<T, 4>(st, B, u, y, done, qcap, tlds, lds);
+  if (rpt <= 8) return launch_wg<T, 8>(st, B, u, y, done, qcap, tlds, lds);
+  if (rpt <= 12) return launch_wg<T, 12>(st, B, u, y, done, qcap, tlds, lds);
+  return launch_wg<T, 16>(st, B, u, y, done, qcap, tlds, lds);
 }
 
 }  // namespace
@@ -224,6 +861,25 @@ hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, con
   int* err = inner_err_flag();
   if (!err) return hipErrorOutOfMemory;
   const int G = B.groups < 1 ? 1 : B.groups;
+  if (G > 1 && B.sell && G <= 16) {
+    if (B.idx16)
+      return mixed ? launch_grp<float, uint16_t>(st, B, u, y, done, err)
+                   : launch_grp<double, uint16_t>(st, B, u, y, done, err);
+    return mixed ? launch_grp<float, int>(st, B, u, y, done, err)
+                 : launch_grp<double, int>(st, B, u, y, done, err);
+  }
+  // one workgroup per block with q in LDS whenever the rows fit
+  if (G == 1 && B.max_m <= 16 * WG_THREADS &&
+      (size_t)B.max_m * (mixed ? sizeof(float) : sizeof(double)) <= 128 * 1024) {
+    if (B.sell) {
+      if (B.idx16)
+        return mixed ? launch_sell_rows<float, uint16_t>(st, B, u, y, done)
+                     : launch_sell_rows<double, uint16_t>(st, B, u, y, done);
+      return mixed ? launch_sell_rows<float, int>(st, B, u, y, done)
+                   : launch_sell_rows<double, int>(st, B, u, y, done);
+    }
+    return mixed ? launch_wg_rows<float>(st, B, u, y, done) : launch_wg_rows<double>(st, B, u, y, done);
+  }
   const int per_xcd = (B.nblk + NXCD - 1) / NXCD;
   const int grid = per_xcd * G * NXCD;
   if (G == 1) {
@@ -245,6 +901,21 @@ hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, con
                                       dim3(IN_THREADS), args, 0, st);
   return hipLaunchCooperativeKernel((const void*)k_inner_cg<double, true>, dim3(grid),
                                     dim3(IN_THREADS), args, 0, st);
+}
+
+int inner_grp_max_resident(bool mixed, int max_m) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const int rcap = (max_m + 1) / 2 * 2;
+  const size_t lds = (size_t)2 * rcap * (mixed ? sizeof(float) : sizeof(double));
+  const void* fn = mixed ? (const void*)k_inner_grp<float, uint16_t, 2>
+                         : (const void*)k_inner_grp<double, uint16_t, 2>;
+  if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, GRP_THREADS, lds) != hipSuccess)
+    return 0;
+  return per_cu * ncu;
 }
 
 int inner_max_resident_groups(bool mixed) {
