@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -689,6 +690,13 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       while (G > 1 && per_xcd * G * 8 > cap) --G;
     }
     B.groups = G;
+    B.trace = nullptr;
+    if (std::getenv("BC_INNER_TRACE")) {
+      unsigned long long* ptr;
+      BC_TRY(A.alloc(&ptr, 16 * 8 * 64));
+      BC_HIP(hipMemsetAsync(ptr, 0, 16 * 8 * 64 * sizeof(unsigned long long), st));
+      B.trace = ptr;
+    }
     BC_TRY(A.alloc(&B.red, (size_t)B.nblk * 2 * std::max(G, 1)));
     std::vector<unsigned> bz(32 * B.nblk, 0u);
     unsigned* pbar;
@@ -844,6 +852,16 @@ extern "C" bc_status bc_setup(bc_ctx** ctx, int32_t n, const int32_t* rowptr,
 extern "C" void bc_destroy(bc_ctx* ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->inner.trace && std::getenv("BC_INNER_TRACE")) {
+    std::vector<unsigned long long> h(16 * 8 * 64);
+    if (hipMemcpy(h.data(), ctx->inner.trace, h.size() * 8, hipMemcpyDeviceToHost) == hipSuccess) {
+      FILE* fp = std::fopen(std::getenv("BC_INNER_TRACE"), "w");
+      if (fp) {
+        for (size_t q = 0; q < h.size(); ++q) std::fprintf(fp, "%llu\n", h[q]);
+        std::fclose(fp);
+      }
+    }
+  }
   delete ctx;
 }
 

@@ -181,6 +181,7 @@ struct InnerBlocks {
   int max_nsup;            // largest support
   // Sliced ELL copies (slices of 64 rows / 64 support columns; entry k of
   // lane l of slice s at ptr[s] + 64 k + l; padding has index 0, value 0)
+  unsigned long long* trace; // optional phase timestamps (block 0), null when off
   int sell;                // 1 if built
   int idx16;               // indices stored as uint16 (else int32)
   const int* a_s0;         // per block first row slice

@@ -692,17 +692,22 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   for (int q = 0; q < G; ++q) gamma0 += agent_load<double>(&slots[q]);
   int it = 0;
   T zz[RPT];
+  unsigned long long* tr = (B.trace && b == 0 && threadIdx.x == 0) ? B.trace + (size_t)g * 8 * 64 : nullptr;
+#define TRACE_AT(slot) do { if (tr && it <= 64) tr[(it - 1) * 8 + (slot)] = wall_clock64(); } while (0)
   if (gamma0 > 0.0 && ok) {
     const double thr = B.tol * B.tol * gamma0;
     double gamma = gamma0;
     while (it < B.maxit) {
       ++it;
+      TRACE_AT(0);
       // t = A_i^T q on the own column slices (q from LDS)
       for (int s = st0 + wave; s < st1; s += NW) {
         const T acc = sell_row<T, IX>(tidx, tval, tptr[s] + lane, tw[s], qs);
         if (s * 64 + lane < ns) tg[s * 64 + lane] = acc;
       }
+      TRACE_AT(1);
       if (!flag_barrier(fb, err)) { ok = false; break; }
+      TRACE_AT(2);
       // z = A_i t on the own row slices, t gathered from global
       part = 0.0;
 #pragma unroll
@@ -736,9 +741,11 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
         }
         __asm__ __volatile__("" ::: "memory");
       }
+      TRACE_AT(3);
       part = block_sum(part, sh);
       if (threadIdx.x == 0) slots[g] = part;
       if (!flag_barrier(fb, err)) { ok = false; break; }
+      TRACE_AT(4);
       double delta = 0.0;
       for (int q = 0; q < G; ++q) delta += agent_load<double>(&slots[q]);
       if (!(delta > 0.0) || !isfinite(delta)) break;
@@ -759,9 +766,11 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
         rs[i] = rn;
         if (i >= i_lo && i < i_hi) part += (double)rn * (double)rn;
       }
+      TRACE_AT(5);
       part = block_sum(part, sh);
       if (threadIdx.x == 0) slots[G + g] = part;
       if (!flag_barrier(fb, err)) { ok = false; break; }
+      TRACE_AT(6);
       double gnew = 0.0;
       for (int q = 0; q < G; ++q) gnew += agent_load<double>(&slots[G + q]);
       if (gnew <= thr) break;
@@ -769,8 +778,10 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
       gamma = gnew;
       for (int i = threadIdx.x; i < m; i += GRP_THREADS) qs[i] = rs[i] + beta * qs[i];
       __syncthreads();
+      TRACE_AT(7);
     }
   }
+#undef TRACE_AT
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int s = sa0 + wave + k * NW;
