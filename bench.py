@@ -33,7 +33,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg2")
-    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed"])
+    ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed", "mixed-proj"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
     return ap.parse_args()
@@ -72,15 +72,18 @@ class Workload:
             p = W.config5()
             self.problems = [p]
             self.partition = "greedy-rip" if name == "cfg5-rip" else "contiguous"
-            self.opts = {"projection": bc.BC_PROJ_DENSE_CHOL}
-            self.desc = "st27-100 n=1e6 K=512 %s, dense Cholesky" % self.partition
+            self.opts = {"projection": bc.BC_PROJ_DENSE_CHOL, "precision": bc.BC_MIXED_PROJ}
+            self.desc = ("st27-100 n=1e6 K=512 %s, dense FP64 Cholesky, FP32 triangular applies"
+                         % self.partition)
         else:
             raise SystemExit("unknown workload " + name)
         if precision == "fp64":
             self.opts["precision"] = bc.BC_FP64
         elif precision == "mixed":
             self.opts["precision"] = bc.BC_MIXED
-        self.mixed = self.opts.get("precision", 0) == bc.BC_MIXED
+        elif precision == "mixed-proj":
+            self.opts["precision"] = bc.BC_MIXED_PROJ
+        self.mixed = self.opts.get("precision", 0) in (bc.BC_MIXED, bc.BC_MIXED_PROJ)
         self.n = sum(q.n for q in self.problems)
         self.nnz = sum(q.A.nnz for q in self.problems)
 

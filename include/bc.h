@@ -56,13 +56,17 @@ typedef enum {
   BC_ERR_NOMEM = -5          /* device or host allocation failed */
 } bc_status;
 
-enum { BC_FP64 = 0, BC_MIXED = 1 };
+enum { BC_FP64 = 0, BC_MIXED = 1, BC_MIXED_PROJ = 2 };
 enum { BC_PROJ_AUTO = 0, BC_PROJ_DENSE_CHOL = 1, BC_PROJ_INNER_CG = 2 };
 enum { BC_STOP_REL2 = 0, BC_STOP_BACKWARD_ERR = 1 };
 
 typedef struct {
-  int32_t precision;      /* BC_FP64 (default) or BC_MIXED: FP32 products and
-                             projections, FP64 outer CG scalars, x, residuals */
+  int32_t precision;      /* BC_FP64 (default); BC_MIXED: FP32 sparse products
+                             and projections, FP64 outer CG scalars, x and
+                             residuals, stop test on the FP64 true residual at
+                             each replacement; BC_MIXED_PROJ: FP64 sparse
+                             products, FP32 projections (dense factor copies /
+                             inner CG), FP64 everything else */
   int32_t projection;     /* BC_PROJ_AUTO (default): dense Cholesky when the
                              block has at most dense_max_m rows, else inner CG */
   int32_t dense_max_m;    /* default 4096 */

@@ -34,7 +34,7 @@ _lib = C.CDLL(LIB_PATH)
 BC_OK, BC_NOT_CONVERGED = 0, 1
 BC_ERR_INVALID, BC_ERR_SINGULAR_BLOCK, BC_ERR_BREAKDOWN = -1, -2, -3
 BC_ERR_DEVICE, BC_ERR_NOMEM = -4, -5
-BC_FP64, BC_MIXED = 0, 1
+BC_FP64, BC_MIXED, BC_MIXED_PROJ = 0, 1, 2
 BC_PROJ_AUTO, BC_PROJ_DENSE_CHOL, BC_PROJ_INNER_CG = 0, 1, 2
 BC_STOP_REL2, BC_STOP_BACKWARD_ERR = 0, 1
 

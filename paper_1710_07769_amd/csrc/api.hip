@@ -227,7 +227,8 @@ struct bc_ctx {
   double t_proj_ms = 0.0;           // harvested projection time of the current solve
   int proj_launches = 0;
   bool timing = false;
-  bool mixed = false;
+  bool mixed = false;     // FP32 projections (BC_MIXED or BC_MIXED_PROJ)
+  bool spmv32 = false;    // FP32 sparse products (BC_MIXED)
   int nsys = 0;
   int n_total = 0;
   long long nnz_total = 0;
@@ -306,6 +307,7 @@ struct bc_ctx {
     S.part_g = d_part_g;
     S.normA = d_normA;
     S.finf = d_finf;
+    S.rec_stop = spmv32 ? 0 : 1;
     return S;
   }
 };
@@ -327,7 +329,8 @@ bc_status leave(bc_ctx* c, void* user_stream) {
 
 bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   const bc_opts& o = c->opts;
-  c->mixed = o.precision == BC_MIXED;
+  c->mixed = o.precision == BC_MIXED || o.precision == BC_MIXED_PROJ;
+  c->spmv32 = o.precision == BC_MIXED;
   c->nsys = (int)sys.size();
   // ---- sizes
   c->sys_off.assign(c->nsys + 1, 0);
@@ -369,6 +372,41 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   }
   c->nblk = (int)blk_m.size();
   c->blk_m = blk_m;
+  // Rows of an inner-CG block are ordered by decreasing length (stable) when
+  // their 64-row slices would otherwise be padded by more than 25%: the order
+  // of rows inside a block does not change its projection (Section 2.2).
+  const int dmax_pre = std::min(o.dense_max_m, 4096);
+  for (int b = 0; b < c->nblk; ++b) {
+    const bool inner = o.projection == BC_PROJ_INNER_CG ||
+                       (o.projection == BC_PROJ_AUTO && blk_m[b] > dmax_pre);
+    if (!inner) continue;
+    const int r0 = blk_row0[b], m = blk_m[b];
+    auto len = [&](int i) {
+      const int g = perm[i];
+      const int s = (int)(std::upper_bound(c->sys_off.begin(), c->sys_off.end(), g) - c->sys_off.begin()) - 1;
+      const int r = g - c->sys_off[s];
+      return sys[s].rowptr[r + 1] - sys[s].rowptr[r];
+    };
+    long long used = 0, padded = 0;
+    for (int s0 = 0; s0 < m; s0 += 64) {
+      int w = 0;
+      for (int l = s0; l < std::min(m, s0 + 64); ++l) {
+        const int L = len(r0 + l);
+        used += L;
+        w = std::max(w, L);
+      }
+      padded += (long long)64 * w;
+    }
+    if (padded > used + used / 4) {
+      std::vector<int> idx(perm.begin() + r0, perm.begin() + r0 + m);
+      std::vector<int> L(m);
+      for (int l = 0; l < m; ++l) L[l] = len(r0 + l);
+      std::vector<int> ord(m);
+      std::iota(ord.begin(), ord.end(), 0);
+      std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return L[x] > L[y]; });
+      for (int l = 0; l < m; ++l) perm[r0 + l] = idx[ord[l]];
+    }
+  }
   // ---- permuted CSR (global columns)
   std::vector<int> rowptr(n + 1, 0), col(nnz);
   std::vector<double> val(nnz);
@@ -392,6 +430,18 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       c->normA_inf[s] = std::max(c->normA_inf[s], rs);
       rowptr[i + 1] = e;
     }
+  }
+  // ---- row scales 1/||a_r||_2 of the permuted rows (the projections work on
+  // rows of unit 2-norm, which leaves every P_i unchanged; Section 3.1)
+  std::vector<double> dsc(n);
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) s += val[e] * val[e];
+    if (!(s > 0.0)) {
+      bc_set_error("row " + std::to_string(perm[i]) + " of A is zero: A is singular");
+      return BC_ERR_SINGULAR_BLOCK;
+    }
+    dsc[i] = 1.0 / std::sqrt(s);
   }
   // ---- A^T: per column, permuted rows ascending
   std::vector<int> tptr(n + 1, 0), trow(nnz);
@@ -449,6 +499,25 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
         for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) sup.push_back(col[e]);
       std::sort(sup.begin(), sup.end());
       sup.erase(std::unique(sup.begin(), sup.end()), sup.end());
+      {
+        // support columns by decreasing count (stable) when 64-column slices
+        // would be padded by more than 25%
+        for (size_t q = 0; q < sup.size(); ++q) mark[sup[q]] = 0;
+        for (int i = r0; i < r0 + m; ++i)
+          for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) mark[col[e]]++;
+        long long used = 0, padded = 0;
+        for (size_t s0 = 0; s0 < sup.size(); s0 += 64) {
+          int w = 0;
+          for (size_t l = s0; l < std::min(sup.size(), s0 + 64); ++l) {
+            used += mark[sup[l]];
+            w = std::max(w, mark[sup[l]]);
+          }
+          padded += 64LL * w;
+        }
+        if (padded > used + used / 4) {
+          std::stable_sort(sup.begin(), sup.end(), [&](int x, int y) { return mark[x] > mark[y]; });
+        }
+      }
       for (size_t q = 0; q < sup.size(); ++q) mark[sup[q]] = (int)q;
       for (int i = r0; i < r0 + m; ++i)
         for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) loc[e] = mark[col[e]];
@@ -515,6 +584,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     BC_TRY(A.upload(&c->d_val32, v32, st));
     BC_TRY(A.upload(&c->d_tval32, t32, st));
   }
+  double* d_dsc;
+  BC_TRY(A.upload(&d_dsc, dsc, st));
   BC_TRY(A.upload(&c->d_tile_start, tile_start, st));
   BC_TRY(A.upload(&c->d_tile_sys, tile_sys, st));
   BC_TRY(A.upload(&c->d_sys_tile, sys_tile, st));
@@ -563,6 +634,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     BC_TRY(A.upload(&pbr, btrow, st));
     BC_TRY(A.upload(&pbv, btval, st));
     B.row0 = p0; B.m = p1; B.sup0 = p2; B.nsup = p3; B.sys = p4;
+    B.dsc = d_dsc;
     B.rowptr = c->d_rowptr; B.loc = ploc; B.val = c->d_val; B.val32 = c->d_val32;
     B.btptr = pbp; B.btrow = pbr; B.btval = pbv;
     const int sup_total = (int)btptr.size() - 1;
@@ -583,6 +655,11 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     }
     B.max_m = *std::max_element(in_m.begin(), in_m.end());
     B.max_nsup = *std::max_element(in_nsup.begin(), in_nsup.end());
+    if (B.max_m > 16384) {
+      bc_set_error("inner-CG blocks are limited to 16384 rows (largest block has " +
+                   std::to_string(B.max_m) + ")");
+      return BC_ERR_INVALID;
+    }
     // Sliced ELL copies of every inner block (slices of 64 rows and of 64
     // support columns, widths padded to a multiple of 8).
     {
@@ -600,7 +677,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
             const int i = r0 + s * 64 + l;
             w = std::max(w, rowptr[i + 1] - rowptr[i]);
           }
-          w = (w + 7) / 8 * 8;
+          if (w >= 5) w = (w + 7) / 8 * 8;
           const long long base = (long long)a_ix.size();
           a_ptr.push_back(base);
           a_w.push_back(w);
@@ -610,7 +687,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
             const int i = r0 + s * 64 + l;
             for (int e = rowptr[i], k = 0; e < rowptr[i + 1]; ++e, ++k) {
               a_ix[base + (long long)k * 64 + l] = loc[e];
-              a_v[base + (long long)k * 64 + l] = val[e];
+              a_v[base + (long long)k * 64 + l] = val[e] * dsc[i];
             }
           }
         }
@@ -621,7 +698,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
             const int cc = s0 + s * 64 + l;
             w = std::max(w, btptr[cc + 1] - btptr[cc]);
           }
-          w = (w + 7) / 8 * 8;
+          if (w >= 5) w = (w + 7) / 8 * 8;
           const long long base = (long long)t_ix.size();
           t_ptr.push_back(base);
           t_w.push_back(w);
@@ -631,7 +708,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
             const int cc = s0 + s * 64 + l;
             for (int e = btptr[cc], k = 0; e < btptr[cc + 1]; ++e, ++k) {
               t_ix[base + (long long)k * 64 + l] = btrow[e];
-              t_v[base + (long long)k * 64 + l] = btval[e];
+              t_v[base + (long long)k * 64 + l] = btval[e] * dsc[r0 + btrow[e]];
             }
           }
         }
@@ -684,6 +761,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       G = std::min(G, std::max(1, minm / 256));
     }
     G = std::min(G, 16);
+    // the group kernel keeps two full block vectors in LDS
+    if ((size_t)2 * ((B.max_m + 1) / 2 * 2) * (c->mixed ? 4 : 8) > 150 * 1024) G = 1;
     if (G > 1) {
       const int per_xcd = (B.nblk + 7) / 8;
       const int cap = inner_grp_max_resident(c->mixed, B.max_m);
@@ -711,7 +790,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     BC_TRY(A.alloc(&pbt, B.nblk));
     BC_HIP(hipMemsetAsync(pbt, 0, B.nblk * sizeof(unsigned long long), st));
     B.blk_total = pbt;
-    B.tol = (c->mixed && o.inner_tol < 1e-5) ? 1e-5 : o.inner_tol;
+    // FP32 inner CG cannot resolve residuals far below its unit roundoff
+    B.tol = (c->mixed && o.inner_tol < 1e-6) ? 1e-6 : o.inner_tol;
     B.maxit = o.inner_maxit;
   }
   // dense blocks
@@ -732,6 +812,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     std::vector<int> iz(D.nblk, 0);
     BC_TRY(A.upload(&pinfo, iz, st));
     D.row0 = p0; D.m = p1; D.nt = p2; D.sys = p3; D.loff = pl; D.doff = pd; D.info = pinfo;
+    D.dsc = d_dsc;
     unsigned long long* pap;
     BC_TRY(A.alloc(&pap, D.nblk));
     BC_HIP(hipMemsetAsync(pap, 0, D.nblk * sizeof(unsigned long long), st));
@@ -798,7 +879,8 @@ extern "C" bc_status bc_setup_batched(bc_ctx** ctx, int32_t nsys, const int32_t*
     bc_set_error("bc_setup_batched: null argument or nsys < 1");
     return BC_ERR_INVALID;
   }
-  if (opts && (opts->precision != BC_FP64 && opts->precision != BC_MIXED)) {
+  if (opts && (opts->precision != BC_FP64 && opts->precision != BC_MIXED &&
+               opts->precision != BC_MIXED_PROJ)) {
     bc_set_error("unknown precision");
     return BC_ERR_INVALID;
   }
@@ -962,10 +1044,10 @@ extern "C" bc_status bc_project(bc_ctx* c, const double* v, double* Hv) {
   OuterState S = c->outer(0, 0);
   S.done = c->d_zero_flags;
   hipStream_t st = c->stream;
-  BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->mixed, v,
+  BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, v,
                      c->d_u, S, false));
   BC_TRY(block_solves(c, c->d_u, c->d_y, nullptr));
-  BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->mixed,
+  BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
                           c->d_y, Hv, v, S));
   BC_TRY(leave(c, c->opts.stream));
   int* err = inner_err_flag();
@@ -993,6 +1075,11 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   hipStream_t st = c->stream;
   const int n = c->n_total, ns = c->nsys;
   const bool backward = o.stop_rule == BC_STOP_BACKWARD_ERR;
+  const bool verbose = std::getenv("BC_VERBOSE") != nullptr;
+  if (backward && c->spmv32) {
+    bc_set_error("the backward-error stop rule needs FP64 sparse products (not BC_MIXED)");
+    return BC_ERR_INVALID;
+  }
   BC_TRY(enter(c, o.stream));
   OuterState S = c->outer(maxit, backward ? 1 : 0);
   S.tol_bw = tol;
@@ -1008,9 +1095,9 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   c->timing = true;
   // r = sum_i A_i^+ (f_i - A_i x0) = A^T D^{-1} s ; p = r
   BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
-  BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->mixed,
+  BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
                           c->d_y, c->d_r, c->d_p, S));
-  BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S));
+  BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S, 0));
 
   const int R = o.check_every;
   std::vector<int> done(ns, 0), status(ns, 0), iters(ns, 0);
@@ -1022,23 +1109,25 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   while (!all_done && it < maxit) {
     for (int q = 0; q < R && it < maxit; ++q) {
       ++it;
-      BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->mixed,
+      BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32,
                          c->d_p, c->d_u, S, true));
       BC_TRY(block_solves(c, c->d_u, c->d_y, c->d_done));
       BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
-                              c->mixed, c->d_y, c->d_psi, c->d_p, S));
+                              c->spmv32, c->d_y, c->d_psi, c->d_p, S));
       BC_HIP(launch_update_xrs(st, x, c->d_r, c->d_s, c->d_p, c->d_psi, c->d_u, S, it));
       BC_HIP(launch_update_p(st, c->d_p, c->d_r, S, it));
       if (c->mixed && o.replace_every > 0 && it % o.replace_every == 0) {
-        // FP64 true residual s = f - A x, then r = A^T D^{-1} s through the
-        // working-precision projection; p is kept
+        // FP64 true residual s = f - A x (and, with FP32 sparse products, the
+        // stop test on it), then r = A^T D^{-1} s through the working-precision
+        // projection and a CG restart p = r: each cycle is a defect correction
+        // of x by replace_every CG steps on the FP32-projected operator
         BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s,
                                S, nullptr));
+        if (c->spmv32) BC_HIP(launch_true_check(st, S));
         BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
         BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
-                                c->mixed, c->d_y, c->d_r, c->d_p, S));
-        BC_HIP(launch_sqnorm_tiles(st, c->d_r, c->d_part_b, S));
-        BC_HIP(launch_rr_from_partials(st, S, it & 1));
+                                c->spmv32, c->d_y, c->d_r, c->d_p, S));
+        BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S, it & 1));
         for (int s2 = 0; s2 < ns; ++s2) replacements[s2]++;
       }
     }
@@ -1046,6 +1135,20 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
     BC_HIP(hipMemcpyAsync(status.data(), c->d_status, ns * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
     harvest_proj_events(c);
+    if (verbose) {
+      std::vector<double> hs(ns), th(ns);
+      BC_HIP(hipMemcpy(hs.data(), c->d_hist, ns * sizeof(double), hipMemcpyDeviceToHost));
+      BC_HIP(hipMemcpy(th.data(), c->d_thr, ns * sizeof(double), hipMemcpyDeviceToHost));
+      int nd = 0;
+      double worst = 0.0;
+      for (int s2 = 0; s2 < ns; ++s2) {
+        nd += done[s2] != 0;
+        if (!done[s2] && th[s2] > 0) worst = std::max(worst, std::sqrt(hs[s2] / th[s2]) * tol);
+      }
+      std::fprintf(stderr, "[bc] it=%d done=%d/%d max_rel_res(recursive)=%.3e proj_ms=%.1f\n", it,
+                   nd, ns, worst, c->t_proj_ms);
+      std::fflush(stderr);
+    }
     // verify newly converged systems on the true residual; resume those that fail
     std::vector<int> mask(ns, 0);
     bool any = false;

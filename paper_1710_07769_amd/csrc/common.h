@@ -63,6 +63,7 @@ struct OuterState {
   double* part_g;          // ntiles partial max |f|
   const double* normA;     // per system ||A||_inf
   double* finf;            // per system ||f||_inf
+  int rec_stop;            // 1: k_update_p may stop on the recursively updated s
 };
 
 // ---------------------------------------------------------- device helpers
@@ -141,8 +142,10 @@ hipError_t launch_update_xrs(hipStream_t st, double* x, double* r, double* s, co
                              const double* psi, const double* u, const OuterState& S, int it);
 hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const OuterState& S,
                            int it);
-hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S);
+hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S,
+                          int slot);
 hipError_t launch_rr_from_partials(hipStream_t st, const OuterState& S, int slot);
+hipError_t launch_true_check(hipStream_t st, const OuterState& S);
 hipError_t launch_init_norms(hipStream_t st, const double* f, const double* s, const double* x,
                              double* part_f, const OuterState& S);
 hipError_t launch_gather(hipStream_t st, const double* src, const int* idx, double* dst, int n);
@@ -182,6 +185,8 @@ struct InnerBlocks {
   // Sliced ELL copies (slices of 64 rows / 64 support columns; entry k of
   // lane l of slice s at ptr[s] + 64 k + l; padding has index 0, value 0)
   unsigned long long* trace; // optional phase timestamps (block 0), null when off
+  const double* dsc;       // per permuted row 1/||a_r||_2: the projections solve the
+                           // scaled normal equations (D A_i A_i^T D) z = D u, y = D z
   int sell;                // 1 if built
   int idx16;               // indices stored as uint16 (else int32)
   const int* a_s0;         // per block first row slice
@@ -217,6 +222,7 @@ struct DenseBlocks {
   int* info;               // per block: 0 ok, j+1 = first pivot at or below m*eps*G_jj
   double* gdiag;           // diagonal of every block's Gram matrix (permuted row index)
   unsigned long long* applies; // per block running count of applications
+  const double* dsc;       // per permuted row 1/||a_r||_2 (see InnerBlocks)
 };
 hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);

@@ -48,9 +48,10 @@ k_gram(DenseBlocks D, const int4* __restrict__ tiles, const int* __restrict__ ro
   const int clo = row0 + tj * DT, chi = row0 + min(m, tj * DT + DT);
   if (lr < m) {
     const int grow = row0 + lr;
+    const double dr = D.dsc[grow];
     for (int e = rowptr[grow]; e < rowptr[grow + 1]; ++e) {
       const int k = col[e];
-      const double a = val[e];
+      const double a = val[e] * dr;
       // rows of column k are sorted: find the first >= clo
       int lo = tptr[k], hi = tptr[k + 1];
       while (lo < hi) {
@@ -58,7 +59,7 @@ k_gram(DenseBlocks D, const int4* __restrict__ tiles, const int* __restrict__ ro
         if (trow[mid] < clo) lo = mid + 1; else hi = mid;
       }
       for (int f = lo; f < tptr[k + 1] && trow[f] < chi; ++f)
-        acc[(trow[f] - clo) * DT + r] += a * tval[f];
+        acc[(trow[f] - clo) * DT + r] += a * (tval[f] * D.dsc[trow[f]]);
     }
   } else if (ti == tj) {
     acc[r * DT + r] = 1.0;  // identity padding
@@ -299,7 +300,7 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
     __syncthreads();
     if (w == 0) {
       const int gi = i * DT + lane;
-      T a = gi < m ? (T)u[row0 + gi] : (T)0;
+      T a = gi < m ? (T)(u[row0 + gi] * D.dsc[row0 + gi]) : (T)0;
       for (int q = 0; q < NW; ++q) a -= part[q][lane];
       accs[lane] = a;
     }
@@ -337,7 +338,7 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
       for (int c = 0; c < DT; ++c) s += invT[c * DT + lane] * accs[c];
       zs[i * DT + lane] = s;
       const int gi = i * DT + lane;
-      if (gi < m) y[row0 + gi] = (double)s;
+      if (gi < m) y[row0 + gi] = (double)s * D.dsc[row0 + gi];
     }
     __syncthreads();
   }

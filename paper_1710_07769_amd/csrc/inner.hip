@@ -26,42 +26,6 @@ constexpr int NXCD = 8;
 // about 2 s of the 100 MHz constant clock
 constexpr unsigned long long WAIT_LIMIT = 200000000ull;
 
-struct GroupCtx {
-  unsigned* bar;      // [0] arrival count, [1] generation
-  unsigned gen;       // generation this workgroup waits to leave
-  int groups;
-};
-
-__device__ __forceinline__ bool group_barrier(GroupCtx& gc, int* err) {
-  __shared__ int ok_sh;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    __threadfence();
-    const unsigned arrived = atomicAdd(&gc.bar[0], 1u);
-    if (arrived == (unsigned)(gc.groups - 1)) {
-      atomicExch(&gc.bar[0], 0u);
-      __threadfence();
-      atomicAdd(&gc.bar[1], 1u);
-    } else {
-      const unsigned long long t0 = wall_clock64();
-      while (__hip_atomic_load(&gc.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gc.gen) {
-        __builtin_amdgcn_s_sleep(2);
-        if (wall_clock64() - t0 > WAIT_LIMIT) {
-          ok = 0;
-          atomicExch(err, 1);
-          break;
-        }
-      }
-    }
-    __threadfence();
-    gc.gen += 1;
-    ok_sh = ok;
-  }
-  __syncthreads();
-  return ok_sh != 0;
-}
-
 template <typename T>
 struct Vec;
 template <>
@@ -83,236 +47,7 @@ struct Vec<float> {
   static __device__ const float* bv(const InnerBlocks& B) { return B.btval32; }
 };
 
-// Sum of a workgroup-local partial over the `groups` workgroups of a block,
-// in a fixed order.  slots: this block's `groups` doubles.
-template <bool MULTI>
-__device__ __forceinline__ double group_allreduce(double v, double* sh, double* slots, int g,
-                                                  GroupCtx& gc, int* err, bool& ok) {
-  v = block_sum(v, sh);
-  if constexpr (!MULTI) {
-    return v;
-  } else {
-    if (threadIdx.x == 0) slots[g] = v;
-    ok = group_barrier(gc, err) && ok;
-    double s = 0.0;
-    for (int i = 0; i < gc.groups; ++i) s += slots[i];
-    return s;
-  }
-}
-
-template <typename T, bool MULTI>
-__global__ void __launch_bounds__(IN_THREADS)
-k_inner_cg(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
-           const int* __restrict__ done, int nslots_per_xcd, int* err) {
-  __shared__ double sh[IN_THREADS / 64];
-  const int G = MULTI ? B.groups : 1;
-  // XCD-aware placement: workgroup w runs on XCD w % 8; block b lives on XCD
-  // b % 8 and uses that XCD's workgroup slots [lb*G, lb*G+G), lb = b / 8.
-  const int w = blockIdx.x;
-  const int xcd = w % NXCD, k = w / NXCD;
-  const int lb = k / G, g = k % G;
-  const int b = lb * NXCD + xcd;
-  if (b >= B.nblk) return;
-  if (done && done[B.sys[b]]) return;
-
-  const int row0 = B.row0[b], m = B.m[b];
-  const int sup0 = B.sup0[b], ns = B.nsup[b];
-  const int lo = (int)((long long)m * g / G), hi = (int)((long long)m * (g + 1) / G);
-  const int slo = (int)((long long)ns * g / G), shi = (int)((long long)ns * (g + 1) / G);
-  T* q = Vec<T>::q(B) + row0;
-  T* z = Vec<T>::z(B) + row0;
-  T* r = Vec<T>::r(B) + row0;
-  T* t = Vec<T>::t(B) + sup0;
-  const T* av = Vec<T>::v(B);
-  const T* bv = Vec<T>::bv(B);
-  const int* __restrict__ rowptr = B.rowptr + row0;
-  const int* __restrict__ btptr = B.btptr + sup0;
-  double* slots_a = B.red + (size_t)b * 2 * G;
-  double* slots_b = slots_a + G;
-  GroupCtx gc{B.bar + 32 * (size_t)b, 0u, G};
-  if (MULTI && threadIdx.x == 0)
-    gc.gen = __hip_atomic_load(&gc.bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  bool ok = true;
-
-  // r = u, q = u, y = 0 on this workgroup's rows; gamma0 = ||u_i||^2
-  double part = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += IN_THREADS) {
-    const double ui = u[row0 + i];
-    const T uv = (T)ui;
-    r[i] = uv;
-    q[i] = uv;
-    y[row0 + i] = 0.0;
-    part += (double)uv * (double)uv;
-  }
-  const double gamma0 = group_allreduce<MULTI>(part, sh, slots_a, g, gc, err, ok);
-  if (gamma0 == 0.0 || !ok) {
-    if (g == 0 && threadIdx.x == 0) B.iters[b] = 0;
-    return;
-  }
-  const double thr = B.tol * B.tol * gamma0;
-  double gamma = gamma0;
-  // y accumulates in registers? No: rows per thread vary; keep y in memory.
-  int it = 0;
-  while (it < B.maxit) {
-    ++it;
-    // t = A_i^T q on this workgroup's support columns
-    for (int c = slo + threadIdx.x; c < shi; c += IN_THREADS) {
-      const int e0 = btptr[c], e1 = btptr[c + 1];
-      T acc = (T)0;
-      for (int e = e0; e < e1; ++e) acc += bv[e] * q[B.btrow[e]];
-      t[c] = acc;
-    }
-    if constexpr (MULTI) {
-      if (!group_barrier(gc, err)) { ok = false; break; }
-    } else {
-      __syncthreads();
-    }
-    // z = A_i t on this workgroup's rows; q.z
-    part = 0.0;
-    for (int i = lo + threadIdx.x; i < hi; i += IN_THREADS) {
-      const int e0 = rowptr[i], e1 = rowptr[i + 1];
-      T acc = (T)0;
-      for (int e = e0; e < e1; ++e) acc += av[e] * t[B.loc[e]];
-      z[i] = acc;
-      part += (double)q[i] * (double)acc;
-    }
-    const double delta = group_allreduce<MULTI>(part, sh, slots_a, g, gc, err, ok);
-    if (!ok) break;
-    if (!(delta > 0.0) || !isfinite(delta)) break;
-    const double alpha = gamma / delta;
-    part = 0.0;
-    for (int i = lo + threadIdx.x; i < hi; i += IN_THREADS) {
-      y[row0 + i] += alpha * (double)q[i];
-      const T ri = r[i] - (T)alpha * z[i];
-      r[i] = ri;
-      part += (double)ri * (double)ri;
-    }
-    const double gnew = group_allreduce<MULTI>(part, sh, slots_b, g, gc, err, ok);
-    if (!ok) break;
-    if (gnew <= thr) break;
-    const T beta = (T)(gnew / gamma);
-    gamma = gnew;
-    for (int i = lo + threadIdx.x; i < hi; i += IN_THREADS) q[i] = r[i] + beta * q[i];
-    if constexpr (MULTI) {
-      if (!group_barrier(gc, err)) { ok = false; break; }
-    } else {
-      __syncthreads();
-    }
-  }
-  if (g == 0 && threadIdx.x == 0) {
-    B.iters[b] = ok ? it : -1;
-    atomicAdd(B.total, (unsigned long long)it);
-    atomicAdd(&B.blk_total[b], (unsigned long long)it);
-  }
-}
-
-// One workgroup per block (no cross-CU synchronisation).  q lives in LDS,
-// t in LDS when the block's column support fits beside it, and the
-// residual, iterate and z of the thread's own rows in registers
-// (row i = tid + k * 1024, k < RPT), so that each iteration reads only the
-// block's matrix from L2.
 constexpr int WG_THREADS = 1024;
-
-template <typename T, int RPT, bool TLDS>
-__global__ void __launch_bounds__(WG_THREADS)
-k_inner_wg(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
-           const int* __restrict__ done, int qcap) {
-  extern __shared__ double lds_d[];
-  __shared__ double sh[WG_THREADS / 64];
-  const int b = blockIdx.x;
-  if (done && done[B.sys[b]]) return;
-  const int row0 = B.row0[b], m = B.m[b];
-  const int sup0 = B.sup0[b], ns = B.nsup[b];
-  T* qs = reinterpret_cast<T*>(lds_d);
-  T* ts = TLDS ? qs + qcap : Vec<T>::t(B) + sup0;
-  const T* __restrict__ av = Vec<T>::v(B);
-  const T* __restrict__ bv = Vec<T>::bv(B);
-  const int* __restrict__ rowptr = B.rowptr + row0;
-  const int* __restrict__ btptr = B.btptr + sup0;
-  const int* __restrict__ btrow = B.btrow;
-  const int* __restrict__ loc = B.loc;
-  const int tid = threadIdx.x;
-
-  T rr[RPT], zz[RPT];
-  double yy[RPT];
-  double part = 0.0;
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * WG_THREADS;
-    yy[k] = 0.0;
-    zz[k] = (T)0;
-    rr[k] = (T)0;
-    if (i < m) {
-      const T v = (T)u[row0 + i];
-      rr[k] = v;
-      qs[i] = v;
-      part += (double)v * (double)v;
-    }
-  }
-  const double gamma0 = block_sum(part, sh);
-  int it = 0;
-  if (gamma0 > 0.0) {
-    const double thr = B.tol * B.tol * gamma0;
-    double gamma = gamma0;
-    while (it < B.maxit) {
-      ++it;
-      __syncthreads();
-      // t = A_i^T q over the support columns
-      for (int c = tid; c < ns; c += WG_THREADS) {
-        const int e0 = btptr[c], e1 = btptr[c + 1];
-        T acc = (T)0;
-        for (int e = e0; e < e1; ++e) acc += bv[e] * qs[btrow[e]];
-        ts[c] = acc;
-      }
-      __syncthreads();
-      // z = A_i t on the own rows; q.z
-      part = 0.0;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int i = tid + k * WG_THREADS;
-        if (i < m) {
-          const int e0 = rowptr[i], e1 = rowptr[i + 1];
-          T acc = (T)0;
-          for (int e = e0; e < e1; ++e) acc += av[e] * ts[loc[e]];
-          zz[k] = acc;
-          part += (double)qs[i] * (double)acc;
-        }
-      }
-      const double delta = block_sum(part, sh);
-      if (!(delta > 0.0) || !isfinite(delta)) break;
-      const double alpha = gamma / delta;
-      part = 0.0;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int i = tid + k * WG_THREADS;
-        if (i < m) {
-          yy[k] += alpha * (double)qs[i];
-          rr[k] = rr[k] - (T)alpha * zz[k];
-          part += (double)rr[k] * (double)rr[k];
-        }
-      }
-      const double gnew = block_sum(part, sh);
-      if (gnew <= thr) break;
-      const T beta = (T)(gnew / gamma);
-      gamma = gnew;
-#pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int i = tid + k * WG_THREADS;
-        if (i < m) qs[i] = rr[k] + beta * qs[i];
-      }
-    }
-  }
-#pragma unroll
-  for (int k = 0; k < RPT; ++k) {
-    const int i = tid + k * WG_THREADS;
-    if (i < m) y[row0 + i] = yy[k];
-  }
-  if (tid == 0) {
-    B.iters[b] = it;
-    atomicAdd(B.total, (unsigned long long)it);
-    atomicAdd(&B.blk_total[b], (unsigned long long)it);
-  }
-}
 
 // Same single-workgroup inner CG on the sliced ELL copies: for a slice
 // every load address is known without reading a row pointer, so a wavefront
@@ -328,7 +63,8 @@ template <typename T, typename IX>
 __device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const T* __restrict__ val,
                                       long long e, int w, const T* __restrict__ x) {
   T acc = (T)0;
-  for (int k0 = 0; k0 < w; k0 += 8) {
+  int k0 = 0;
+  for (; k0 + 8 <= w; k0 += 8) {
     IX ix[8];
     T vv[8];
 #pragma unroll
@@ -339,6 +75,7 @@ __device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const T* __res
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc += vv[k] * x[ix[k]];
   }
+  for (; k0 < w; ++k0) acc += val[e + (long long)k0 * 64] * x[idx[e + (long long)k0 * 64]];
   return acc;
 }
 
@@ -404,12 +141,13 @@ k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y
   }
   T zz[RPT];
   double part = 0.0;
+  const double* __restrict__ dsc = B.dsc + row0;  // row scaling: solve on D A_i A_i^T D
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int i = (wave + k * NW) * 64 + lane;
     zz[k] = (T)0;
     if (i < m) {
-      const T v = (T)u[row0 + i];
+      const T v = (T)(u[row0 + i] * dsc[i]);
       rg[i] = v;
       qs[i] = v;
       yg[i] = 0.0;
@@ -494,6 +232,9 @@ k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y
       }
     }
   }
+  // y_i = D z~ where z~ solved the scaled system
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += WG_THREADS) yg[i] *= dsc[i];
   if (threadIdx.x == 0) {
     B.iters[b] = it;
     atomicAdd(B.total, (unsigned long long)it);
@@ -669,9 +410,10 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   __syncthreads();
   fb.fenced = fenced_sh != 0;
 
-  // full r = q = u in LDS; y = 0 on the own rows
+  // full r = q = D u in LDS (row scaling); y = 0 on the own rows
+  const double* __restrict__ dsc = B.dsc + row0;
   for (int i = threadIdx.x; i < m; i += GRP_THREADS) {
-    const T v = (T)u[row0 + i];
+    const T v = (T)(u[row0 + i] * dsc[i]);
     qs[i] = v;
     rs[i] = v;
   }
@@ -681,7 +423,10 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   for (int k = 0; k < RPT; ++k) {
     yy[k] = 0.0;
     const int i = (sa0 + wave + k * NW) * 64 + lane;
-    if (sa0 + wave + k * NW < sa1 && i < m) part += (double)u[row0 + i] * (double)u[row0 + i];
+    if (sa0 + wave + k * NW < sa1 && i < m) {
+      const double v = (double)(T)(u[row0 + i] * dsc[i]);
+      part += v * v;
+    }
   }
   __syncthreads();
   // gamma0 over the own rows, summed over the group in slot order
@@ -718,7 +463,8 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
           const long long e = aptr[s] + lane;
           const int ww = aw[s];
           T acc = (T)0;
-          for (int k0 = 0; k0 < ww; k0 += 8) {
+          int k0 = 0;
+          for (; k0 + 8 <= ww; k0 += 8) {
             IX ix[8];
             T vv[8];
 #pragma unroll
@@ -732,6 +478,8 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc += vv[q] * tv[q];
           }
+          for (; k0 < ww; ++k0)
+            acc += aval[e + (long long)k0 * 64] * agent_load<T>(&tg[aidx[e + (long long)k0 * 64]]);
           const int i = s * 64 + lane;
           if (i < m) {
             zz[k] = acc;
@@ -786,7 +534,7 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   for (int k = 0; k < RPT; ++k) {
     const int s = sa0 + wave + k * NW;
     const int i = s * 64 + lane;
-    if (s < sa1 && i < m) y[row0 + i] = yy[k];
+    if (s < sa1 && i < m) y[row0 + i] = yy[k] * dsc[i];
   }
   if (g == 0 && threadIdx.x == 0) {
     B.iters[b] = ok ? it : -1;
@@ -824,35 +572,6 @@ hipError_t launch_grp(hipStream_t st, const InnerBlocks& B, const double* u, dou
   return launch_grp_t<T, IX, 8>(st, B, u, y, done, err);
 }
 
-template <typename T, int RPT>
-hipError_t launch_wg(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
-                     const int* done, int qcap, bool tlds, size_t lds) {
-  const void* fn = tlds ? (const void*)k_inner_wg<T, RPT, true> : (const void*)k_inner_wg<T, RPT, false>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  if (tlds)
-    hipLaunchKernelGGL((k_inner_wg<T, RPT, true>), dim3(B.nblk), dim3(WG_THREADS), lds, st, B, u, y,
-                       done, qcap);
-  else
-    hipLaunchKernelGGL((k_inner_wg<T, RPT, false>), dim3(B.nblk), dim3(WG_THREADS), lds, st, B, u,
-                       y, done, qcap);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t launch_wg_rows(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
-                          const int* done) {
-  const int rpt = (B.max_m + WG_THREADS - 1) / WG_THREADS;
-  const int qcap = ((B.max_m + 1) / 2) * 2;
-  const size_t lds_budget = 160 * 1024 - (WG_THREADS / 64) * sizeof(double) - 256;
-  const bool tlds = (size_t)(qcap + B.max_nsup) * sizeof(T) <= lds_budget;
-  const size_t lds = (size_t)(qcap + (tlds ? B.max_nsup : 0)) * sizeof(T);
-  if (rpt <= 4) return launch_wg<T, 4>(st, B, u, y, done, qcap, tlds, lds);
-  if (rpt <= 8) return launch_wg<T, 8>(st, B, u, y, done, qcap, tlds, lds);
-  if (rpt <= 12) return launch_wg<T, 12>(st, B, u, y, done, qcap, tlds, lds);
-  return launch_wg<T, 16>(st, B, u, y, done, qcap, tlds, lds);
-}
-
 }  // namespace
 
 // Device-side error flag of the inner CG (wait timeouts); allocated once per process.
@@ -871,47 +590,18 @@ hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, con
   if (B.nblk == 0) return hipSuccess;
   int* err = inner_err_flag();
   if (!err) return hipErrorOutOfMemory;
-  const int G = B.groups < 1 ? 1 : B.groups;
-  if (G > 1 && B.sell && G <= 16) {
+  if (B.groups > 1) {
     if (B.idx16)
       return mixed ? launch_grp<float, uint16_t>(st, B, u, y, done, err)
                    : launch_grp<double, uint16_t>(st, B, u, y, done, err);
     return mixed ? launch_grp<float, int>(st, B, u, y, done, err)
                  : launch_grp<double, int>(st, B, u, y, done, err);
   }
-  // one workgroup per block with q in LDS whenever the rows fit
-  if (G == 1 && B.max_m <= 16 * WG_THREADS &&
-      (size_t)B.max_m * (mixed ? sizeof(float) : sizeof(double)) <= 128 * 1024) {
-    if (B.sell) {
-      if (B.idx16)
-        return mixed ? launch_sell_rows<float, uint16_t>(st, B, u, y, done)
-                     : launch_sell_rows<double, uint16_t>(st, B, u, y, done);
-      return mixed ? launch_sell_rows<float, int>(st, B, u, y, done)
-                   : launch_sell_rows<double, int>(st, B, u, y, done);
-    }
-    return mixed ? launch_wg_rows<float>(st, B, u, y, done) : launch_wg_rows<double>(st, B, u, y, done);
-  }
-  const int per_xcd = (B.nblk + NXCD - 1) / NXCD;
-  const int grid = per_xcd * G * NXCD;
-  if (G == 1) {
-    if (mixed)
-      hipLaunchKernelGGL((k_inner_cg<float, false>), dim3(grid), dim3(IN_THREADS), 0, st, B, u, y,
-                         done, per_xcd, err);
-    else
-      hipLaunchKernelGGL((k_inner_cg<double, false>), dim3(grid), dim3(IN_THREADS), 0, st, B, u,
-                         y, done, per_xcd, err);
-    return hipGetLastError();
-  }
-  // Workgroups of a block wait for each other: launch cooperatively so that
-  // the whole grid is resident.
-  InnerBlocks Bc = B;
-  int nsl = per_xcd;
-  void* args[] = {&Bc, (void*)&u, (void*)&y, (void*)&done, &nsl, &err};
-  if (mixed)
-    return hipLaunchCooperativeKernel((const void*)k_inner_cg<float, true>, dim3(grid),
-                                      dim3(IN_THREADS), args, 0, st);
-  return hipLaunchCooperativeKernel((const void*)k_inner_cg<double, true>, dim3(grid),
-                                    dim3(IN_THREADS), args, 0, st);
+  if (B.idx16)
+    return mixed ? launch_sell_rows<float, uint16_t>(st, B, u, y, done)
+                 : launch_sell_rows<double, uint16_t>(st, B, u, y, done);
+  return mixed ? launch_sell_rows<float, int>(st, B, u, y, done)
+               : launch_sell_rows<double, int>(st, B, u, y, done);
 }
 
 int inner_grp_max_resident(bool mixed, int max_m) {
@@ -929,14 +619,3 @@ int inner_grp_max_resident(bool mixed, int max_m) {
   return per_cu * ncu;
 }
 
-int inner_max_resident_groups(bool mixed) {
-  int dev = 0, ncu = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &per_cu, (const void*)k_inner_cg<float, true>, IN_THREADS, 0)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &per_cu, (const void*)k_inner_cg<double, true>, IN_THREADS, 0);
-  if (e != hipSuccess) return 0;
-  return per_cu * ncu;
-}

@@ -219,7 +219,7 @@ k_update_p(double* __restrict__ p, const double* __restrict__ r, OuterState S, i
           const double den = S.normA[sys] * xsum + S.finf[sys];
           conv = den > 0.0 ? (smax / den < S.tol_bw) : true;
         } else {
-          conv = ss <= S.thr[sys];
+          conv = S.rec_stop && ss <= S.thr[sys];
         }
         S.pending[sys] = conv ? 1 : (it >= S.maxit ? 2 : 0);
       }
@@ -229,6 +229,17 @@ k_update_p(double* __restrict__ p, const double* __restrict__ r, OuterState S, i
   const double beta = beta_sh;
   const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
   for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) p[i] = r[i] + beta * p[i];
+}
+
+// Stop test on the FP64 true residual (partials of s.s in part_c from
+// k_residual), used where the recursively updated s is not accurate enough.
+__global__ void k_true_check(OuterState S) {
+  const int sys = blockIdx.x;
+  const double ss = sys_sum_wave(S.part_c, S.sys_tile[sys], S.sys_tile[sys + 1]);
+  if (threadIdx.x == 0 && !S.done[sys] && ss <= S.thr[sys]) {
+    S.status[sys] = BC_OK;
+    S.done[sys] = 1;
+  }
 }
 
 // Per-system bookkeeping after k_update_p: apply the stop decision.
@@ -424,10 +435,16 @@ hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const Out
   return hipGetLastError();
 }
 
-hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S) {
+hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S,
+                          int slot) {
   if (S.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_init_cg, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, p, r, S);
-  hipLaunchKernelGGL(k_rr_from_partials, dim3(S.nsys), dim3(64), 0, st, S, 0);
+  hipLaunchKernelGGL(k_rr_from_partials, dim3(S.nsys), dim3(64), 0, st, S, slot);
+  return hipGetLastError();
+}
+
+hipError_t launch_true_check(hipStream_t st, const OuterState& S) {
+  hipLaunchKernelGGL(k_true_check, dim3(S.nsys), dim3(64), 0, st, S);
   return hipGetLastError();
 }
 

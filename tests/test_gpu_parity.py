@@ -324,3 +324,50 @@ def test_mixed_precision_reaches_tolerance(dev):
         assert err <= 1e-6
     finally:
         solver.close()
+
+
+MIXED_CASES = {
+    # name: (problem maker, K, opts)
+    "powerlaw-6000-K4-mixed-inner": (lambda: workloads.small_config3(n=6000, K=4), 4,
+                                     {"projection": bc.BC_PROJ_INNER_CG, "precision": bc.BC_MIXED}),
+    "st27-10-K6-fp32-dense-applies": (lambda: workloads.small_config5(N=10, K=6), 6,
+                                      {"projection": bc.BC_PROJ_DENSE_CHOL,
+                                       "precision": bc.BC_MIXED_PROJ}),
+    "cd3d-12-K4-fp32-inner": (lambda: workloads.small_config2(N=12, K=4), 4,
+                              {"projection": bc.BC_PROJ_INNER_CG, "precision": bc.BC_MIXED_PROJ}),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MIXED_CASES))
+def test_mixed_precision_modes(dev, name):
+    banner("mixed precision " + name)
+    maker, K, opts = MIXED_CASES[name]
+    p = maker()
+    part = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, K))
+    ref = block_cimmino_cg(p.A.to_scipy(), p.f, part, K, tol=1e-10)
+    solver = bc.BlockCimmino(p.A, part, K, **opts)
+    try:
+        x, st = solver.solve(to_dev(p.f, dev), tol=1e-10, maxit=3000)
+        err = rel(x.cpu().numpy(), ref.x)
+        print("%s: iters=%d (oracle %d) rel_res=%.2e err_vs_oracle=%.2e replacements=%d"
+              % (name, st.iterations, ref.iterations, st.rel_residual, err, st.replacements))
+        assert st.status == bc.BC_OK
+        assert st.rel_residual <= 1e-10 * (1 + 1e-6)
+        assert err <= 1e-6
+    finally:
+        solver.close()
+
+
+def test_batched_mixed(dev):
+    banner("bc_solve_batched 6 systems, mixed precision")
+    probs = workloads.small_config4()
+    solver = bc.BlockCimminoBatched([(q.A, q.part(), q.K) for q in probs], precision=bc.BC_MIXED)
+    try:
+        f = to_dev(np.concatenate([q.f for q in probs]), dev)
+        x, sts = solver.solve(f, tol=1e-10, maxit=3000)
+        xs = np.split(x.cpu().numpy(), np.cumsum([q.n for q in probs])[:-1])
+        for q, st, xg in zip(probs, sts, xs):
+            assert st.status == bc.BC_OK and st.rel_residual <= 1e-10 * (1 + 1e-6)
+            assert rel(xg, q.xstar) <= 1e-6
+    finally:
+        solver.close()
