@@ -26,6 +26,15 @@ sys.path.insert(0, ROOT)
 METRIC = "outer Cimmino iters/s + time-to-1e-10 residual; % HBM roofline; mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per dispatch of the dominant projection kernel, from separate
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this same command, scaled by
+# the factors a plain 1 GiB copy gives (FETCH x2.0, WRITE x1.0).  An entry is
+# removed whenever its kernel changes.
+MEASURED_TRAFFIC = {
+    "cfg5": {"kernel": "k_dense_apply<float>", "bytes_per_launch": 6.884e9,
+             "profile": "profiles/k_dense_apply_f32_st27_100cubed_K512.md"},
+}
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -36,6 +45,9 @@ def parse():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed", "mixed-proj"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--compare", action="store_true",
+                    help="also time plain FP64 on the same matrices (per system, one after "
+                         "another, for a batch) and report the time-to-tolerance ratio")
     return ap.parse_args()
 
 
@@ -165,6 +177,43 @@ def cpu_baseline(wl, iters):
                       % (q.name, t1 - t0, iters, t2 - t1, len(os.sched_getaffinity(0)))}
 
 
+def fp64_comparison(wl, f_dev, t_config_ms):
+    """Plain FP64 GPU solves of the same systems and partitions: a batch is
+    solved system by system (one context and one bc_solve each)."""
+    import torch
+    import paper_1710_07769_amd as bc
+    opts = dict(wl.opts)
+    opts["precision"] = bc.BC_FP64
+    t_solve = 0.0
+    iters = []
+    off = 0
+    for q in wl.problems:
+        part = q.part() if wl.partition == "contiguous" else None
+        if part is None:
+            g = bc.rip_graph(q.n, q.A.rowptr, q.A.col, q.A.val)
+            part = bc.bc_partition_greedy(g, q.K)
+        ctx = bc.bc_setup(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, part, bc.make_opts(**opts))
+        try:
+            fq = f_dev[off:off + q.n].contiguous()
+            x = torch.empty_like(fq)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = bc.bc_solve(ctx, fq, None, wl.tol, 10000, x)
+            torch.cuda.synchronize()
+            t_solve += time.perf_counter() - t0
+            iters.append(st.iterations)
+        finally:
+            bc.bc_destroy(ctx)
+        off += q.n
+    print("[bench] plain FP64 per system: %.1f ms total" % (t_solve * 1e3), file=sys.stderr,
+          flush=True)
+    return {"fp64_time_to_tol_ms": t_solve * 1e3,
+            "speedup_vs_fp64": (t_solve * 1e3) / t_config_ms if t_config_ms > 0 else None,
+            "fp64_iterations_total": int(sum(iters)),
+            "fp64_iterations_max": int(max(iters)),
+            "mode": "one bc_solve per system, one after another" if wl.batched else "bc_solve"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -236,8 +285,11 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "avg_launch_ms": proj_ms / max(launches, 1),
                      "bytes_per_launch": pbytes / max(launches, 1),
-                     "traffic": None},
+                     "traffic": (MEASURED_TRAFFIC[wl.name]["bytes_per_launch"]
+                                 if wl.name in MEASURED_TRAFFIC else None)},
     }
+    if args.compare:
+        line["fp64_comparison"] = fp64_comparison(wl, f, line["time_to_tol_ms"])
     if not args.no_cpu_baseline and not wl.batched:
         print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)
