@@ -64,6 +64,7 @@ class Workload:
         if name == "cfg1":
             p = W.config1()
             self.problems, self.partition = [p], "contiguous"
+            self.opts = {"projection": bc.BC_PROJ_DENSE_CHOL}
             self.desc = "cd2d-32 n=1024 K=4 contiguous, dense Cholesky, FP64"
         elif name == "cfg2":
             p = W.config2()
@@ -79,7 +80,8 @@ class Workload:
             self.problems, self.partition = W.config4(), "contiguous"
             self.batched = True
             self.opts = {"precision": bc.BC_MIXED}
-            self.desc = "256 x cd2d sides 48..256, K=8 each, batched, mixed"
+            self.desc = ("256 x cd2d sides 48..256, K=8 each, batched, projection kind per "
+                         "block by the byte model (banded FP64 Cholesky, FP32 applies), mixed")
         elif name in ("cfg5", "cfg5-rip"):
             p = W.config5()
             self.problems = [p]
@@ -130,6 +132,12 @@ def run_step(wl, f_dev):
         ctx = bc.bc_setup(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, parts[0], opts)
     torch.cuda.synchronize()
     out["setup_ms"] = (time.perf_counter() - t0) * 1e3
+    kind, bw = bc.bc_block_info(ctx)
+    out["block_kinds"] = {"dense": int((kind == bc.KIND_DENSE).sum()),
+                          "inner_cg": int((kind == bc.KIND_INNER).sum()),
+                          "banded": int((kind == bc.KIND_BAND).sum())}
+    if (kind == bc.KIND_BAND).any():
+        out["block_kinds"]["max_half_bandwidth"] = int(bw.max())
     try:
         x = torch.empty_like(f_dev)
         t0 = time.perf_counter()
@@ -205,9 +213,28 @@ def fp64_comparison(wl, f_dev, t_config_ms):
         finally:
             bc.bc_destroy(ctx)
         off += q.n
+        if len(iters) % 16 == 0:
+            print("[bench] plain FP64: %d/%d systems, %.1f ms so far"
+                  % (len(iters), len(wl.problems), t_solve * 1e3), file=sys.stderr, flush=True)
     print("[bench] plain FP64 per system: %.1f ms total" % (t_solve * 1e3), file=sys.stderr,
           flush=True)
-    return {"fp64_time_to_tol_ms": t_solve * 1e3,
+    extra = {}
+    if wl.batched:
+        ctx = bc.bc_setup_batched([(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, q.part())
+                                   for q in wl.problems], bc.make_opts(**opts))
+        try:
+            x = torch.empty_like(f_dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = bc.bc_solve_batched(ctx, f_dev, None, wl.tol, 10000, x)
+            torch.cuda.synchronize()
+            extra["fp64_batched_time_to_tol_ms"] = (time.perf_counter() - t0) * 1e3
+            extra["fp64_batched_iterations_max"] = int(max(st.iterations for st in sts))
+        finally:
+            bc.bc_destroy(ctx)
+        print("[bench] FP64 batched: %.1f ms" % extra["fp64_batched_time_to_tol_ms"],
+              file=sys.stderr, flush=True)
+    return {**extra, "fp64_time_to_tol_ms": t_solve * 1e3,
             "speedup_vs_fp64": (t_solve * 1e3) / t_config_ms if t_config_ms > 0 else None,
             "fp64_iterations_total": int(sum(iters)),
             "fp64_iterations_max": int(max(iters)),
@@ -270,6 +297,7 @@ def main():
                    "K": [q.K for q in wl.problems][0] if not wl.batched else 8,
                    "systems": len(wl.problems), "partition": wl.partition, "tol": wl.tol},
         "iterations": runs[-1]["iterations"],
+        "max_iterations_per_system": runs[-1]["max_iterations"],
         "time_to_tol_ms": float(np.mean([r["solve_ms"] for r in runs])),
         "setup_ms": float(np.mean([r["setup_ms"] for r in runs])),
         "rip_graph_ms": float(np.mean([r["rip_ms"] for r in runs])),
@@ -278,9 +306,12 @@ def main():
         "rel_residual": max(r["rel_residual"] for r in runs),
         "rel_error_vs_xstar": float(np.linalg.norm(xs - xstar) / np.linalg.norm(xstar)),
         "inner_iterations_per_solve": runs[-1]["inner_iterations"],
-        "roofline": {"bound": "hbm", "kernel": "block projections (%s)" %
-                     ("inner CG" if wl.opts.get("projection") == bc.BC_PROJ_INNER_CG
-                      else "dense triangular sweeps"),
+        "block_kinds": runs[-1]["block_kinds"],
+        "roofline": {"bound": "hbm", "kernel": "block projections (%s)" % ", ".join(
+                         name for name, key in (("dense triangular sweeps", "dense"),
+                                                ("inner CG", "inner_cg"),
+                                                ("banded triangular sweeps", "banded"))
+                         if runs[-1]["block_kinds"][key] > 0),
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "avg_launch_ms": proj_ms / max(launches, 1),

@@ -57,7 +57,7 @@ typedef enum {
 } bc_status;
 
 enum { BC_FP64 = 0, BC_MIXED = 1, BC_MIXED_PROJ = 2 };
-enum { BC_PROJ_AUTO = 0, BC_PROJ_DENSE_CHOL = 1, BC_PROJ_INNER_CG = 2 };
+enum { BC_PROJ_AUTO = 0, BC_PROJ_DENSE_CHOL = 1, BC_PROJ_INNER_CG = 2, BC_PROJ_BAND_CHOL = 3 };
 enum { BC_STOP_REL2 = 0, BC_STOP_BACKWARD_ERR = 1 };
 
 typedef struct {
@@ -67,8 +67,18 @@ typedef struct {
                              each replacement; BC_MIXED_PROJ: FP64 sparse
                              products, FP32 projections (dense factor copies /
                              inner CG), FP64 everything else */
-  int32_t projection;     /* BC_PROJ_AUTO (default): dense Cholesky when the
-                             block has at most dense_max_m rows, else inner CG */
+  int32_t projection;     /* How y_i = (A_i A_i^T)^{-1} u_i is computed per block.
+                             BC_PROJ_DENSE_CHOL: dense FP64 Cholesky factor
+                             (blocks of at most 4096 rows); BC_PROJ_INNER_CG:
+                             matrix-free CG; BC_PROJ_BAND_CHOL: rows of each
+                             block in reverse Cuthill-McKee order and a banded
+                             FP64 Cholesky factor (every block must reach a
+                             half-bandwidth of at most 127, else BC_ERR_INVALID);
+                             BC_PROJ_AUTO (default): per block, banded when the
+                             half-bandwidth is at most 127 and the block either
+                             has more than dense_max_m rows or its band holds
+                             at most 1/4 of the dense factor; otherwise dense
+                             for at most dense_max_m rows, else inner CG */
   int32_t dense_max_m;    /* default 4096 */
   double inner_tol;       /* inner CG stops when ||u_i - G_i y_i|| <= inner_tol ||u_i||; default 1e-12 */
   int32_t inner_maxit;    /* default 20000 */
@@ -144,6 +154,12 @@ bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, doubl
  * number of blocks using the dense Cholesky projection.  Any pointer may be NULL. */
 bc_status bc_info(const bc_ctx* ctx, int64_t* n_total, int32_t* nsys, int32_t* nblocks,
                   int32_t* ndense);
+
+/* Per block (in block order: systems in order, blocks by part id): the
+ * projection kind (0 dense Cholesky, 1 inner CG, 2 banded Cholesky) and the
+ * half-bandwidth of banded blocks (-1 for the others).  kind and bandwidth are
+ * host arrays of bc_info's nblocks entries, either may be NULL. */
+bc_status bc_block_info(const bc_ctx* ctx, int32_t* kind, int32_t* bandwidth);
 
 /* Releases the context and all its device memory.  NULL is allowed. */
 void bc_destroy(bc_ctx* ctx);

@@ -35,7 +35,8 @@ BC_OK, BC_NOT_CONVERGED = 0, 1
 BC_ERR_INVALID, BC_ERR_SINGULAR_BLOCK, BC_ERR_BREAKDOWN = -1, -2, -3
 BC_ERR_DEVICE, BC_ERR_NOMEM = -4, -5
 BC_FP64, BC_MIXED, BC_MIXED_PROJ = 0, 1, 2
-BC_PROJ_AUTO, BC_PROJ_DENSE_CHOL, BC_PROJ_INNER_CG = 0, 1, 2
+BC_PROJ_AUTO, BC_PROJ_DENSE_CHOL, BC_PROJ_INNER_CG, BC_PROJ_BAND_CHOL = 0, 1, 2, 3
+KIND_DENSE, KIND_INNER, KIND_BAND = 0, 1, 2
 BC_STOP_REL2, BC_STOP_BACKWARD_ERR = 0, 1
 
 
@@ -85,6 +86,7 @@ _SIGS = {
     "bc_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
     "bc_solve_batched": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
     "bc_info": (C.c_int, [_P, _I64P, _I32P, _I32P, _I32P]),
+    "bc_block_info": (C.c_int, [_P, _I32P, _I32P]),
     "bc_destroy": (None, [_P]),
     "rip_opts_default": (None, [C.POINTER(rip_opts)]),
     "rip_graph": (C.c_int, [C.c_int32, _I32P, _I32P, _DP, C.POINTER(rip_opts),
@@ -214,6 +216,17 @@ def bc_info(ctx) -> dict:
     return {"n_total": n.value, "nsys": ns.value, "nblocks": nb.value, "ndense": nd.value}
 
 
+def bc_block_info(ctx):
+    """Per block: projection kind (KIND_DENSE, KIND_INNER, KIND_BAND) and
+    half-bandwidth (-1 unless banded), as int32 numpy arrays."""
+    nb = bc_info(ctx)["nblocks"]
+    kind = np.zeros(nb, dtype=np.int32)
+    bw = np.zeros(nb, dtype=np.int32)
+    _check(_lib.bc_block_info(ctx, kind.ctypes.data_as(_I32P), bw.ctypes.data_as(_I32P)),
+           "bc_block_info")
+    return kind, bw
+
+
 def bc_destroy(ctx):
     _lib.bc_destroy(ctx)
 
@@ -308,6 +321,9 @@ class BlockCimmino:
 
     def info(self):
         return bc_info(self.ctx)
+
+    def block_info(self):
+        return bc_block_info(self.ctx)
 
     def close(self):
         if self.ctx is not None:

@@ -17,8 +17,8 @@ HIP_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result",
 ]
-HIP_SOURCES = ["outer.hip", "inner.hip", "dense.hip", "rip.hip", "api.hip"]
-CXX_SOURCES = ["partition.cpp"]
+HIP_SOURCES = ["outer.hip", "inner.hip", "dense.hip", "band.hip", "rip.hip", "api.hip"]
+CXX_SOURCES = ["partition.cpp", "order.cpp"]
 
 
 def _run(cmd):

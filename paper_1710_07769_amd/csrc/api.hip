@@ -89,6 +89,9 @@ hipError_t rip_launch_long(hipStream_t st, bool emit, const int* rows, int nrows
                            double alpha, int* overflow);
 int rip_short_max();
 
+// csrc/order.cpp
+int bc_rcm_order(int m, const int* xadj, const int* adj, int* order);
+
 // ------------------------------------------------------------- helpers
 
 namespace {
@@ -257,6 +260,7 @@ struct bc_ctx {
   int* d_status = nullptr;
   int* d_pending = nullptr;
   int* d_mask = nullptr;
+  int* d_restart = nullptr;
   double* d_thr = nullptr;
   double* d_rr = nullptr;
   double* d_hist = nullptr;
@@ -271,9 +275,11 @@ struct bc_ctx {
   int nblk = 0;
   InnerBlocks inner{};
   DenseBlocks dense{};
+  BandBlocks band{};
+  std::vector<long long> bd_m_h, bd_bw_h;  // per banded block rows and half-bandwidth
+  std::vector<int> blk_kind, blk_bw;       // per block: 0 dense, 1 inner CG, 2 banded; bandwidth or -1
   unsigned long long* d_inner_total = nullptr;
   std::vector<int> blk_m;
-  std::vector<int> blk_dense;
   std::vector<long long> in_nnz, in_m_h, dn_m_h;  // per inner / dense block sizes
 
   ~bc_ctx() {
@@ -327,6 +333,66 @@ bc_status leave(bc_ctx* c, void* user_stream) {
   return BC_OK;
 }
 
+enum { KIND_DENSE = 0, KIND_INNER = 1, KIND_BAND = 2 };
+constexpr int BAND_MAX_ROWS = 65536;  // largest block considered for the banded form
+
+// Reverse Cuthill-McKee order of the m rows rows[0..m) (global ids of system
+// S, offset off) on the graph of A_i A_i^T (rows sharing a column).  Returns
+// the half-bandwidth under that order and order[new] = old local index, or -1
+// without an order when a row has more than 2 BAND_MAX neighbours (then no
+// order can bring the bandwidth within BAND_MAX).  cid: scratch of size >= n
+// filled with -1, restored on return.
+int block_rcm(const SysIn& S, int off, const int* rows, int m, std::vector<int>& cid,
+              std::vector<int>& order) {
+  std::vector<int> touched;
+  for (int l = 0; l < m; ++l) {
+    const int r = rows[l] - off;
+    for (int q = S.rowptr[r]; q < S.rowptr[r + 1]; ++q) {
+      const int cc = S.col[q];
+      if (cid[cc] < 0) {
+        cid[cc] = (int)touched.size();
+        touched.push_back(cc);
+      }
+    }
+  }
+  const int nc = (int)touched.size();
+  std::vector<int> cptr(nc + 1, 0);
+  for (int l = 0; l < m; ++l) {
+    const int r = rows[l] - off;
+    for (int q = S.rowptr[r]; q < S.rowptr[r + 1]; ++q) cptr[cid[S.col[q]] + 1]++;
+  }
+  for (int k = 0; k < nc; ++k) cptr[k + 1] += cptr[k];
+  std::vector<int> crow(cptr[nc]);
+  {
+    std::vector<int> cur(cptr.begin(), cptr.end() - 1);
+    for (int l = 0; l < m; ++l) {
+      const int r = rows[l] - off;
+      for (int q = S.rowptr[r]; q < S.rowptr[r + 1]; ++q) crow[cur[cid[S.col[q]]]++] = l;
+    }
+  }
+  std::vector<int> xadj(m + 1, 0), adj, stamp(m, -1);
+  bool too_wide = false;
+  for (int l = 0; l < m && !too_wide; ++l) {
+    const int r = rows[l] - off;
+    for (int q = S.rowptr[r]; q < S.rowptr[r + 1]; ++q) {
+      const int k = cid[S.col[q]];
+      for (int e = cptr[k]; e < cptr[k + 1]; ++e) {
+        const int l2 = crow[e];
+        if (l2 != l && stamp[l2] != l) {
+          stamp[l2] = l;
+          adj.push_back(l2);
+        }
+      }
+    }
+    xadj[l + 1] = (int)adj.size();
+    if (xadj[l + 1] - xadj[l] > 2 * BAND_MAX) too_wide = true;
+  }
+  for (int cc : touched) cid[cc] = -1;
+  if (too_wide) return -1;
+  order.resize(m);
+  return bc_rcm_order(m, xadj.data(), adj.data(), order.data());
+}
+
 bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   const bc_opts& o = c->opts;
   c->mixed = o.precision == BC_MIXED || o.precision == BC_MIXED_PROJ;
@@ -372,14 +438,61 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   }
   c->nblk = (int)blk_m.size();
   c->blk_m = blk_m;
+  // ---- block kinds.  Every kind computes y_i = (A_i A_i^T)^{-1} u_i
+  // (Section 1, eq. (H)); they differ in how.  Banded blocks get their rows
+  // in reverse Cuthill-McKee order (the order of rows inside a block does not
+  // change its projection, Section 2.2).
+  const int dmax = std::min(o.dense_max_m, 4096);
+  std::vector<int> kind(c->nblk, KIND_INNER), bandw(c->nblk, -1);
+  {
+    int maxn = 0;
+    for (int s = 0; s < c->nsys; ++s) maxn = std::max(maxn, sys[s].n);
+    std::vector<int> cid(maxn, -1);
+    for (int b = 0; b < c->nblk; ++b) {
+      const int m = blk_m[b];
+      if (o.projection == BC_PROJ_DENSE_CHOL) {
+        if (m > 4096) {
+          bc_set_error("dense Cholesky projection needs blocks of at most 4096 rows");
+          return BC_ERR_INVALID;
+        }
+        kind[b] = KIND_DENSE;
+        continue;
+      }
+      if (o.projection == BC_PROJ_INNER_CG) continue;
+      std::vector<int> order;
+      const int bwid = m <= BAND_MAX_ROWS
+                           ? block_rcm(sys[blk_sys[b]], c->sys_off[blk_sys[b]], perm.data() + blk_row0[b], m,
+                                       cid, order)
+                           : -1;
+      const bool band_ok = bwid >= 0 && bwid <= BAND_MAX;
+      if (o.projection == BC_PROJ_BAND_CHOL) {
+        if (!band_ok) {
+          bc_set_error("block " + std::to_string(b) + " (" + std::to_string(m) +
+                       " rows) has no banded form within half-bandwidth " + std::to_string(BAND_MAX) +
+                       (bwid >= 0 ? " (reverse Cuthill-McKee gives " + std::to_string(bwid) + ")" : ""));
+          return BC_ERR_INVALID;
+        }
+        kind[b] = KIND_BAND;
+      } else {
+        // bytes per application: band 2 m (bw+1), dense m (m+1), inner CG
+        // (thousands of sparse products) the most; band wins by a margin
+        kind[b] = band_ok && (m > dmax || 8LL * (bwid + 1) <= (long long)m + 1)
+                      ? KIND_BAND
+                      : (m <= dmax ? KIND_DENSE : KIND_INNER);
+      }
+      if (kind[b] == KIND_BAND) {
+        bandw[b] = bwid;
+        std::vector<int> idx(perm.begin() + blk_row0[b], perm.begin() + blk_row0[b] + m);
+        for (int l = 0; l < m; ++l) perm[blk_row0[b] + l] = idx[order[l]];
+      }
+    }
+  }
+  c->blk_kind = kind;
+  c->blk_bw = bandw;
   // Rows of an inner-CG block are ordered by decreasing length (stable) when
-  // their 64-row slices would otherwise be padded by more than 25%: the order
-  // of rows inside a block does not change its projection (Section 2.2).
-  const int dmax_pre = std::min(o.dense_max_m, 4096);
+  // their 64-row slices would otherwise be padded by more than 25%.
   for (int b = 0; b < c->nblk; ++b) {
-    const bool inner = o.projection == BC_PROJ_INNER_CG ||
-                       (o.projection == BC_PROJ_AUTO && blk_m[b] > dmax_pre);
-    if (!inner) continue;
+    if (kind[b] != KIND_INNER) continue;
     const int r0 = blk_row0[b], m = blk_m[b];
     auto len = [&](int i) {
       const int g = perm[i];
@@ -469,21 +582,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   c->ntiles = (int)tile_start.size();
   tile_start.push_back(n);
   c->lanes = o.spmv_lanes > 0 ? o.spmv_lanes : choose_lanes(nnz, n);
-  // ---- block kinds
-  const int dmax = std::min(o.dense_max_m, 4096);
   std::vector<int> is_dense(c->nblk, 0);
-  for (int b = 0; b < c->nblk; ++b) {
-    if (o.projection == BC_PROJ_DENSE_CHOL) {
-      if (blk_m[b] > 4096) {
-        bc_set_error("dense Cholesky projection needs blocks of at most 4096 rows");
-        return BC_ERR_INVALID;
-      }
-      is_dense[b] = 1;
-    } else if (o.projection == BC_PROJ_AUTO) {
-      is_dense[b] = blk_m[b] <= dmax;
-    }
-  }
-  c->blk_dense = is_dense;
+  for (int b = 0; b < c->nblk; ++b) is_dense[b] = kind[b] == KIND_DENSE;
   // ---- inner-CG block data
   std::vector<int> in_row0, in_m, in_sup0, in_nsup, in_sys;
   std::vector<int> loc(nnz, 0), btptr(1, 0), btrow;
@@ -492,7 +592,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     std::vector<int> mark(n, -1);
     int sup_total = 0;
     for (int b = 0; b < c->nblk; ++b) {
-      if (is_dense[b]) continue;
+      if (kind[b] != KIND_INNER) continue;
       const int r0 = blk_row0[b], m = blk_m[b];
       std::vector<int> sup;
       for (int i = r0; i < r0 + m; ++i)
@@ -597,6 +697,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   BC_TRY(A.upload(&c->d_status, zeros_ns, st));
   BC_TRY(A.upload(&c->d_pending, zeros_ns, st));
   BC_TRY(A.upload(&c->d_mask, zeros_ns, st));
+  BC_TRY(A.upload(&c->d_restart, zeros_ns, st));
   BC_TRY(A.alloc(&c->d_thr, ns));
   BC_TRY(A.alloc(&c->d_rr, 2 * ns));
   BC_TRY(A.alloc(&c->d_hist, ns));
@@ -840,6 +941,70 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
         return BC_ERR_SINGULAR_BLOCK;
       }
   }
+  // banded blocks
+  BandBlocks& Bd = c->band;
+  Bd = BandBlocks{};
+  {
+    std::vector<int> bd_row0, bd_m, bd_bw, bd_ld, bd_sys;
+    std::vector<long long> bd_off;
+    long long btot = 0;
+    int ldmax = 0;
+    for (int b = 0; b < c->nblk; ++b) {
+      if (kind[b] != KIND_BAND) continue;
+      const int m = blk_m[b], W = (bandw[b] + 1 + 3) / 4 * 4;
+      ldmax = std::max(ldmax, W);
+      bd_row0.push_back(blk_row0[b]);
+      bd_m.push_back(m);
+      bd_bw.push_back(bandw[b]);
+      bd_ld.push_back(W);
+      bd_sys.push_back(blk_sys[b]);
+      bd_off.push_back(btot);
+      c->bd_m_h.push_back(m);
+      c->bd_bw_h.push_back(bandw[b]);
+      btot += (long long)((m + 63) / 64) * 64 * W;
+    }
+    Bd.nblk = (int)bd_m.size();
+    if (Bd.nblk > 0) {
+      int *p0, *p1, *p2, *p3, *p4, *pinfo;
+      long long* po;
+      BC_TRY(A.upload(&p0, bd_row0, st));
+      BC_TRY(A.upload(&p1, bd_m, st));
+      BC_TRY(A.upload(&p2, bd_bw, st));
+      BC_TRY(A.upload(&p4, bd_ld, st));
+      BC_TRY(A.upload(&p3, bd_sys, st));
+      BC_TRY(A.upload(&po, bd_off, st));
+      std::vector<int> iz(Bd.nblk, 0);
+      BC_TRY(A.upload(&pinfo, iz, st));
+      Bd.row0 = p0; Bd.m = p1; Bd.bw = p2; Bd.ld = p4; Bd.sys = p3; Bd.off = po; Bd.info = pinfo;
+      Bd.ldmax = ldmax;
+      Bd.dsc = d_dsc;
+      unsigned long long* pap;
+      BC_TRY(A.alloc(&pap, Bd.nblk));
+      BC_HIP(hipMemsetAsync(pap, 0, Bd.nblk * sizeof(unsigned long long), st));
+      Bd.applies = pap;
+      BC_TRY(A.alloc(&Bd.L, btot));
+      BC_TRY(A.alloc(&Bd.dinv, n));
+      if (c->mixed) {
+        BC_TRY(A.alloc(&Bd.L32, btot));
+        BC_TRY(A.alloc(&Bd.R32, btot));
+        BC_TRY(A.alloc(&Bd.dinv32, n));
+      } else {
+        BC_TRY(A.alloc(&Bd.R, btot));
+      }
+      BC_HIP(launch_band_gram(st, Bd, c->d_rowptr, c->d_col, c->d_val, c->d_tptr, c->d_trow, c->d_tval));
+      BC_HIP(launch_band_cholesky(st, Bd));
+      std::vector<int> info(Bd.nblk);
+      BC_HIP(hipMemcpyAsync(info.data(), pinfo, Bd.nblk * sizeof(int), hipMemcpyDeviceToHost, st));
+      BC_HIP(hipStreamSynchronize(st));
+      for (int b = 0; b < Bd.nblk; ++b)
+        if (info[b] != 0) {
+          bc_set_error("banded block " + std::to_string(b) + " has a non-positive pivot at row " +
+                       std::to_string(info[b] - 1) + ": A_i A_i^T is numerically singular");
+          return BC_ERR_SINGULAR_BLOCK;
+        }
+      BC_HIP(launch_band_finish(st, Bd, c->mixed));
+    }
+  }
   BC_HIP(hipStreamSynchronize(st));
   return BC_OK;
 }
@@ -884,7 +1049,7 @@ extern "C" bc_status bc_setup_batched(bc_ctx** ctx, int32_t nsys, const int32_t*
     bc_set_error("unknown precision");
     return BC_ERR_INVALID;
   }
-  if (opts && (opts->projection < BC_PROJ_AUTO || opts->projection > BC_PROJ_INNER_CG ||
+  if (opts && (opts->projection < BC_PROJ_AUTO || opts->projection > BC_PROJ_BAND_CHOL ||
                opts->inner_tol < 0.0 || opts->inner_maxit < 1 || opts->dense_max_m < 0 ||
                opts->stop_rule < 0 || opts->stop_rule > 1 || opts->spmv_lanes < 0 ||
                (opts->spmv_lanes & (opts->spmv_lanes - 1)) || opts->spmv_lanes > 64)) {
@@ -960,6 +1125,18 @@ extern "C" bc_status bc_info(const bc_ctx* c, int64_t* n_total, int32_t* nsys, i
   return BC_OK;
 }
 
+extern "C" bc_status bc_block_info(const bc_ctx* c, int32_t* kind, int32_t* bandwidth) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  for (int b = 0; b < c->nblk; ++b) {
+    if (kind) kind[b] = c->blk_kind[b];
+    if (bandwidth) bandwidth[b] = c->blk_bw[b];
+  }
+  return BC_OK;
+}
+
 // ------------------------------------------------------------- projections
 
 namespace {
@@ -978,6 +1155,7 @@ bc_status block_solves(bc_ctx* c, const double* u, double* y, const int* done) {
     BC_HIP(hipEventRecord(c->ev_proj[2 * c->ev_used], st));
   }
   BC_HIP(launch_dense_apply(st, c->dense, c->mixed, u, y, done));
+  BC_HIP(launch_band_apply(st, c->band, c->mixed, u, y, done));
   BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u, y, done));
   if (c->timing) {
     BC_HIP(hipEventRecord(c->ev_proj[2 * c->ev_used + 1], st));
@@ -1017,6 +1195,12 @@ bc_status proj_bytes(bc_ctx* c, double* out) {
       bytes += (double)ap[b] * m * (m + 1.0) * w;
     }
   }
+  if (c->band.nblk) {
+    std::vector<unsigned long long> ap(c->band.nblk);
+    BC_HIP(hipMemcpy(ap.data(), c->band.applies, ap.size() * sizeof(ap[0]), hipMemcpyDeviceToHost));
+    for (int b = 0; b < c->band.nblk; ++b)
+      bytes += (double)ap[b] * 2.0 * (double)c->bd_m_h[b] * (double)(c->bd_bw_h[b] + 1) * w;
+  }
   *out = bytes;
   return BC_OK;
 }
@@ -1026,6 +1210,8 @@ bc_status reset_proj_counters(bc_ctx* c) {
     BC_HIP(hipMemsetAsync(c->inner.blk_total, 0, c->inner.nblk * sizeof(unsigned long long), c->stream));
   if (c->dense.nblk)
     BC_HIP(hipMemsetAsync(c->dense.applies, 0, c->dense.nblk * sizeof(unsigned long long), c->stream));
+  if (c->band.nblk)
+    BC_HIP(hipMemsetAsync(c->band.applies, 0, c->band.nblk * sizeof(unsigned long long), c->stream));
   c->ev_used = 0;
   c->t_proj_ms = 0.0;
   c->proj_launches = 0;
@@ -1119,15 +1305,26 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
       if (c->mixed && o.replace_every > 0 && it % o.replace_every == 0) {
         // FP64 true residual s = f - A x (and, with FP32 sparse products, the
         // stop test on it), then r = A^T D^{-1} s through the working-precision
-        // projection and a CG restart p = r: each cycle is a defect correction
-        // of x by replace_every CG steps on the FP32-projected operator
+        // projections.  With factor-based projections the FP32 operator is the
+        // same at every application: r and r.r are replaced and the search
+        // direction is kept (a reliable update), unless the new residual is
+        // more than twice the recursive one (the recursion had drifted: near
+        // the attainable accuracy of the FP32 operator), where CG restarts.
+        // With inner-CG projections the operator changes from one application
+        // to the next, and CG always restarts with p = r: each cycle is then a
+        // defect correction of x by replace_every CG steps.
         BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s,
                                S, nullptr));
         if (c->spmv32) BC_HIP(launch_true_check(st, S));
         BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
         BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
                                 c->spmv32, c->d_y, c->d_r, c->d_p, S));
-        BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S, it & 1));
+        if (c->inner.nblk > 0) {
+          BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S, it & 1));
+        } else {
+          BC_HIP(launch_sqnorm_tiles(st, c->d_r, c->d_part_b, S));
+          BC_HIP(launch_replace_decide(st, S, it & 1, c->d_restart, c->d_p, c->d_r));
+        }
         for (int s2 = 0; s2 < ns; ++s2) replacements[s2]++;
       }
     }

@@ -1,0 +1,440 @@
+// Banded Cholesky projections.
+//
+// For a block whose rows are in reverse Cuthill-McKee order, the scaled
+// normal-equation matrix G = D A_i A_i^T D (D = unit-row scaling; Section 1,
+// eq. (H): y_i = (A_i A_i^T)^{-1} u_i) is banded with a small half-bandwidth
+// bw, and so is its Cholesky factor (a banded matrix factors without fill
+// outside its band).  Setup forms G in the band storage (k_band_gram),
+// factors it in FP64 in place (k_band_chol) and derives the reversed
+// transpose and the FP32 copies (k_band_finish).  Each projection then runs
+// two banded triangular sweeps (k_band_apply): L z = D u and L^T w = z, y = D w.
+//
+// Storage (see BandBlocks): per 64-row tile, diagonal-major, entry d of local
+// row p at tile*64*ld + d*64 + p%64, column p - bw + d (ld = bw+1 rounded up
+// to a multiple of 4).  Lanes of a wave own consecutive rows, so every band
+// access of the sweeps is coalesced, and a tile is one contiguous chunk.
+#include "common.h"
+
+#include <cmath>
+
+namespace {
+
+__device__ __forceinline__ long long band_at(int p, int d, int ld) {
+  return (long long)(p >> 6) * 64 * ld + (long long)d * 64 + (p & 63);
+}
+
+// ------------------------------------------------------------------ Gram
+// One workgroup per block; thread-per-row.  Row p of G: for every entry
+// (c, a_pc) of row p and every row s of column c with p - bw <= s <= p,
+// G[p][s] += (a_pc d_p)(a_sc d_s), accumulated in the fixed order (entries of
+// row p by ascending column, rows of a column ascending).
+__global__ void __launch_bounds__(256)
+k_band_gram(BandBlocks B, const int* __restrict__ rowptr, const int* __restrict__ col,
+            const double* __restrict__ val, const int* __restrict__ tptr,
+            const int* __restrict__ trow, const double* __restrict__ tval) {
+  const int blk = blockIdx.x;
+  const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk], row0 = B.row0[blk];
+  const int nt = (m + 63) >> 6;
+  double* G = B.L + B.off[blk];
+  for (int p = threadIdx.x; p < nt * 64; p += blockDim.x) {
+    for (int d = 0; d < ld; ++d) G[band_at(p, d, ld)] = 0.0;
+    if (p >= m) continue;
+    const int i = row0 + p;
+    const double di = B.dsc[i];
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+      const int c = col[e];
+      const double a = val[e] * di;
+      for (int q = tptr[c]; q < tptr[c + 1]; ++q) {
+        const int s = trow[q] - row0;
+        if (s < p - bw) continue;
+        if (s > p) break;  // rows of a column are ascending
+        const double gs = a * (tval[q] * B.dsc[row0 + s]);
+        G[band_at(p, s - p + bw, ld)] += gs;
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- Cholesky
+// Right-looking banded Cholesky, one workgroup per block, with the active
+// window (rows j..j+bw, each with its bw+1 band entries) held in LDS as a
+// circular buffer of rows.  Step j: pivot L_jj = sqrt(G_jj) with the relative
+// test G_jj > m eps G_jj(original); multipliers l_i = G_ij / L_jj for the
+// rows i <= j+bw below it; rank-1 update of the trailing window; row j is
+// final and goes back to global memory, and row j+bw+1 enters its slot.
+__global__ void __launch_bounds__(256)
+k_band_chol(BandBlocks B) {
+  extern __shared__ double lds[];
+  const int blk = blockIdx.x;
+  const int m = B.m[blk], bw = B.bw[blk], W = bw + 1, ld = B.ld[blk];
+  double* win = lds;            // W x W
+  double* gd = lds + W * W;     // original diagonal of the row in each slot
+  double* G = B.L + B.off[blk];
+  const int tid = threadIdx.x;
+  const double rel_piv = (double)m * 2.220446049250313e-16;
+  for (int e = tid; e < W * W; e += blockDim.x) {
+    const int r = e / W, d = e - r * W;
+    win[e] = r < m ? G[band_at(r, d, ld)] : 0.0;
+  }
+  for (int r = tid; r < W; r += blockDim.x) gd[r] = r < m ? G[band_at(r, bw, ld)] : 1.0;
+  __syncthreads();
+  for (int j = 0; j < m; ++j) {
+    const int sj = j % W;
+    const double a = win[sj * W + bw];
+    if (!(a > rel_piv * gd[sj])) {  // uniform: every thread reads the same value
+      if (tid == 0) B.info[blk] = j + 1;
+      return;
+    }
+    const double ljj = sqrt(a);
+    const double inv = 1.0 / ljj;
+    const int nb = min(bw, m - 1 - j);
+    // multipliers: row i = j+1+t holds column j at d = bw-1-t
+    if (tid < nb) {
+      const int si = (j + 1 + tid) % W;
+      win[si * W + (bw - 1 - tid)] *= inv;
+    }
+    __syncthreads();
+    // trailing update over pairs (i, k), j < k <= i <= j + nb
+    const int npairs = nb * (nb + 1) / 2;
+    for (int q = tid; q < npairs; q += blockDim.x) {
+      int ii = (int)((sqrtf(8.0f * (float)q + 1.0f) - 1.0f) * 0.5f);
+      while ((ii + 1) * (ii + 2) / 2 <= q) ++ii;
+      while (ii * (ii + 1) / 2 > q) --ii;
+      const int kk = q - ii * (ii + 1) / 2;
+      const int si = (j + 1 + ii) % W, sk = (j + 1 + kk) % W;
+      const double li = win[si * W + (bw - 1 - ii)];
+      const double lk = win[sk * W + (bw - 1 - kk)];
+      win[si * W + (kk - ii + bw)] -= li * lk;
+    }
+    // row j is final (its slot is not touched by the update above): write it
+    // out and bring in row j + W
+    for (int d = tid; d < W; d += blockDim.x) {
+      G[band_at(j, d, ld)] = d == bw ? ljj : win[sj * W + d];
+      const int nr = j + W;
+      const double v = nr < m ? G[band_at(nr, d, ld)] : 0.0;
+      win[sj * W + d] = v;
+      if (d == bw) gd[sj] = nr < m ? v : 1.0;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- finish
+// Reversed transpose R[p][d] = L[m-1-p+bw-d][d] (zero outside the matrix and
+// for d >= bw), 1/L_pp, and the FP32 copies (diagonal zero).  Grid: (tiles,
+// blocks).  k_band_zero_diag then clears the diagonal of the FP64 factor, so
+// that every copy the sweeps read has a zero diagonal.
+__global__ void __launch_bounds__(256)
+k_band_finish(BandBlocks B, int mixed) {
+  const int blk = blockIdx.y;
+  const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk], row0 = B.row0[blk];
+  const int nt = (m + 63) >> 6;
+  const long long off = B.off[blk];
+  const double* L = B.L + off;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    for (int e = threadIdx.x; e < 64 * ld; e += blockDim.x) {
+      const int d = e >> 6, p = t * 64 + (e & 63);
+      const long long at = band_at(p, d, ld);
+      double r = 0.0;
+      const int k = p - bw + d;          // column of R, reversed row of L
+      const int src = m - 1 - k;         // row of L holding R[p][k]
+      if (d < bw && p < m && k >= 0 && src < m) r = L[band_at(src, d, ld)];
+      // the sweeps take 1/L_pp from dinv; their copies keep a zero diagonal
+      if (mixed) {
+        B.L32[off + at] = d == bw ? 0.f : (float)L[at];
+        B.R32[off + at] = (float)r;
+      } else {
+        B.R[off + at] = r;
+      }
+      if (d == bw && p < m) {
+        const double iv = 1.0 / L[at];
+        B.dinv[row0 + p] = iv;
+        if (mixed) B.dinv32[row0 + p] = (float)iv;
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_band_zero_diag(BandBlocks B) {
+  const int blk = blockIdx.y;
+  const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk];
+  double* L = B.L + B.off[blk];
+  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x)
+    L[band_at(p, bw, ld)] = 0.0;
+}
+
+// ----------------------------------------------------------------- apply
+template <typename T>
+__device__ __forceinline__ T lane_bcast(T v, int lane);
+template <>
+__device__ __forceinline__ float lane_bcast<float>(float v, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+template <>
+__device__ __forceinline__ double lane_bcast<double>(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// One wave per block; lane l owns row p = i0 + l of the current 64-row tile.
+// The tiles of the forward sweep (factor L, right-hand side D u) and then of
+// the backward sweep (factor R, right-hand side the reversed forward result)
+// are processed in one sequence.  While a tile is computed, the next tile's
+// band (64*ld contiguous values) is already in flight as 16-byte loads into
+// registers, and is written into the (single) LDS stage once the tile is done
+// with it, so the wave
+// never waits on HBM inside a tile.  Per tile: the
+// off-tile part acc -= sum_{k < i0} F[p][k] w[k] reads the stage against the
+// solved values kept in a 256-entry circular window (bw <= BAND_MAX < 192,
+// so rows i0-bw..i0-1 are all still there); the in-tile triangle is a column
+// sweep: at step j, w_j = acc_j / F_jj is broadcast from lane j and the lanes
+// below it subtract F[p][i0+j] w_j (read from the stage: lane l's entry sits
+// in its own bank column, no conflicts).
+// Ordering point for the one-wave workgroup of k_band_apply: LDS operations
+// of a wave execute in program order, so a compiler barrier with
+// wavefront-scope fences orders the lanes' LDS accesses without the
+// memory-counter waits of a workgroup barrier (which would also wait for the
+// prefetch loads in flight and for the global stores of the last tile).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int NVP>
+__global__ void __launch_bounds__(64)
+k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
+             const int* __restrict__ done) {
+  extern __shared__ float4 lds4[];
+  const int blk = blockIdx.x;
+  if (done && done[B.sys[blk]]) return;
+  const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk], row0 = B.row0[blk];
+  const int nt = (m + 63) >> 6;
+  const int l = threadIdx.x;
+  T* stage = (T*)lds4;                         // band of the current tile, 64*ld
+  T* yw = stage + 64 * B.ldmax;                // solved values, circular, 256
+  double* ra = (double*)(yw + 256);            // staged right-hand side of the tile
+  double* rs = ra + 64;                        // staged output scale
+  T* rd = (T*)(rs + 64);                       // staged pivot reciprocal
+  constexpr int VT = 16 / (int)sizeof(T);
+  const int nv = ld / VT;          // 16-byte vectors per lane per tile
+  const int npre = min(nv, NVP);   // of which prefetched during compute
+  if (l == 0) atomicAdd(&B.applies[blk], 1ull);
+  const T* Fl;
+  const T* Fr;
+  const T* dv;
+  if constexpr (sizeof(T) == 8) {
+    Fl = (const T*)(B.L + B.off[blk]);
+    Fr = (const T*)(B.R + B.off[blk]);
+    dv = (const T*)(B.dinv + row0);
+  } else {
+    Fl = (const T*)(B.L32 + B.off[blk]);
+    Fr = (const T*)(B.R32 + B.off[blk]);
+    dv = (const T*)(B.dinv32 + row0);
+  }
+  const double* dsc = B.dsc + row0;
+  double* yb = y + row0;
+  const int total = 2 * nt;
+  auto chunk = [&](int idx) -> const float4* {
+    const bool bwd = idx >= nt;
+    const int t = bwd ? idx - nt : idx;
+    return (const float4*)((bwd ? Fr : Fl) + (long long)t * 64 * ld);
+  };
+  // Row of tile idx whose right-hand side, output scale and pivot lane l
+  // loads: clamped into the block so the loads carry no predicate.
+  auto rhs_row = [&](int idx) -> int {
+    const int bwd = idx >= nt;
+    const int pc = min((bwd ? idx - nt : idx) * 64 + l, m - 1);
+    return bwd ? m - 1 - pc : pc;
+  };
+  {
+    const float4* src = chunk(0);
+    float4* dst = (float4*)stage;
+    for (int q = 0; q < nv; ++q) dst[q * 64 + l] = src[q * 64 + l];
+    const int r = rhs_row(0);
+    ra[l] = u[row0 + r] * dsc[r];
+    rd[l] = dv[r];
+  }
+  wave_sync();
+  for (int idx = 0; idx < total; ++idx) {
+    const bool bwd = idx >= nt;
+    const int t = bwd ? idx - nt : idx;
+    const int i0 = t * 64, p = i0 + l;
+    if (idx == nt) {
+      // the backward sweep starts from the forward result written by all lanes
+      __threadfence_block();
+      __syncthreads();
+      const int r = rhs_row(idx);
+      ra[l] = yb[r];
+      rs[l] = dsc[r];
+      rd[l] = dv[r];
+      wave_sync();
+    }
+    if (t == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) yw[q * 64 + l] = (T)0;
+    }
+    yw[p & 255] = (T)0;
+    T acc = p < m ? (T)ra[l] : (T)0;
+    const T dp = p < m ? rd[l] : (T)0;
+    const double sc = rs[l];
+    wave_sync();
+    // prefetch of the next tile: right-hand side (except across the switch of
+    // sweeps, which needs this sweep's result) and band.  Vectors q >= npre
+    // re-read vector 0 (in bounds), so the loads carry no predicate; the
+    // prefetch lives in named registers (an array here ends up in scratch).
+    const bool has_next = idx + 1 < total;
+    const int nidx = has_next ? idx + 1 : idx;
+    const int nr = rhs_row(nidx);
+    const bool nbwd = nidx >= nt;
+    const double na = nbwd ? yb[nr] : u[row0 + nr];
+    const double ns = dsc[nr];
+    const T nd = dv[nr];
+    const float4* nsrc = chunk(nidx);
+#define BC_PF(q) float4 pf##q; if constexpr (NVP > q) pf##q = nsrc[((q) < npre ? (q) : 0) * 64 + l];
+    BC_PF(0) BC_PF(1) BC_PF(2) BC_PF(3) BC_PF(4) BC_PF(5) BC_PF(6) BC_PF(7)
+    BC_PF(8) BC_PF(9) BC_PF(10) BC_PF(11) BC_PF(12) BC_PF(13) BC_PF(14) BC_PF(15)
+    BC_PF(16) BC_PF(17) BC_PF(18) BC_PF(19) BC_PF(20) BC_PF(21) BC_PF(22) BC_PF(23)
+    BC_PF(24) BC_PF(25) BC_PF(26) BC_PF(27) BC_PF(28) BC_PF(29) BC_PF(30) BC_PF(31)
+#undef BC_PF
+    const T* buf = stage;
+    // Off-tile part acc -= sum_d F[p][p-bw+d] w[p-bw+d], d < bw.  The window
+    // slots of this tile's rows are zeroed first (they held rows 256 back, no
+    // longer referenced), and slots of rows below 0 are zero from the start
+    // of the sweep, so in-tile and out-of-matrix columns contribute nothing
+    // and the batches of 16 need no mask; only the tail batch is masked.
+    // All LDS reads of a batch are issued before its arithmetic.
+    {
+      const int kb = p - bw;
+      int d0 = 0;
+      for (; d0 + 16 <= bw; d0 += 16) {
+        T v[16], yk[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          v[i] = buf[(d0 + i) * 64 + l];
+          yk[i] = yw[(kb + d0 + i) & 255];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc -= v[i] * yk[i];
+      }
+      if (d0 < bw) {
+        T v[16], yk[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          v[i] = buf[min(d0 + i, ld - 1) * 64 + l];
+          yk[i] = yw[(kb + d0 + i) & 255];
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc -= (d0 + i < bw) ? v[i] * yk[i] : (T)0;
+      }
+    }
+    // In-tile column sweep, 64 steps in batches of 16: step j broadcasts
+    // w_j = acc_j / F_jj from lane j and every lane subtracts F[p][i0+j] w_j.
+    // Entries outside the band of row p (including j >= l) are read from the
+    // zero diagonal slot, so a step is a multiply, a broadcast and an FMA;
+    // lane l's value stops changing after step l, and rows past m have a zero
+    // pivot reciprocal.
+#pragma unroll
+    for (int j0 = 0; j0 < 64; j0 += 16) {
+      T e[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int dd = bw - l + j0 + i;  // entry of row p for column i0 + j
+        e[i] = buf[((unsigned)dd <= (unsigned)bw ? dd : bw) * 64 + l];
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const T s = lane_bcast<T>(acc * dp, j0 + i);
+        acc -= e[i] * s;
+      }
+    }
+    const T w = acc * dp;
+    wave_sync();  // every lane is done with the stage and the window
+    yw[p & 255] = w;
+    if (has_next) {
+      // stage the next tile (the one wait for HBM per tile)
+      float4* nbuf = (float4*)stage;
+      // vectors q >= npre hold vector 0 again: writing them back to slot 0
+      // is idempotent and keeps the stores unpredicated
+#define BC_ST(q) if constexpr (NVP > q) nbuf[((q) < npre ? (q) : 0) * 64 + l] = pf##q;
+      BC_ST(0) BC_ST(1) BC_ST(2) BC_ST(3) BC_ST(4) BC_ST(5) BC_ST(6) BC_ST(7)
+      BC_ST(8) BC_ST(9) BC_ST(10) BC_ST(11) BC_ST(12) BC_ST(13) BC_ST(14) BC_ST(15)
+      BC_ST(16) BC_ST(17) BC_ST(18) BC_ST(19) BC_ST(20) BC_ST(21) BC_ST(22) BC_ST(23)
+      BC_ST(24) BC_ST(25) BC_ST(26) BC_ST(27) BC_ST(28) BC_ST(29) BC_ST(30) BC_ST(31)
+#undef BC_ST
+      for (int q = npre; q < nv; ++q) nbuf[q * 64 + l] = nsrc[q * 64 + l];
+      ra[l] = nbwd ? na : na * ns;
+      rs[l] = ns;
+      rd[l] = nd;
+    }
+    if (p < m) {
+      if (!bwd) yb[p] = (double)w;
+      else yb[m - 1 - p] = (double)w * sc;
+    }
+    wave_sync();
+  }
+}
+
+template <typename T>
+hipError_t launch_apply_t(hipStream_t st, const BandBlocks& B, const double* u, double* y,
+                          const int* done) {
+  const int nvmax = B.ldmax * (int)sizeof(T) / 16;
+  const size_t lds = (size_t)(64 * B.ldmax + 256) * sizeof(T) + 64 * (2 * sizeof(double) + sizeof(T));
+  // smallest register bucket that holds a whole tile (FP64 bands wider than
+  // 64 entries load their tail after the tile is computed)
+  const int nvp = nvmax <= 4 ? 4 : nvmax <= 8 ? 8 : nvmax <= 16 ? 16 : nvmax <= 24 ? 24 : 32;
+  const void* fn = nvp == 4    ? (const void*)k_band_apply<T, 4>
+                   : nvp == 8  ? (const void*)k_band_apply<T, 8>
+                   : nvp == 16 ? (const void*)k_band_apply<T, 16>
+                   : nvp == 24 ? (const void*)k_band_apply<T, 24>
+                               : (const void*)k_band_apply<T, 32>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (nvp == 4)
+    hipLaunchKernelGGL((k_band_apply<T, 4>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
+  else if (nvp == 8)
+    hipLaunchKernelGGL((k_band_apply<T, 8>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
+  else if (nvp == 16)
+    hipLaunchKernelGGL((k_band_apply<T, 16>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
+  else if (nvp == 24)
+    hipLaunchKernelGGL((k_band_apply<T, 24>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
+  else
+    hipLaunchKernelGGL((k_band_apply<T, 32>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_band_gram(hipStream_t st, const BandBlocks& B, const int* rowptr, const int* col,
+                            const double* val, const int* tptr, const int* trow, const double* tval) {
+  if (B.nblk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_gram, dim3(B.nblk), dim3(256), 0, st, B, rowptr, col, val, tptr, trow,
+                     tval);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_cholesky(hipStream_t st, const BandBlocks& B) {
+  if (B.nblk == 0) return hipSuccess;
+  const size_t lds = (size_t)(BAND_MAX + 1) * (BAND_MAX + 2) * sizeof(double);
+  hipError_t e = hipFuncSetAttribute((const void*)k_band_chol,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_band_chol, dim3(B.nblk), dim3(256), lds, st, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_finish(hipStream_t st, const BandBlocks& B, bool mixed) {
+  if (B.nblk == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_finish, dim3(32, B.nblk), dim3(256), 0, st, B, (int)mixed);
+  if (!mixed) hipLaunchKernelGGL(k_band_zero_diag, dim3(4, B.nblk), dim3(256), 0, st, B);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, const double* u,
+                             double* y, const int* done) {
+  if (B.nblk == 0) return hipSuccess;
+  return mixed ? launch_apply_t<float>(st, B, u, y, done) : launch_apply_t<double>(st, B, u, y, done);
+}

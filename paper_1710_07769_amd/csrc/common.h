@@ -145,6 +145,8 @@ hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const Out
 hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S,
                           int slot);
 hipError_t launch_rr_from_partials(hipStream_t st, const OuterState& S, int slot);
+hipError_t launch_replace_decide(hipStream_t st, const OuterState& S, int slot, int* restart,
+                                 double* p, const double* r);
 hipError_t launch_true_check(hipStream_t st, const OuterState& S);
 hipError_t launch_init_norms(hipStream_t st, const double* f, const double* s, const double* x,
                              double* part_f, const OuterState& S);
@@ -228,3 +230,38 @@ hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);
 hipError_t launch_dense_apply(hipStream_t st, const DenseBlocks& D, bool mixed, const double* u,
                               double* y, const int* done);
+
+// Banded blocks: rows of the block in reverse Cuthill-McKee order, so that the
+// scaled normal-equation matrix G = D A_i A_i^T D has half-bandwidth bw.  The
+// factor is stored per 64-row tile in diagonal-major order: entry d (0..bw)
+// of local row p, i.e. L[p][p - bw + d], is at off + (p/64)*64*ld + d*64 +
+// p%64, with ld = bw+1 rounded up to a multiple of 4 (entries left of column
+// 0, entries d > bw and rows past m are zero; a tile is 64*ld contiguous
+// values, a multiple of 16 bytes).  R is the reversed transpose,
+// R[p][k] = L[m-1-k][m-1-p], in the same layout, so the backward sweep with
+// L^T is a forward sweep with R on reversed vectors.
+constexpr int BAND_MAX = 127;  // largest half-bandwidth (LDS window of the factorization)
+struct BandBlocks {
+  int nblk;
+  const int* row0;
+  const int* m;
+  const int* bw;           // half-bandwidth per block
+  const int* ld;           // stored entries per row (bw+1 rounded up to a multiple of 4)
+  int ldmax;               // largest ld
+  const int* sys;
+  const long long* off;    // element offset of the block's tiles
+  double* L;               // Gram matrix on entry to the factorization, FP64 factor after
+  double* R;               // FP64 reversed transpose (FP64 projections only)
+  float* L32; float* R32;  // FP32 copies (FP32 projections only)
+  double* dinv;            // per permuted row: 1 / L[p][p]
+  float* dinv32;
+  int* info;               // per block: 0 ok, j+1 = first pivot at or below m*eps*G_jj
+  unsigned long long* applies; // per block running count of applications
+  const double* dsc;       // per permuted row 1/||a_r||_2 (see InnerBlocks)
+};
+hipError_t launch_band_gram(hipStream_t st, const BandBlocks& B, const int* rowptr, const int* col,
+                            const double* val, const int* tptr, const int* trow, const double* tval);
+hipError_t launch_band_cholesky(hipStream_t st, const BandBlocks& B);
+hipError_t launch_band_finish(hipStream_t st, const BandBlocks& B, bool mixed);
+hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, const double* u,
+                             double* y, const int* done);

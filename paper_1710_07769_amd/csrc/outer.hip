@@ -278,6 +278,31 @@ __global__ void k_rr_from_partials(OuterState S, int slot) {
   if (threadIdx.x == 0 && !S.done[sys]) S.rr[2 * sys + slot] = rr;
 }
 
+// Residual replacement with factor-based projections, per system: the new
+// r.r (partials in part_b) replaces slot `slot`; when it exceeds 4x the
+// recursive value it replaces (the recursion had drifted away from the true
+// residual) the system restarts CG (flag set for k_restart_where), otherwise
+// the search direction is kept.
+__global__ void k_replace_decide(OuterState S, int slot, int* __restrict__ restart) {
+  const int sys = blockIdx.x;
+  const double rr = sys_sum_wave(S.part_b, S.sys_tile[sys], S.sys_tile[sys + 1]);
+  if (threadIdx.x == 0 && !S.done[sys]) {
+    const double old = S.rr[2 * sys + slot];
+    restart[sys] = !(rr <= 4.0 * old);
+    S.rr[2 * sys + slot] = rr;
+  }
+}
+
+__global__ void __launch_bounds__(VEC_THREADS)
+k_restart_where(double* __restrict__ p, const double* __restrict__ r,
+                const int* __restrict__ restart, OuterState S) {
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (S.done[sys] || !restart[sys]) return;
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) p[i] = r[i];
+}
+
 // Tile partials at the start of a solve: f.f (part_f), max|f| (part_g),
 // max|s| (part_d) and sum|x| (part_e).
 __global__ void __launch_bounds__(VEC_THREADS)
@@ -445,6 +470,13 @@ hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const Oute
 
 hipError_t launch_true_check(hipStream_t st, const OuterState& S) {
   hipLaunchKernelGGL(k_true_check, dim3(S.nsys), dim3(64), 0, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_replace_decide(hipStream_t st, const OuterState& S, int slot, int* restart,
+                                 double* p, const double* r) {
+  hipLaunchKernelGGL(k_replace_decide, dim3(S.nsys), dim3(64), 0, st, S, slot, restart);
+  hipLaunchKernelGGL(k_restart_where, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, p, r, restart, S);
   return hipGetLastError();
 }
 

@@ -104,9 +104,18 @@ def test_rip_partition_bitexact(dev):
 
 PROJ_CASES = {
     # name: (problem maker, K, opts)
-    "cd2d-32-K4-dense": (workloads.config1, 4, {}),
-    "st27-8-K5-dense": (lambda: workloads.small_config5(N=8, K=5), 5, {}),
-    "cd3d-10-K3-dense-ragged": (lambda: workloads.small_config2(N=10, K=3), 3, {}),
+    "cd2d-32-K4-dense": (workloads.config1, 4, {"projection": bc.BC_PROJ_DENSE_CHOL}),
+    "st27-8-K5-dense": (lambda: workloads.small_config5(N=8, K=5), 5,
+                        {"projection": bc.BC_PROJ_DENSE_CHOL}),
+    "cd3d-10-K3-dense-ragged": (lambda: workloads.small_config2(N=10, K=3), 3,
+                                {"projection": bc.BC_PROJ_DENSE_CHOL}),
+    "cd2d-32-K4-band": (workloads.config1, 4, {"projection": bc.BC_PROJ_BAND_CHOL}),
+    "cd2d-45-K7-band-ragged": (lambda: workloads.small_config4(nsys=1, smin=45, smax=45)[0], 7,
+                               {"projection": bc.BC_PROJ_BAND_CHOL}),
+    "cd3d-8-K3-band": (lambda: workloads.small_config2(N=8, K=3), 3,
+                       {"projection": bc.BC_PROJ_BAND_CHOL}),
+    "st27-6-K4-band": (lambda: workloads.small_config5(N=6, K=4), 4,
+                       {"projection": bc.BC_PROJ_BAND_CHOL}),
     "cd3d-12-K4-inner": (lambda: workloads.small_config2(N=12, K=4), 4,
                          {"projection": bc.BC_PROJ_INNER_CG, "inner_tol": 1e-13}),
     "powerlaw-3000-K3-inner": (lambda: workloads.small_config3(n=3000, K=3), 3,
@@ -168,13 +177,57 @@ def _check_solve(dev, p, part, K, tol=1e-10, **opts):
 def test_solve_config1(dev):
     banner("bc_solve cd2d-32 K=4 dense FP64")
     p = workloads.config1()
-    _check_solve(dev, p, p.part(), p.K)
+    _check_solve(dev, p, p.part(), p.K, projection=bc.BC_PROJ_DENSE_CHOL)
 
 
 def test_solve_st27_dense(dev):
     banner("bc_solve st27-10 K=6 dense FP64")
     p = workloads.small_config5(N=10, K=6)
-    _check_solve(dev, p, p.part(), p.K)
+    _check_solve(dev, p, p.part(), p.K, projection=bc.BC_PROJ_DENSE_CHOL)
+
+
+@pytest.mark.parametrize("case", ["cd2d-32-K4", "cd2d-70-K8", "st27-8-K8"])
+def test_solve_band(dev, case):
+    banner("bc_solve %s banded Cholesky FP64" % case)
+    if case == "cd2d-32-K4":
+        p = workloads.config1()
+    elif case == "cd2d-70-K8":
+        p = workloads.small_config4(nsys=1, smin=70, smax=70)[0]
+    else:
+        p = workloads.small_config5(N=8, K=8)
+    _check_solve(dev, p, p.part(), p.K, projection=bc.BC_PROJ_BAND_CHOL)
+
+
+def test_auto_picks_band_for_slabs(dev):
+    banner("BC_PROJ_AUTO on cd2d-96 K=8: every block banded, half-bandwidth ~ 2 * 12 lines")
+    p = workloads.small_config4(nsys=1, smin=96, smax=96)[0]
+    solver = bc.BlockCimmino(p.A, p.part(), p.K)
+    try:
+        kind, bw = solver.block_info()
+        assert np.all(kind == bc.KIND_BAND)
+        assert np.all((bw >= 12) & (bw <= 2 * 12 + 4))
+    finally:
+        solver.close()
+
+
+def test_band_rejects_wide_blocks(dev):
+    banner("BC_PROJ_BAND_CHOL on st27-10 K=1: no band within 127, BC_ERR_INVALID")
+    p = workloads.small_config5(N=10, K=1)
+    with pytest.raises(bc.BCError) as ei:
+        bc.BlockCimmino(p.A, np.zeros(p.n, dtype=np.int32), 1, projection=bc.BC_PROJ_BAND_CHOL)
+    assert ei.value.status == bc.BC_ERR_INVALID
+
+
+def test_band_singular_block_detected(dev):
+    banner("duplicate row inside a banded block: singular block")
+    A = workloads.cd2d(6).to_scipy().tolil()
+    A[1] = A[0]
+    A = Csr.from_scipy(A.tocsr())
+    part = np.zeros(A.n, dtype=np.int32)
+    part[18:] = 1
+    with pytest.raises(bc.BCError) as ei:
+        bc.BlockCimmino(A, part, 2, projection=bc.BC_PROJ_BAND_CHOL)
+    assert ei.value.status == bc.BC_ERR_SINGULAR_BLOCK
 
 
 def test_solve_inner_cg_rip_partition(dev):
@@ -314,7 +367,8 @@ def test_mixed_precision_reaches_tolerance(dev):
     banner("mixed precision cd2d-32 K=4 dense FP32 applies, FP64 outer")
     p = workloads.config1()
     ref = block_cimmino_cg(p.A.to_scipy(), p.f, p.part(), p.K, tol=1e-10)
-    solver = bc.BlockCimmino(p.A, p.part(), p.K, precision=bc.BC_MIXED)
+    solver = bc.BlockCimmino(p.A, p.part(), p.K, precision=bc.BC_MIXED,
+                             projection=bc.BC_PROJ_DENSE_CHOL)
     try:
         x, st = solver.solve(to_dev(p.f, dev), tol=1e-10, maxit=2000)
         err = rel(x.cpu().numpy(), ref.x)
@@ -335,6 +389,8 @@ MIXED_CASES = {
                                        "precision": bc.BC_MIXED_PROJ}),
     "cd3d-12-K4-fp32-inner": (lambda: workloads.small_config2(N=12, K=4), 4,
                               {"projection": bc.BC_PROJ_INNER_CG, "precision": bc.BC_MIXED_PROJ}),
+    "cd2d-90-K8-fp32-band": (lambda: workloads.small_config4(nsys=1, smin=90, smax=90)[0], 8,
+                             {"projection": bc.BC_PROJ_BAND_CHOL, "precision": bc.BC_MIXED}),
 }
 
 
@@ -367,6 +423,24 @@ def test_batched_mixed(dev):
         x, sts = solver.solve(f, tol=1e-10, maxit=3000)
         xs = np.split(x.cpu().numpy(), np.cumsum([q.n for q in probs])[:-1])
         for q, st, xg in zip(probs, sts, xs):
+            assert st.status == bc.BC_OK and st.rel_residual <= 1e-10 * (1 + 1e-6)
+            assert rel(xg, q.xstar) <= 1e-6
+    finally:
+        solver.close()
+
+
+def test_batched_band_mixed(dev):
+    banner("bc_solve_batched 5 systems cd2d sides 40..130, K=8, banded FP32 applies, FP64 outer")
+    probs = workloads.small_config4(nsys=5, smin=40, smax=130)
+    solver = bc.BlockCimminoBatched([(q.A, q.part(), q.K) for q in probs],
+                                    precision=bc.BC_MIXED_PROJ, projection=bc.BC_PROJ_BAND_CHOL)
+    try:
+        f = to_dev(np.concatenate([q.f for q in probs]), dev)
+        x, sts = solver.solve(f, tol=1e-10, maxit=5000)
+        xs = np.split(x.cpu().numpy(), np.cumsum([q.n for q in probs])[:-1])
+        for q, st, xg in zip(probs, sts, xs):
+            print("%s: iters=%d rel_res=%.2e err=%.2e" % (q.name, st.iterations, st.rel_residual,
+                                                         rel(xg, q.xstar)))
             assert st.status == bc.BC_OK and st.rel_residual <= 1e-10 * (1 + 1e-6)
             assert rel(xg, q.xstar) <= 1e-6
     finally:
