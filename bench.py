@@ -27,10 +27,14 @@ METRIC = "outer Cimmino iters/s + time-to-1e-10 residual; % HBM roofline; mixed 
 HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per dispatch of the dominant projection kernel, from separate
-# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this same command, scaled by
-# the factors a plain 1 GiB copy gives (FETCH x2.0, WRITE x1.0).  An entry is
-# removed whenever its kernel changes.
+# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this same command (default
+# precision of the workload), scaled by the factors a plain 1 GiB copy gives
+# (FETCH x2.0, WRITE x1.0).  An entry is removed whenever its kernel changes.
 MEASURED_TRAFFIC = {
+    "cfg2": {"kernel": "k_inner_grp<double>", "bytes_per_launch": 1.184e+10,
+             "profile": "profiles/k_inner_grp_f64_cd3d_64cubed_K32.md"},
+    "cfg4": {"kernel": "k_band_apply<float>", "bytes_per_launch": 2.573e+09,
+             "profile": "profiles/k_band_apply_f32_cd2d_batch256_K8.md"},
     "cfg5": {"kernel": "k_dense_apply<float>", "bytes_per_launch": 6.884e9,
              "profile": "profiles/k_dense_apply_f32_st27_100cubed_K512.md"},
 }
@@ -79,9 +83,10 @@ class Workload:
         elif name == "cfg4":
             self.problems, self.partition = W.config4(), "contiguous"
             self.batched = True
-            self.opts = {"precision": bc.BC_MIXED}
+            self.opts = {"precision": bc.BC_MIXED_PROJ}
             self.desc = ("256 x cd2d sides 48..256, K=8 each, batched, projection kind per "
-                         "block by the byte model (banded FP64 Cholesky, FP32 applies), mixed")
+                         "block by the byte model (banded FP64 Cholesky, FP32 applies), "
+                         "FP64 sparse products and outer CG")
         elif name in ("cfg5", "cfg5-rip"):
             p = W.config5()
             self.problems = [p]
@@ -317,7 +322,8 @@ def main():
                      "avg_launch_ms": proj_ms / max(launches, 1),
                      "bytes_per_launch": pbytes / max(launches, 1),
                      "traffic": (MEASURED_TRAFFIC[wl.name]["bytes_per_launch"]
-                                 if wl.name in MEASURED_TRAFFIC else None)},
+                                 if wl.name in MEASURED_TRAFFIC and args.precision is None
+                                 else None)},
     }
     if args.compare:
         line["fp64_comparison"] = fp64_comparison(wl, f, line["time_to_tol_ms"])
