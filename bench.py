@@ -137,6 +137,7 @@ def run_step(wl, f_dev):
         ctx = bc.bc_setup(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, parts[0], opts)
     torch.cuda.synchronize()
     out["setup_ms"] = (time.perf_counter() - t0) * 1e3
+    out["lanes"] = bc.bc_schedule(ctx)
     kind, bw = bc.bc_block_info(ctx)
     out["block_kinds"] = {"dense": int((kind == bc.KIND_DENSE).sum()),
                           "inner_cg": int((kind == bc.KIND_INNER).sum()),
@@ -312,6 +313,7 @@ def main():
         "rel_error_vs_xstar": float(np.linalg.norm(xs - xstar) / np.linalg.norm(xstar)),
         "inner_iterations_per_solve": runs[-1]["inner_iterations"],
         "block_kinds": runs[-1]["block_kinds"],
+        "spmv_lanes_per_row": {"A": runs[-1]["lanes"][0], "AT": runs[-1]["lanes"][1]},
         "roofline": {"bound": "hbm", "kernel": "block projections (%s)" % ", ".join(
                          name for name, key in (("dense triangular sweeps", "dense"),
                                                 ("inner CG", "inner_cg"),

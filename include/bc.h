@@ -87,7 +87,16 @@ typedef struct {
   int32_t stop_rule;      /* BC_STOP_REL2 (default): ||f - A x||_2 <= tol ||f||_2;
                              BC_STOP_BACKWARD_ERR: gamma < tol, eq. (stopping) */
   int32_t check_every;    /* outer iterations between host convergence checks; default 8 */
-  int32_t spmv_lanes;     /* lanes per row in the sparse products; 0 = choose */
+  int32_t spmv_lanes;     /* lanes of a wave sharing one row in the sparse
+                             products (1..64, power of two); 0 (default): each
+                             of A p and A^T y is timed at setup for every lane
+                             count and the fastest is kept (cached per
+                             sparsity pattern within the process) */
+  int32_t use_graph;      /* 1 (default): when every block uses a Cholesky
+                             factor (dense or banded), groups of outer
+                             iterations (gcd of check_every and, with FP32
+                             projections, replace_every) are captured once in
+                             a hipGraph and replayed; 0: plain stream launches */
   void* stream;           /* caller's hipStream_t; NULL = null stream */
 } bc_opts;
 
@@ -154,6 +163,11 @@ bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, doubl
  * number of blocks using the dense Cholesky projection.  Any pointer may be NULL. */
 bc_status bc_info(const bc_ctx* ctx, int64_t* n_total, int32_t* nsys, int32_t* nblocks,
                   int32_t* ndense);
+
+/* The lane counts chosen for the sparse products: lanes_a for A p and the
+ * residuals, lanes_at for A^T y (64/lanes rows per wavefront).  Either
+ * pointer may be NULL. */
+bc_status bc_schedule(const bc_ctx* ctx, int32_t* lanes_a, int32_t* lanes_at);
 
 /* Per block (in block order: systems in order, blocks by part id): the
  * projection kind (0 dense Cholesky, 1 inner CG, 2 banded Cholesky) and the

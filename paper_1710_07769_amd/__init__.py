@@ -45,7 +45,7 @@ class bc_opts(C.Structure):
                 ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("inner_groups", C.c_int32), ("replace_every", C.c_int32),
                 ("stop_rule", C.c_int32), ("check_every", C.c_int32),
-                ("spmv_lanes", C.c_int32), ("stream", C.c_void_p)]
+                ("spmv_lanes", C.c_int32), ("use_graph", C.c_int32), ("stream", C.c_void_p)]
 
 
 class bc_stats(C.Structure):
@@ -87,6 +87,7 @@ _SIGS = {
     "bc_solve_batched": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
     "bc_info": (C.c_int, [_P, _I64P, _I32P, _I32P, _I32P]),
     "bc_block_info": (C.c_int, [_P, _I32P, _I32P]),
+    "bc_schedule": (C.c_int, [_P, _I32P, _I32P]),
     "bc_destroy": (None, [_P]),
     "rip_opts_default": (None, [C.POINTER(rip_opts)]),
     "rip_graph": (C.c_int, [C.c_int32, _I32P, _I32P, _DP, C.POINTER(rip_opts),
@@ -225,6 +226,13 @@ def bc_block_info(ctx):
     _check(_lib.bc_block_info(ctx, kind.ctypes.data_as(_I32P), bw.ctypes.data_as(_I32P)),
            "bc_block_info")
     return kind, bw
+
+
+def bc_schedule(ctx):
+    """Lanes per row chosen for A p and for A^T y."""
+    a, t = C.c_int32(), C.c_int32()
+    _check(_lib.bc_schedule(ctx, C.byref(a), C.byref(t)), "bc_schedule")
+    return a.value, t.value
 
 
 def bc_destroy(ctx):

@@ -9,7 +9,10 @@
 #include <cstdlib>
 #include <cstring>
 #include <numeric>
+#include <cstdio>
 #include <string>
+#include <mutex>
+#include <unordered_map>
 #include <vector>
 
 #include "common.h"
@@ -46,6 +49,7 @@ extern "C" void bc_opts_default(bc_opts* o) {
   o->stop_rule = BC_STOP_REL2;
   o->check_every = 8;
   o->spmv_lanes = 0;
+  o->use_graph = 1;
   o->stream = nullptr;
 }
 
@@ -235,7 +239,8 @@ struct bc_ctx {
   int nsys = 0;
   int n_total = 0;
   long long nnz_total = 0;
-  int lanes = 4;
+  int lanes = 4;      // lanes per row of A in the sparse products (u = A p, residuals)
+  int lanesT = 4;     // lanes per row of A^T (psi = A^T y)
   std::vector<int> sys_off;        // nsys + 1
   std::vector<double> normA_inf;   // per system
   // permuted A and A^T
@@ -282,7 +287,18 @@ struct bc_ctx {
   std::vector<int> blk_m;
   std::vector<long long> in_nnz, in_m_h, dn_m_h;  // per inner / dense block sizes
 
+  // captured group of outer iterations (factor-based projections only)
+  hipGraphExec_t gexec = nullptr;
+  unsigned long long* d_stamps = nullptr;  // wall-clock stamps around the sweeps of a replay
+  double wall_khz = 0.0;                    // rate of the device wall clock
+  OuterState gS{};                 // state the graph was captured with
+  double* gx = nullptr;            // solution vector the graph was captured with
+  int gG = 0;                      // iterations per replay
+  bool graph_off = false;          // capture failed once: plain launches from then on
+  int graph_pending = 0;           // event pairs of the last replay not yet harvested
+
   ~bc_ctx() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
     for (hipEvent_t e : ev_proj) (void)hipEventDestroy(e);
     if (ev_sync) (void)hipEventDestroy(ev_sync);
     if (stream) (void)hipStreamDestroy(stream);
@@ -330,6 +346,95 @@ bc_status leave(bc_ctx* c, void* user_stream) {
   BC_HIP(hipEventRecord(c->ev_sync, c->stream));
   BC_HIP(hipStreamWaitEvent((hipStream_t)user_stream, c->ev_sync, 0));
   BC_HIP(hipStreamSynchronize(c->stream));
+  return BC_OK;
+}
+
+// ---- rows-per-wavefront autotuner for the two sparse products.  Each
+// candidate lane count L (lanes of a wave sharing one row, so 64/L rows per
+// wavefront) is timed with HIP events on the library stream on the actual
+// permuted matrix; the fastest L is kept for A and for A^T separately.  The
+// choice is cached per sparsity pattern so that a matrix set up twice in a
+// process gets the same schedule (and the same rounding).
+struct LaneChoice {
+  int a, t;
+};
+std::mutex g_tune_mu;
+std::unordered_map<unsigned long long, LaneChoice> g_tune;
+
+unsigned long long pattern_key(const std::vector<int>& rowptr, const std::vector<int>& col, int n,
+                               bool fp32) {
+  unsigned long long h = 1469598103934665603ULL;
+  auto mix = [&](unsigned long long v) {
+    h ^= v;
+    h *= 1099511628211ULL;
+  };
+  mix((unsigned long long)n);
+  mix((unsigned long long)col.size());
+  mix(fp32 ? 1 : 0);
+  for (size_t i = 0; i < rowptr.size(); i += 7) mix((unsigned long long)rowptr[i]);
+  for (size_t i = 0; i < col.size(); i += 61) mix((unsigned long long)col[i]);
+  return h;
+}
+
+bc_status autotune_lanes(bc_ctx* c, unsigned long long key) {
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      c->lanes = it->second.a;
+      c->lanesT = it->second.t;
+      return BC_OK;
+    }
+  }
+  hipStream_t st = c->stream;
+  const int n = c->n_total;
+  BC_HIP(hipMemsetAsync(c->d_p, 0, (size_t)n * sizeof(double), st));
+  BC_HIP(hipMemsetAsync(c->d_y, 0, (size_t)n * sizeof(double), st));
+  OuterState S = c->outer(0, 0);
+  S.done = c->d_zero_flags;
+  hipEvent_t e0, e1;
+  BC_HIP(hipEventCreate(&e0));
+  BC_HIP(hipEventCreate(&e1));
+  float best_a = 1e30f, best_t = 1e30f;
+  int la = c->lanes, lt = c->lanesT;
+  bc_status rc = BC_OK;
+  for (int L = 1; L <= 64 && rc == BC_OK; L *= 2) {
+    for (int which = 0; which < 2 && rc == BC_OK; ++which) {
+      float ms = 0.f;
+      for (int rep = 0; rep < 4; ++rep) {
+        if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = BC_ERR_DEVICE;
+        hipError_t e = which == 0
+                           ? launch_spmv(L, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32,
+                                         c->d_p, c->d_u, S, false)
+                           : launch_spmvT_dot(L, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
+                                              c->spmv32, c->d_y, c->d_psi, c->d_p, S);
+        if (e != hipSuccess) rc = BC_ERR_DEVICE;
+      }
+      if (rc != BC_OK || hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = BC_ERR_DEVICE;
+        break;
+      }
+      if (which == 0 && ms < best_a) {
+        best_a = ms;
+        la = L;
+      }
+      if (which == 1 && ms < best_t) {
+        best_t = ms;
+        lt = L;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != BC_OK) {
+    bc_set_error("sparse-product autotuning failed");
+    return rc;
+  }
+  c->lanes = la;
+  c->lanesT = lt;
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune[key] = LaneChoice{la, lt};
   return BC_OK;
 }
 
@@ -581,7 +686,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   }
   c->ntiles = (int)tile_start.size();
   tile_start.push_back(n);
-  c->lanes = o.spmv_lanes > 0 ? o.spmv_lanes : choose_lanes(nnz, n);
+  c->lanes = c->lanesT = o.spmv_lanes > 0 ? o.spmv_lanes : choose_lanes(nnz, n);
   std::vector<int> is_dense(c->nblk, 0);
   for (int b = 0; b < c->nblk; ++b) is_dense[b] = kind[b] == KIND_DENSE;
   // ---- inner-CG block data
@@ -1003,8 +1108,10 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
           return BC_ERR_SINGULAR_BLOCK;
         }
       BC_HIP(launch_band_finish(st, Bd, c->mixed));
+      BC_HIP(prepare_band_apply(Bd, c->mixed));
     }
   }
+  if (o.spmv_lanes == 0) BC_TRY(autotune_lanes(c, pattern_key(rowptr, col, n, c->spmv32)));
   BC_HIP(hipStreamSynchronize(st));
   return BC_OK;
 }
@@ -1051,7 +1158,8 @@ extern "C" bc_status bc_setup_batched(bc_ctx** ctx, int32_t nsys, const int32_t*
   }
   if (opts && (opts->projection < BC_PROJ_AUTO || opts->projection > BC_PROJ_BAND_CHOL ||
                opts->inner_tol < 0.0 || opts->inner_maxit < 1 || opts->dense_max_m < 0 ||
-               opts->stop_rule < 0 || opts->stop_rule > 1 || opts->spmv_lanes < 0 ||
+               opts->stop_rule < 0 || opts->stop_rule > 1 || opts->spmv_lanes < 0 || opts->use_graph < 0 ||
+               opts->use_graph > 1 ||
                (opts->spmv_lanes & (opts->spmv_lanes - 1)) || opts->spmv_lanes > 64)) {
     bc_set_error("invalid option value");
     return BC_ERR_INVALID;
@@ -1125,6 +1233,16 @@ extern "C" bc_status bc_info(const bc_ctx* c, int64_t* n_total, int32_t* nsys, i
   return BC_OK;
 }
 
+extern "C" bc_status bc_schedule(const bc_ctx* c, int32_t* lanes_a, int32_t* lanes_at) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  if (lanes_a) *lanes_a = c->lanes;
+  if (lanes_at) *lanes_at = c->lanesT;
+  return BC_OK;
+}
+
 extern "C" bc_status bc_block_info(const bc_ctx* c, int32_t* kind, int32_t* bandwidth) {
   if (!c) {
     bc_set_error("ctx is null");
@@ -1172,6 +1290,8 @@ void harvest_proj_events(bc_ctx* c) {
     if (hipEventElapsedTime(&ms, c->ev_proj[2 * q], c->ev_proj[2 * q + 1]) == hipSuccess) {
       c->t_proj_ms += ms;
       ++c->proj_launches;
+    } else {
+      (void)hipGetLastError();  // leave no sticky error for the next launch check
     }
   }
   c->ev_used = 0;
@@ -1233,7 +1353,7 @@ extern "C" bc_status bc_project(bc_ctx* c, const double* v, double* Hv) {
   BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, v,
                      c->d_u, S, false));
   BC_TRY(block_solves(c, c->d_u, c->d_y, nullptr));
-  BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
+  BC_HIP(launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
                           c->d_y, Hv, v, S));
   BC_TRY(leave(c, c->opts.stream));
   int* err = inner_err_flag();
@@ -1249,6 +1369,109 @@ extern "C" bc_status bc_project(bc_ctx* c, const double* v, double* Hv) {
 // ------------------------------------------------------------------- solve
 
 namespace {
+
+// One outer iteration of Algorithm 2 on every system not yet done: u = A p,
+// y_i = (A_i A_i^T)^{-1} u_i, psi = A^T y with p.psi, then alpha, x, r, s,
+// beta, p and the per-system bookkeeping.
+bc_status outer_iteration(bc_ctx* c, double* x, const OuterState& S, bool timed) {
+  hipStream_t st = c->stream;
+  BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, c->d_p,
+                     c->d_u, S, true));
+  const bool keep = c->timing;
+  c->timing = timed && keep;
+  const bc_status rs = block_solves(c, c->d_u, c->d_y, c->d_done);
+  c->timing = keep;
+  BC_TRY(rs);
+  BC_HIP(launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
+                          c->d_y, c->d_psi, c->d_p, S));
+  BC_HIP(launch_update_xrs(st, x, c->d_r, c->d_s, c->d_p, c->d_psi, c->d_u, S));
+  BC_HIP(launch_update_p(st, c->d_p, c->d_r, S));
+  return BC_OK;
+}
+
+// Runs G outer iterations as one replay of a captured hipGraph.  The graph
+// is captured on first use and again whenever the solve state or x changes
+// (every kernel argument is fixed; each system's iteration number lives on
+// the device).  Projection times come from event pairs captured around each
+// factor sweep and are harvested once the stream has been synchronised.
+// *ran is false when capture is not available (then the caller launches the
+// iterations itself, and this context stops trying).
+bc_status group_graph(bc_ctx* c, double* x, const OuterState& S, int G, bool* ran) {
+  *ran = false;
+  hipStream_t st = c->stream;
+  // everything else in S is fixed for the context
+  const bool same_state = c->gS.maxit == S.maxit && c->gS.use_backward == S.use_backward &&
+                          c->gS.tol_bw == S.tol_bw && c->gS.rec_stop == S.rec_stop &&
+                          c->gS.done == S.done;
+  if (!c->gexec || c->gx != x || c->gG != G || !same_state) {
+    if (c->gexec) {
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+    if (!c->d_stamps) {
+      BC_TRY(c->arena.alloc(&c->d_stamps, 2 * 64));
+      int dev = 0, khz = 0;
+      BC_HIP(hipGetDevice(&dev));
+      BC_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+      c->wall_khz = khz;
+    }
+    if (G > 64) {
+      c->graph_off = true;
+      return BC_OK;
+    }
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipGetLastError();
+      c->graph_off = true;
+      return BC_OK;
+    }
+    bool ok = true;
+    for (int q = 0; q < G && ok; ++q) {
+      ok = launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, c->d_p,
+                       c->d_u, S, true) == hipSuccess &&
+           launch_stamp(st, c->d_stamps, 2 * q) == hipSuccess &&
+           launch_dense_apply(st, c->dense, c->mixed, c->d_u, c->d_y, c->d_done) == hipSuccess &&
+           launch_band_apply(st, c->band, c->mixed, c->d_u, c->d_y, c->d_done) == hipSuccess &&
+           launch_stamp(st, c->d_stamps, 2 * q + 1) == hipSuccess &&
+           launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
+                            c->spmv32, c->d_y, c->d_psi, c->d_p, S) == hipSuccess &&
+           launch_update_xrs(st, x, c->d_r, c->d_s, c->d_p, c->d_psi, c->d_u, S) == hipSuccess &&
+           launch_update_p(st, c->d_p, c->d_r, S) == hipSuccess;
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(st, &g);
+    hipGraphExec_t ex = nullptr;
+    if (ok && ec == hipSuccess && g && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess) {
+      c->gexec = ex;
+    } else {
+      (void)hipGetLastError();
+      c->graph_off = true;
+    }
+    if (g) (void)hipGraphDestroy(g);
+    if (!c->gexec) return BC_OK;
+    c->gS = S;
+    c->gx = x;
+    c->gG = G;
+  }
+  BC_HIP(hipGraphLaunch(c->gexec, st));
+  *ran = true;
+  c->graph_pending = G;
+  return BC_OK;
+}
+
+// Adds the projection times of the last graph replay (stream synchronised):
+// wall-clock stamps written by the device right before and after each sweep.
+bc_status harvest_graph_events(bc_ctx* c) {
+  if (c->graph_pending == 0) return BC_OK;
+  std::vector<unsigned long long> t(2 * c->graph_pending);
+  BC_HIP(hipMemcpy(t.data(), c->d_stamps, t.size() * sizeof(t[0]), hipMemcpyDeviceToHost));
+  if (c->wall_khz > 0.0)
+    for (int q = 0; q < c->graph_pending; ++q) {
+      c->t_proj_ms += (double)(t[2 * q + 1] - t[2 * q]) / c->wall_khz;
+      ++c->proj_launches;
+    }
+  c->graph_pending = 0;
+  return BC_OK;
+}
 
 bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, int maxit,
                      double* x, bc_stats* stats) {
@@ -1281,11 +1504,15 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   c->timing = true;
   // r = sum_i A_i^+ (f_i - A_i x0) = A^T D^{-1} s ; p = r
   BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
-  BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
+  BC_HIP(launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
                           c->d_y, c->d_r, c->d_p, S));
-  BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S, 0));
+  BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S));
 
-  const int R = o.check_every;
+  // Outer iterations run in groups of G between host checks; with FP32
+  // projections G divides replace_every, so replacements fall between groups.
+  int G = std::max(1, o.check_every);
+  if (c->mixed && o.replace_every > 0) G = std::gcd(G, o.replace_every);
+  const bool graphs = o.use_graph && c->inner.nblk == 0 && !c->graph_off;
   std::vector<int> done(ns, 0), status(ns, 0), iters(ns, 0);
   std::vector<int> verified(ns, 0), replacements(ns, 0);
   int it = 0;
@@ -1293,45 +1520,48 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   BC_HIP(hipStreamSynchronize(st));
   bool all_done = std::all_of(done.begin(), done.end(), [](int d) { return d != 0; });
   while (!all_done && it < maxit) {
-    for (int q = 0; q < R && it < maxit; ++q) {
-      ++it;
-      BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32,
-                         c->d_p, c->d_u, S, true));
-      BC_TRY(block_solves(c, c->d_u, c->d_y, c->d_done));
-      BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
-                              c->spmv32, c->d_y, c->d_psi, c->d_p, S));
-      BC_HIP(launch_update_xrs(st, x, c->d_r, c->d_s, c->d_p, c->d_psi, c->d_u, S, it));
-      BC_HIP(launch_update_p(st, c->d_p, c->d_r, S, it));
-      if (c->mixed && o.replace_every > 0 && it % o.replace_every == 0) {
-        // FP64 true residual s = f - A x (and, with FP32 sparse products, the
-        // stop test on it), then r = A^T D^{-1} s through the working-precision
-        // projections.  With factor-based projections the FP32 operator is the
-        // same at every application: r and r.r are replaced and the search
-        // direction is kept (a reliable update), unless the new residual is
-        // more than twice the recursive one (the recursion had drifted: near
-        // the attainable accuracy of the FP32 operator), where CG restarts.
-        // With inner-CG projections the operator changes from one application
-        // to the next, and CG always restarts with p = r: each cycle is then a
-        // defect correction of x by replace_every CG steps.
-        BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s,
-                               S, nullptr));
-        if (c->spmv32) BC_HIP(launch_true_check(st, S));
-        BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
-        BC_HIP(launch_spmvT_dot(c->lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
-                                c->spmv32, c->d_y, c->d_r, c->d_p, S));
-        if (c->inner.nblk > 0) {
-          BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S, it & 1));
-        } else {
-          BC_HIP(launch_sqnorm_tiles(st, c->d_r, c->d_part_b, S));
-          BC_HIP(launch_replace_decide(st, S, it & 1, c->d_restart, c->d_p, c->d_r));
-        }
-        for (int s2 = 0; s2 < ns; ++s2) replacements[s2]++;
+    const int steps = std::min(G, maxit - it);
+    bool replayed = false;
+    if (graphs && steps == G && !c->graph_off) {
+      BC_TRY(group_graph(c, x, S, G, &replayed));
+      if (replayed) it += G;
+    }
+    if (!replayed) {
+      for (int q = 0; q < steps; ++q) {
+        ++it;
+        BC_TRY(outer_iteration(c, x, S, true));
       }
+    }
+    if (c->mixed && o.replace_every > 0 && it % o.replace_every == 0) {
+      // FP64 true residual s = f - A x (and, with FP32 sparse products, the
+      // stop test on it), then r = A^T D^{-1} s through the working-precision
+      // projections.  With factor-based projections the FP32 operator is the
+      // same at every application: r and r.r are replaced and the search
+      // direction is kept (a reliable update), unless the new residual is
+      // more than twice the recursive one (the recursion had drifted: near
+      // the attainable accuracy of the FP32 operator), where CG restarts.
+      // With inner-CG projections the operator changes from one application
+      // to the next, and CG always restarts with p = r: each cycle is then a
+      // defect correction of x by replace_every CG steps.
+      BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s,
+                             S, nullptr));
+      if (c->spmv32) BC_HIP(launch_true_check(st, S));
+      BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
+      BC_HIP(launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
+                              c->spmv32, c->d_y, c->d_r, c->d_p, S));
+      if (c->inner.nblk > 0) {
+        BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S));
+      } else {
+        BC_HIP(launch_sqnorm_tiles(st, c->d_r, c->d_part_b, S));
+        BC_HIP(launch_replace_decide(st, S, c->d_restart, c->d_p, c->d_r));
+      }
+      for (int s2 = 0; s2 < ns; ++s2) replacements[s2]++;
     }
     BC_HIP(hipMemcpyAsync(done.data(), c->d_done, ns * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipMemcpyAsync(status.data(), c->d_status, ns * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
     harvest_proj_events(c);
+    BC_TRY(harvest_graph_events(c));
     if (verbose) {
       std::vector<double> hs(ns), th(ns);
       BC_HIP(hipMemcpy(hs.data(), c->d_hist, ns * sizeof(double), hipMemcpyDeviceToHost));

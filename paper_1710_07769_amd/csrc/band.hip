@@ -386,13 +386,6 @@ hipError_t launch_apply_t(hipStream_t st, const BandBlocks& B, const double* u, 
   // smallest register bucket that holds a whole tile (FP64 bands wider than
   // 64 entries load their tail after the tile is computed)
   const int nvp = nvmax <= 4 ? 4 : nvmax <= 8 ? 8 : nvmax <= 16 ? 16 : nvmax <= 24 ? 24 : 32;
-  const void* fn = nvp == 4    ? (const void*)k_band_apply<T, 4>
-                   : nvp == 8  ? (const void*)k_band_apply<T, 8>
-                   : nvp == 16 ? (const void*)k_band_apply<T, 16>
-                   : nvp == 24 ? (const void*)k_band_apply<T, 24>
-                               : (const void*)k_band_apply<T, 32>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
   if (nvp == 4)
     hipLaunchKernelGGL((k_band_apply<T, 4>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
   else if (nvp == 8)
@@ -431,6 +424,27 @@ hipError_t launch_band_finish(hipStream_t st, const BandBlocks& B, bool mixed) {
   hipLaunchKernelGGL(k_band_finish, dim3(32, B.nblk), dim3(256), 0, st, B, (int)mixed);
   if (!mixed) hipLaunchKernelGGL(k_band_zero_diag, dim3(4, B.nblk), dim3(256), 0, st, B);
   return hipGetLastError();
+}
+
+// Raises the dynamic LDS limit of every sweep instantiation to what the
+// widest band needs (set once at setup, so that a launch inside a stream
+// capture is a plain kernel launch).
+template <typename T>
+hipError_t prepare_apply_t(const BandBlocks& B) {
+  const int lds = (int)((64 * B.ldmax + 256) * sizeof(T) + 64 * (2 * sizeof(double) + sizeof(T)));
+  const void* fns[] = {(const void*)k_band_apply<T, 4>, (const void*)k_band_apply<T, 8>,
+                       (const void*)k_band_apply<T, 16>, (const void*)k_band_apply<T, 24>,
+                       (const void*)k_band_apply<T, 32>};
+  for (const void* fn : fns) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t prepare_band_apply(const BandBlocks& B, bool mixed) {
+  if (B.nblk == 0) return hipSuccess;
+  return mixed ? prepare_apply_t<float>(B) : prepare_apply_t<double>(B);
 }
 
 hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, const double* u,

@@ -139,14 +139,13 @@ hipError_t launch_residual(int lanes, hipStream_t st, const int* rowptr, const i
                            const double* val, const double* x, const double* fperm, double* s,
                            const OuterState& S, const int* mask);
 hipError_t launch_update_xrs(hipStream_t st, double* x, double* r, double* s, const double* p,
-                             const double* psi, const double* u, const OuterState& S, int it);
-hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const OuterState& S,
-                           int it);
-hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S,
-                          int slot);
-hipError_t launch_rr_from_partials(hipStream_t st, const OuterState& S, int slot);
-hipError_t launch_replace_decide(hipStream_t st, const OuterState& S, int slot, int* restart,
-                                 double* p, const double* r);
+                             const double* psi, const double* u, const OuterState& S);
+hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const OuterState& S);
+hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S);
+hipError_t launch_rr_from_partials(hipStream_t st, const OuterState& S);
+hipError_t launch_stamp(hipStream_t st, unsigned long long* t, int i);
+hipError_t launch_replace_decide(hipStream_t st, const OuterState& S, int* restart, double* p,
+                                 const double* r);
 hipError_t launch_true_check(hipStream_t st, const OuterState& S);
 hipError_t launch_init_norms(hipStream_t st, const double* f, const double* s, const double* x,
                              double* part_f, const OuterState& S);
@@ -265,3 +264,4 @@ hipError_t launch_band_cholesky(hipStream_t st, const BandBlocks& B);
 hipError_t launch_band_finish(hipStream_t st, const BandBlocks& B, bool mixed);
 hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, const double* u,
                              double* y, const int* done);
+hipError_t prepare_band_apply(const BandBlocks& B, bool mixed);

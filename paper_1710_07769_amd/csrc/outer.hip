@@ -135,13 +135,14 @@ k_residual(const int* __restrict__ rowptr, const int* __restrict__ col,
 __global__ void __launch_bounds__(VEC_THREADS)
 k_update_xrs(double* __restrict__ x, double* __restrict__ r, double* __restrict__ s,
              const double* __restrict__ p, const double* __restrict__ psi,
-             const double* __restrict__ u, OuterState S, int it) {
+             const double* __restrict__ u, OuterState S) {
   __shared__ double sh[VEC_THREADS / 64];
   __shared__ double alpha_sh;
   __shared__ int bad_sh;
   const int t = tile_of_block();
   const int sys = S.tile_sys[t];
   if (S.done[sys]) return;
+  const int it = S.iters[sys] + 1;  // this iteration of the system (k_book advances the count)
   if (threadIdx.x < 64) {
     const double ppsi = sys_sum_wave(S.part_a, S.sys_tile[sys], S.sys_tile[sys + 1]);
     if (threadIdx.x == 0) {
@@ -196,11 +197,12 @@ k_update_xrs(double* __restrict__ x, double* __restrict__ r, double* __restrict_
 // and the stop decision in `pending`; `done` itself is only changed by
 // k_book after this kernel, so every tile of a system sees the same flags.
 __global__ void __launch_bounds__(VEC_THREADS)
-k_update_p(double* __restrict__ p, const double* __restrict__ r, OuterState S, int it) {
+k_update_p(double* __restrict__ p, const double* __restrict__ r, OuterState S) {
   __shared__ double beta_sh;
   const int t = tile_of_block();
   const int sys = S.tile_sys[t];
   if (S.done[sys]) return;
+  const int it = S.iters[sys] + 1;
   if (threadIdx.x < 64) {
     const int a = S.sys_tile[sys], b = S.sys_tile[sys + 1];
     const double rrn = sys_sum_wave(S.part_b, a, b);
@@ -210,7 +212,6 @@ k_update_p(double* __restrict__ p, const double* __restrict__ r, OuterState S, i
       beta_sh = rrn / rro;
       if (t == a) {
         S.rr[2 * sys + (it & 1)] = rrn;
-        S.iters[sys] = it;
         if (S.hist) S.hist[sys] = ss;
         bool conv;
         if (S.use_backward) {
@@ -246,6 +247,7 @@ __global__ void k_true_check(OuterState S) {
 __global__ void k_book(OuterState S) {
   const int sys = blockIdx.x * blockDim.x + threadIdx.x;
   if (sys >= S.nsys || S.done[sys]) return;
+  S.iters[sys] += 1;  // the iteration every kernel of this system just ran
   const int pend = S.pending[sys];
   if (pend) {
     S.status[sys] = pend == 1 ? BC_OK : BC_NOT_CONVERGED;
@@ -271,20 +273,22 @@ k_init_cg(double* __restrict__ p, const double* __restrict__ r, OuterState S) {
   if (threadIdx.x == 0) S.part_b[t] = rr;
 }
 
-// Per system: rr slot `slot` from the partials in part_b.
-__global__ void k_rr_from_partials(OuterState S, int slot) {
+// Per system: r.r from the partials in part_b into the slot the next
+// iteration reads (iteration iters+1 reads slot iters & 1).
+__global__ void k_rr_from_partials(OuterState S) {
   const int sys = blockIdx.x;
   const double rr = sys_sum_wave(S.part_b, S.sys_tile[sys], S.sys_tile[sys + 1]);
-  if (threadIdx.x == 0 && !S.done[sys]) S.rr[2 * sys + slot] = rr;
+  if (threadIdx.x == 0 && !S.done[sys]) S.rr[2 * sys + (S.iters[sys] & 1)] = rr;
 }
 
 // Residual replacement with factor-based projections, per system: the new
-// r.r (partials in part_b) replaces slot `slot`; when it exceeds 4x the
-// recursive value it replaces (the recursion had drifted away from the true
-// residual) the system restarts CG (flag set for k_restart_where), otherwise
-// the search direction is kept.
-__global__ void k_replace_decide(OuterState S, int slot, int* __restrict__ restart) {
+// r.r (partials in part_b) replaces the slot the next iteration reads; when it
+// exceeds 4x the recursive value it replaces (the recursion had drifted away
+// from the true residual) the system restarts CG (flag set for
+// k_restart_where), otherwise the search direction is kept.
+__global__ void k_replace_decide(OuterState S, int* __restrict__ restart) {
   const int sys = blockIdx.x;
+  const int slot = S.iters[sys] & 1;
   const double rr = sys_sum_wave(S.part_b, S.sys_tile[sys], S.sys_tile[sys + 1]);
   if (threadIdx.x == 0 && !S.done[sys]) {
     const double old = S.rr[2 * sys + slot];
@@ -445,26 +449,24 @@ hipError_t launch_residual(int lanes, hipStream_t st, const int* rowptr, const i
 }
 
 hipError_t launch_update_xrs(hipStream_t st, double* x, double* r, double* s, const double* p,
-                             const double* psi, const double* u, const OuterState& S, int it) {
+                             const double* psi, const double* u, const OuterState& S) {
   if (S.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_update_xrs, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, x, r, s, p, psi, u,
-                     S, it);
+                     S);
   return hipGetLastError();
 }
 
-hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const OuterState& S,
-                           int it) {
+hipError_t launch_update_p(hipStream_t st, double* p, const double* r, const OuterState& S) {
   if (S.ntiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_update_p, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, p, r, S, it);
+  hipLaunchKernelGGL(k_update_p, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, p, r, S);
   hipLaunchKernelGGL(k_book, dim3((S.nsys + 63) / 64), dim3(64), 0, st, S);
   return hipGetLastError();
 }
 
-hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S,
-                          int slot) {
+hipError_t launch_init_cg(hipStream_t st, double* p, const double* r, const OuterState& S) {
   if (S.ntiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_init_cg, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, p, r, S);
-  hipLaunchKernelGGL(k_rr_from_partials, dim3(S.nsys), dim3(64), 0, st, S, slot);
+  hipLaunchKernelGGL(k_rr_from_partials, dim3(S.nsys), dim3(64), 0, st, S);
   return hipGetLastError();
 }
 
@@ -473,15 +475,25 @@ hipError_t launch_true_check(hipStream_t st, const OuterState& S) {
   return hipGetLastError();
 }
 
-hipError_t launch_replace_decide(hipStream_t st, const OuterState& S, int slot, int* restart,
-                                 double* p, const double* r) {
-  hipLaunchKernelGGL(k_replace_decide, dim3(S.nsys), dim3(64), 0, st, S, slot, restart);
+// Device wall-clock stamp (constant-rate counter) for timing inside graphs.
+__global__ void k_stamp(unsigned long long* __restrict__ t, int i) {
+  if (threadIdx.x == 0) t[i] = wall_clock64();
+}
+
+hipError_t launch_stamp(hipStream_t st, unsigned long long* t, int i) {
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, st, t, i);
+  return hipGetLastError();
+}
+
+hipError_t launch_replace_decide(hipStream_t st, const OuterState& S, int* restart, double* p,
+                                 const double* r) {
+  hipLaunchKernelGGL(k_replace_decide, dim3(S.nsys), dim3(64), 0, st, S, restart);
   hipLaunchKernelGGL(k_restart_where, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, p, r, restart, S);
   return hipGetLastError();
 }
 
-hipError_t launch_rr_from_partials(hipStream_t st, const OuterState& S, int slot) {
-  hipLaunchKernelGGL(k_rr_from_partials, dim3(S.nsys), dim3(64), 0, st, S, slot);
+hipError_t launch_rr_from_partials(hipStream_t st, const OuterState& S) {
+  hipLaunchKernelGGL(k_rr_from_partials, dim3(S.nsys), dim3(64), 0, st, S);
   return hipGetLastError();
 }
 

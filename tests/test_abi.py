@@ -35,7 +35,7 @@ def test_defaults_and_status_strings():
     o = bc.make_opts()
     assert o.precision == bc.BC_FP64 and o.projection == bc.BC_PROJ_AUTO
     assert o.dense_max_m == 4096 and o.inner_tol == 1e-12 and o.replace_every == 20
-    assert o.stop_rule == bc.BC_STOP_REL2
+    assert o.stop_rule == bc.BC_STOP_REL2 and o.use_graph == 1 and o.spmv_lanes == 0
     for s in (0, 1, -1, -2, -3, -4, -5):
         assert bc.status_str(s) not in ("", "unknown status")
 

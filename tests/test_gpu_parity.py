@@ -445,3 +445,73 @@ def test_batched_band_mixed(dev):
             assert rel(xg, q.xstar) <= 1e-6
     finally:
         solver.close()
+
+
+# ------------------------------------------------- graphs and autotuning
+
+@pytest.mark.parametrize("case", ["band-fp64", "dense-fp32"])
+def test_graph_replays_match_stream_launches(dev, case):
+    banner("captured iteration groups vs plain launches (%s), three solves each" % case)
+    p = workloads.small_config4(nsys=1, smin=60, smax=60)[0]
+    if case == "band-fp64":
+        opts = {"projection": bc.BC_PROJ_BAND_CHOL}
+    else:
+        opts = {"projection": bc.BC_PROJ_DENSE_CHOL, "precision": bc.BC_MIXED_PROJ}
+    eager = bc.BlockCimmino(p.A, p.part(), p.K, use_graph=0, **opts)
+    graph = bc.BlockCimmino(p.A, p.part(), p.K, use_graph=1, **opts)
+    try:
+        rng = np.random.default_rng(11)
+        for k in range(3):
+            f = to_dev(p.f if k == 0 else rng.standard_normal(p.n), dev)
+            x1, s1 = eager.solve(f, tol=1e-10)
+            x2, s2 = graph.solve(f, tol=1e-10)
+            torch.cuda.synchronize()
+            assert s1.status == bc.BC_OK and s2.status == bc.BC_OK
+            assert s1.iterations == s2.iterations
+            assert torch.equal(x1, x2), "replay %d differs" % k
+    finally:
+        eager.close()
+        graph.close()
+
+
+def test_graph_batched_mixed_matches_stream_launches(dev):
+    banner("captured iteration groups, batched banded FP32 projections, vs plain launches")
+    probs = workloads.small_config4(nsys=4, smin=30, smax=90)
+    mats = [(q.A, q.part(), q.K) for q in probs]
+    opts = {"projection": bc.BC_PROJ_BAND_CHOL, "precision": bc.BC_MIXED_PROJ}
+    eager = bc.BlockCimminoBatched(mats, use_graph=0, **opts)
+    graph = bc.BlockCimminoBatched(mats, use_graph=1, **opts)
+    try:
+        f = to_dev(np.concatenate([q.f for q in probs]), dev)
+        for _ in range(2):
+            x1, s1 = eager.solve(f, tol=1e-10, maxit=5000)
+            x2, s2 = graph.solve(f, tol=1e-10, maxit=5000)
+            assert [s.iterations for s in s1] == [s.iterations for s in s2]
+            assert all(s.status == bc.BC_OK for s in s2)
+            assert torch.equal(x1, x2)
+    finally:
+        eager.close()
+        graph.close()
+
+
+def test_autotuned_lanes_are_reproducible(dev):
+    banner("sparse-product lane autotuning: valid choice, same result when fixed explicitly")
+    p = workloads.small_config2(N=16, K=4)
+    part = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, p.K))
+    tuned = bc.BlockCimmino(p.A, part, p.K, projection=bc.BC_PROJ_DENSE_CHOL)
+    try:
+        la, lt = bc.bc_schedule(tuned.ctx)
+        assert la in (1, 2, 4, 8, 16, 32, 64) and lt in (1, 2, 4, 8, 16, 32, 64)
+        again = bc.BlockCimmino(p.A, part, p.K, projection=bc.BC_PROJ_DENSE_CHOL)
+        assert bc.bc_schedule(again.ctx) == (la, lt)
+        again.close()
+        f = to_dev(p.f, dev)
+        x1, s1 = tuned.solve(f)
+        if la == lt:
+            fixed = bc.BlockCimmino(p.A, part, p.K, projection=bc.BC_PROJ_DENSE_CHOL,
+                                    spmv_lanes=la)
+            x2, s2 = fixed.solve(f)
+            fixed.close()
+            assert s1.iterations == s2.iterations and torch.equal(x1, x2)
+    finally:
+        tuned.close()
