@@ -1109,6 +1109,42 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
         }
       BC_HIP(launch_band_finish(st, Bd, c->mixed));
       BC_HIP(prepare_band_apply(Bd, c->mixed));
+      // Prefetch register-set size of the sweeps, chosen by timing each
+      // candidate on these blocks (the arithmetic does not depend on it).
+      {
+        BC_HIP(hipMemsetAsync(c->d_u, 0, (size_t)n * sizeof(double), st));
+        const std::vector<int> cand = band_apply_candidates(Bd, c->mixed);
+        hipEvent_t e0, e1;
+        BC_HIP(hipEventCreate(&e0));
+        BC_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        int pick = cand.back();
+        bc_status rc = BC_OK;
+        for (int v : cand) {
+          Bd.nvp = v;
+          float ms = 0.f;
+          if (launch_band_apply(st, Bd, c->mixed, c->d_u, c->d_y, nullptr) != hipSuccess ||
+              hipEventRecord(e0, st) != hipSuccess ||
+              launch_band_apply(st, Bd, c->mixed, c->d_u, c->d_y, nullptr) != hipSuccess ||
+              launch_band_apply(st, Bd, c->mixed, c->d_u, c->d_y, nullptr) != hipSuccess ||
+              hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            rc = BC_ERR_DEVICE;
+            break;
+          }
+          if (ms < best) {
+            best = ms;
+            pick = v;
+          }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc != BC_OK) {
+          bc_set_error("banded sweep tuning failed");
+          return rc;
+        }
+        Bd.nvp = pick;
+      }
     }
   }
   if (o.spmv_lanes == 0) BC_TRY(autotune_lanes(c, pattern_key(rowptr, col, n, c->spmv32)));

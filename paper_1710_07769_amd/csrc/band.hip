@@ -16,6 +16,9 @@
 #include "common.h"
 
 #include <cmath>
+#include <vector>
+
+std::vector<int> band_nvp_buckets(const BandBlocks& B, size_t elem);
 
 namespace {
 
@@ -179,20 +182,78 @@ __device__ __forceinline__ double lane_bcast<double>(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// The computation of one tile of a sweep for lane l (row p): the off-tile
+// part against the window, then the in-tile column sweep; returns w_p.
+// The window slots of the tile's rows are zero (they held rows 256 back, no
+// longer referenced) and slots of rows below 0 are zero from the start of the
+// sweep, so in-tile and out-of-matrix columns contribute nothing and the
+// batches of 8 need no mask; only the tail batch is masked.  All LDS reads
+// of a batch are issued before its arithmetic.  In the column sweep, entries
+// outside the band of row p (including j >= l) are read from the zero
+// diagonal slot, so a step is a multiply, a broadcast and an FMA; lane l's
+// value stops changing after step l, and rows past m have a zero pivot
+// reciprocal.
+template <typename T>
+__device__ __forceinline__ T band_tile(const T* buf, const T* yw, T acc, T dp, int p, int l, int bw,
+                                       int ld) {
+  // The entry indices of the column sweep are the same for every tile; an
+  // opaque copy of the lane index keeps the compiler from holding all 64 of
+  // them in registers across the tile loop (recomputing them is cheap).
+  asm volatile("" : "+v"(l));
+  const int kb = p - bw;
+  int d0 = 0;
+  for (; d0 + 8 <= bw; d0 += 8) {
+    T v[8], yk[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      v[i] = buf[(d0 + i) * 64 + l];
+      yk[i] = yw[(kb + d0 + i) & 255];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc -= v[i] * yk[i];
+  }
+  if (d0 < bw) {
+    T v[8], yk[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      v[i] = buf[min(d0 + i, ld - 1) * 64 + l];
+      yk[i] = yw[(kb + d0 + i) & 255];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc -= (d0 + i < bw) ? v[i] * yk[i] : (T)0;
+  }
+#pragma unroll
+  for (int j0 = 0; j0 < 64; j0 += 8) {
+    T e[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int dd = bw - l + j0 + i;  // entry of row p for column i0 + j
+      e[i] = buf[((unsigned)dd <= (unsigned)bw ? dd : bw) * 64 + l];
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const T s = lane_bcast<T>(acc * dp, j0 + i);
+      acc -= e[i] * s;
+    }
+  }
+  return acc * dp;
+}
+
 // One wave per block; lane l owns row p = i0 + l of the current 64-row tile.
 // The tiles of the forward sweep (factor L, right-hand side D u) and then of
 // the backward sweep (factor R, right-hand side the reversed forward result)
-// are processed in one sequence.  While a tile is computed, the next tile's
-// band (64*ld contiguous values) is already in flight as 16-byte loads into
-// registers, and is written into the (single) LDS stage once the tile is done
-// with it, so the wave
-// never waits on HBM inside a tile.  Per tile: the
-// off-tile part acc -= sum_{k < i0} F[p][k] w[k] reads the stage against the
-// solved values kept in a 256-entry circular window (bw <= BAND_MAX < 192,
-// so rows i0-bw..i0-1 are all still there); the in-tile triangle is a column
-// sweep: at step j, w_j = acc_j / F_jj is broadcast from lane j and the lanes
-// below it subtract F[p][i0+j] w_j (read from the stage: lane l's entry sits
-// in its own bank column, no conflicts).
+// are processed in one sequence.  The band of a tile (64*ld contiguous
+// values) and its right-hand side are loaded two tiles ahead into one of two
+// named register sets and written to the (single) LDS stage at the end of the
+// tile before their use, so each load has two tiles of compute to arrive
+// (the first two backward tiles need the forward result and load their
+// right-hand side after the forward sweep instead).  Per tile: the off-tile
+// part acc -= sum_{k < i0} F[p][k] w[k] reads the stage against the solved
+// values kept in a 256-entry circular window (bw <= BAND_MAX < 192, so rows
+// i0-bw..i0-1 are all still there); the in-tile triangle is a column sweep:
+// at step j, w_j = acc_j / F_jj is broadcast from lane j and the lanes below
+// it subtract F[p][i0+j] w_j.
+
 // Ordering point for the one-wave workgroup of k_band_apply: LDS operations
 // of a wave execute in program order, so a compiler barrier with
 // wavefront-scope fences orders the lanes' LDS accesses without the
@@ -203,6 +264,17 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+#define BC_LIST(M, S)                                                                   \
+  M(S, 0) M(S, 1) M(S, 2) M(S, 3) M(S, 4) M(S, 5) M(S, 6) M(S, 7) M(S, 8) M(S, 9)        \
+  M(S, 10) M(S, 11) M(S, 12) M(S, 13) M(S, 14) M(S, 15) M(S, 16) M(S, 17) M(S, 18)       \
+  M(S, 19) M(S, 20) M(S, 21) M(S, 22) M(S, 23) M(S, 24) M(S, 25) M(S, 26) M(S, 27)       \
+  M(S, 28) M(S, 29) M(S, 30) M(S, 31)
+#define BC_DECL(S, q) float4 S##q;
+// vectors q >= npre re-read / re-write vector 0 (in bounds, idempotent), so
+// the loads and stores of a set carry no predicate
+#define BC_LOAD(S, q) if constexpr (NVP > q) S##q = src_[((q) < npre ? (q) : 0) * 64 + l];
+#define BC_STORE(S, q) if constexpr (NVP > q) dst_[((q) < npre ? (q) : 0) * 64 + l] = S##q;
 
 template <typename T, int NVP>
 __global__ void __launch_bounds__(64)
@@ -221,7 +293,7 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
   T* rd = (T*)(rs + 64);                       // staged pivot reciprocal
   constexpr int VT = 16 / (int)sizeof(T);
   const int nv = ld / VT;          // 16-byte vectors per lane per tile
-  const int npre = min(nv, NVP);   // of which prefetched during compute
+  const int npre = min(nv, NVP);   // of which prefetched
   if (l == 0) atomicAdd(&B.applies[blk], 1ull);
   const T* Fl;
   const T* Fr;
@@ -238,18 +310,25 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
   const double* dsc = B.dsc + row0;
   double* yb = y + row0;
   const int total = 2 * nt;
+  // band of tile idx (clamped into the sequence, so any idx is in bounds)
   auto chunk = [&](int idx) -> const float4* {
+    idx = min(idx, total - 1);
     const bool bwd = idx >= nt;
     const int t = bwd ? idx - nt : idx;
     return (const float4*)((bwd ? Fr : Fl) + (long long)t * 64 * ld);
   };
-  // Row of tile idx whose right-hand side, output scale and pivot lane l
-  // loads: clamped into the block so the loads carry no predicate.
+  // row whose right-hand side, output scale and pivot lane l loads for tile
+  // idx, clamped into the block so the loads carry no predicate
   auto rhs_row = [&](int idx) -> int {
+    idx = min(idx, total - 1);
     const int bwd = idx >= nt;
     const int pc = min((bwd ? idx - nt : idx) * 64 + l, m - 1);
     return bwd ? m - 1 - pc : pc;
   };
+  auto rhs_src = [&](int idx, int r) -> const double* {
+    return min(idx, total - 1) >= nt ? yb + r : u + row0 + r;
+  };
+  // prologue: tile 0 staged, tile 1 in set A
   {
     const float4* src = chunk(0);
     float4* dst = (float4*)stage;
@@ -258,138 +337,100 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
     ra[l] = u[row0 + r] * dsc[r];
     rd[l] = dv[r];
   }
-  wave_sync();
-  for (int idx = 0; idx < total; ++idx) {
-    const bool bwd = idx >= nt;
-    const int t = bwd ? idx - nt : idx;
-    const int i0 = t * 64, p = i0 + l;
-    if (idx == nt) {
-      // the backward sweep starts from the forward result written by all lanes
-      __threadfence_block();
-      __syncthreads();
-      const int r = rhs_row(idx);
-      ra[l] = yb[r];
-      rs[l] = dsc[r];
-      rd[l] = dv[r];
-      wave_sync();
-    }
-    if (t == 0) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) yw[q * 64 + l] = (T)0;
-    }
-    yw[p & 255] = (T)0;
-    T acc = p < m ? (T)ra[l] : (T)0;
-    const T dp = p < m ? rd[l] : (T)0;
-    const double sc = rs[l];
-    wave_sync();
-    // prefetch of the next tile: right-hand side (except across the switch of
-    // sweeps, which needs this sweep's result) and band.  Vectors q >= npre
-    // re-read vector 0 (in bounds), so the loads carry no predicate; the
-    // prefetch lives in named registers (an array here ends up in scratch).
-    const bool has_next = idx + 1 < total;
-    const int nidx = has_next ? idx + 1 : idx;
-    const int nr = rhs_row(nidx);
-    const bool nbwd = nidx >= nt;
-    const double na = nbwd ? yb[nr] : u[row0 + nr];
-    const double ns = dsc[nr];
-    const T nd = dv[nr];
-    const float4* nsrc = chunk(nidx);
-#define BC_PF(q) float4 pf##q; if constexpr (NVP > q) pf##q = nsrc[((q) < npre ? (q) : 0) * 64 + l];
-    BC_PF(0) BC_PF(1) BC_PF(2) BC_PF(3) BC_PF(4) BC_PF(5) BC_PF(6) BC_PF(7)
-    BC_PF(8) BC_PF(9) BC_PF(10) BC_PF(11) BC_PF(12) BC_PF(13) BC_PF(14) BC_PF(15)
-    BC_PF(16) BC_PF(17) BC_PF(18) BC_PF(19) BC_PF(20) BC_PF(21) BC_PF(22) BC_PF(23)
-    BC_PF(24) BC_PF(25) BC_PF(26) BC_PF(27) BC_PF(28) BC_PF(29) BC_PF(30) BC_PF(31)
-#undef BC_PF
-    const T* buf = stage;
-    // Off-tile part acc -= sum_d F[p][p-bw+d] w[p-bw+d], d < bw.  The window
-    // slots of this tile's rows are zeroed first (they held rows 256 back, no
-    // longer referenced), and slots of rows below 0 are zero from the start
-    // of the sweep, so in-tile and out-of-matrix columns contribute nothing
-    // and the batches of 16 need no mask; only the tail batch is masked.
-    // All LDS reads of a batch are issued before its arithmetic.
-    {
-      const int kb = p - bw;
-      int d0 = 0;
-      for (; d0 + 16 <= bw; d0 += 16) {
-        T v[16], yk[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          v[i] = buf[(d0 + i) * 64 + l];
-          yk[i] = yw[(kb + d0 + i) & 255];
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc -= v[i] * yk[i];
-      }
-      if (d0 < bw) {
-        T v[16], yk[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          v[i] = buf[min(d0 + i, ld - 1) * 64 + l];
-          yk[i] = yw[(kb + d0 + i) & 255];
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc -= (d0 + i < bw) ? v[i] * yk[i] : (T)0;
-      }
-    }
-    // In-tile column sweep, 64 steps in batches of 16: step j broadcasts
-    // w_j = acc_j / F_jj from lane j and every lane subtracts F[p][i0+j] w_j.
-    // Entries outside the band of row p (including j >= l) are read from the
-    // zero diagonal slot, so a step is a multiply, a broadcast and an FMA;
-    // lane l's value stops changing after step l, and rows past m have a zero
-    // pivot reciprocal.
-#pragma unroll
-    for (int j0 = 0; j0 < 64; j0 += 16) {
-      T e[16];
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const int dd = bw - l + j0 + i;  // entry of row p for column i0 + j
-        e[i] = buf[((unsigned)dd <= (unsigned)bw ? dd : bw) * 64 + l];
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        const T s = lane_bcast<T>(acc * dp, j0 + i);
-        acc -= e[i] * s;
-      }
-    }
-    const T w = acc * dp;
-    wave_sync();  // every lane is done with the stage and the window
-    yw[p & 255] = w;
-    if (has_next) {
-      // stage the next tile (the one wait for HBM per tile)
-      float4* nbuf = (float4*)stage;
-      // vectors q >= npre hold vector 0 again: writing them back to slot 0
-      // is idempotent and keeps the stores unpredicated
-#define BC_ST(q) if constexpr (NVP > q) nbuf[((q) < npre ? (q) : 0) * 64 + l] = pf##q;
-      BC_ST(0) BC_ST(1) BC_ST(2) BC_ST(3) BC_ST(4) BC_ST(5) BC_ST(6) BC_ST(7)
-      BC_ST(8) BC_ST(9) BC_ST(10) BC_ST(11) BC_ST(12) BC_ST(13) BC_ST(14) BC_ST(15)
-      BC_ST(16) BC_ST(17) BC_ST(18) BC_ST(19) BC_ST(20) BC_ST(21) BC_ST(22) BC_ST(23)
-      BC_ST(24) BC_ST(25) BC_ST(26) BC_ST(27) BC_ST(28) BC_ST(29) BC_ST(30) BC_ST(31)
-#undef BC_ST
-      for (int q = npre; q < nv; ++q) nbuf[q * 64 + l] = nsrc[q * 64 + l];
-      ra[l] = nbwd ? na : na * ns;
-      rs[l] = ns;
-      rd[l] = nd;
-    }
-    if (p < m) {
-      if (!bwd) yb[p] = (double)w;
-      else yb[m - 1 - p] = (double)w * sc;
-    }
-    wave_sync();
+  BC_LIST(BC_DECL, pa)
+  BC_LIST(BC_DECL, pb)
+  double xa_a, xa_s, xb_a, xb_s;
+  T xa_d, xb_d;
+  {
+    const int r = rhs_row(1);
+    xa_a = *rhs_src(1, r);
+    xa_s = dsc[r];
+    xa_d = dv[r];
+    const float4* src_ = chunk(1);
+    BC_LIST(BC_LOAD, pa)
   }
+  wave_sync();
+
+  // One tile: CUR holds tile idx+1 (loaded one tile ago), NXT receives tile
+  // idx+2.
+#define BC_TILE(CUR, XC, NXT, XN)                                                         \
+  {                                                                                      \
+    const bool bwd = idx >= nt;                                                          \
+    const int t = bwd ? idx - nt : idx;                                                  \
+    const int i0 = t * 64, p = i0 + l;                                                   \
+    if (idx == nt || idx == nt + 1) {                                                    \
+      /* the first backward tiles start from the forward result of all lanes */         \
+      if (idx == nt) {                                                                   \
+        __threadfence_block();                                                           \
+        __syncthreads();                                                                 \
+      }                                                                                  \
+      const int r = rhs_row(idx);                                                        \
+      ra[l] = yb[r];                                                                     \
+      rs[l] = dsc[r];                                                                    \
+      rd[l] = dv[r];                                                                     \
+    }                                                                                    \
+    if (t == 0) {                                                                        \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) yw[q * 64 + l] = (T)0;              \
+    }                                                                                    \
+    yw[p & 255] = (T)0;                                                                  \
+    wave_sync();                                                                         \
+    T acc = p < m ? (T)ra[l] : (T)0;                                                     \
+    const T dp = p < m ? rd[l] : (T)0;                                                   \
+    const double sc = rs[l];                                                             \
+    /* prefetch tile idx+2: right-hand side first, then band */                         \
+    {                                                                                    \
+      const int r = rhs_row(idx + 2);                                                    \
+      XN##_a = *rhs_src(idx + 2, r);                                                     \
+      XN##_s = dsc[r];                                                                   \
+      XN##_d = dv[r];                                                                    \
+      const float4* src_ = chunk(idx + 2);                                               \
+      BC_LIST(BC_LOAD, NXT)                                                              \
+    }                                                                                    \
+    const T w = band_tile<T>(stage, yw, acc, dp, p, l, bw, ld);                          \
+    wave_sync(); /* every lane is done with the stage and the window */                 \
+    yw[p & 255] = w;                                                                     \
+    if (idx + 1 < total) {                                                               \
+      /* stage tile idx+1 (the one wait for HBM per tile) */                            \
+      float4* dst_ = (float4*)stage;                                                     \
+      BC_LIST(BC_STORE, CUR)                                                             \
+      const float4* nsrc = chunk(idx + 1);                                               \
+      for (int q = npre; q < nv; ++q) dst_[q * 64 + l] = nsrc[q * 64 + l];               \
+      ra[l] = (idx + 1 >= nt) ? XC##_a : XC##_a * XC##_s;                                \
+      rs[l] = XC##_s;                                                                    \
+      rd[l] = XC##_d;                                                                    \
+    }                                                                                    \
+    if (p < m) {                                                                         \
+      if (!bwd) yb[p] = (double)w;                                                       \
+      else yb[m - 1 - p] = (double)w * sc;                                               \
+    }                                                                                    \
+    wave_sync();                                                                         \
+  }
+
+  for (int idx = 0; idx < total; ++idx) {
+    BC_TILE(pa, xa, pb, xb)
+    if (++idx >= total) break;
+    BC_TILE(pb, xb, pa, xa)
+  }
+#undef BC_TILE
 }
+#undef BC_LIST
+#undef BC_DECL
+#undef BC_LOAD
+#undef BC_STORE
 
 template <typename T>
 hipError_t launch_apply_t(hipStream_t st, const BandBlocks& B, const double* u, double* y,
                           const int* done) {
-  const int nvmax = B.ldmax * (int)sizeof(T) / 16;
   const size_t lds = (size_t)(64 * B.ldmax + 256) * sizeof(T) + 64 * (2 * sizeof(double) + sizeof(T));
-  // smallest register bucket that holds a whole tile (FP64 bands wider than
-  // 64 entries load their tail after the tile is computed)
-  const int nvp = nvmax <= 4 ? 4 : nvmax <= 8 ? 8 : nvmax <= 16 ? 16 : nvmax <= 24 ? 24 : 32;
+  const int nvp = B.nvp > 0 ? B.nvp : band_nvp_buckets(B, sizeof(T)).back();
   if (nvp == 4)
     hipLaunchKernelGGL((k_band_apply<T, 4>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
   else if (nvp == 8)
     hipLaunchKernelGGL((k_band_apply<T, 8>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
+  else if (nvp == 12)
+    hipLaunchKernelGGL((k_band_apply<T, 12>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
+  else if (nvp == 20)
+    hipLaunchKernelGGL((k_band_apply<T, 20>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
   else if (nvp == 16)
     hipLaunchKernelGGL((k_band_apply<T, 16>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
   else if (nvp == 24)
@@ -426,14 +467,29 @@ hipError_t launch_band_finish(hipStream_t st, const BandBlocks& B, bool mixed) {
   return hipGetLastError();
 }
 
+// Register-set sizes (16-byte vectors per lane and tile) worth trying for
+// these blocks: every instantiated size up to the first one that holds a
+// whole tile of the widest band.
+std::vector<int> band_nvp_buckets(const BandBlocks& B, size_t elem) {
+  static const int sizes[] = {4, 8, 12, 16, 20, 24, 32};
+  const int nvmax = B.ldmax * (int)elem / 16;
+  std::vector<int> out;
+  for (int v : sizes) {
+    out.push_back(v);
+    if (v >= nvmax) break;
+  }
+  return out;
+}
+
 // Raises the dynamic LDS limit of every sweep instantiation to what the
 // widest band needs (set once at setup, so that a launch inside a stream
 // capture is a plain kernel launch).
 template <typename T>
 hipError_t prepare_apply_t(const BandBlocks& B) {
   const int lds = (int)((64 * B.ldmax + 256) * sizeof(T) + 64 * (2 * sizeof(double) + sizeof(T)));
-  const void* fns[] = {(const void*)k_band_apply<T, 4>, (const void*)k_band_apply<T, 8>,
-                       (const void*)k_band_apply<T, 16>, (const void*)k_band_apply<T, 24>,
+  const void* fns[] = {(const void*)k_band_apply<T, 4>,  (const void*)k_band_apply<T, 8>,
+                       (const void*)k_band_apply<T, 12>, (const void*)k_band_apply<T, 16>,
+                       (const void*)k_band_apply<T, 20>, (const void*)k_band_apply<T, 24>,
                        (const void*)k_band_apply<T, 32>};
   for (const void* fn : fns) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -451,4 +507,8 @@ hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, co
                              double* y, const int* done) {
   if (B.nblk == 0) return hipSuccess;
   return mixed ? launch_apply_t<float>(st, B, u, y, done) : launch_apply_t<double>(st, B, u, y, done);
+}
+
+std::vector<int> band_apply_candidates(const BandBlocks& B, bool mixed) {
+  return band_nvp_buckets(B, mixed ? sizeof(float) : sizeof(double));
 }

@@ -247,6 +247,7 @@ struct BandBlocks {
   const int* bw;           // half-bandwidth per block
   const int* ld;           // stored entries per row (bw+1 rounded up to a multiple of 4)
   int ldmax;               // largest ld
+  int nvp;                 // 16-byte vectors per lane of a prefetch register set (0 = default)
   const int* sys;
   const long long* off;    // element offset of the block's tiles
   double* L;               // Gram matrix on entry to the factorization, FP64 factor after
@@ -265,3 +266,4 @@ hipError_t launch_band_finish(hipStream_t st, const BandBlocks& B, bool mixed);
 hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, const double* u,
                              double* y, const int* done);
 hipError_t prepare_band_apply(const BandBlocks& B, bool mixed);
+std::vector<int> band_apply_candidates(const BandBlocks& B, bool mixed);

@@ -69,30 +69,48 @@ k_gram(DenseBlocks D, const int4* __restrict__ tiles, const int* __restrict__ ro
   for (int c = 0; c < DT; ++c) dst[c * DT + r] = acc[c * DT + r];
 }
 
-// C (64x64, LDS) -= X * Y^T with X, Y 64x64 tiles in LDS (column-major).
-// Thread t owns rows 4*(t%16).. and columns 4*(t/16)..
-__device__ __forceinline__ void tile_gemm_nt_sub(double* C, const double* X, const double* Y) {
-  const int tr = (threadIdx.x & 15) * 4, tc = (threadIdx.x >> 4) * 4;
-  double c[4][4];
+// C (64x64, LDS, column-major) = X Y^T (SUB: C -= X Y^T) with X, Y 64x64
+// column-major LDS tiles, on the FP64 matrix cores: v_mfma_f64_16x16x4f64
+// takes A[i][k] from lane i + 16k and B[k][j] from lane j + 16k, and leaves
+// D[i][j] in register r of lane j + 16g with i = 4r + g.  Wave w of the four
+// owns the 32x32 quadrant (rows 32 (w & 1), columns 32 (w >> 1)) as 2x2 such
+// tiles and runs 16 k-steps of 4.  The caller separates reads of an aliased
+// operand from the writes with a barrier (SUB = false writes C only after
+// all of the wave's products are in registers).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+template <bool SUB>
+__device__ __forceinline__ void tile_mfma_nt(double* C, const double* X, const double* Y,
+                                             bool sync_before_store) {
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w & 1), c0 = 32 * (w >> 1);
+  const int li = l & 15, lk = l >> 4;
+  dbl4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int bb = 0; bb < 4; ++bb) c[a][bb] = 0.0;
-  for (int p = 0; p < DT; ++p) {
-    double xa[4], yb[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) xa[a] = X[p * DT + tr + a];
-#pragma unroll
-    for (int bb = 0; bb < 4; ++bb) yb[bb] = Y[p * DT + tc + bb];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int bb = 0; bb < 4; ++bb) c[a][bb] += xa[a] * yb[bb];
+    for (int tj = 0; tj < 2; ++tj) acc[ti][tj] = dbl4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int p0 = 0; p0 < DT; p0 += 4) {
+    const int p = p0 + lk;
+    const double a0 = X[p * DT + r0 + li], a1 = X[p * DT + r0 + 16 + li];
+    const double b0 = Y[p * DT + c0 + li], b1 = Y[p * DT + c0 + 16 + li];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
+  if (sync_before_store) __syncthreads();
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
-    for (int bb = 0; bb < 4; ++bb) C[(tc + bb) * DT + tr + a] -= c[a][bb];
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = r0 + 16 * ti + 4 * r + lk, col = c0 + 16 * tj + li;
+        if constexpr (SUB) C[col * DT + row] -= acc[ti][tj][r];
+        else C[col * DT + row] = acc[ti][tj][r];
+      }
 }
 
 __device__ __forceinline__ void load_tile(double* dst, const double* src) {
@@ -180,27 +198,8 @@ k_cholesky(DenseBlocks D) {
       __syncthreads();
       load_tile(T2, L + ltile(i, k));
       __syncthreads();
-      // X = A_ik * Linv^T:  X[r][c] = sum_p A_ik[r][p] * Linv[c][p]
-      {
-        const int tr = (threadIdx.x & 15) * 4, tc = (threadIdx.x >> 4) * 4;
-        double acc[4][4] = {};
-        for (int p = 0; p < DT; ++p) {
-          double xa[4], yb[4];
-#pragma unroll
-          for (int a = 0; a < 4; ++a) xa[a] = T2[p * DT + tr + a];
-#pragma unroll
-          for (int bb = 0; bb < 4; ++bb) yb[bb] = T1[p * DT + tc + bb];
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int bb = 0; bb < 4; ++bb) acc[a][bb] += xa[a] * yb[bb];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int bb = 0; bb < 4; ++bb) T2[(tc + bb) * DT + tr + a] = acc[a][bb];
-      }
+      // X = A_ik * Linv^T:  X[r][c] = sum_p A_ik[r][p] * Linv[c][p] (in place)
+      tile_mfma_nt<false>(T2, T2, T1, true);
       __syncthreads();
       store_tile(L + ltile(i, k), T2);
       // A_ij -= L_ik L_jk^T for k < j <= i
@@ -213,7 +212,7 @@ k_cholesky(DenseBlocks D) {
         }
         load_tile(T0, L + ltile(i, j));
         __syncthreads();
-        tile_gemm_nt_sub(T0, T2, T3);
+        tile_mfma_nt<true>(T0, T2, T3, false);
         __syncthreads();
         store_tile(L + ltile(i, j), T0);
       }
