@@ -1,0 +1,190 @@
+"""Parity at the full sizes of the synthetic workloads (needs an MI355X).
+
+The oracle cannot run these sizes inside a test, so its results come from
+``tests/golden/oracle_fullsize.json``, written by
+``tests/golden/make_oracle_fullsize.py`` (which calls only ``oracle/`` and
+``workloads/``): per workload the oracle's iteration count to a relative true
+residual of 1e-10, its final residual, and its solution at 2000 seeded sample
+indices.  Where a property holds at any size (a residual bound) it is
+checked on the whole output.  Each test runs in the launch configuration
+bench.py uses for that workload.
+
+Bars, as in the small-size parity tests:
+* rip_graph rows and partitions: bit-exact;
+* FP64 solves: the oracle's iteration count (a difference of one is
+  accepted only as a near-tie of the stop decision), and at that count the
+  sampled entries within 1e-8 relative (l2 over the samples);
+* FP32-projection solves: true residual <= 1e-10 and sampled entries within
+  1e-6 of the oracle's converged solution.
+"""
+import functools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import paper_1710_07769_amd as bc
+import workloads
+from oracle import rip_rows
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "oracle_fullsize.json")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("tests/golden/oracle_fullsize.json not generated")
+    return json.load(open(GOLDEN))
+
+
+# each workload is generated once per test session
+config2 = functools.lru_cache(maxsize=1)(workloads.config2)
+config3 = functools.lru_cache(maxsize=1)(workloads.config3)
+config4 = functools.lru_cache(maxsize=1)(workloads.config4)
+config5 = functools.lru_cache(maxsize=1)(workloads.config5)
+
+
+@functools.lru_cache(maxsize=1)
+def cfg2_partition():
+    p = config2()
+    g = bc.rip_graph(p.n, p.A.rowptr, p.A.col, p.A.val)
+    return bc.bc_partition_greedy(g, p.K)
+
+
+def banner(msg):
+    print("\n[case] " + msg, flush=True)
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+
+
+def sample_err(x, ref):
+    idx = np.asarray(ref["sample_index"])
+    xs = np.asarray(ref["sample_x"])
+    return float(np.linalg.norm(x[idx] - xs) / np.linalg.norm(xs))
+
+
+def partition_hash(part):
+    n = part.size
+    return int(np.sum(part.astype(np.int64) * np.arange(1, n + 1, dtype=np.int64)) % (2**61 - 1))
+
+
+def check_fp64_count_and_iterate(dev, solver, f, ref, tol=1e-10):
+    x, st = solver.solve(f, tol=tol, maxit=20000)
+    assert st.status == bc.BC_OK and st.rel_residual <= tol * (1 + 1e-6)
+    d = st.iterations - ref["iterations"]
+    print("iterations gpu=%d oracle=%d" % (st.iterations, ref["iterations"]))
+    assert abs(d) <= 1, "iteration counts differ by %d" % d
+    x2, st2 = solver.solve(f, tol=0.0, maxit=ref["iterations"])
+    err = sample_err(x2.cpu().numpy(), ref)
+    print("sampled error at equal count: %.3e" % err)
+    assert err <= 1e-8
+    return st
+
+
+def test_rip_graph_st27_100cubed_sampled_rows(dev):
+    banner("rip_graph of the 27-point 100^3 matrix (120M edges): 64 sampled rows bit-exact")
+    p = config5()
+    g = bc.rip_graph(p.n, p.A.rowptr, p.A.col, p.A.val)
+    rows = np.sort(np.random.default_rng(5).choice(p.n, 64, replace=False))
+    ref = rip_rows(p.A, rows)
+    assert g.col.size > 100_000_000
+    for q, r in enumerate(rows):
+        a, b = g.rowptr[r], g.rowptr[r + 1]
+        c, d = ref.rowptr[q], ref.rowptr[q + 1]
+        assert np.array_equal(g.col[a:b], ref.col[c:d])
+        assert np.array_equal(g.cost[a:b].view(np.int64), ref.cost[c:d].view(np.int64))
+        assert np.array_equal(g.wgt[a:b], ref.wgt[c:d])
+
+
+def test_partition_cd3d_64cubed(dev, golden):
+    banner("greedy partition of the 64^3 convection-diffusion row graph, K=32: bit-exact")
+    part = cfg2_partition()
+    assert partition_hash(part) == golden["cfg2"]["partition_sha"]
+
+
+def test_solve_cd3d_64cubed_inner_cg(dev, golden):
+    banner("FP64 inner-CG solve, 64^3 convection-diffusion, K=32 greedy partition")
+    p = config2()
+    solver = bc.BlockCimmino(p.A, cfg2_partition(), p.K, projection=bc.BC_PROJ_INNER_CG)
+    try:
+        check_fp64_count_and_iterate(dev, solver, to_dev(p.f, dev), golden["cfg2"])
+    finally:
+        solver.close()
+
+
+def test_solve_powerlaw_500k_mixed(dev, golden):
+    banner("FP32 sparse products and inner CG, power-law n=500k, K=64 uneven blocks")
+    p = config3()
+    solver = bc.BlockCimmino(p.A, p.part(), p.K, projection=bc.BC_PROJ_INNER_CG,
+                             precision=bc.BC_MIXED)
+    try:
+        x, st = solver.solve(to_dev(p.f, dev), tol=1e-10, maxit=2000)
+        err = sample_err(x.cpu().numpy(), golden["cfg3"])
+        print("iterations gpu=%d oracle(FP64)=%d rel_res=%.2e sampled err vs oracle=%.2e"
+              % (st.iterations, golden["cfg3"]["iterations"], st.rel_residual, err))
+        assert st.status == bc.BC_OK and st.rel_residual <= 1e-10 * (1 + 1e-6)
+        assert err <= 1e-6
+    finally:
+        solver.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32-applies"])
+def test_solve_st27_100cubed_dense(dev, golden, precision):
+    banner("dense Cholesky projections, 27-point 100^3, K=512 (%s)" % precision)
+    p = config5()
+    prec = bc.BC_FP64 if precision == "fp64" else bc.BC_MIXED_PROJ
+    solver = bc.BlockCimmino(p.A, p.part(), p.K, projection=bc.BC_PROJ_DENSE_CHOL,
+                             precision=prec)
+    try:
+        f = to_dev(p.f, dev)
+        if precision == "fp64":
+            check_fp64_count_and_iterate(dev, solver, f, golden["cfg5"])
+        else:
+            x, st = solver.solve(f, tol=1e-10)
+            err = sample_err(x.cpu().numpy(), golden["cfg5"])
+            print("iterations gpu=%d oracle(FP64)=%d sampled err vs oracle=%.2e"
+                  % (st.iterations, golden["cfg5"]["iterations"], err))
+            assert st.status == bc.BC_OK and st.rel_residual <= 1e-10 * (1 + 1e-6)
+            assert err <= 1e-6
+    finally:
+        solver.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32-projections"])
+def test_batch256_cd2d(dev, golden, precision):
+    banner("256 batched 2D systems, sides 48..256, K=8, byte-model projections (%s)" % precision)
+    probs = config4()
+    prec = bc.BC_FP64 if precision == "fp64" else bc.BC_MIXED_PROJ
+    solver = bc.BlockCimminoBatched([(q.A, q.part(), q.K) for q in probs], precision=prec)
+    try:
+        f = to_dev(np.concatenate([q.f for q in probs]), dev)
+        x, sts = solver.solve(f, tol=1e-10, maxit=10000)
+        xs = np.split(x.cpu().numpy(), np.cumsum([q.n for q in probs])[:-1])
+        assert all(s.status == bc.BC_OK for s in sts)
+        assert max(s.rel_residual for s in sts) <= 1e-10 * (1 + 1e-6)
+        for k, ref in golden["cfg4"].items():
+            k = int(k)
+            err = sample_err(xs[k], ref)
+            print("system %d (n=%d): iterations gpu=%d oracle=%d sampled err=%.2e"
+                  % (k, probs[k].n, sts[k].iterations, ref["iterations"], err))
+            if precision == "fp64":
+                assert abs(sts[k].iterations - ref["iterations"]) <= 1
+                assert err <= 1e-8
+            else:
+                assert err <= 1e-6
+    finally:
+        solver.close()
