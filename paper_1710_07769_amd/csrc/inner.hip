@@ -279,12 +279,14 @@ hipError_t launch_sell_rows(hipStream_t st, const InnerBlocks& B, const double* 
 }
 
 // ------------------------------------------------------------------------
-// Several workgroups per block (`groups`, all on the block's XCD).  Every
-// workgroup keeps the block's whole q and r in LDS (updated redundantly, so q
-// is never exchanged); t and z are exchanged through global memory.  Per
-// inner iteration: t on the own column slices -> barrier -> z on the own row
-// slices (t gathered from global) and q.z -> barrier -> r -= alpha z on all
-// rows (z read from global), y on the own rows, r.r -> barrier -> q = r + beta q.
+// Several workgroups per block (`groups`, all on the block's XCD), running CG
+// in the Chronopoulos-Gear arrangement (two barriers per iteration).  Every
+// workgroup keeps the block's whole r and s = G q in LDS (updated
+// redundantly); t and w = G r are exchanged through global memory.  Per
+// inner iteration: t = A_i^T r on the own column slices -> barrier -> w = A_i t
+// on the own row slices (t gathered from global), (r,r) and (w,r) -> barrier
+// -> alpha, beta; q and y on the own rows; s and r on all rows (w read from
+// global).
 //
 // The barrier is a flag array: each workgroup stores its epoch with an
 // agent-scope store after its stores have completed, and polls the block's
@@ -410,55 +412,49 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   __syncthreads();
   fb.fenced = fenced_sh != 0;
 
-  // full r = q = D u in LDS (row scaling); y = 0 on the own rows
+  // CG in the Chronopoulos-Gear arrangement: one product w = G r and one
+  // fused reduction of (r, r) and (w, r) per iteration, with
+  //   beta = gamma / gamma_old,  alpha = gamma / (delta - beta gamma / alpha_old),
+  //   q = r + beta q,  s = w + beta s (= G q),  y += alpha q,  r -= alpha s.
+  // r and s are kept whole in every workgroup's LDS (updated redundantly;
+  // w is exchanged through global memory), q and y only on the own rows.
+  // Full r = D u in LDS (row scaling), s = 0.
   const double* __restrict__ dsc = B.dsc + row0;
+  T* ss = qs;  // the first LDS vector holds s
   for (int i = threadIdx.x; i < m; i += GRP_THREADS) {
-    const T v = (T)(u[row0 + i] * dsc[i]);
-    qs[i] = v;
-    rs[i] = v;
+    rs[i] = (T)(u[row0 + i] * dsc[i]);
+    ss[i] = (T)0;
   }
   double yy[RPT];
-  double part = 0.0;
+  T qq[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     yy[k] = 0.0;
-    const int i = (sa0 + wave + k * NW) * 64 + lane;
-    if (sa0 + wave + k * NW < sa1 && i < m) {
-      const double v = (double)(T)(u[row0 + i] * dsc[i]);
-      part += v * v;
-    }
+    qq[k] = (T)0;
   }
   __syncthreads();
-  // gamma0 over the own rows, summed over the group in slot order
-  part = block_sum(part, sh);
-  if (threadIdx.x == 0) slots[g] = part;
-  ok = flag_barrier(fb, err) && ok;
-  double gamma0 = 0.0;
-  for (int q = 0; q < G; ++q) gamma0 += agent_load<double>(&slots[q]);
   int it = 0;
-  T zz[RPT];
+  T* wg = zg;  // exchanged w of the block
   unsigned long long* tr = (B.trace && b == 0 && threadIdx.x == 0) ? B.trace + (size_t)g * 8 * 64 : nullptr;
 #define TRACE_AT(slot) do { if (tr && it <= 64) tr[(it - 1) * 8 + (slot)] = wall_clock64(); } while (0)
-  if (gamma0 > 0.0 && ok) {
-    const double thr = B.tol * B.tol * gamma0;
-    double gamma = gamma0;
+  if (ok) {
+    double thr = -1.0, gamma_old = 0.0, alpha_old = 0.0;
     while (it < B.maxit) {
       ++it;
       TRACE_AT(0);
-      // t = A_i^T q on the own column slices (q from LDS)
+      // t = A_i^T r on the own column slices (r from LDS)
       for (int s = st0 + wave; s < st1; s += NW) {
-        const T acc = sell_row<T, IX>(tidx, tval, tptr[s] + lane, tw[s], qs);
+        const T acc = sell_row<T, IX>(tidx, tval, tptr[s] + lane, tw[s], rs);
         if (s * 64 + lane < ns) tg[s * 64 + lane] = acc;
       }
       TRACE_AT(1);
       if (!flag_barrier(fb, err)) { ok = false; break; }
       TRACE_AT(2);
-      // z = A_i t on the own row slices, t gathered from global
-      part = 0.0;
+      // w = A_i t on the own row slices, t gathered from global; (r,r), (w,r)
+      double pg = 0.0, pd = 0.0;
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int s = sa0 + wave + k * NW;
-        zz[k] = (T)0;
         if (s < sa1) {
           const long long e = aptr[s] + lane;
           const int ww = aw[s];
@@ -482,51 +478,62 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
             acc += aval[e + (long long)k0 * 64] * agent_load<T>(&tg[aidx[e + (long long)k0 * 64]]);
           const int i = s * 64 + lane;
           if (i < m) {
-            zz[k] = acc;
-            zg[i] = acc;
-            part += (double)qs[i] * (double)acc;
+            wg[i] = acc;
+            const double ri = (double)rs[i];
+            pg += ri * ri;
+            pd += (double)acc * ri;
           }
         }
         __asm__ __volatile__("" ::: "memory");
       }
       TRACE_AT(3);
-      part = block_sum(part, sh);
-      if (threadIdx.x == 0) slots[g] = part;
+      pg = block_sum(pg, sh);
+      pd = block_sum(pd, sh);
+      if (threadIdx.x == 0) {
+        slots[g] = pg;
+        slots[G + g] = pd;
+      }
       if (!flag_barrier(fb, err)) { ok = false; break; }
       TRACE_AT(4);
-      double delta = 0.0;
-      for (int q = 0; q < G; ++q) delta += agent_load<double>(&slots[q]);
-      if (!(delta > 0.0) || !isfinite(delta)) break;
-      const double alpha = gamma / delta;
-      // y on the own rows (before q changes)
+      double gamma = 0.0, delta = 0.0;
+      for (int q = 0; q < G; ++q) {
+        gamma += agent_load<double>(&slots[q]);
+        delta += agent_load<double>(&slots[G + q]);
+      }
+      if (thr < 0.0) {
+        if (!(gamma > 0.0)) break;  // u_i = 0: y_i = 0
+        thr = B.tol * B.tol * gamma;
+      }
+      if (gamma <= thr) break;
+      double beta = 0.0, alpha;
+      if (it == 1) {
+        alpha = gamma / delta;
+      } else {
+        beta = gamma / gamma_old;
+        alpha = gamma / (delta - beta * gamma / alpha_old);
+      }
+      if (!(alpha > 0.0) || !isfinite(alpha)) break;
+      gamma_old = gamma;
+      alpha_old = alpha;
+      // own rows: q = r + beta q, y += alpha q
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int s = sa0 + wave + k * NW;
         const int i = s * 64 + lane;
-        if (s < sa1 && i < m) yy[k] += alpha * (double)qs[i];
+        if (s < sa1 && i < m) {
+          qq[k] = rs[i] + (T)beta * qq[k];
+          yy[k] += alpha * (double)qq[k];
+        }
       }
-      // r -= alpha z on all rows (z from global); r.r on the own rows
-      part = 0.0;
-      const int i_lo = sa0 * 64, i_hi = min(m, sa1 * 64);
+      __syncthreads();  // own-row reads of r done before r changes
+      // all rows: s = w + beta s, r -= alpha s (w from global)
       for (int i = threadIdx.x; i < m; i += GRP_THREADS) {
-        const T zi = agent_load<T>(&zg[i]);
-        const T rn = rs[i] - (T)alpha * zi;
-        rs[i] = rn;
-        if (i >= i_lo && i < i_hi) part += (double)rn * (double)rn;
+        const T si = agent_load<T>(&wg[i]) + (T)beta * ss[i];
+        ss[i] = si;
+        rs[i] = rs[i] - (T)alpha * si;
       }
-      TRACE_AT(5);
-      part = block_sum(part, sh);
-      if (threadIdx.x == 0) slots[G + g] = part;
-      if (!flag_barrier(fb, err)) { ok = false; break; }
-      TRACE_AT(6);
-      double gnew = 0.0;
-      for (int q = 0; q < G; ++q) gnew += agent_load<double>(&slots[G + q]);
-      if (gnew <= thr) break;
-      const T beta = (T)(gnew / gamma);
-      gamma = gnew;
-      for (int i = threadIdx.x; i < m; i += GRP_THREADS) qs[i] = rs[i] + beta * qs[i];
       __syncthreads();
-      TRACE_AT(7);
+      TRACE_AT(5);
     }
   }
 #undef TRACE_AT
