@@ -124,6 +124,26 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;
 }
 
+// Two block sums at the cost of one (sh holds 2 * waves doubles).
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  a = wave_sum_lane0(a);
+  b = wave_sum_lane0(b);
+  __syncthreads();
+  if (lane == 0) {
+    sh[w] = a;
+    sh[nw + w] = b;
+  }
+  __syncthreads();
+  double ta = 0.0, tb = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    ta += sh[i];
+    tb += sh[nw + i];
+  }
+  a = ta;
+  b = tb;
+}
+
 #endif
 
 // ------------------------------------------------------- kernel launchers

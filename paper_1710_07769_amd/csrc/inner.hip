@@ -357,6 +357,7 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
             const int* __restrict__ done, int rcap, int* err) {
   extern __shared__ double lds_d[];
   __shared__ double sh[GRP_THREADS / 64];
+  __shared__ double sh2[2 * (GRP_THREADS / 64)];
   __shared__ int fenced_sh;
   const int G = B.groups;
   const int w = blockIdx.x;
@@ -487,18 +488,27 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
         __asm__ __volatile__("" ::: "memory");
       }
       TRACE_AT(3);
-      pg = block_sum(pg, sh);
-      pd = block_sum(pd, sh);
+      block_sum2(pg, pd, sh2);
       if (threadIdx.x == 0) {
         slots[g] = pg;
         slots[G + g] = pd;
       }
       if (!flag_barrier(fb, err)) { ok = false; break; }
       TRACE_AT(4);
+      // all 2G partials in flight at once, then summed in slot order
+      double sg[16], sd[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        sg[q] = q < G ? agent_load<double>(&slots[q]) : 0.0;
+        sd[q] = q < G ? agent_load<double>(&slots[G + q]) : 0.0;
+      }
       double gamma = 0.0, delta = 0.0;
-      for (int q = 0; q < G; ++q) {
-        gamma += agent_load<double>(&slots[q]);
-        delta += agent_load<double>(&slots[G + q]);
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        if (q < G) {
+          gamma += sg[q];
+          delta += sd[q];
+        }
       }
       if (thr < 0.0) {
         if (!(gamma > 0.0)) break;  // u_i = 0: y_i = 0
@@ -526,11 +536,24 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
         }
       }
       __syncthreads();  // own-row reads of r done before r changes
-      // all rows: s = w + beta s, r -= alpha s (w from global)
-      for (int i = threadIdx.x; i < m; i += GRP_THREADS) {
-        const T si = agent_load<T>(&wg[i]) + (T)beta * ss[i];
-        ss[i] = si;
-        rs[i] = rs[i] - (T)alpha * si;
+      // all rows: s = w + beta s, r -= alpha s (w from global; the loads of
+      // a group of 4 rows per thread are issued before their use)
+      for (int i0 = threadIdx.x; i0 < m; i0 += 4 * GRP_THREADS) {
+        T wv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = i0 + k * GRP_THREADS;
+          wv[k] = i < m ? agent_load<T>(&wg[i]) : (T)0;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = i0 + k * GRP_THREADS;
+          if (i < m) {
+            const T si = wv[k] + (T)beta * ss[i];
+            ss[i] = si;
+            rs[i] = rs[i] - (T)alpha * si;
+          }
+        }
       }
       __syncthreads();
       TRACE_AT(5);
