@@ -33,6 +33,33 @@ __device__ __forceinline__ float group_sumf(float v) {
   return v;
 }
 
+// This lane's part of a row sum: entries e0 + l, e0 + l + L, ... in that
+// order (so the rounding is that of the plain loop), in batches of U whose
+// index and value loads, then gathers, are all issued before the arithmetic.
+template <int L, typename V, typename ACC>
+__device__ __forceinline__ ACC lane_row_sum(const int* __restrict__ col, const V* __restrict__ val,
+                                            const double* __restrict__ x, int e0, int e1, int l) {
+  constexpr int U = L <= 2 ? 8 : 4;
+  ACC acc = (ACC)0;
+  for (int e = e0 + l; e < e1; e += U * L) {
+    int c[U];
+    V v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+      const int ek = e + k * L;
+      c[k] = ek < e1 ? col[ek] : 0;
+      v[k] = ek < e1 ? val[ek] : (V)0;
+    }
+    ACC xv[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) xv[k] = e + k * L < e1 ? (ACC)x[c[k]] : (ACC)0;
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+      if (e + k * L < e1) acc += (ACC)v[k] * xv[k];
+  }
+  return acc;
+}
+
 // y[i] = sum_e val[e] * x[col[e]] for the rows of this tile (row-space tile).
 template <int L, bool MIXED>
 __global__ void __launch_bounds__(VEC_THREADS)
@@ -48,13 +75,11 @@ k_spmv(const int* __restrict__ rowptr, const int* __restrict__ col,
   for (int i = r0 + g; i < r1; i += RPP) {
     const int e0 = rowptr[i], e1 = rowptr[i + 1];
     if constexpr (MIXED) {
-      float acc = 0.f;
-      for (int e = e0 + l; e < e1; e += L) acc += val32[e] * (float)x[col[e]];
+      float acc = lane_row_sum<L, float, float>(col, val32, x, e0, e1, l);
       acc = group_sumf<L>(acc);
       if (l == 0) y[i] = (double)acc;
     } else {
-      double acc = 0.0;
-      for (int e = e0 + l; e < e1; e += L) acc += val[e] * x[col[e]];
+      double acc = lane_row_sum<L, double, double>(col, val, x, e0, e1, l);
       acc = group_sum<L>(acc);
       if (l == 0) y[i] = acc;
     }
@@ -81,12 +106,10 @@ k_spmvT_dot(const int* __restrict__ tptr, const int* __restrict__ trow,
     const int e0 = tptr[j], e1 = tptr[j + 1];
     double acc;
     if constexpr (MIXED) {
-      float a = 0.f;
-      for (int e = e0 + l; e < e1; e += L) a += tval32[e] * (float)y[trow[e]];
+      const float a = lane_row_sum<L, float, float>(trow, tval32, y, e0, e1, l);
       acc = (double)group_sumf<L>(a);
     } else {
-      double a = 0.0;
-      for (int e = e0 + l; e < e1; e += L) a += tval[e] * y[trow[e]];
+      const double a = lane_row_sum<L, double, double>(trow, tval, y, e0, e1, l);
       acc = group_sum<L>(a);
     }
     if (l == 0) {
@@ -116,8 +139,7 @@ k_residual(const int* __restrict__ rowptr, const int* __restrict__ col,
   double ss = 0.0;
   for (int i = r0 + g; i < r1; i += RPP) {
     const int e0 = rowptr[i], e1 = rowptr[i + 1];
-    double acc = 0.0;
-    for (int e = e0 + l; e < e1; e += L) acc += val[e] * x[col[e]];
+    double acc = lane_row_sum<L, double, double>(col, val, x, e0, e1, l);
     acc = group_sum<L>(acc);
     if (l == 0) {
       const double v = f[i] - acc;
