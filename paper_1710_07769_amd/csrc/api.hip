@@ -982,7 +982,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       BC_HIP(hipMemsetAsync(ptr, 0, 16 * 8 * 64 * sizeof(unsigned long long), st));
       B.trace = ptr;
     }
-    BC_TRY(A.alloc(&B.red, (size_t)B.nblk * 2 * std::max(G, 1)));
+    BC_TRY(A.alloc(&B.xp, (size_t)B.nblk * 2 * 64));
+    BC_HIP(hipMemsetAsync(B.xp, 0, (size_t)B.nblk * 2 * 64 * sizeof(unsigned long long), st));
     std::vector<unsigned> bz(32 * B.nblk, 0u);
     unsigned* pbar;
     BC_TRY(A.upload(&pbar, bz, st));

@@ -193,8 +193,9 @@ struct InnerBlocks {
   const float* btval32;
   double* q; double* z; double* ri; double* t;   // scratch (rows / support)
   float* q32; float* z32; float* ri32; float* t32;
-  double* red;             // per block 2 * groups partial slots
-  unsigned* bar;           // per block 2 barrier words (count, generation)
+  unsigned long long* xp;  // per block 2 x 16 groups x 4 words: the (r,r), (w,r) partials
+                           // of each workgroup as words {payload32, epoch32}
+  unsigned* bar;           // per block barrier flags (epochs) and placement words
   int* iters;              // per block inner iterations of the last call
   unsigned long long* total; // running sum of inner iterations over blocks and calls
   unsigned long long* blk_total; // per block running sum of inner iterations

@@ -61,8 +61,7 @@ __device__ __forceinline__ const float* sel_val<float>(const double*, const floa
 
 template <typename T, typename IX>
 __device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const T* __restrict__ val,
-                                      long long e, int w, const T* __restrict__ x) {
-  T acc = (T)0;
+                                      long long e, int w, const T* __restrict__ x, T acc = (T)0) {
   int k0 = 0;
   for (; k0 + 8 <= w; k0 += 8) {
     IX ix[8];
@@ -72,8 +71,11 @@ __device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const T* __res
       ix[k] = idx[e + (long long)(k0 + k) * 64];
       vv[k] = val[e + (long long)(k0 + k) * 64];
     }
+    T xv[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc += vv[k] * x[ix[k]];
+    for (int k = 0; k < 8; ++k) xv[k] = x[ix[k]];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc += vv[k] * xv[k];
   }
   for (; k0 < w; ++k0) acc += val[e + (long long)k0 * 64] * x[idx[e + (long long)k0 * 64]];
   return acc;
@@ -280,20 +282,25 @@ hipError_t launch_sell_rows(hipStream_t st, const InnerBlocks& B, const double* 
 
 // ------------------------------------------------------------------------
 // Several workgroups per block (`groups`, all on the block's XCD), running CG
-// in the Chronopoulos-Gear arrangement (two barriers per iteration).  Every
-// workgroup keeps the block's whole r and s = G q in LDS (updated
-// redundantly); t and w = G r are exchanged through global memory.  Per
-// inner iteration: t = A_i^T r on the own column slices -> barrier -> w = A_i t
-// on the own row slices (t gathered from global), (r,r) and (w,r) -> barrier
-// -> alpha, beta; q and y on the own rows; s and r on all rows (w read from
-// global).
+// in the Chronopoulos-Gear arrangement.  Every workgroup keeps the block's
+// whole r and s = G q in LDS (updated redundantly); t and w = G r are
+// exchanged through global memory.  Per inner iteration:
+//   t = A_i^T r on the own column slices -> barrier
+//   w = A_i t on the own row slices (t gathered from global), (r,r), (w,r)
+//     -> each workgroup publishes its two partials, tagged with the epoch
+//   alpha, beta from the G partials; q and y on the own rows, s and r on all
+//   rows (w read from global).
 //
 // The barrier is a flag array: each workgroup stores its epoch with an
 // agent-scope store after its stores have completed, and polls the block's
 // flags with agent-scope loads; exchanged data is read with agent-scope loads.
-// This relies on the workgroups of a block sharing one L2: the kernel checks
-// the XCC id of every workgroup at entry and, if any is misplaced, the whole
-// group uses full agent-scope fences instead.
+// The partials need no barrier of their own: each is stored, once the
+// workgroup's w stores have completed, as two 64-bit words {half, epoch}
+// (an aligned 64-bit atomic store is seen whole), and a reader that finds the
+// current epoch in both words of every workgroup has the partials and, by
+// that ordering, all of w.  This relies on the workgroups of a block sharing
+// one L2: the kernel checks the XCC id of every workgroup at entry and, if any
+// is misplaced, the whole group adds full agent-scope fences.
 constexpr int GRP_THREADS = 1024;
 
 __device__ __forceinline__ unsigned xcc_id() {
@@ -351,6 +358,39 @@ __device__ __forceinline__ bool flag_barrier(FlagBar& fb, int* err) {
   return ok_sh != 0;
 }
 
+// A value published as two words {low or high half, epoch}.
+__device__ __forceinline__ void put_tagged(unsigned long long* p, double v, unsigned ep) {
+  const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+  const unsigned long long tag = (unsigned long long)ep << 32;
+  __hip_atomic_store(p, tag | (bits & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, tag | (bits >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Waits (bounded) for the two tagged values at p and p + 2 of epoch ep on
+// every lane of the wavefront where `active` (the others pass).
+__device__ __forceinline__ bool get_tagged2(const unsigned long long* p, bool active, unsigned ep,
+                                            double& a, double& b, int* err) {
+  const unsigned long long idle = (unsigned long long)ep << 32;
+  const unsigned long long t0 = wall_clock64();
+  while (true) {
+    unsigned long long v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      v[q] = active ? __hip_atomic_load(p + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : idle;
+    const bool here = (unsigned)(v[0] >> 32) == ep && (unsigned)(v[1] >> 32) == ep &&
+                      (unsigned)(v[2] >> 32) == ep && (unsigned)(v[3] >> 32) == ep;
+    if (__all(here)) {
+      a = __builtin_bit_cast(double, (v[1] << 32) | (v[0] & 0xffffffffull));
+      b = __builtin_bit_cast(double, (v[3] << 32) | (v[2] & 0xffffffffull));
+      return true;
+    }
+    if (wall_clock64() - t0 > WAIT_LIMIT) {
+      if ((threadIdx.x & 63) == 0) atomicExch(err, 1);
+      return false;
+    }
+  }
+}
+
 template <typename T, typename IX, int RPT>
 __global__ void __launch_bounds__(GRP_THREADS)
 k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
@@ -387,7 +427,23 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   const int* __restrict__ tw = B.t_w + B.t_s0[b];
   T* tg = Vec<T>::t(B) + sup0;     // exchanged t of the block
   T* zg = Vec<T>::z(B) + row0;     // exchanged z of the block
-  double* slots = B.red + (size_t)b * 2 * G;
+  unsigned long long* const xp = B.xp + (size_t)b * 2 * 64;  // tagged partials, 2 parities
+  // entry offsets and widths of the own slices (loop invariant); the first
+  // RPT own column slices of a wavefront, all its own row slices
+  long long ea[RPT], et[RPT];
+  int wa[RPT], wt[RPT];
+#pragma unroll
+  for (int k = 0; k < RPT; ++k) {
+    const int s = sa0 + wave + k * NW;
+    ea[k] = s < sa1 ? aptr[s] + lane : 0;
+    wa[k] = s < sa1 ? aw[s] : 0;
+    const int c = st0 + wave + k * NW;
+    et[k] = c < st1 ? tptr[c] + lane : 0;
+    wt[k] = c < st1 ? tw[c] : 0;
+  }
+  const int nown = sa1 - sa0;
+  __shared__ double gd_sh[2];
+  __shared__ int fail_sh;
   FlagBar fb{B.bar + (size_t)b * 32, 0u, g, G, false};
   if (threadIdx.x == 0) {
     fb.epoch = __hip_atomic_load(&fb.flags[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -443,22 +499,44 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
     while (it < B.maxit) {
       ++it;
       TRACE_AT(0);
-      // t = A_i^T r on the own column slices (r from LDS)
-      for (int s = st0 + wave; s < st1; s += NW) {
-        const T acc = sell_row<T, IX>(tidx, tval, tptr[s] + lane, tw[s], rs);
-        if (s * 64 + lane < ns) tg[s * 64 + lane] = acc;
+      // t = A_i^T r on the own column slices (r from LDS).  The stores come
+      // after all the loads: a load issued after a store is not complete
+      // before the store is.
+      T tacc[RPT];
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int c = st0 + wave + k * NW;
+        tacc[k] = (T)0;
+        if (c < st1) {
+          // opaque to the compiler, so that the entry addresses are formed
+          // here rather than held across the whole loop
+          long long e = et[k];
+          asm volatile("" : "+v"(e));
+          tacc[k] = sell_row<T, IX>(tidx, tval, e, wt[k], rs);
+        }
+      }
+      for (int c = st0 + wave + RPT * NW; c < st1; c += NW) {
+        const T acc = sell_row<T, IX>(tidx, tval, tptr[c] + lane, tw[c], rs);
+        if (c * 64 + lane < ns) tg[c * 64 + lane] = acc;
+      }
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int c = st0 + wave + k * NW;
+        if (c < st1 && c * 64 + lane < ns) tg[c * 64 + lane] = tacc[k];
       }
       TRACE_AT(1);
       if (!flag_barrier(fb, err)) { ok = false; break; }
       TRACE_AT(2);
+      const unsigned E = fb.epoch;
       // w = A_i t on the own row slices, t gathered from global; (r,r), (w,r)
       double pg = 0.0, pd = 0.0;
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int s = sa0 + wave + k * NW;
         if (s < sa1) {
-          const long long e = aptr[s] + lane;
-          const int ww = aw[s];
+          long long e = ea[k];
+          asm volatile("" : "+v"(e));
+          const int ww = wa[k];
           T acc = (T)0;
           int k0 = 0;
           for (; k0 + 8 <= ww; k0 += 8) {
@@ -485,31 +563,57 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
             pd += (double)acc * ri;
           }
         }
-        __asm__ __volatile__("" ::: "memory");
       }
       TRACE_AT(3);
-      block_sum2(pg, pd, sh2);
+      // workgroup partials (wave sums, then the waves in order), published by
+      // thread 0 once every wavefront's w stores have completed
+      pg = wave_sum_lane0(pg);
+      pd = wave_sum_lane0(pd);
+      __builtin_amdgcn_s_waitcnt(0);
+      if (lane == 0) {
+        sh2[wave] = pg;
+        sh2[NW + wave] = pd;
+      }
+      __syncthreads();
+      TRACE_AT(6);
+      unsigned long long* const xpe = xp + (E & 1u) * 64;
       if (threadIdx.x == 0) {
-        slots[g] = pg;
-        slots[G + g] = pd;
-      }
-      if (!flag_barrier(fb, err)) { ok = false; break; }
-      TRACE_AT(4);
-      // all 2G partials in flight at once, then summed in slot order
-      double sg[16], sd[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        sg[q] = q < G ? agent_load<double>(&slots[q]) : 0.0;
-        sd[q] = q < G ? agent_load<double>(&slots[G + q]) : 0.0;
-      }
-      double gamma = 0.0, delta = 0.0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        if (q < G) {
-          gamma += sg[q];
-          delta += sd[q];
+        double ta = 0.0, tb = 0.0;
+        for (int q = 0; q < NW; ++q) {
+          ta += sh2[q];
+          tb += sh2[NW + q];
         }
+        if (fb.fenced) __threadfence();
+        put_tagged(xpe + g * 4, ta, E);
+        put_tagged(xpe + g * 4 + 2, tb, E);
       }
+      // the G partials, summed in group order by wavefront 0
+      if (wave == 0) {
+        double pgq = 0.0, pdq = 0.0;
+        bool okp = true;
+        okp = get_tagged2(xpe + (lane < G ? lane : 0) * 4, lane < G, E, pgq, pdq, err);
+        if (lane >= G) pgq = pdq = 0.0;
+        if (fb.fenced) __threadfence();
+        double gsum = 0.0, dsum = 0.0;
+        for (int q = 0; q < G; ++q) {
+          gsum += __shfl(pgq, q, 64);
+          dsum += __shfl(pdq, q, 64);
+        }
+        if (lane == 0) {
+          gd_sh[0] = gsum;
+          gd_sh[1] = dsum;
+          fail_sh = 0;
+        }
+        TRACE_AT(7);
+        if (__any(!okp) && lane == 0) fail_sh = 1;
+      }
+      __syncthreads();
+      TRACE_AT(4);
+      if (fail_sh) {
+        ok = false;
+        break;
+      }
+      const double gamma = gd_sh[0], delta = gd_sh[1];
       if (thr < 0.0) {
         if (!(gamma > 0.0)) break;  // u_i = 0: y_i = 0
         thr = B.tol * B.tol * gamma;
@@ -525,31 +629,37 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
       if (!(alpha > 0.0) || !isfinite(alpha)) break;
       gamma_old = gamma;
       alpha_old = alpha;
-      // own rows: q = r + beta q, y += alpha q
+      // s = w + beta s, r -= alpha s on all rows, and on the own rows first
+      // q = r + beta q, y += alpha q.  Slice j = wave + c NW of this
+      // wavefront is slice sa0 + j (mod nsa): the own slices come first and
+      // stay with the thread that holds their q and y.  The w loads of UB
+      // slices are issued before their use.
+      constexpr int UB = 8;  // slices per batch of loads
+      // (lane index opaque: the row indices are formed here, not kept live)
+      int ln = lane;
+      asm volatile("" : "+v"(ln));
 #pragma unroll
-      for (int k = 0; k < RPT; ++k) {
-        const int s = sa0 + wave + k * NW;
-        const int i = s * 64 + lane;
-        if (s < sa1 && i < m) {
-          qq[k] = rs[i] + (T)beta * qq[k];
-          yy[k] += alpha * (double)qq[k];
+      for (int c0 = 0; c0 < 16; c0 += UB) {
+        if (wave + c0 * NW >= nsa) break;
+        int ri[UB];
+        T wv[UB];
+#pragma unroll
+        for (int c = 0; c < UB; ++c) {
+          const int j = wave + (c0 + c) * NW;
+          int sl = sa0 + j;
+          if (sl >= nsa) sl -= nsa;
+          ri[c] = j < nsa ? sl * 64 + ln : m;
+          wv[c] = ri[c] < m ? agent_load<T>(&wg[ri[c]]) : (T)0;
         }
-      }
-      __syncthreads();  // own-row reads of r done before r changes
-      // all rows: s = w + beta s, r -= alpha s (w from global; the loads of
-      // a group of 4 rows per thread are issued before their use)
-      for (int i0 = threadIdx.x; i0 < m; i0 += 4 * GRP_THREADS) {
-        T wv[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int i = i0 + k * GRP_THREADS;
-          wv[k] = i < m ? agent_load<T>(&wg[i]) : (T)0;
-        }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int i = i0 + k * GRP_THREADS;
+        for (int c = 0; c < UB; ++c) {
+          const int i = ri[c];
           if (i < m) {
-            const T si = wv[k] + (T)beta * ss[i];
+            if (c0 + c < RPT && wave + (c0 + c) * NW < nown) {
+              qq[(c0 + c) % RPT] = rs[i] + (T)beta * qq[(c0 + c) % RPT];
+              yy[(c0 + c) % RPT] += alpha * (double)qq[(c0 + c) % RPT];
+            }
+            const T si = wv[c] + (T)beta * ss[i];
             ss[i] = si;
             rs[i] = rs[i] - (T)alpha * si;
           }
