@@ -358,6 +358,15 @@ __device__ __forceinline__ bool flag_barrier(FlagBar& fb, int* err) {
   return ok_sh != 0;
 }
 
+// A wavefront-uniform double moved to scalar registers (frees vector
+// registers for loop-carried scalars).
+__device__ __forceinline__ double uniform_f64(double v) {
+  const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)bits);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(bits >> 32));
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // A value published as two words {low or high half, epoch}.
 __device__ __forceinline__ void put_tagged(unsigned long long* p, double v, unsigned ep) {
   const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
@@ -428,20 +437,29 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   T* tg = Vec<T>::t(B) + sup0;     // exchanged t of the block
   T* zg = Vec<T>::z(B) + row0;     // exchanged z of the block
   unsigned long long* const xp = B.xp + (size_t)b * 2 * 64;  // tagged partials, 2 parities
-  // entry offsets and widths of the own slices (loop invariant); the first
-  // RPT own column slices of a wavefront, all its own row slices
-  long long ea[RPT], et[RPT];
+  // entry offsets (relative to the block's first slice, 32 bit) and widths
+  // of the own slices, loop invariant: the first RPT own column slices of a
+  // wavefront and all its own row slices
+  const long long abase = aptr[0], tbase = tptr[0];
+  const IX* __restrict__ aidxb = aidx + abase;
+  const T* __restrict__ avalb = aval + abase;
+  const IX* __restrict__ tidxb = tidx + tbase;
+  const T* __restrict__ tvalb = tval + tbase;
+  int ea[RPT], et[RPT];
   int wa[RPT], wt[RPT];
 #pragma unroll
   for (int k = 0; k < RPT; ++k) {
     const int s = sa0 + wave + k * NW;
-    ea[k] = s < sa1 ? aptr[s] + lane : 0;
+    ea[k] = s < sa1 ? (int)(aptr[s] - abase) + lane : 0;
     wa[k] = s < sa1 ? aw[s] : 0;
     const int c = st0 + wave + k * NW;
-    et[k] = c < st1 ? tptr[c] + lane : 0;
+    et[k] = c < st1 ? (int)(tptr[c] - tbase) + lane : 0;
     wt[k] = c < st1 ? tw[c] : 0;
   }
   const int nown = sa1 - sa0;
+  // stores of t and w held back to the end of their phase (registers allow
+  // it for up to two slices per wavefront)
+  constexpr bool DEFER = RPT <= 2;
   __shared__ double gd_sh[2];
   __shared__ int fail_sh;
   FlagBar fb{B.bar + (size_t)b * 32, 0u, g, G, false};
@@ -499,9 +517,9 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
     while (it < B.maxit) {
       ++it;
       TRACE_AT(0);
-      // t = A_i^T r on the own column slices (r from LDS).  The stores come
-      // after all the loads: a load issued after a store is not complete
-      // before the store is.
+      // t = A_i^T r on the own column slices (r from LDS).  With few slices
+      // per wavefront the stores come after all the loads: a load issued
+      // after a store is not complete before the store is.
       T tacc[RPT];
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
@@ -510,9 +528,10 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
         if (c < st1) {
           // opaque to the compiler, so that the entry addresses are formed
           // here rather than held across the whole loop
-          long long e = et[k];
+          int e = et[k];
           asm volatile("" : "+v"(e));
-          tacc[k] = sell_row<T, IX>(tidx, tval, e, wt[k], rs);
+          tacc[k] = sell_row<T, IX>(tidxb, tvalb, e, wt[k], rs);
+          if (!DEFER && c * 64 + lane < ns) tg[c * 64 + lane] = tacc[k];
         }
       }
       for (int c = st0 + wave + RPT * NW; c < st1; c += NW) {
@@ -522,7 +541,7 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int c = st0 + wave + k * NW;
-        if (c < st1 && c * 64 + lane < ns) tg[c * 64 + lane] = tacc[k];
+        if (DEFER && c < st1 && c * 64 + lane < ns) tg[c * 64 + lane] = tacc[k];
       }
       TRACE_AT(1);
       if (!flag_barrier(fb, err)) { ok = false; break; }
@@ -530,11 +549,12 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
       const unsigned E = fb.epoch;
       // w = A_i t on the own row slices, t gathered from global; (r,r), (w,r)
       double pg = 0.0, pd = 0.0;
+      T wacc[RPT];
 #pragma unroll
       for (int k = 0; k < RPT; ++k) {
         const int s = sa0 + wave + k * NW;
         if (s < sa1) {
-          long long e = ea[k];
+          int e = ea[k];
           asm volatile("" : "+v"(e));
           const int ww = wa[k];
           T acc = (T)0;
@@ -544,8 +564,8 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
             T vv[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
-              ix[q] = aidx[e + (long long)(k0 + q) * 64];
-              vv[q] = aval[e + (long long)(k0 + q) * 64];
+              ix[q] = aidxb[e + (k0 + q) * 64];
+              vv[q] = avalb[e + (k0 + q) * 64];
             }
             T tv[8];
 #pragma unroll
@@ -553,16 +573,24 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc += vv[q] * tv[q];
           }
-          for (; k0 < ww; ++k0)
-            acc += aval[e + (long long)k0 * 64] * agent_load<T>(&tg[aidx[e + (long long)k0 * 64]]);
+          for (; k0 < ww; ++k0) acc += avalb[e + k0 * 64] * agent_load<T>(&tg[aidxb[e + k0 * 64]]);
           const int i = s * 64 + lane;
-          if (i < m) {
+          if (DEFER)
+            wacc[k] = acc;
+          else if (i < m)
             wg[i] = acc;
+          if (i < m) {
             const double ri = (double)rs[i];
             pg += ri * ri;
             pd += (double)acc * ri;
           }
         }
+      }
+      // (stores after all the loads, as in the t phase)
+#pragma unroll
+      for (int k = 0; k < RPT; ++k) {
+        const int s = sa0 + wave + k * NW;
+        if (DEFER && s < sa1 && s * 64 + lane < m) wg[s * 64 + lane] = wacc[k];
       }
       TRACE_AT(3);
       // workgroup partials (wave sums, then the waves in order), published by
@@ -613,7 +641,7 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
         ok = false;
         break;
       }
-      const double gamma = gd_sh[0], delta = gd_sh[1];
+      const double gamma = uniform_f64(gd_sh[0]), delta = uniform_f64(gd_sh[1]);
       if (thr < 0.0) {
         if (!(gamma > 0.0)) break;  // u_i = 0: y_i = 0
         thr = B.tol * B.tol * gamma;
@@ -626,6 +654,8 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
         beta = gamma / gamma_old;
         alpha = gamma / (delta - beta * gamma / alpha_old);
       }
+      alpha = uniform_f64(alpha);
+      beta = uniform_f64(beta);
       if (!(alpha > 0.0) || !isfinite(alpha)) break;
       gamma_old = gamma;
       alpha_old = alpha;
