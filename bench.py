@@ -31,7 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # precision of the workload), scaled by the factors a plain 1 GiB copy gives
 # (FETCH x2.0, WRITE x1.0).  An entry is removed whenever its kernel changes.
 MEASURED_TRAFFIC = {
-    "cfg2": {"kernel": "k_inner_grp<double>", "bytes_per_launch": 1.173e+10,
+    "cfg2": {"kernel": "k_inner_grp<double>", "bytes_per_launch": 1.166e+10,
              "profile": "profiles/k_inner_grp_f64_cd3d_64cubed_K32.md"},
     "cfg4": {"kernel": "k_band_apply<float, 20>", "bytes_per_launch": 2.569e+09,
              "profile": "profiles/k_band_apply_f32_cd2d_batch256_K8.md"},
