@@ -271,6 +271,7 @@ struct bc_ctx {
   double* d_hist = nullptr;
   double *d_part_a = nullptr, *d_part_b = nullptr, *d_part_c = nullptr, *d_part_f = nullptr;
   double *d_part_d = nullptr, *d_part_e = nullptr, *d_part_g = nullptr;
+  double* d_final = nullptr;  // per system 5 figures of the final residual (k_final_stats)
   double* d_normA = nullptr;
   double* d_finf = nullptr;
   // vectors
@@ -813,6 +814,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   BC_TRY(A.alloc(&c->d_part_d, c->ntiles));
   BC_TRY(A.alloc(&c->d_part_e, c->ntiles));
   BC_TRY(A.alloc(&c->d_part_g, c->ntiles));
+  BC_TRY(A.alloc(&c->d_final, (size_t)5 * c->nsys));
   BC_TRY(A.upload(&c->d_normA, c->normA_inf, st));
   BC_TRY(A.alloc(&c->d_finf, ns));
   BC_TRY(A.alloc(&c->d_r, n));
@@ -1676,23 +1678,18 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   const double t_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats) {
-    // true residuals and backward errors in FP64 from x
-    std::vector<double> xh(n), sh(n), fh(n);
+    // true residuals and backward errors in FP64 from x, reduced on the device
     BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s, S,
                            nullptr));
-    BC_HIP(hipMemcpyAsync(xh.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, st));
-    BC_HIP(hipMemcpyAsync(sh.data(), c->d_s, n * sizeof(double), hipMemcpyDeviceToHost, st));
-    BC_HIP(hipMemcpyAsync(fh.data(), c->d_f, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    BC_HIP(launch_init_norms(st, c->d_f, c->d_s, x, c->d_part_f, S));
+    BC_HIP(launch_final_stats(st, c->d_part_f, S, c->d_final));
+    std::vector<double> fin((size_t)5 * ns);
+    BC_HIP(hipMemcpyAsync(fin.data(), c->d_final, fin.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
     for (int s2 = 0; s2 < ns; ++s2) {
-      double ss = 0, ff = 0, smax = 0, fmax = 0, x1 = 0;
-      for (int i = c->sys_off[s2]; i < c->sys_off[s2 + 1]; ++i) {
-        ss += sh[i] * sh[i];
-        ff += fh[i] * fh[i];
-        smax = std::max(smax, std::fabs(sh[i]));
-        fmax = std::max(fmax, std::fabs(fh[i]));
-        x1 += std::fabs(xh[i]);
-      }
+      const double ss = fin[5 * s2], ff = fin[5 * s2 + 1], smax = fin[5 * s2 + 2];
+      const double fmax = fin[5 * s2 + 3], x1 = fin[5 * s2 + 4];
       bc_stats& q = stats[s2];
       q.iterations = iters[s2];
       q.status = status[s2];

@@ -169,6 +169,8 @@ hipError_t launch_replace_decide(hipStream_t st, const OuterState& S, int* resta
 hipError_t launch_true_check(hipStream_t st, const OuterState& S);
 hipError_t launch_init_norms(hipStream_t st, const double* f, const double* s, const double* x,
                              double* part_f, const OuterState& S);
+hipError_t launch_final_stats(hipStream_t st, const double* part_f, const OuterState& S,
+                              double* out);
 hipError_t launch_gather(hipStream_t st, const double* src, const int* idx, double* dst, int n);
 hipError_t launch_sqnorm_tiles(hipStream_t st, const double* v, double* part, const OuterState& S);
 hipError_t launch_set_thresholds(hipStream_t st, const double* part_f, double tol, const OuterState& S);

@@ -356,6 +356,25 @@ k_init_norms(const double* __restrict__ f, const double* __restrict__ s,
   }
 }
 
+// Per system, from the tile partials (fixed order): ||s||^2, ||f||^2, max|s|,
+// max|f| and sum|x|, into out[5 sys + 0..4] (the figures the solve reports:
+// relative residual and the normwise backward error of eq. (stopping)).
+__global__ void k_final_stats(const double* __restrict__ part_f, OuterState S,
+                              double* __restrict__ out) {
+  const int sys = blockIdx.x;
+  const int a = S.sys_tile[sys], b = S.sys_tile[sys + 1];
+  const double ss = sys_sum_wave(S.part_c, a, b);
+  const double ff = sys_sum_wave(part_f, a, b);
+  const double xs = sys_sum_wave(S.part_e, a, b);
+  if (threadIdx.x == 0) {
+    out[5 * sys + 0] = ss;
+    out[5 * sys + 1] = ff;
+    out[5 * sys + 2] = sys_max_serial(S.part_d, a, b);
+    out[5 * sys + 3] = sys_max_serial(S.part_g, a, b);
+    out[5 * sys + 4] = xs;
+  }
+}
+
 // Tile partials of v.v (into part).
 __global__ void __launch_bounds__(VEC_THREADS)
 k_sqnorm_tiles(const double* __restrict__ v, double* __restrict__ part, OuterState S) {
@@ -535,6 +554,12 @@ hipError_t launch_sqnorm_tiles(hipStream_t st, const double* v, double* part, co
 hipError_t launch_set_thresholds(hipStream_t st, const double* part_f, double tol,
                                  const OuterState& S) {
   hipLaunchKernelGGL(k_set_thresholds, dim3(S.nsys), dim3(64), 0, st, part_f, tol * tol, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_final_stats(hipStream_t st, const double* part_f, const OuterState& S,
+                              double* out) {
+  hipLaunchKernelGGL(k_final_stats, dim3(S.nsys), dim3(64), 0, st, part_f, S, out);
   return hipGetLastError();
 }
 
