@@ -8,7 +8,7 @@ true residual of 1e-10 (GPU).  The headline `value` is outer CG iterations
 per second of the solve phase (inputs resident in HBM); time-to-tolerance
 and the other phases are reported beside it.
 
-Usage: python bench.py [--steps K] [--warmup W] [--workload cfg2|cfg1|cfg3|cfg4|cfg5|cfg5-rip]
+Usage: python bench.py [--steps K] [--warmup W] [--workload cfg2|cfg1|cfg3|cfg4|cfg5|cfg5-rip|cfg5-band]
 """
 from __future__ import annotations
 
@@ -94,6 +94,14 @@ class Workload:
             self.opts = {"projection": bc.BC_PROJ_DENSE_CHOL, "precision": bc.BC_MIXED_PROJ}
             self.desc = ("st27-100 n=1e6 K=512 %s, dense FP64 Cholesky, FP32 triangular applies"
                          % self.partition)
+        elif name == "cfg5-band":
+            # the same matrix and blocks with sparse-factor projections:
+            # banded FP64 Cholesky of each block after reverse Cuthill-McKee
+            p = W.config5()
+            self.problems, self.partition = [p], "contiguous"
+            self.opts = {"projection": bc.BC_PROJ_BAND_CHOL, "precision": bc.BC_MIXED_PROJ}
+            self.desc = ("st27-100 n=1e6 K=512 contiguous, banded FP64 Cholesky (RCM), FP32 "
+                         "triangular applies")
         else:
             raise SystemExit("unknown workload " + name)
         if precision == "fp64":

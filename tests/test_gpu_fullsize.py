@@ -164,6 +164,31 @@ def test_solve_st27_100cubed_dense(dev, golden, precision):
         solver.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32-applies"])
+def test_solve_st27_100cubed_banded(dev, golden, precision):
+    banner("banded Cholesky projections (reverse Cuthill-McKee), 27-point 100^3, K=512 (%s)"
+           % precision)
+    p = config5()
+    prec = bc.BC_FP64 if precision == "fp64" else bc.BC_MIXED_PROJ
+    solver = bc.BlockCimmino(p.A, p.part(), p.K, projection=bc.BC_PROJ_BAND_CHOL, precision=prec)
+    try:
+        kind, bw = solver.block_info()
+        assert (kind == bc.KIND_BAND).all() and 0 < bw.max() <= 127
+        print("half-bandwidths %d..%d" % (bw.min(), bw.max()))
+        f = to_dev(p.f, dev)
+        if precision == "fp64":
+            check_fp64_count_and_iterate(dev, solver, f, golden["cfg5"])
+        else:
+            x, st = solver.solve(f, tol=1e-10)
+            err = sample_err(x.cpu().numpy(), golden["cfg5"])
+            print("iterations gpu=%d oracle(FP64)=%d sampled err vs oracle=%.2e"
+                  % (st.iterations, golden["cfg5"]["iterations"], err))
+            assert st.status == bc.BC_OK and st.rel_residual <= 1e-10 * (1 + 1e-6)
+            assert err <= 1e-6
+    finally:
+        solver.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32-projections"])
 def test_batch256_cd2d(dev, golden, precision):
     banner("256 batched 2D systems, sides 48..256, K=8, byte-model projections (%s)" % precision)
