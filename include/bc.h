@@ -88,10 +88,14 @@ typedef struct {
                              BC_STOP_BACKWARD_ERR: gamma < tol, eq. (stopping) */
   int32_t check_every;    /* outer iterations between host convergence checks; default 8 */
   int32_t spmv_lanes;     /* lanes of a wave sharing one row in the sparse
-                             products (1..64, power of two); 0 (default): each
-                             of A p and A^T y is timed at setup for every lane
-                             count and the fastest is kept (cached per
-                             sparsity pattern within the process) */
+                             products (1..64, power of two), or -1: sliced-ELL
+                             copies of A and A^T (slices of 64 rows, one row
+                             per lane, entries column by column); 0 (default):
+                             each of A p and A^T y is timed at setup for every
+                             lane count and, when its padding adds at most a
+                             quarter to the entries, the sliced-ELL form; the
+                             fastest is kept (cached per sparsity pattern
+                             within the process) */
   int32_t use_graph;      /* 1 (default): when every block uses a Cholesky
                              factor (dense or banded), groups of outer
                              iterations (gcd of check_every and, with FP32
@@ -165,8 +169,8 @@ bc_status bc_info(const bc_ctx* ctx, int64_t* n_total, int32_t* nsys, int32_t* n
                   int32_t* ndense);
 
 /* The lane counts chosen for the sparse products: lanes_a for A p and the
- * residuals, lanes_at for A^T y (64/lanes rows per wavefront).  Either
- * pointer may be NULL. */
+ * residuals, lanes_at for A^T y (64/lanes rows per wavefront; -1 for the
+ * sliced-ELL form, one row per lane).  Either pointer may be NULL. */
 bc_status bc_schedule(const bc_ctx* ctx, int32_t* lanes_a, int32_t* lanes_at);
 
 /* Per block (in block order: systems in order, blocks by part id): the

@@ -211,6 +211,49 @@ int choose_lanes(int64_t nnz, int64_t rows) {
   return std::max(1, std::min(64, l));
 }
 
+// Sliced-ELL copy (SellMat) of the CSR matrix (rp, ci, v) over the tiles.
+// Without `force` nothing is built (false) when padding would add more than
+// a quarter to the stored entries.
+bool build_sell(const std::vector<int>& rp, const std::vector<int>& ci, const std::vector<double>& v,
+                const std::vector<int>& tile_start, bool force, std::vector<long long>& ptr,
+                std::vector<int>& wid, std::vector<int>& col, std::vector<double>& val) {
+  const int ntiles = (int)tile_start.size() - 1;
+  ptr.assign((size_t)ntiles * SELL_SLICES, 0);
+  wid.assign((size_t)ntiles * SELL_SLICES, 0);
+  long long total = 0;
+  for (int t = 0; t < ntiles; ++t)
+    for (int j = 0; j < SELL_SLICES; ++j) {
+      const int ra = tile_start[t] + 64 * j, rb = std::min(ra + 64, tile_start[t + 1]);
+      int w = 0;
+      for (int i = ra; i < rb; ++i) w = std::max(w, rp[i + 1] - rp[i]);
+      ptr[(size_t)t * SELL_SLICES + j] = total;
+      wid[(size_t)t * SELL_SLICES + j] = w;
+      total += 64LL * w;
+    }
+  const long long nnz = rp.back();
+  if (!force && (double)total > 1.25 * (double)nnz) return false;
+  col.assign((size_t)total, 0);
+  val.assign((size_t)total, 0.0);
+  for (int t = 0; t < ntiles; ++t)
+    for (int j = 0; j < SELL_SLICES; ++j) {
+      const int ra = tile_start[t] + 64 * j;
+      const long long base = ptr[(size_t)t * SELL_SLICES + j];
+      const int w = wid[(size_t)t * SELL_SLICES + j];
+      for (int l = 0; l < 64; ++l) {
+        const int i = ra + l;
+        const bool row = i < tile_start[t + 1];
+        const int e0 = row ? rp[i] : 0, len = row ? rp[i + 1] - rp[i] : 0;
+        const int pad = len > 0 ? ci[e0 + len - 1] : tile_start[t];
+        for (int k = 0; k < w; ++k) {
+          const size_t q = (size_t)(base + 64LL * k + l);
+          col[q] = k < len ? ci[e0 + k] : pad;
+          val[q] = k < len ? v[e0 + k] : 0.0;
+        }
+      }
+    }
+  return true;
+}
+
 struct SysIn {
   int32_t n;
   const int32_t* rowptr;
@@ -253,6 +296,8 @@ struct bc_ctx {
   int* d_trow = nullptr;
   double* d_tval = nullptr;
   float* d_tval32 = nullptr;
+  bool have_sell = false;          // sliced-ELL copies of A and A^T built
+  SellMat sellA{}, sellT{};
   // tiles
   int ntiles = 0;
   int* d_tile_start = nullptr;
@@ -377,6 +422,26 @@ unsigned long long pattern_key(const std::vector<int>& rowptr, const std::vector
   return h;
 }
 
+// The three sparse products, on the CSR arrays with `lanes` lanes per row or
+// on the sliced-ELL copies (lanes == LANES_SELL).
+hipError_t spmv_a(const bc_ctx* c, hipStream_t st, int lanes, const double* x, double* y,
+                  const OuterState& S, bool skip_done) {
+  if (lanes == LANES_SELL) return launch_spmv_sell(st, c->sellA, c->spmv32, x, y, S, skip_done);
+  return launch_spmv(lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, x, y, S,
+                     skip_done);
+}
+hipError_t spmv_t(const bc_ctx* c, hipStream_t st, int lanes, const double* y, double* psi,
+                  const double* p, const OuterState& S) {
+  if (lanes == LANES_SELL) return launch_spmvT_dot_sell(st, c->sellT, c->spmv32, y, psi, p, S);
+  return launch_spmvT_dot(lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32, y,
+                          psi, p, S);
+}
+hipError_t residual_a(const bc_ctx* c, hipStream_t st, int lanes, const double* x, const double* f,
+                      double* s, const OuterState& S, const int* mask) {
+  if (lanes == LANES_SELL) return launch_residual_sell(st, c->sellA, x, f, s, S, mask);
+  return launch_residual(lanes, st, c->d_rowptr, c->d_col, c->d_val, x, f, s, S, mask);
+}
+
 bc_status autotune_lanes(bc_ctx* c, unsigned long long key) {
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
@@ -399,16 +464,17 @@ bc_status autotune_lanes(bc_ctx* c, unsigned long long key) {
   float best_a = 1e30f, best_t = 1e30f;
   int la = c->lanes, lt = c->lanesT;
   bc_status rc = BC_OK;
-  for (int L = 1; L <= 64 && rc == BC_OK; L *= 2) {
+  std::vector<int> cand;
+  for (int L = 1; L <= 64; L *= 2) cand.push_back(L);
+  if (c->have_sell) cand.push_back(LANES_SELL);
+  for (size_t ci = 0; ci < cand.size() && rc == BC_OK; ++ci) {
+    const int L = cand[ci];
     for (int which = 0; which < 2 && rc == BC_OK; ++which) {
       float ms = 0.f;
       for (int rep = 0; rep < 4; ++rep) {
         if (rep == 1 && hipEventRecord(e0, st) != hipSuccess) rc = BC_ERR_DEVICE;
-        hipError_t e = which == 0
-                           ? launch_spmv(L, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32,
-                                         c->d_p, c->d_u, S, false)
-                           : launch_spmvT_dot(L, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
-                                              c->spmv32, c->d_y, c->d_psi, c->d_p, S);
+        hipError_t e = which == 0 ? spmv_a(c, st, L, c->d_p, c->d_u, S, false)
+                                  : spmv_t(c, st, L, c->d_y, c->d_psi, c->d_p, S);
         if (e != hipSuccess) rc = BC_ERR_DEVICE;
       }
       if (rc != BC_OK || hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
@@ -687,7 +753,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   }
   c->ntiles = (int)tile_start.size();
   tile_start.push_back(n);
-  c->lanes = c->lanesT = o.spmv_lanes > 0 ? o.spmv_lanes : choose_lanes(nnz, n);
+  c->lanes = c->lanesT = o.spmv_lanes != 0 ? o.spmv_lanes : choose_lanes(nnz, n);
   std::vector<int> is_dense(c->nblk, 0);
   for (int b = 0; b < c->nblk; ++b) is_dense[b] = kind[b] == KIND_DENSE;
   // ---- inner-CG block data
@@ -789,6 +855,42 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     std::vector<float> v32(val.begin(), val.end()), t32(tval.begin(), tval.end());
     BC_TRY(A.upload(&c->d_val32, v32, st));
     BC_TRY(A.upload(&c->d_tval32, t32, st));
+  }
+  // sliced-ELL copies for the sparse products (a candidate of the autotuner,
+  // or requested with spmv_lanes = -1)
+  {
+    const bool force = o.spmv_lanes == LANES_SELL;
+    if (force || o.spmv_lanes == 0) {
+      std::vector<long long> pa, pt;
+      std::vector<int> wa, wt, ca, ct;
+      std::vector<double> va, vt;
+      if (build_sell(rowptr, col, val, tile_start, force, pa, wa, ca, va) &&
+          build_sell(tptr, trow, tval, tile_start, force, pt, wt, ct, vt)) {
+        long long *ppa, *ppt;
+        int *pwa, *pwt, *pca, *pct;
+        double *pva, *pvt;
+        BC_TRY(A.upload(&ppa, pa, st));
+        BC_TRY(A.upload(&pwa, wa, st));
+        BC_TRY(A.upload(&pca, ca, st));
+        BC_TRY(A.upload(&pva, va, st));
+        BC_TRY(A.upload(&ppt, pt, st));
+        BC_TRY(A.upload(&pwt, wt, st));
+        BC_TRY(A.upload(&pct, ct, st));
+        BC_TRY(A.upload(&pvt, vt, st));
+        c->sellA = SellMat{ppa, pwa, pca, pva, nullptr};
+        c->sellT = SellMat{ppt, pwt, pct, pvt, nullptr};
+        if (c->spmv32) {
+          std::vector<float> a32(va.begin(), va.end()), t32(vt.begin(), vt.end());
+          float *pa32, *pt32;
+          BC_TRY(A.upload(&pa32, a32, st));
+          BC_TRY(A.upload(&pt32, t32, st));
+          c->sellA.val32 = pa32;
+          c->sellT.val32 = pt32;
+        }
+        c->have_sell = true;
+        BC_HIP(hipStreamSynchronize(st));  // host staging vectors go out of scope
+      }
+    }
   }
   double* d_dsc;
   BC_TRY(A.upload(&d_dsc, dsc, st));
@@ -1197,9 +1299,10 @@ extern "C" bc_status bc_setup_batched(bc_ctx** ctx, int32_t nsys, const int32_t*
   }
   if (opts && (opts->projection < BC_PROJ_AUTO || opts->projection > BC_PROJ_BAND_CHOL ||
                opts->inner_tol < 0.0 || opts->inner_maxit < 1 || opts->dense_max_m < 0 ||
-               opts->stop_rule < 0 || opts->stop_rule > 1 || opts->spmv_lanes < 0 || opts->use_graph < 0 ||
-               opts->use_graph > 1 ||
-               (opts->spmv_lanes & (opts->spmv_lanes - 1)) || opts->spmv_lanes > 64)) {
+               opts->stop_rule < 0 || opts->stop_rule > 1 || opts->spmv_lanes < LANES_SELL ||
+               opts->use_graph < 0 || opts->use_graph > 1 ||
+               (opts->spmv_lanes > 0 && (opts->spmv_lanes & (opts->spmv_lanes - 1))) ||
+               opts->spmv_lanes > 64)) {
     bc_set_error("invalid option value");
     return BC_ERR_INVALID;
   }
@@ -1389,11 +1492,9 @@ extern "C" bc_status bc_project(bc_ctx* c, const double* v, double* Hv) {
   OuterState S = c->outer(0, 0);
   S.done = c->d_zero_flags;
   hipStream_t st = c->stream;
-  BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, v,
-                     c->d_u, S, false));
+  BC_HIP(spmv_a(c, st, c->lanes, v, c->d_u, S, false));
   BC_TRY(block_solves(c, c->d_u, c->d_y, nullptr));
-  BC_HIP(launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
-                          c->d_y, Hv, v, S));
+  BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, Hv, v, S));
   BC_TRY(leave(c, c->opts.stream));
   int* err = inner_err_flag();
   int h = 0;
@@ -1414,15 +1515,13 @@ namespace {
 // beta, p and the per-system bookkeeping.
 bc_status outer_iteration(bc_ctx* c, double* x, const OuterState& S, bool timed) {
   hipStream_t st = c->stream;
-  BC_HIP(launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, c->d_p,
-                     c->d_u, S, true));
+  BC_HIP(spmv_a(c, st, c->lanes, c->d_p, c->d_u, S, true));
   const bool keep = c->timing;
   c->timing = timed && keep;
   const bc_status rs = block_solves(c, c->d_u, c->d_y, c->d_done);
   c->timing = keep;
   BC_TRY(rs);
-  BC_HIP(launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
-                          c->d_y, c->d_psi, c->d_p, S));
+  BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, c->d_psi, c->d_p, S));
   BC_HIP(launch_update_xrs(st, x, c->d_r, c->d_s, c->d_p, c->d_psi, c->d_u, S));
   BC_HIP(launch_update_p(st, c->d_p, c->d_r, S));
   return BC_OK;
@@ -1465,14 +1564,12 @@ bc_status group_graph(bc_ctx* c, double* x, const OuterState& S, int G, bool* ra
     }
     bool ok = true;
     for (int q = 0; q < G && ok; ++q) {
-      ok = launch_spmv(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, c->d_p,
-                       c->d_u, S, true) == hipSuccess &&
+      ok = spmv_a(c, st, c->lanes, c->d_p, c->d_u, S, true) == hipSuccess &&
            launch_stamp(st, c->d_stamps, 2 * q) == hipSuccess &&
            launch_dense_apply(st, c->dense, c->mixed, c->d_u, c->d_y, c->d_done) == hipSuccess &&
            launch_band_apply(st, c->band, c->mixed, c->d_u, c->d_y, c->d_done) == hipSuccess &&
            launch_stamp(st, c->d_stamps, 2 * q + 1) == hipSuccess &&
-           launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
-                            c->spmv32, c->d_y, c->d_psi, c->d_p, S) == hipSuccess &&
+           spmv_t(c, st, c->lanesT, c->d_y, c->d_psi, c->d_p, S) == hipSuccess &&
            launch_update_xrs(st, x, c->d_r, c->d_s, c->d_p, c->d_psi, c->d_u, S) == hipSuccess &&
            launch_update_p(st, c->d_p, c->d_r, S) == hipSuccess;
     }
@@ -1534,8 +1631,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   // f in block order, x = x0 (or 0), s = f - A x
   BC_HIP(launch_gather(st, f, c->d_perm, c->d_f, n));
   if (x0) BC_HIP(launch_copy(st, x0, x, n)); else BC_HIP(launch_zero(st, x, n));
-  BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s, S,
-                         nullptr));
+  BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, nullptr));
   BC_HIP(launch_init_norms(st, c->d_f, c->d_s, x, c->d_part_f, S));
   BC_HIP(launch_set_thresholds(st, c->d_part_f, backward ? 0.0 : tol, S));
   BC_HIP(hipMemsetAsync(c->d_inner_total, 0, sizeof(unsigned long long), st));
@@ -1543,8 +1639,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   c->timing = true;
   // r = sum_i A_i^+ (f_i - A_i x0) = A^T D^{-1} s ; p = r
   BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
-  BC_HIP(launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32,
-                          c->d_y, c->d_r, c->d_p, S));
+  BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, c->d_r, c->d_p, S));
   BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S));
 
   // Outer iterations run in groups of G between host checks; with FP32
@@ -1582,12 +1677,10 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
       // With inner-CG projections the operator changes from one application
       // to the next, and CG always restarts with p = r: each cycle is then a
       // defect correction of x by replace_every CG steps.
-      BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s,
-                             S, nullptr));
+      BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, nullptr));
       if (c->spmv32) BC_HIP(launch_true_check(st, S));
       BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
-      BC_HIP(launch_spmvT_dot(c->lanesT, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32,
-                              c->spmv32, c->d_y, c->d_r, c->d_p, S));
+      BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, c->d_r, c->d_p, S));
       if (c->inner.nblk > 0) {
         BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S));
       } else {
@@ -1625,8 +1718,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
       }
     if (any) {
       BC_HIP(hipMemcpyAsync(c->d_mask, mask.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
-      BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s, S,
-                             c->d_mask));
+      BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, c->d_mask));
       std::vector<double> pc(c->ntiles), thr(ns);
       std::vector<int> st_h(c->ntiles + 1);
       BC_HIP(hipMemcpyAsync(pc.data(), c->d_part_c, c->ntiles * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1679,8 +1771,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats) {
     // true residuals and backward errors in FP64 from x, reduced on the device
-    BC_HIP(launch_residual(c->lanes, st, c->d_rowptr, c->d_col, c->d_val, x, c->d_f, c->d_s, S,
-                           nullptr));
+    BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, nullptr));
     BC_HIP(launch_init_norms(st, c->d_f, c->d_s, x, c->d_part_f, S));
     BC_HIP(launch_final_stats(st, c->d_part_f, S, c->d_final));
     std::vector<double> fin((size_t)5 * ns);

@@ -66,6 +66,24 @@ struct OuterState {
   int rec_stop;            // 1: k_update_p may stop on the recursively updated s
 };
 
+// Sliced-ELL copy of a sparse matrix for the sparse products (built when
+// its padding is modest): the rows of every tile are cut into slices of 64
+// consecutive rows, SELL_SLICES per tile (slice t * SELL_SLICES + j starts at
+// row tile_start[t] + 64 j; slices past the tile's end have width 0); entry
+// k of lane l of slice s is at ptr[s] + 64 k + l, in the row's stored order;
+// padding entries repeat the row's last column (or the tile's first index
+// for absent rows) with value 0.
+constexpr int SELL_SLICES = TILE / 64;
+struct SellMat {
+  const long long* ptr;   // ntiles * SELL_SLICES entry offsets
+  const int* wid;         // ntiles * SELL_SLICES widths
+  const int* col;
+  const double* val;
+  const float* val32;     // FP32 copy for FP32 products, else null
+};
+// `lanes` value that selects the sliced-ELL kernels
+constexpr int LANES_SELL = -1;
+
 // ---------------------------------------------------------- device helpers
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 
@@ -171,6 +189,12 @@ hipError_t launch_init_norms(hipStream_t st, const double* f, const double* s, c
                              double* part_f, const OuterState& S);
 hipError_t launch_final_stats(hipStream_t st, const double* part_f, const OuterState& S,
                               double* out);
+hipError_t launch_spmv_sell(hipStream_t st, const SellMat& A, bool mixed, const double* x,
+                            double* y, const OuterState& S, bool skip_done);
+hipError_t launch_spmvT_dot_sell(hipStream_t st, const SellMat& AT, bool mixed, const double* y,
+                                 double* psi, const double* p, const OuterState& S);
+hipError_t launch_residual_sell(hipStream_t st, const SellMat& A, const double* x, const double* f,
+                                double* s, const OuterState& S, const int* mask);
 hipError_t launch_gather(hipStream_t st, const double* src, const int* idx, double* dst, int n);
 hipError_t launch_sqnorm_tiles(hipStream_t st, const double* v, double* part, const OuterState& S);
 hipError_t launch_set_thresholds(hipStream_t st, const double* part_f, double tol, const OuterState& S);

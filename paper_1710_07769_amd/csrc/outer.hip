@@ -86,6 +86,122 @@ k_spmv(const int* __restrict__ rowptr, const int* __restrict__ col,
   }
 }
 
+// ---------------------------------------------------------- sliced ELL
+// The same three products on the sliced-ELL copies (SellMat): one workgroup
+// per tile, one wavefront per 64-row slice, one row per lane.  Every index
+// and value load of a wavefront is a contiguous 256- or 512-byte line.  A
+// lane sums its row's entries in their stored order, as the one-lane-per-row
+// CSR kernels do, in batches of 8 whose loads, then gathers, are issued
+// before the arithmetic; padding entries carry the value 0.
+constexpr int SELL_THREADS = 64 * SELL_SLICES;
+
+template <typename V, typename ACC>
+__device__ __forceinline__ ACC sell_row_sum(const int* __restrict__ col, const V* __restrict__ val,
+                                            const double* __restrict__ x, long long e, int w) {
+  ACC acc = (ACC)0;
+  int k0 = 0;
+  for (; k0 + 8 <= w; k0 += 8) {
+    int c[8];
+    V v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      c[q] = col[e + (long long)(k0 + q) * 64];
+      v[q] = val[e + (long long)(k0 + q) * 64];
+    }
+    ACC xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = (ACC)x[c[q]];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc += (ACC)v[q] * xv[q];
+  }
+  if (k0 < w) {
+    const int nb = w - k0;
+    int c[8];
+    V v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      c[q] = q < nb ? col[e + (long long)(k0 + q) * 64] : 0;
+      v[q] = q < nb ? val[e + (long long)(k0 + q) * 64] : (V)0;
+    }
+    ACC xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xv[q] = q < nb ? (ACC)x[c[q]] : (ACC)0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < nb) acc += (ACC)v[q] * xv[q];
+  }
+  return acc;
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(SELL_THREADS)
+k_spmv_sell(SellMat A, const double* __restrict__ x, double* __restrict__ y, OuterState S,
+            int skip_done) {
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (skip_done && S.done[sys]) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = t * SELL_SLICES + wave;
+  const int i = S.tile_start[t] + wave * 64 + lane;
+  const long long e = A.ptr[sl] + lane;
+  const int w = A.wid[sl];
+  if constexpr (MIXED) {
+    const float acc = sell_row_sum<float, float>(A.col, A.val32, x, e, w);
+    if (i < S.tile_start[t + 1]) y[i] = (double)acc;
+  } else {
+    const double acc = sell_row_sum<double, double>(A.col, A.val, x, e, w);
+    if (i < S.tile_start[t + 1]) y[i] = acc;
+  }
+}
+
+template <bool MIXED>
+__global__ void __launch_bounds__(SELL_THREADS)
+k_spmvT_dot_sell(SellMat AT, const double* __restrict__ y, double* __restrict__ psi,
+                 const double* __restrict__ p, OuterState S) {
+  __shared__ double sh[SELL_SLICES];
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (S.done[sys]) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = t * SELL_SLICES + wave;
+  const int j = S.tile_start[t] + wave * 64 + lane;
+  const long long e = AT.ptr[sl] + lane;
+  const int w = AT.wid[sl];
+  double acc;
+  if constexpr (MIXED)
+    acc = (double)sell_row_sum<float, float>(AT.col, AT.val32, y, e, w);
+  else
+    acc = sell_row_sum<double, double>(AT.col, AT.val, y, e, w);
+  double dot = 0.0;
+  if (j < S.tile_start[t + 1]) {
+    psi[j] = acc;
+    dot = p[j] * acc;
+  }
+  dot = block_sum(dot, sh);
+  if (threadIdx.x == 0) S.part_a[t] = dot;
+}
+
+__global__ void __launch_bounds__(SELL_THREADS)
+k_residual_sell(SellMat A, const double* __restrict__ x, const double* __restrict__ f,
+                double* __restrict__ s, OuterState S, const int* __restrict__ mask) {
+  __shared__ double sh[SELL_SLICES];
+  const int t = tile_of_block();
+  const int sys = S.tile_sys[t];
+  if (mask && !mask[sys]) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = t * SELL_SLICES + wave;
+  const int i = S.tile_start[t] + wave * 64 + lane;
+  const double acc = sell_row_sum<double, double>(A.col, A.val, x, A.ptr[sl] + lane, A.wid[sl]);
+  double ss = 0.0;
+  if (i < S.tile_start[t + 1]) {
+    const double v = f[i] - acc;
+    s[i] = v;
+    ss = v * v;
+  }
+  ss = block_sum(ss, sh);
+  if (threadIdx.x == 0) S.part_c[t] = ss;
+}
+
 // psi[j] = sum over column j of A of a_ij * y[i] (stored A^T), plus the
 // tile's partial of p . psi.
 template <int L, bool MIXED>
@@ -554,6 +670,35 @@ hipError_t launch_sqnorm_tiles(hipStream_t st, const double* v, double* part, co
 hipError_t launch_set_thresholds(hipStream_t st, const double* part_f, double tol,
                                  const OuterState& S) {
   hipLaunchKernelGGL(k_set_thresholds, dim3(S.nsys), dim3(64), 0, st, part_f, tol * tol, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_sell(hipStream_t st, const SellMat& A, bool mixed, const double* x,
+                            double* y, const OuterState& S, bool skip_done) {
+  if (mixed)
+    hipLaunchKernelGGL(k_spmv_sell<true>, dim3(S.ntiles), dim3(SELL_THREADS), 0, st, A, x, y, S,
+                       (int)skip_done);
+  else
+    hipLaunchKernelGGL(k_spmv_sell<false>, dim3(S.ntiles), dim3(SELL_THREADS), 0, st, A, x, y, S,
+                       (int)skip_done);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmvT_dot_sell(hipStream_t st, const SellMat& AT, bool mixed, const double* y,
+                                 double* psi, const double* p, const OuterState& S) {
+  if (mixed)
+    hipLaunchKernelGGL(k_spmvT_dot_sell<true>, dim3(S.ntiles), dim3(SELL_THREADS), 0, st, AT, y,
+                       psi, p, S);
+  else
+    hipLaunchKernelGGL(k_spmvT_dot_sell<false>, dim3(S.ntiles), dim3(SELL_THREADS), 0, st, AT, y,
+                       psi, p, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_sell(hipStream_t st, const SellMat& A, const double* x, const double* f,
+                                double* s, const OuterState& S, const int* mask) {
+  hipLaunchKernelGGL(k_residual_sell, dim3(S.ntiles), dim3(SELL_THREADS), 0, st, A, x, f, s, S,
+                     mask);
   return hipGetLastError();
 }
 
