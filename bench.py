@@ -49,6 +49,10 @@ def parse():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed", "mixed-proj"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--method", default="cg", choices=["cg", "alg1"],
+                    help="cg: Algorithm 2 (default); alg1: Algorithm 1 (plain block Cimmino) "
+                         "with omega = 2 / (lambda_min + lambda_max) of H estimated by Lanczos "
+                         "through bc_project before the timed solve")
     ap.add_argument("--compare", action="store_true",
                     help="also time plain FP64 on the same matrices (per system, one after "
                          "another, for a batch) and report the time-to-tolerance ratio")
@@ -115,7 +119,7 @@ class Workload:
         self.nnz = sum(q.A.nnz for q in self.problems)
 
 
-def run_step(wl, f_dev):
+def run_step(wl, f_dev, method="cg"):
     """One pass of the whole path; returns a dict of phase times and stats."""
     import torch
     import paper_1710_07769_amd as bc
@@ -154,10 +158,22 @@ def run_step(wl, f_dev):
         out["block_kinds"]["max_half_bandwidth"] = int(bw.max())
     try:
         x = torch.empty_like(f_dev)
-        t0 = time.perf_counter()
-        if wl.batched:
+        if method == "alg1":
+            # relaxation parameter from the spectrum of H (outside the timed solve)
+            from paper_1710_07769_amd.spectrum import spectrum_of
+            t0 = time.perf_counter()
+            spec = spectrum_of(ctx, wl.n, steps=40, seed=0)
+            out["lanczos_ms"] = (time.perf_counter() - t0) * 1e3
+            out["spectrum"] = {"lambda_min": spec.lambda_min, "lambda_max": spec.lambda_max,
+                               "omega": spec.omega_opt, "lanczos_steps": spec.steps}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = bc.bc_cimmino(ctx, f_dev, None, spec.omega_opt, wl.tol, 100000, x)
+        elif wl.batched:
+            t0 = time.perf_counter()
             sts = bc.bc_solve_batched(ctx, f_dev, None, wl.tol, 10000, x)
         else:
+            t0 = time.perf_counter()
             sts = [bc.bc_solve(ctx, f_dev, None, wl.tol, 10000, x)]
         torch.cuda.synchronize()
         out["solve_ms"] = (time.perf_counter() - t0) * 1e3
@@ -175,12 +191,14 @@ def run_step(wl, f_dev):
     return out
 
 
-def cpu_baseline(wl, iters):
+def cpu_baseline(wl, iters, omega=None):
     """The oracle timed on the host cores on a bounded sample of the workload:
     its projection setup for the whole system, then the first `iters` outer
-    iterations of its Algorithm 2 (tol = 0)."""
+    iterations of its Algorithm 2 (tol = 0), or of its Algorithm 1 with
+    relaxation `omega` when that is given."""
     import workloads as W
-    from oracle import BlockProjections, block_cimmino_cg, rip_graph, greedy_partition
+    from oracle import (BlockProjections, block_cimmino_cg, block_cimmino_plain, rip_graph,
+                        greedy_partition)
     q = wl.problems[0]
     if wl.partition == "greedy-rip":
         part = greedy_partition(rip_graph(q.A), q.K)
@@ -190,13 +208,17 @@ def cpu_baseline(wl, iters):
     t0 = time.perf_counter()
     B = BlockProjections(A, part, q.K)
     t1 = time.perf_counter()
-    block_cimmino_cg(A, q.f, part, q.K, tol=0.0, maxit=iters, proj=B)
+    if omega is None:
+        block_cimmino_cg(A, q.f, part, q.K, tol=0.0, maxit=iters, proj=B)
+    else:
+        block_cimmino_plain(A, q.f, part, q.K, omega=omega, tol=0.0, maxit=iters, proj=B)
     t2 = time.perf_counter()
     return {"value": iters / (t2 - t1), "unit": "outer iters/s", "cores": 1, "kind": "oracle",
             "sample": "%s: oracle projection setup (%.1f s, seminormal equations with SuperLU / "
-                      "LAPACK per block) then its first %d outer CG iterations (%.1f s); "
+                      "LAPACK per block) then its first %d %s iterations (%.1f s); "
                       "single-threaded SciPy; %d host cores visible"
-                      % (q.name, t1 - t0, iters, t2 - t1, len(os.sched_getaffinity(0)))}
+                      % (q.name, t1 - t0, iters, "outer CG" if omega is None else
+                         "Algorithm 1", t2 - t1, len(os.sched_getaffinity(0)))}
 
 
 def fp64_comparison(wl, f_dev, t_config_ms):
@@ -269,15 +291,17 @@ def main():
     f = torch.from_numpy(np.concatenate([q.f for q in wl.problems])).to(dev)
     print("[bench] workload %s: %s; n=%d nnz=%d" % (wl.name, wl.desc, wl.n, wl.nnz),
           file=sys.stderr, flush=True)
+    if args.method == "alg1" and wl.batched:
+        raise SystemExit("--method alg1 takes a single-system workload")
     for w in range(args.warmup):
-        r = run_step(wl, f)
+        r = run_step(wl, f, args.method)
         print("[bench] warmup %d: iters=%d solve=%.1f ms" % (w, r["iterations"], r["solve_ms"]),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T0 = time.perf_counter()
     runs = []
     for k in range(args.steps):
-        r = run_step(wl, f)
+        r = run_step(wl, f, args.method)
         runs.append(r)
         print("[bench] step %d: iters=%d solve=%.1f ms setup=%.1f ms rip=%.1f ms part=%.1f ms"
               % (k, r["iterations"], r["solve_ms"], r["setup_ms"], r["rip_ms"],
@@ -307,7 +331,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if wl.mixed else "f64",
         "data": "synthetic",
-        "config": {"workload": wl.desc, "n": wl.n, "nnz": wl.nnz,
+        "config": {"workload": wl.desc + ("; Algorithm 1 (plain block Cimmino)"
+                                          if args.method == "alg1" else ""),
+                   "n": wl.n, "nnz": wl.nnz,
                    "K": [q.K for q in wl.problems][0] if not wl.batched else 8,
                    "systems": len(wl.problems), "partition": wl.partition, "tol": wl.tol},
         "iterations": runs[-1]["iterations"],
@@ -335,11 +361,15 @@ def main():
                                  if wl.name in MEASURED_TRAFFIC and args.precision is None
                                  else None)},
     }
+    if args.method == "alg1":
+        line["spectrum"] = runs[-1]["spectrum"]
+        line["lanczos_ms"] = runs[-1]["lanczos_ms"]
     if args.compare:
         line["fp64_comparison"] = fp64_comparison(wl, f, line["time_to_tol_ms"])
     if not args.no_cpu_baseline and not wl.batched:
         print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(wl, args.cpu_iters)
+        line["cpu_baseline"] = cpu_baseline(
+            wl, args.cpu_iters, line["spectrum"]["omega"] if args.method == "alg1" else None)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

@@ -163,6 +163,19 @@ bc_status bc_solve(bc_ctx* ctx, const double* f, const double* x0, double tol,
 bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, double tol,
                            int32_t maxit, double* x, bc_stats* stats);
 
+/* Algorithm 1 (plain block Cimmino, Section 1, eq. (iterscheme)):
+ * x <- x + omega sum_i A_i^+ (f_i - A_i x), from x0 (device float64[n], or
+ * NULL for zero), until ||f - A x||_2 <= tol ||f||_2 (the residual of the
+ * current iterate, FP64, tested before each update) or maxit updates.  It
+ * converges for 0 < omega < 2 / lambda_max(H), fastest near
+ * omega = 2 / (lambda_min + lambda_max).  Works on single and batched
+ * contexts (f, x0, x concatenated; stats: host, nsys entries, may be NULL);
+ * the iteration count is the number of updates made.  The context's
+ * projections and precision are used; stop_rule must be BC_STOP_REL2.
+ * Returns the worst status over the systems, as bc_solve_batched. */
+bc_status bc_cimmino(bc_ctx* ctx, const double* f, const double* x0, double omega, double tol,
+                     int32_t maxit, double* x, bc_stats* stats);
+
 /* Sizes of a context: total order, number of systems and of blocks, and the
  * number of blocks using the dense Cholesky projection.  Any pointer may be NULL. */
 bc_status bc_info(const bc_ctx* ctx, int64_t* n_total, int32_t* nsys, int32_t* nblocks,

@@ -85,6 +85,8 @@ _SIGS = {
     "bc_project": (C.c_int, [_P, _P, _P]),
     "bc_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
     "bc_solve_batched": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
+    "bc_cimmino": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, _P,
+                             C.POINTER(bc_stats)]),
     "bc_info": (C.c_int, [_P, _I64P, _I32P, _I32P, _I32P]),
     "bc_block_info": (C.c_int, [_P, _I32P, _I32P]),
     "bc_schedule": (C.c_int, [_P, _I32P, _I32P]),
@@ -211,6 +213,16 @@ def bc_solve_batched(ctx, f, x0, tol: float, maxit: int, x) -> List[bc_stats]:
     return list(st)
 
 
+def bc_cimmino(ctx, f, x0, omega: float, tol: float, maxit: int, x) -> List[bc_stats]:
+    """Algorithm 1 (plain block Cimmino with relaxation omega); one stats entry per system."""
+    ns = bc_info(ctx)["nsys"]
+    st = (bc_stats * ns)()
+    s = _lib.bc_cimmino(ctx, _dev(f, "f"), None if x0 is None else _dev(x0, "x0"), float(omega),
+                        float(tol), int(maxit), _dev(x, "x"), st)
+    _check(s, "bc_cimmino", ok=(BC_OK, BC_NOT_CONVERGED, BC_ERR_BREAKDOWN))
+    return list(st)
+
+
 def bc_info(ctx) -> dict:
     n, ns, nb, nd = C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32()
     _check(_lib.bc_info(ctx, C.byref(n), C.byref(ns), C.byref(nb), C.byref(nd)), "bc_info")
@@ -326,6 +338,12 @@ class BlockCimmino:
         x = torch.empty_like(f)
         st = bc_solve(self.ctx, f, x0, tol, maxit, x)
         return x, st
+
+    def cimmino(self, f, omega, x0=None, tol=1e-10, maxit=10000):
+        """Algorithm 1 on this context: x, per-system stats."""
+        import torch
+        x = torch.empty_like(f)
+        return x, bc_cimmino(self.ctx, f, x0, omega, tol, maxit, x)
 
     def info(self):
         return bc_info(self.ctx)

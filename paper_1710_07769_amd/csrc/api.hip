@@ -1609,6 +1609,39 @@ bc_status harvest_graph_events(bc_ctx* c) {
   return BC_OK;
 }
 
+// Per-system statistics of a finished solve: the FP64 true residual of x and
+// the normwise backward error of eq. (stopping), reduced on the device.
+bc_status fill_stats(bc_ctx* c, double* x, const OuterState& S, const std::vector<int>& iters,
+                     const std::vector<int>& status, const std::vector<int>& replacements,
+                     double t_ms, double pbytes, unsigned long long inner_total, bc_stats* stats) {
+  hipStream_t st = c->stream;
+  const int ns = c->nsys;
+  BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, nullptr));
+  BC_HIP(launch_init_norms(st, c->d_f, c->d_s, x, c->d_part_f, S));
+  BC_HIP(launch_final_stats(st, c->d_part_f, S, c->d_final));
+  std::vector<double> fin((size_t)5 * ns);
+  BC_HIP(hipMemcpyAsync(fin.data(), c->d_final, fin.size() * sizeof(double), hipMemcpyDeviceToHost,
+                        st));
+  BC_HIP(hipStreamSynchronize(st));
+  for (int s2 = 0; s2 < ns; ++s2) {
+    const double ss = fin[5 * s2], ff = fin[5 * s2 + 1], smax = fin[5 * s2 + 2];
+    const double fmax = fin[5 * s2 + 3], x1 = fin[5 * s2 + 4];
+    bc_stats& q = stats[s2];
+    q.iterations = iters[s2];
+    q.status = status[s2];
+    q.rel_residual = ff > 0 ? std::sqrt(ss / ff) : 0.0;
+    const double den = c->normA_inf[s2] * x1 + fmax;
+    q.backward_err = den > 0 ? smax / den : 0.0;
+    q.t_solve_ms = t_ms;
+    q.t_proj_ms = c->t_proj_ms;
+    q.proj_launches = c->proj_launches;
+    q.proj_bytes = pbytes;
+    q.replacements = replacements[s2];
+    q.inner_iterations = (int64_t)inner_total;
+  }
+  return BC_OK;
+}
+
 bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, int maxit,
                      double* x, bc_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1769,32 +1802,88 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   }
   const double t_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-  if (stats) {
-    // true residuals and backward errors in FP64 from x, reduced on the device
-    BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, nullptr));
-    BC_HIP(launch_init_norms(st, c->d_f, c->d_s, x, c->d_part_f, S));
-    BC_HIP(launch_final_stats(st, c->d_part_f, S, c->d_final));
-    std::vector<double> fin((size_t)5 * ns);
-    BC_HIP(hipMemcpyAsync(fin.data(), c->d_final, fin.size() * sizeof(double),
-                          hipMemcpyDeviceToHost, st));
+  if (stats)
+    BC_TRY(fill_stats(c, x, S, iters, status, replacements, t_ms, pbytes, inner_total, stats));
+  BC_TRY(leave(c, o.stream));
+  int worst = BC_OK;
+  for (int s2 = 0; s2 < ns; ++s2) {
+    const int v = status[s2];
+    if (v < 0 && (worst >= 0 || v < worst)) worst = v;
+    else if (v > 0 && worst == BC_OK) worst = v;
+  }
+  return (bc_status)worst;
+}
+
+// Algorithm 1 (plain block Cimmino): per iteration s = f - A x in FP64, the
+// stop test on it, y_i = (A_i A_i^T)^{-1} s_i through the block projections,
+// and x += omega A^T y, i.e. x += omega sum_i A_i^+ (f_i - A_i x).  The
+// iteration count is the number of updates made (as for Algorithm 2).
+bc_status cimmino_impl(bc_ctx* c, const double* f, const double* x0, double omega, double tol,
+                       int maxit, double* x, bc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!f || !x || !(tol >= 0.0) || maxit < 0 || !(omega > 0.0) || !std::isfinite(omega)) {
+    bc_set_error("bc_cimmino: null f/x, negative tol or maxit, or omega not positive");
+    return BC_ERR_INVALID;
+  }
+  const bc_opts& o = c->opts;
+  if (o.stop_rule != BC_STOP_REL2) {
+    bc_set_error("bc_cimmino stops on the relative residual only (stop_rule BC_STOP_REL2)");
+    return BC_ERR_INVALID;
+  }
+  hipStream_t st = c->stream;
+  const int n = c->n_total, ns = c->nsys;
+  BC_TRY(enter(c, o.stream));
+  OuterState S = c->outer(maxit, 0);
+  BC_HIP(launch_gather(st, f, c->d_perm, c->d_f, n));
+  if (x0) BC_HIP(launch_copy(st, x0, x, n)); else BC_HIP(launch_zero(st, x, n));
+  BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, nullptr));
+  BC_HIP(launch_init_norms(st, c->d_f, c->d_s, x, c->d_part_f, S));
+  BC_HIP(launch_set_thresholds(st, c->d_part_f, tol, S));
+  BC_HIP(hipMemsetAsync(c->d_inner_total, 0, sizeof(unsigned long long), st));
+  BC_TRY(reset_proj_counters(c));
+  c->timing = true;
+  const int G = std::max(1, o.check_every);
+  std::vector<int> done(ns, 0), status(ns, 0), iters(ns, 0), replacements(ns, 0);
+  int passes = 0;
+  bool all_done = false;
+  while (!all_done) {
+    // one pass more than maxit updates: the last pass only tests the stop rule
+    for (int q = 0; q < G && passes <= maxit; ++q, ++passes) {
+      if (passes > 0) BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, nullptr));
+      BC_HIP(launch_cimmino_check(st, S));
+      BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
+      BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, c->d_psi, c->d_p, S));
+      BC_HIP(launch_cimmino_update(st, x, c->d_psi, omega, S));
+    }
+    BC_HIP(hipMemcpyAsync(done.data(), c->d_done, ns * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
-    for (int s2 = 0; s2 < ns; ++s2) {
-      const double ss = fin[5 * s2], ff = fin[5 * s2 + 1], smax = fin[5 * s2 + 2];
-      const double fmax = fin[5 * s2 + 3], x1 = fin[5 * s2 + 4];
-      bc_stats& q = stats[s2];
-      q.iterations = iters[s2];
-      q.status = status[s2];
-      q.rel_residual = ff > 0 ? std::sqrt(ss / ff) : 0.0;
-      const double den = c->normA_inf[s2] * x1 + fmax;
-      q.backward_err = den > 0 ? smax / den : 0.0;
-      q.t_solve_ms = t_ms;
-      q.t_proj_ms = c->t_proj_ms;
-      q.proj_launches = c->proj_launches;
-      q.proj_bytes = pbytes;
-      q.replacements = replacements[s2];
-      q.inner_iterations = (int64_t)inner_total;
+    harvest_proj_events(c);
+    all_done = passes > maxit || std::all_of(done.begin(), done.end(), [](int d) { return d != 0; });
+  }
+  BC_HIP(hipMemcpyAsync(iters.data(), c->d_iters, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  BC_HIP(hipMemcpyAsync(status.data(), c->d_status, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  unsigned long long inner_total = 0;
+  BC_HIP(hipMemcpyAsync(&inner_total, c->d_inner_total, sizeof(inner_total), hipMemcpyDeviceToHost, st));
+  BC_HIP(hipStreamSynchronize(st));
+  harvest_proj_events(c);
+  c->timing = false;
+  double pbytes = 0.0;
+  BC_TRY(proj_bytes(c, &pbytes));
+  for (int s2 = 0; s2 < ns; ++s2)
+    if (!done[s2]) status[s2] = BC_NOT_CONVERGED;
+  {
+    int* err = inner_err_flag();
+    int h = 0;
+    BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
+    if (h) {
+      bc_set_error("inner CG workgroups timed out waiting for each other");
+      return BC_ERR_DEVICE;
     }
   }
+  const double t_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats)
+    BC_TRY(fill_stats(c, x, S, iters, status, replacements, t_ms, pbytes, inner_total, stats));
   BC_TRY(leave(c, o.stream));
   int worst = BC_OK;
   for (int s2 = 0; s2 < ns; ++s2) {
@@ -1827,6 +1916,15 @@ extern "C" bc_status bc_solve_batched(bc_ctx* c, const double* f, const double* 
     return BC_ERR_INVALID;
   }
   return solve_impl(c, f, x0, tol, maxit, x, stats);
+}
+
+extern "C" bc_status bc_cimmino(bc_ctx* c, const double* f, const double* x0, double omega,
+                                double tol, int32_t maxit, double* x, bc_stats* stats) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  return cimmino_impl(c, f, x0, omega, tol, maxit, x, stats);
 }
 
 // ------------------------------------------------------- row inner-product graph

@@ -189,6 +189,9 @@ hipError_t launch_init_norms(hipStream_t st, const double* f, const double* s, c
                              double* part_f, const OuterState& S);
 hipError_t launch_final_stats(hipStream_t st, const double* part_f, const OuterState& S,
                               double* out);
+hipError_t launch_cimmino_check(hipStream_t st, const OuterState& S);
+hipError_t launch_cimmino_update(hipStream_t st, double* x, const double* psi, double omega,
+                                 const OuterState& S);
 hipError_t launch_spmv_sell(hipStream_t st, const SellMat& A, bool mixed, const double* x,
                             double* y, const OuterState& S, bool skip_done);
 hipError_t launch_spmvT_dot_sell(hipStream_t st, const SellMat& AT, bool mixed, const double* y,

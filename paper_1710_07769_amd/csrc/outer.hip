@@ -491,6 +491,41 @@ __global__ void k_final_stats(const double* __restrict__ part_f, OuterState S,
   }
 }
 
+// Algorithm 1, per system: the stop test on ||s||^2 of the current iterate
+// (tile partials part_c, fixed order), then the count of the update this
+// iteration makes; a system at maxit updates, or whose residual is not
+// finite, is finished.
+__global__ void k_cimmino_check(OuterState S) {
+  const int sys = blockIdx.x;
+  if (S.done[sys]) return;
+  const int a = S.sys_tile[sys], b = S.sys_tile[sys + 1];
+  const double ss = sys_sum_wave(S.part_c, a, b);
+  if (threadIdx.x == 0) {
+    if (ss <= S.thr[sys]) {
+      S.done[sys] = 1;
+      S.status[sys] = BC_OK;
+    } else if (!isfinite(ss)) {
+      S.done[sys] = 1;
+      S.status[sys] = BC_ERR_BREAKDOWN;
+    } else if (S.iters[sys] >= S.maxit) {
+      S.done[sys] = 1;
+      S.status[sys] = BC_NOT_CONVERGED;
+    } else {
+      S.iters[sys] += 1;
+    }
+  }
+}
+
+// Algorithm 1: x += omega psi (psi = sum_i A_i^+ s_i) on the systems not done.
+__global__ void __launch_bounds__(VEC_THREADS)
+k_cimmino_update(double* __restrict__ x, const double* __restrict__ psi, double omega,
+                 OuterState S) {
+  const int t = tile_of_block();
+  if (S.done[S.tile_sys[t]]) return;
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) x[i] += omega * psi[i];
+}
+
 // Tile partials of v.v (into part).
 __global__ void __launch_bounds__(VEC_THREADS)
 k_sqnorm_tiles(const double* __restrict__ v, double* __restrict__ part, OuterState S) {
@@ -699,6 +734,17 @@ hipError_t launch_residual_sell(hipStream_t st, const SellMat& A, const double* 
                                 double* s, const OuterState& S, const int* mask) {
   hipLaunchKernelGGL(k_residual_sell, dim3(S.ntiles), dim3(SELL_THREADS), 0, st, A, x, f, s, S,
                      mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_cimmino_check(hipStream_t st, const OuterState& S) {
+  hipLaunchKernelGGL(k_cimmino_check, dim3(S.nsys), dim3(64), 0, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_cimmino_update(hipStream_t st, double* x, const double* psi, double omega,
+                                 const OuterState& S) {
+  hipLaunchKernelGGL(k_cimmino_update, dim3(S.ntiles), dim3(VEC_THREADS), 0, st, x, psi, omega, S);
   return hipGetLastError();
 }
 

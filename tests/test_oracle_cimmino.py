@@ -139,3 +139,28 @@ def test_plain_block_cimmino():
     res_p = block_cimmino_plain(Am, p.f, p.part(), p.K, omega=1.0, tol=1e-6, maxit=20000, proj=B)
     res_c = block_cimmino_cg(Am, p.f, p.part(), p.K, tol=1e-6, proj=B)
     assert res_p.status == OK and res_p.iterations > res_c.iterations
+
+
+@pytest.mark.parametrize("omega", [0.7, 1.3])
+def test_plain_block_cimmino_error_recursion(omega):
+    # eq. (iterscheme): e^(t) = (I - omega H)^t e^(0), with H = sum_i pinv(A_i) A_i
+    # formed here from numpy's SVD-based pseudo-inverse of each dense block
+    # (independent of the oracle's QR / seminormal-equation projections)
+    n, K, t = 50, 4, 6
+    A = rand_sparse_nonsing(n, 0.08, 21)
+    part = rand_part(n, K, 21)
+    x_true = np.random.default_rng(5).standard_normal(n)
+    f = A @ x_true
+    Ad = A.toarray()
+    H = np.zeros((n, n))
+    for i in range(K):
+        Ai = Ad[part == i]
+        H += np.linalg.pinv(Ai) @ Ai
+    x0 = np.random.default_rng(6).standard_normal(n)
+    e = x0 - x_true
+    Qm = np.eye(n) - omega * H
+    for _ in range(t):
+        e = Qm @ e
+    res = block_cimmino_plain(A, f, part, K, omega=omega, x0=x0, tol=0.0, maxit=t)
+    assert res.iterations == t
+    assert np.linalg.norm(res.x - (x_true + e)) <= 1e-10 * np.linalg.norm(x_true)
