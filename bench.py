@@ -53,6 +53,10 @@ def parse():
                     help="cg: Algorithm 2 (default); alg1: Algorithm 1 (plain block Cimmino) "
                          "with omega = 2 / (lambda_min + lambda_max) of H estimated by Lanczos "
                          "through bc_project before the timed solve")
+    ap.add_argument("--spectrum", action="store_true",
+                    help="also compare the spectrum of H (Lanczos through bc_project) and the "
+                         "CG iteration count for contiguous and greedy rip_graph blocks of the "
+                         "workload's matrix")
     ap.add_argument("--compare", action="store_true",
                     help="also time plain FP64 on the same matrices (per system, one after "
                          "another, for a batch) and report the time-to-tolerance ratio")
@@ -188,6 +192,42 @@ def run_step(wl, f_dev, method="cg"):
     out["proj_bytes"] = sts[0].proj_bytes
     out["inner_iterations"] = sts[0].inner_iterations
     out["x"] = x
+    return out
+
+
+def spectrum_study(wl, f_dev, steps=60):
+    """Contiguous (uniform) against greedy rip_graph blocks of the same matrix
+    (Section 2, the paper's spectrum study): extreme Ritz values of H after
+    `steps` Lanczos steps through bc_project, kappa, the share of Ritz values
+    within 0.1 of 1, and the CG iterations and time to the workload's tol."""
+    import torch
+    import paper_1710_07769_amd as bc
+    import workloads as W
+    from paper_1710_07769_amd.spectrum import spectrum_of
+    q = wl.problems[0]
+    out = {}
+    for name in ("contiguous", "greedy-rip"):
+        if name == "contiguous":
+            part = W.blocks_to_part(W.contiguous_blocks(q.n, q.K))
+        else:
+            g = bc.rip_graph(q.n, q.A.rowptr, q.A.col, q.A.val)
+            part = bc.bc_partition_greedy(g, q.K)
+        ctx = bc.bc_setup(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, part, bc.make_opts(**wl.opts))
+        try:
+            sp = spectrum_of(ctx, q.n, steps=steps, seed=0)
+            x = torch.empty_like(f_dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = bc.bc_solve(ctx, f_dev, None, wl.tol, 10000, x)
+            torch.cuda.synchronize()
+            out[name] = {"lambda_min": sp.lambda_min, "lambda_max": sp.lambda_max,
+                         "kappa": sp.kappa, "lanczos_steps": sp.steps,
+                         "ritz_within_0.1_of_1": float(np.mean(np.abs(sp.ritz - 1.0) <= 0.1)),
+                         "cg_iterations": st.iterations,
+                         "time_to_tol_ms": (time.perf_counter() - t0) * 1e3}
+        finally:
+            bc.bc_destroy(ctx)
+        print("[bench] spectrum %s: %s" % (name, out[name]), file=sys.stderr, flush=True)
     return out
 
 
@@ -364,6 +404,10 @@ def main():
     if args.method == "alg1":
         line["spectrum"] = runs[-1]["spectrum"]
         line["lanczos_ms"] = runs[-1]["lanczos_ms"]
+    if args.spectrum:
+        if wl.batched:
+            raise SystemExit("--spectrum takes a single-system workload")
+        line["spectrum_study"] = spectrum_study(wl, f)
     if args.compare:
         line["fp64_comparison"] = fp64_comparison(wl, f, line["time_to_tol_ms"])
     if not args.no_cpu_baseline and not wl.batched:
