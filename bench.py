@@ -53,6 +53,9 @@ def parse():
                     help="cg: Algorithm 2 (default); alg1: Algorithm 1 (plain block Cimmino) "
                          "with omega = 2 / (lambda_min + lambda_max) of H estimated by Lanczos "
                          "through bc_project before the timed solve")
+    ap.add_argument("--partitioner", default="greedy", choices=["greedy", "multilevel"],
+                    help="partitioner of the rip_graph workloads (the configurations name the "
+                         "greedy one)")
     ap.add_argument("--spectrum", action="store_true",
                     help="also compare the spectrum of H (Lanczos through bc_project) and the "
                          "CG iteration count for contiguous and greedy rip_graph blocks of the "
@@ -123,7 +126,7 @@ class Workload:
         self.nnz = sum(q.A.nnz for q in self.problems)
 
 
-def run_step(wl, f_dev, method="cg"):
+def run_step(wl, f_dev, method="cg", partitioner="greedy"):
     """One pass of the whole path; returns a dict of phase times and stats."""
     import torch
     import paper_1710_07769_amd as bc
@@ -134,8 +137,10 @@ def run_step(wl, f_dev, method="cg"):
             t0 = time.perf_counter()
             g = bc.rip_graph(q.n, q.A.rowptr, q.A.col, q.A.val)
             t1 = time.perf_counter()
-            part = bc.bc_partition_greedy(g, q.K)
+            part = (bc.bc_partition_multilevel(g, q.K) if partitioner == "multilevel"
+                    else bc.bc_partition_greedy(g, q.K))
             t2 = time.perf_counter()
+            out["cutsize"], out["int_cut"] = bc.bc_partition_cut(g, part)
             out["rip_ms"] += (t1 - t0) * 1e3
             out["rip_spgemm_ms"] += bc.rip_graph_timing()["spgemm_ms"]
             out["partition_ms"] += (t2 - t1) * 1e3
@@ -196,7 +201,7 @@ def run_step(wl, f_dev, method="cg"):
 
 
 def spectrum_study(wl, f_dev, steps=60):
-    """Contiguous (uniform) against greedy rip_graph blocks of the same matrix
+    """Contiguous (uniform) against greedy and multilevel rip_graph blocks of the same matrix
     (Section 2, the paper's spectrum study): extreme Ritz values of H after
     `steps` Lanczos steps through bc_project, kappa, the share of Ritz values
     within 0.1 of 1, and the CG iterations and time to the workload's tol."""
@@ -206,12 +211,14 @@ def spectrum_study(wl, f_dev, steps=60):
     from paper_1710_07769_amd.spectrum import spectrum_of
     q = wl.problems[0]
     out = {}
-    for name in ("contiguous", "greedy-rip"):
+    g = bc.rip_graph(q.n, q.A.rowptr, q.A.col, q.A.val)
+    for name in ("contiguous", "greedy-rip", "multilevel-rip"):
         if name == "contiguous":
             part = W.blocks_to_part(W.contiguous_blocks(q.n, q.K))
-        else:
-            g = bc.rip_graph(q.n, q.A.rowptr, q.A.col, q.A.val)
+        elif name == "greedy-rip":
             part = bc.bc_partition_greedy(g, q.K)
+        else:
+            part = bc.bc_partition_multilevel(g, q.K)
         ctx = bc.bc_setup(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, part, bc.make_opts(**wl.opts))
         try:
             sp = spectrum_of(ctx, q.n, steps=steps, seed=0)
@@ -220,7 +227,8 @@ def spectrum_study(wl, f_dev, steps=60):
             t0 = time.perf_counter()
             st = bc.bc_solve(ctx, f_dev, None, wl.tol, 10000, x)
             torch.cuda.synchronize()
-            out[name] = {"lambda_min": sp.lambda_min, "lambda_max": sp.lambda_max,
+            out[name] = {"cutsize": bc.bc_partition_cut(g, part)[0],
+                         "lambda_min": sp.lambda_min, "lambda_max": sp.lambda_max,
                          "kappa": sp.kappa, "lanczos_steps": sp.steps,
                          "ritz_within_0.1_of_1": float(np.mean(np.abs(sp.ritz - 1.0) <= 0.1)),
                          "cg_iterations": st.iterations,
@@ -334,14 +342,14 @@ def main():
     if args.method == "alg1" and wl.batched:
         raise SystemExit("--method alg1 takes a single-system workload")
     for w in range(args.warmup):
-        r = run_step(wl, f, args.method)
+        r = run_step(wl, f, args.method, args.partitioner)
         print("[bench] warmup %d: iters=%d solve=%.1f ms" % (w, r["iterations"], r["solve_ms"]),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T0 = time.perf_counter()
     runs = []
     for k in range(args.steps):
-        r = run_step(wl, f, args.method)
+        r = run_step(wl, f, args.method, args.partitioner)
         runs.append(r)
         print("[bench] step %d: iters=%d solve=%.1f ms setup=%.1f ms rip=%.1f ms part=%.1f ms"
               % (k, r["iterations"], r["solve_ms"], r["setup_ms"], r["rip_ms"],
@@ -372,7 +380,9 @@ def main():
         "dtype": "f32+f64" if wl.mixed else "f64",
         "data": "synthetic",
         "config": {"workload": wl.desc + ("; Algorithm 1 (plain block Cimmino)"
-                                          if args.method == "alg1" else ""),
+                                          if args.method == "alg1" else "")
+                   + ("; multilevel partitioner" if args.partitioner == "multilevel"
+                      and wl.partition == "greedy-rip" else ""),
                    "n": wl.n, "nnz": wl.nnz,
                    "K": [q.K for q in wl.problems][0] if not wl.batched else 8,
                    "systems": len(wl.problems), "partition": wl.partition, "tol": wl.tol},
@@ -401,6 +411,8 @@ def main():
                                  if wl.name in MEASURED_TRAFFIC and args.precision is None
                                  else None)},
     }
+    if "cutsize" in runs[-1]:
+        line["partition_cutsize"] = runs[-1]["cutsize"]
     if args.method == "alg1":
         line["spectrum"] = runs[-1]["spectrum"]
         line["lanczos_ms"] = runs[-1]["lanczos_ms"]

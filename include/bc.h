@@ -248,6 +248,25 @@ bc_status rip_graph_timing(double* spgemm_ms, double* total_ms);
 bc_status bc_partition_greedy(int32_t n, const int64_t* rowptr, const int32_t* col,
                               const int64_t* wgt, int32_t K, int32_t passes, int32_t* part);
 
+/* Multilevel K-way partition of the same kind of graph (the multilevel
+ * scheme the paper's partitioner follows, Section 3.1, made deterministic):
+ *  1. Coarsening, while the graph has more than 30 K vertices (at most 30
+ *     levels, stopping when a level keeps more than 90% of the vertices):
+ *     vertices in ascending order, each unmatched one matched with the
+ *     unmatched neighbour of largest edge weight (ties: lower index) whose
+ *     combined vertex weight stays within ceil(n / (20 K)); coarse vertices
+ *     numbered in ascending order of their lower fine vertex; parallel edges
+ *     summed, internal edges dropped.
+ *  2. On the coarsest graph, the growth of bc_partition_greedy by vertex
+ *     weight: part k (k < K-1) grows until it weighs ceil(remaining weight /
+ *     parts left), leaving at least one vertex for each later part.
+ *  3. At every level from the coarsest to the original graph (after
+ *     projecting the parts down), the refinement sweeps of
+ *     bc_partition_greedy with vertex weights, W_max as there.
+ * Arguments and errors as bc_partition_greedy. */
+bc_status bc_partition_multilevel(int32_t n, const int64_t* rowptr, const int32_t* col,
+                                  const int64_t* wgt, int32_t K, int32_t passes, int32_t* part);
+
 /* Cutsize of a partition: sum of cost over cut edges, each undirected edge
  * once (eq. (partcut)), and the same sum over the integer weights.  Host arrays. */
 bc_status bc_partition_cut(int32_t n, const int64_t* rowptr, const int32_t* col,

@@ -17,8 +17,9 @@ Contents (each function cites the passage of the paper it follows):
 * :mod:`oracle.ripgraph`  - the row inner-product graph of Section 2.1 built
   from C = A A^T with the dense-column sparsification and integer edge
   weights of Section 2.3.
-* :mod:`oracle.partition` - the deterministic greedy K-way partitioner used in
-  place of METIS, cutsize / interIP (Section 2.2, Appendix A).
+* :mod:`oracle.partition` - the deterministic greedy and multilevel K-way
+  partitioners used in place of METIS, cutsize / interIP (Sections 2.2, 3.1,
+  Appendix A).
 
 Everything is float64 with plain NumPy/SciPy operations; no blocking, fusion
 or reordering beyond what the definitions state.
@@ -27,14 +28,14 @@ from .projection import QRProjector, CSNEProjector, BlockProjections
 from .cimmino import (block_cimmino_cg, block_cimmino_plain, backward_error,
                       CimminoResult, OK, NOT_CONVERGED, BREAKDOWN)
 from .ripgraph import rip_graph, rip_rows, row_norms, sparsify_columns, RipGraph
-from .partition import (greedy_partition, cutsize, int_cut, ip_matrix, imbalance,
-                        brute_force_min_cut, part_max_weight)
+from .partition import (greedy_partition, multilevel_partition, cutsize, int_cut, ip_matrix,
+                        imbalance, brute_force_min_cut, part_max_weight)
 
 __all__ = [
     "QRProjector", "CSNEProjector", "BlockProjections",
     "block_cimmino_cg", "block_cimmino_plain", "backward_error", "CimminoResult",
     "OK", "NOT_CONVERGED", "BREAKDOWN",
     "rip_graph", "rip_rows", "row_norms", "sparsify_columns", "RipGraph",
-    "greedy_partition", "cutsize", "int_cut", "ip_matrix", "imbalance",
+    "greedy_partition", "multilevel_partition", "cutsize", "int_cut", "ip_matrix", "imbalance",
     "brute_force_min_cut", "part_max_weight",
 ]

@@ -100,6 +100,161 @@ def greedy_partition(g, K: int, passes: int = 2) -> np.ndarray:
     return part.astype(np.int32)
 
 
+class _Graph:
+    """A level of the multilevel scheme: CSR with integer edge and vertex weights."""
+
+    def __init__(self, n, rowptr, col, wgt, vw):
+        self.n, self.rowptr, self.col, self.wgt, self.vw = n, rowptr, col, wgt, vw
+
+
+def _grow_weighted(G: _Graph, K: int) -> np.ndarray:
+    """Growth of greedy_partition by vertex weight: part k grows until it
+    weighs ceil(remaining weight / parts left), keeping one vertex for each
+    later part; largest connection first (ties to the lower index), else the
+    lowest-index unassigned vertex; part K-1 takes the rest."""
+    n = G.n
+    part = np.full(n, -1, dtype=np.int64)
+    conn = np.zeros(n, dtype=np.int64)
+    lowest = 0
+    rem_w = int(G.vw.sum())
+    rem_v = n
+    for k in range(K - 1):
+        target = -(-rem_w // (K - k))
+        heap, touched, wk = [], [], 0
+        while wk < target and rem_v > K - 1 - k:
+            v = -1
+            while heap:
+                negc, u = heapq.heappop(heap)
+                if part[u] == -1 and conn[u] == -negc:
+                    v = u
+                    break
+            if v == -1:
+                while part[lowest] != -1:
+                    lowest += 1
+                v = lowest
+            part[v] = k
+            wk += int(G.vw[v])
+            rem_v -= 1
+            for e in range(G.rowptr[v], G.rowptr[v + 1]):
+                u = int(G.col[e])
+                if part[u] == -1:
+                    if conn[u] == 0:
+                        touched.append(u)
+                    conn[u] += int(G.wgt[e])
+                    heapq.heappush(heap, (-int(conn[u]), u))
+        rem_w -= wk
+        for u in touched:
+            conn[u] = 0
+    part[part == -1] = K - 1
+    return part
+
+
+def _refine_weighted(G: _Graph, K: int, wmax: int, passes: int, part: np.ndarray) -> None:
+    """Refinement sweeps of greedy_partition with vertex weights (in place)."""
+    W = np.zeros(K, dtype=np.int64)
+    np.add.at(W, part, G.vw)
+    for _ in range(passes):
+        for v in range(G.n):
+            a = int(part[v])
+            if W[a] <= G.vw[v]:
+                continue
+            to = {}
+            for e in range(G.rowptr[v], G.rowptr[v + 1]):
+                q = int(part[G.col[e]])
+                to[q] = to.get(q, 0) + int(G.wgt[e])
+            inside = to.get(a, 0)
+            best_q, best_gain = -1, 0
+            for q in sorted(to):
+                if q == a or W[q] + G.vw[v] > wmax:
+                    continue
+                gain = to[q] - inside
+                if gain > best_gain:
+                    best_q, best_gain = q, gain
+            if best_q >= 0:
+                part[v] = best_q
+                W[a] -= G.vw[v]
+                W[best_q] += G.vw[v]
+
+
+def _coarsen(G: _Graph, maxvw: int):
+    """Heavy-edge matching in ascending vertex order (heaviest edge to an
+    unmatched neighbour within the vertex-weight cap, ties to the lower
+    index), then contraction: coarse vertices in ascending order of their
+    lower fine vertex, parallel edges summed, internal edges dropped.
+    Returns the coarse graph and the fine-to-coarse map."""
+    n = G.n
+    match = [-1] * n
+    for v in range(n):
+        if match[v] != -1:
+            continue
+        best, bw = -1, 0
+        for e in range(G.rowptr[v], G.rowptr[v + 1]):
+            u = int(G.col[e])
+            if match[u] != -1 or G.vw[v] + G.vw[u] > maxvw:
+                continue
+            w = int(G.wgt[e])
+            if w > bw or (w == bw and best >= 0 and u < best):
+                best, bw = u, w
+        if best >= 0:
+            match[v], match[best] = best, v
+        else:
+            match[v] = v
+    cmap = [-1] * n
+    first = []
+    for v in range(n):
+        if cmap[v] == -1:
+            cmap[v] = cmap[match[v]] = len(first)
+            first.append(v)
+    nc = len(first)
+    vw = np.zeros(nc, dtype=np.int64)
+    rowptr, col, wgt = [0], [], []
+    for c, a in enumerate(first):
+        members = [a] if match[a] == a else [a, match[a]]
+        vw[c] = sum(int(G.vw[x]) for x in members)
+        acc = {}
+        for x in members:
+            for e in range(G.rowptr[x], G.rowptr[x + 1]):
+                d = cmap[int(G.col[e])]
+                if d != c:
+                    acc[d] = acc.get(d, 0) + int(G.wgt[e])
+        for d in sorted(acc):
+            col.append(d)
+            wgt.append(acc[d])
+        rowptr.append(len(col))
+    C = _Graph(nc, np.array(rowptr, dtype=np.int64), np.array(col, dtype=np.int64),
+               np.array(wgt, dtype=np.int64), vw)
+    return C, np.array(cmap, dtype=np.int64)
+
+
+def multilevel_partition(g, K: int, passes: int = 2) -> np.ndarray:
+    """Deterministic multilevel K-way partition (heavy-edge coarsening while
+    the graph has more than 30 K vertices, weighted greedy growth on the
+    coarsest graph, refinement sweeps at every level on the way back);
+    returns int32 part[n].  The same specification as the library's host
+    implementation, written independently."""
+    n = g.n
+    if not (1 <= K <= n):
+        raise ValueError("need 1 <= K <= n")
+    wmax = part_max_weight(n, K)
+    coarse_to = max(30 * K, K)
+    maxvw = max(1, -(-n // (20 * K)))
+    levels = [_Graph(n, np.asarray(g.rowptr, dtype=np.int64), np.asarray(g.col, dtype=np.int64),
+                     np.asarray(g.wgt, dtype=np.int64), np.ones(n, dtype=np.int64))]
+    maps = []
+    while levels[-1].n > coarse_to and len(levels) < 30:
+        C, cmap = _coarsen(levels[-1], maxvw)
+        if C.n > 0.9 * levels[-1].n:
+            break
+        levels.append(C)
+        maps.append(cmap)
+    part = _grow_weighted(levels[-1], K)
+    _refine_weighted(levels[-1], K, wmax, passes, part)
+    for lvl in range(len(levels) - 2, -1, -1):
+        part = part[maps[lvl]]
+        _refine_weighted(levels[lvl], K, wmax, passes, part)
+    return part.astype(np.int32)
+
+
 def _edges_upper(g):
     rowptr = np.asarray(g.rowptr, dtype=np.int64)
     i = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(rowptr))

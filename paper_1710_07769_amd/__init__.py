@@ -98,6 +98,8 @@ _SIGS = {
     "rip_graph_timing": (C.c_int, [_DP, _DP]),
     "bc_partition_greedy": (C.c_int, [C.c_int32, _I64P, _I32P, _I64P, C.c_int32, C.c_int32,
                                       _I32P]),
+    "bc_partition_multilevel": (C.c_int, [C.c_int32, _I64P, _I32P, _I64P, C.c_int32, C.c_int32,
+                                          _I32P]),
     "bc_partition_cut": (C.c_int, [C.c_int32, _I64P, _I32P, _DP, _I64P, _I32P, _DP, _I64P]),
     "bc_status_str": (C.c_char_p, [C.c_int]),
     "bc_last_error": (C.c_char_p, []),
@@ -297,6 +299,17 @@ def bc_partition_greedy(g, K: int, passes: int = 2) -> np.ndarray:
     _check(_lib.bc_partition_greedy(int(g.n), _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32),
                                     _ptr(wgt, C.c_int64), int(K), int(passes),
                                     _ptr(part, C.c_int32)), "bc_partition_greedy")
+    return part
+
+
+def bc_partition_multilevel(g, K: int, passes: int = 2) -> np.ndarray:
+    rowptr = np.ascontiguousarray(g.rowptr, dtype=np.int64)
+    col = _i32(g.col)
+    wgt = np.ascontiguousarray(g.wgt, dtype=np.int64)
+    part = np.empty(g.n, dtype=np.int32)
+    _check(_lib.bc_partition_multilevel(int(g.n), _ptr(rowptr, C.c_int64), _ptr(col, C.c_int32),
+                                        _ptr(wgt, C.c_int64), int(K), int(passes),
+                                        _ptr(part, C.c_int32)), "bc_partition_multilevel")
     return part
 
 

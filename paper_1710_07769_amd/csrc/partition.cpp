@@ -144,3 +144,211 @@ extern "C" bc_status bc_partition_cut(int32_t n, const int64_t* rowptr, const in
   if (int_cut) *int_cut = ic;
   return BC_OK;
 }
+
+// ---------------------------------------------------------------- multilevel
+// Multilevel K-way partitioner on the same integer edge weights (coarsen by
+// heavy-edge matching, grow K parts on the coarsest graph, project back and
+// refine at every level).  The algorithm is specified in include/bc.h next to
+// bc_partition_multilevel; every choice is deterministic.
+namespace {
+
+struct Level {
+  int32_t n = 0;
+  std::vector<int64_t> rowptr;
+  std::vector<int32_t> col;
+  std::vector<int64_t> wgt;
+  std::vector<int64_t> vw;     // vertex weights
+  std::vector<int32_t> cmap;   // fine vertex -> coarse vertex (set on the finer level)
+};
+
+// heavy-edge matching and contraction of L into C (sets L.cmap)
+void coarsen(Level& L, Level& C, int64_t maxvw) {
+  const int32_t n = L.n;
+  std::vector<int32_t> match(n, -1);
+  for (int32_t v = 0; v < n; ++v) {
+    if (match[v] != -1) continue;
+    int32_t best = -1;
+    int64_t bw = 0;
+    for (int64_t e = L.rowptr[v]; e < L.rowptr[v + 1]; ++e) {
+      const int32_t u = L.col[e];
+      if (match[u] != -1 || L.vw[v] + L.vw[u] > maxvw) continue;
+      if (L.wgt[e] > bw || (L.wgt[e] == bw && best >= 0 && u < best)) {
+        best = u;
+        bw = L.wgt[e];
+      }
+    }
+    match[v] = best >= 0 ? best : v;
+    if (best >= 0) match[best] = v;
+  }
+  L.cmap.assign(n, -1);
+  int32_t nc = 0;
+  std::vector<int32_t> first;  // coarse vertex -> its lower fine vertex
+  for (int32_t v = 0; v < n; ++v) {
+    if (L.cmap[v] != -1) continue;
+    L.cmap[v] = nc;
+    L.cmap[match[v]] = nc;
+    first.push_back(v);
+    ++nc;
+  }
+  C.n = nc;
+  C.vw.assign(nc, 0);
+  C.rowptr.assign(1, 0);
+  C.col.clear();
+  C.wgt.clear();
+  std::vector<int64_t> acc(nc, 0);
+  std::vector<int32_t> seen;
+  for (int32_t c = 0; c < nc; ++c) {
+    const int32_t a = first[c], b = match[a];
+    C.vw[c] = L.vw[a] + (b != a ? L.vw[b] : 0);
+    seen.clear();
+    const int32_t members[2] = {a, b};
+    for (int t = 0; t < (b != a ? 2 : 1); ++t) {
+      const int32_t x = members[t];
+      for (int64_t e = L.rowptr[x]; e < L.rowptr[x + 1]; ++e) {
+        const int32_t d = L.cmap[L.col[e]];
+        if (d == c) continue;
+        if (acc[d] == 0) seen.push_back(d);
+        acc[d] += L.wgt[e];
+      }
+    }
+    std::sort(seen.begin(), seen.end());
+    for (int32_t d : seen) {
+      C.col.push_back(d);
+      C.wgt.push_back(acc[d]);
+      acc[d] = 0;
+    }
+    C.rowptr.push_back((int64_t)C.col.size());
+  }
+}
+
+// greedy growth of K parts by weight on L (the rule of bc_partition_greedy
+// with vertex weights)
+void grow(const Level& L, int32_t K, std::vector<int32_t>& p) {
+  const int32_t n = L.n;
+  p.assign(n, -1);
+  std::vector<int64_t> conn(n, 0);
+  std::vector<int32_t> touched;
+  int32_t lowest = 0;
+  int64_t rem_w = 0;
+  for (int32_t v = 0; v < n; ++v) rem_w += L.vw[v];
+  int32_t rem_v = n;
+  using Item = std::pair<int64_t, int32_t>;
+  auto cmp = [](const Item& a, const Item& b) {
+    if (a.first != b.first) return a.first < b.first;
+    return a.second > b.second;
+  };
+  for (int32_t k = 0; k < K - 1; ++k) {
+    const int64_t target = (rem_w + (K - k) - 1) / (K - k);
+    std::priority_queue<Item, std::vector<Item>, decltype(cmp)> heap(cmp);
+    touched.clear();
+    int64_t wk = 0;
+    while (wk < target && rem_v > K - 1 - k) {
+      int32_t v = -1;
+      while (!heap.empty()) {
+        const Item it = heap.top();
+        heap.pop();
+        if (p[it.second] == -1 && conn[it.second] == it.first) {
+          v = it.second;
+          break;
+        }
+      }
+      if (v == -1) {
+        while (p[lowest] != -1) ++lowest;
+        v = lowest;
+      }
+      p[v] = k;
+      wk += L.vw[v];
+      --rem_v;
+      for (int64_t e = L.rowptr[v]; e < L.rowptr[v + 1]; ++e) {
+        const int32_t u = L.col[e];
+        if (p[u] == -1) {
+          if (conn[u] == 0) touched.push_back(u);
+          conn[u] += L.wgt[e];
+          heap.push(Item(conn[u], u));
+        }
+      }
+    }
+    rem_w -= wk;
+    for (int32_t u : touched) conn[u] = 0;
+  }
+  for (int32_t v = 0; v < n; ++v)
+    if (p[v] == -1) p[v] = K - 1;
+}
+
+// refinement passes of bc_partition_greedy with vertex weights
+void refine(const Level& L, int32_t K, int64_t wmax, int32_t passes, std::vector<int32_t>& p) {
+  const int32_t n = L.n;
+  std::vector<int64_t> W(K, 0), to(K, 0);
+  for (int32_t v = 0; v < n; ++v) W[p[v]] += L.vw[v];
+  std::vector<int32_t> seen;
+  for (int32_t pass = 0; pass < passes; ++pass) {
+    for (int32_t v = 0; v < n; ++v) {
+      const int32_t a = p[v];
+      if (W[a] <= L.vw[v]) continue;
+      seen.clear();
+      for (int64_t e = L.rowptr[v]; e < L.rowptr[v + 1]; ++e) {
+        const int32_t q = p[L.col[e]];
+        if (to[q] == 0) seen.push_back(q);
+        to[q] += L.wgt[e];
+      }
+      std::sort(seen.begin(), seen.end());
+      const int64_t inside = to[a];
+      int32_t best = -1;
+      int64_t best_gain = 0;
+      for (int32_t q : seen) {
+        if (q == a || W[q] + L.vw[v] > wmax) continue;
+        const int64_t gain = to[q] - inside;
+        if (gain > best_gain) {
+          best = q;
+          best_gain = gain;
+        }
+      }
+      for (int32_t q : seen) to[q] = 0;
+      if (best >= 0) {
+        p[v] = best;
+        W[a] -= L.vw[v];
+        W[best] += L.vw[v];
+      }
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" bc_status bc_partition_multilevel(int32_t n, const int64_t* rowptr, const int32_t* col,
+                                             const int64_t* wgt, int32_t K, int32_t passes,
+                                             int32_t* part) {
+  if (!part || K < 1 || K > n || passes < 0 || !check_graph(n, rowptr, col, wgt) || !wgt) {
+    bc_set_error("bc_partition_multilevel: invalid graph, K or output");
+    return BC_ERR_INVALID;
+  }
+  const int64_t wmax = std::max<int64_t>((int64_t)std::floor(1.1 * n / K), ((int64_t)n + K - 1) / K);
+  const int64_t coarse_to = std::max<int64_t>(30LL * K, K);
+  const int64_t maxvw = std::max<int64_t>(1, ((int64_t)n + 20LL * K - 1) / (20LL * K));
+  std::vector<Level> lv(1);
+  lv[0].n = n;
+  lv[0].rowptr.assign(rowptr, rowptr + n + 1);
+  lv[0].col.assign(col, col + rowptr[n]);
+  lv[0].wgt.assign(wgt, wgt + rowptr[n]);
+  lv[0].vw.assign(n, 1);
+  while ((int64_t)lv.back().n > coarse_to && lv.size() < 30) {
+    Level C;
+    coarsen(lv.back(), C, maxvw);
+    if ((double)C.n > 0.9 * (double)lv.back().n) {
+      lv.back().cmap.clear();
+      break;
+    }
+    lv.push_back(std::move(C));
+  }
+  std::vector<int32_t> p;
+  grow(lv.back(), K, p);
+  refine(lv.back(), K, wmax, passes, p);
+  for (int l = (int)lv.size() - 2; l >= 0; --l) {
+    std::vector<int32_t> fine(lv[l].n);
+    for (int32_t v = 0; v < lv[l].n; ++v) fine[v] = p[lv[l].cmap[v]];
+    p.swap(fine);
+    refine(lv[l], K, wmax, passes, p);
+  }
+  std::copy(p.begin(), p.end(), part);
+  return BC_OK;
+}

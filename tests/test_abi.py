@@ -1,6 +1,6 @@
 """C-ABI checks that need no GPU: every declared symbol is exported, host-side
 validation rejects malformed input with BC_ERR_INVALID, and the library's
-host partitioner reproduces the oracle's greedy partitions bit for bit."""
+host partitioners reproduce the oracle's greedy and multilevel partitions bit for bit."""
 import ctypes as C
 import os
 import re
@@ -80,6 +80,19 @@ def test_library_partitioner_matches_oracle(maker, K):
     cs, ic = bc.bc_partition_cut(g, got)
     assert ic == int_cut(g, got)
     assert cs == pytest.approx(cutsize(g, got), rel=1e-12)
+
+
+@pytest.mark.parametrize("maker,K", [(workloads.config1, 4), (lambda: workloads.small_config2(N=12, K=6), 6),
+                                     (lambda: workloads.small_config5(N=8, K=5), 5),
+                                     (lambda: workloads.small_config3(n=3000, K=7), 7)])
+def test_library_multilevel_partitioner_matches_oracle(maker, K):
+    from oracle import multilevel_partition
+    p = maker()
+    g = oracle_rip(p.A)
+    for passes in (0, 2):
+        ref = multilevel_partition(g, K, passes=passes)
+        got = bc.bc_partition_multilevel(g, K, passes=passes)
+        assert np.array_equal(ref, got), passes
 
 
 def test_partitioner_rejects_bad_graphs():

@@ -151,3 +151,75 @@ def test_refinement_moves_positive_gain():
     g = graph_from_dense(W)
     assert greedy_partition(g, 3, passes=0).tolist() == [0, 0, 1, 1, 0, 2, 2, 2, 1, 0]
     assert greedy_partition(g, 3).tolist() == [0, 0, 1, 1, 0, 1, 2, 2, 1, 0]
+
+
+# ------------------------------------------------------------- multilevel
+
+from oracle import multilevel_partition  # noqa: E402
+from oracle.partition import _coarsen, _Graph  # noqa: E402
+
+
+@pytest.mark.parametrize("seed,n,K", [(0, 8, 2), (1, 9, 3), (3, 12, 3)])
+def test_multilevel_small_graph_is_greedy_and_not_below_brute_force(seed, n, K):
+    # n <= 30 K: no coarsening; the weighted growth with unit weights is the
+    # greedy growth, so the two partitioners coincide
+    rng = np.random.default_rng(seed)
+    W = np.triu(rng.integers(0, 4, (n, n)) * (rng.random((n, n)) < 0.5), 1)
+    g = graph_from_dense(W + W.T)
+    part = multilevel_partition(g, K)
+    assert np.array_equal(part, greedy_partition(g, K))
+    assert int_cut(g, part) >= brute_force_min_cut(g, K)
+
+
+def test_multilevel_separates_disjoint_cliques_through_coarsening():
+    K, s = 3, 60   # n = 180 > 30 K: two or more coarsening levels
+    W = np.zeros((K * s, K * s), dtype=np.int64)
+    perm = np.random.default_rng(9).permutation(K * s)
+    for k in range(K):
+        idx = perm[k * s:(k + 1) * s]
+        W[np.ix_(idx, idx)] = 2
+    np.fill_diagonal(W, 0)
+    g = graph_from_dense(W)
+    part = multilevel_partition(g, K)
+    assert int_cut(g, part) == 0
+    assert np.all(np.bincount(part, minlength=K) == s)
+
+
+def test_multilevel_on_a_path_gives_contiguous_segments():
+    n, K = 200, 4
+    W = np.zeros((n, n), dtype=np.int64)
+    for i in range(n - 1):
+        W[i, i + 1] = W[i + 1, i] = 1
+    g = graph_from_dense(W)
+    part = multilevel_partition(g, K)
+    assert np.all(np.diff(part) >= 0) and set(part.tolist()) == set(range(K))
+    assert np.bincount(part).max() <= part_max_weight(n, K)
+    assert int_cut(g, part) == K - 1
+
+
+def test_coarsening_invariants():
+    p = workloads.small_config2(N=10, K=4)
+    g = rip_graph(p.A)
+    G = _Graph(g.n, np.asarray(g.rowptr, dtype=np.int64), np.asarray(g.col, dtype=np.int64),
+               np.asarray(g.wgt, dtype=np.int64), np.ones(g.n, dtype=np.int64))
+    C, cmap = _coarsen(G, maxvw=3)
+    assert C.vw.sum() == g.n and C.vw.max() <= 3 and C.n < g.n
+    # edge weight is conserved except on the contracted (internal) edges
+    i = np.repeat(np.arange(g.n), np.diff(G.rowptr))
+    internal = cmap[i] == cmap[G.col]
+    assert C.wgt.sum() == G.wgt.sum() - G.wgt[internal].sum()
+    # the coarse graph is symmetric with positive weights and no loops
+    M = sp.csr_matrix((C.wgt, C.col, C.rowptr), shape=(C.n, C.n))
+    assert (M != M.T).nnz == 0 and M.diagonal().sum() == 0 and C.wgt.min() >= 1
+
+
+def test_multilevel_on_stencil_graph_is_balanced():
+    p = workloads.small_config2(N=12, K=6)
+    g = rip_graph(p.A)
+    part = multilevel_partition(g, p.K)
+    assert set(part.tolist()) == set(range(p.K))
+    assert np.bincount(part, minlength=p.K).max() <= part_max_weight(p.n, p.K)
+    contiguous = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, p.K))
+    print("cut greedy %.3f multilevel %.3f contiguous %.3f"
+          % (cutsize(g, greedy_partition(g, p.K)), cutsize(g, part), cutsize(g, contiguous)))
+    assert cutsize(g, part) <= cutsize(g, contiguous)
