@@ -60,6 +60,11 @@ def parse():
                     help="also compare the spectrum of H (Lanczos through bc_project) and the "
                          "CG iteration count for contiguous and greedy rip_graph blocks of the "
                          "workload's matrix")
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides of the single-system workload solved together by "
+                         "bc_solve_multi (vector 0: the workload's f, the others A times a "
+                         "seeded Gaussian vector); value then counts the outer iterations of "
+                         "every right-hand side")
     ap.add_argument("--compare", action="store_true",
                     help="also time plain FP64 on the same matrices (per system, one after "
                          "another, for a batch) and report the time-to-tolerance ratio")
@@ -126,8 +131,9 @@ class Workload:
         self.nnz = sum(q.A.nnz for q in self.problems)
 
 
-def run_step(wl, f_dev, method="cg", partitioner="greedy"):
-    """One pass of the whole path; returns a dict of phase times and stats."""
+def run_step(wl, f_dev, method="cg", partitioner="greedy", nrhs=1):
+    """One pass of the whole path; returns a dict of phase times and stats.
+    With nrhs > 1, f_dev holds nrhs right-hand sides (nrhs x n)."""
     import torch
     import paper_1710_07769_amd as bc
     out = {"rip_ms": 0.0, "rip_spgemm_ms": 0.0, "partition_ms": 0.0}
@@ -178,6 +184,9 @@ def run_step(wl, f_dev, method="cg", partitioner="greedy"):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sts = bc.bc_cimmino(ctx, f_dev, None, spec.omega_opt, wl.tol, 100000, x)
+        elif nrhs > 1:
+            t0 = time.perf_counter()
+            sts = bc.bc_solve_multi(ctx, nrhs, f_dev, None, wl.tol, 10000, x)
         elif wl.batched:
             t0 = time.perf_counter()
             sts = bc.bc_solve_batched(ctx, f_dev, None, wl.tol, 10000, x)
@@ -341,15 +350,25 @@ def main():
           file=sys.stderr, flush=True)
     if args.method == "alg1" and wl.batched:
         raise SystemExit("--method alg1 takes a single-system workload")
+    xstar = np.concatenate([q.xstar for q in wl.problems])
+    if args.nrhs > 1:
+        if wl.batched or args.method != "cg":
+            raise SystemExit("--nrhs takes a single-system workload and --method cg")
+        import workloads as W
+        q = wl.problems[0]
+        F, Xs = W.multi_rhs(q.A, args.nrhs, seed=1000)
+        F[0], Xs[0] = q.f, q.xstar
+        f = torch.from_numpy(np.ascontiguousarray(F)).to(dev)
+        xstar = Xs.reshape(-1)
     for w in range(args.warmup):
-        r = run_step(wl, f, args.method, args.partitioner)
+        r = run_step(wl, f, args.method, args.partitioner, args.nrhs)
         print("[bench] warmup %d: iters=%d solve=%.1f ms" % (w, r["iterations"], r["solve_ms"]),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     T0 = time.perf_counter()
     runs = []
     for k in range(args.steps):
-        r = run_step(wl, f, args.method, args.partitioner)
+        r = run_step(wl, f, args.method, args.partitioner, args.nrhs)
         runs.append(r)
         print("[bench] step %d: iters=%d solve=%.1f ms setup=%.1f ms rip=%.1f ms part=%.1f ms"
               % (k, r["iterations"], r["solve_ms"], r["setup_ms"], r["rip_ms"],
@@ -364,8 +383,7 @@ def main():
     launches = sum(r["proj_launches"] for r in runs)
     pbytes = sum(r["proj_bytes"] for r in runs)
     achieved = pbytes / (proj_ms / 1e3) / 1e9 if proj_ms > 0 else 0.0
-    xs = runs[-1]["x"].cpu().numpy()
-    xstar = np.concatenate([q.xstar for q in wl.problems])
+    xs = runs[-1]["x"].cpu().numpy().reshape(-1)
     line = {
         "metric": METRIC,
         "value": value,
@@ -382,7 +400,9 @@ def main():
         "config": {"workload": wl.desc + ("; Algorithm 1 (plain block Cimmino)"
                                           if args.method == "alg1" else "")
                    + ("; multilevel partitioner" if args.partitioner == "multilevel"
-                      and wl.partition == "greedy-rip" else ""),
+                      and wl.partition == "greedy-rip" else "")
+                   + ("; %d right-hand sides solved together (bc_solve_multi)" % args.nrhs
+                      if args.nrhs > 1 else ""),
                    "n": wl.n, "nnz": wl.nnz,
                    "K": [q.K for q in wl.problems][0] if not wl.batched else 8,
                    "systems": len(wl.problems), "partition": wl.partition, "tol": wl.tol},
@@ -409,10 +429,13 @@ def main():
                      "bytes_per_launch": pbytes / max(launches, 1),
                      "traffic": (MEASURED_TRAFFIC[wl.name]["bytes_per_launch"]
                                  if wl.name in MEASURED_TRAFFIC and args.precision is None
-                                 else None)},
+                                 and args.nrhs == 1 else None)},
     }
     if "cutsize" in runs[-1]:
         line["partition_cutsize"] = runs[-1]["cutsize"]
+    if args.nrhs > 1:
+        line["nrhs"] = args.nrhs
+        line["rhs_solves_per_s"] = args.nrhs / (line["time_to_tol_ms"] / 1e3)
     if args.method == "alg1":
         line["spectrum"] = runs[-1]["spectrum"]
         line["lanczos_ms"] = runs[-1]["lanczos_ms"]

@@ -163,6 +163,28 @@ bc_status bc_solve(bc_ctx* ctx, const double* f, const double* x0, double tol,
 bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, double tol,
                            int32_t maxit, double* x, bc_stats* stats);
 
+/* Algorithm 2 for nrhs right-hand sides of the one system of a bc_setup
+ * context (the same matrix A with several f: Section 3.1 names the
+ * multiple-right-hand-side case, and Section 3.5 notes that sequences of
+ * right-hand sides with one matrix amortize the partitioning cost further).
+ * Each right-hand side runs its
+ * own CG recurrence and stops on its own, exactly as one bc_solve with it
+ * would (same iterations and bits, given the same sparse-product schedule:
+ * spmv_lanes = -1); the right-hand sides share every read of A, A^T and the
+ * dense block factors: the sparse products take chunks of 4 vectors per
+ * matrix read, the dense triangular sweeps chunks of up to 8 per factor read.
+ * Banded and inner-CG blocks take the vectors one after another.
+ * f, x0 (or NULL for zero), x: device float64[nrhs * n], vector j at
+ * offset j * n (original row / column order, as bc_solve).  stats: host,
+ * nrhs entries, may be NULL.  Needs the sliced-ELL copies of A
+ * (bc_opts.spmv_lanes = -1, or 0 when their padding is modest); no
+ * hipGraph capture.  The per-vector state (8 n-vectors per right-hand side)
+ * is allocated on the first call with a given nrhs and kept until another
+ * nrhs or bc_destroy.  Returns the worst status, as bc_solve_batched;
+ * BC_ERR_INVALID for a batched context, nrhs < 1 or nrhs * n >= 2^31. */
+bc_status bc_solve_multi(bc_ctx* ctx, int32_t nrhs, const double* f, const double* x0,
+                         double tol, int32_t maxit, double* x, bc_stats* stats);
+
 /* Algorithm 1 (plain block Cimmino, Section 1, eq. (iterscheme)):
  * x <- x + omega sum_i A_i^+ (f_i - A_i x), from x0 (device float64[n], or
  * NULL for zero), until ||f - A x||_2 <= tol ||f||_2 (the residual of the

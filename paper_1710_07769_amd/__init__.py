@@ -87,6 +87,8 @@ _SIGS = {
     "bc_solve_batched": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
     "bc_cimmino": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, _P,
                              C.POINTER(bc_stats)]),
+    "bc_solve_multi": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, C.c_int32, _P,
+                                 C.POINTER(bc_stats)]),
     "bc_info": (C.c_int, [_P, _I64P, _I32P, _I32P, _I32P]),
     "bc_block_info": (C.c_int, [_P, _I32P, _I32P]),
     "bc_schedule": (C.c_int, [_P, _I32P, _I32P]),
@@ -212,6 +214,23 @@ def bc_solve_batched(ctx, f, x0, tol: float, maxit: int, x) -> List[bc_stats]:
     s = _lib.bc_solve_batched(ctx, _dev(f, "f"), None if x0 is None else _dev(x0, "x0"),
                               float(tol), int(maxit), _dev(x, "x"), st)
     _check(s, "bc_solve_batched", ok=(BC_OK, BC_NOT_CONVERGED, BC_ERR_BREAKDOWN))
+    return list(st)
+
+
+def bc_solve_multi(ctx, nrhs: int, f, x0, tol: float, maxit: int, x) -> List[bc_stats]:
+    """Algorithm 2 for nrhs right-hand sides of one system (f, x0, x: nrhs
+    concatenated vectors, e.g. (nrhs, n) tensors); one stats entry per
+    right-hand side."""
+    nrhs = int(nrhs)
+    if nrhs < 1:
+        raise ValueError("nrhs must be >= 1")
+    for t, name in ((f, "f"), (x, "x")) + (() if x0 is None else ((x0, "x0"),)):
+        if t.numel() != nrhs * bc_info(ctx)["n_total"]:
+            raise ValueError("%s must hold nrhs * n entries" % name)
+    st = (bc_stats * nrhs)()
+    s = _lib.bc_solve_multi(ctx, nrhs, _dev(f, "f"), None if x0 is None else _dev(x0, "x0"),
+                            float(tol), int(maxit), _dev(x, "x"), st)
+    _check(s, "bc_solve_multi", ok=(BC_OK, BC_NOT_CONVERGED, BC_ERR_BREAKDOWN))
     return list(st)
 
 
@@ -351,6 +370,13 @@ class BlockCimmino:
         x = torch.empty_like(f)
         st = bc_solve(self.ctx, f, x0, tol, maxit, x)
         return x, st
+
+    def solve_multi(self, F, X0=None, tol=1e-10, maxit=10000):
+        """Algorithm 2 for the rows of F (nrhs x n, one right-hand side per
+        row) at once: X (nrhs x n) and one stats entry per right-hand side."""
+        import torch
+        X = torch.empty_like(F)
+        return X, bc_solve_multi(self.ctx, F.shape[0], F, X0, tol, maxit, X)
 
     def cimmino(self, f, omega, x0=None, tol=1e-10, maxit=10000):
         """Algorithm 1 on this context: x, per-system stats."""

@@ -11,6 +11,7 @@
 #include <numeric>
 #include <cstdio>
 #include <string>
+#include <memory>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -263,6 +264,31 @@ struct SysIn {
   const int32_t* part;
 };
 
+// Per-vector state of a solve with several right-hand sides of a one-system
+// context: the context's per-system arrays, tiles and work vectors for nrhs
+// copies of its system.  swap_view exchanges them with the context's own for
+// the duration of the solve, so the outer iteration runs unchanged on nrhs
+// "systems" that share one matrix and one set of block factors.
+struct MultiView {
+  Arena arena;
+  int nrhs = 0;
+  int nsys = 0;
+  int n_total = 0;
+  std::vector<int> sys_off;
+  std::vector<double> normA_inf;
+  int* d_perm = nullptr;
+  int ntiles = 0;
+  int *d_tile_start = nullptr, *d_tile_sys = nullptr, *d_sys_tile = nullptr;
+  int *d_done = nullptr, *d_zero_flags = nullptr, *d_iters = nullptr, *d_status = nullptr;
+  int *d_pending = nullptr, *d_mask = nullptr, *d_restart = nullptr;
+  double *d_thr = nullptr, *d_rr = nullptr, *d_hist = nullptr;
+  double *d_part_a = nullptr, *d_part_b = nullptr, *d_part_c = nullptr, *d_part_f = nullptr;
+  double *d_part_d = nullptr, *d_part_e = nullptr, *d_part_g = nullptr;
+  double *d_final = nullptr, *d_normA = nullptr, *d_finf = nullptr;
+  double *d_r = nullptr, *d_p = nullptr, *d_psi = nullptr;
+  double *d_s = nullptr, *d_u = nullptr, *d_y = nullptr, *d_f = nullptr;
+};
+
 }  // namespace
 
 // ------------------------------------------------------------------ context
@@ -298,6 +324,8 @@ struct bc_ctx {
   float* d_tval32 = nullptr;
   bool have_sell = false;          // sliced-ELL copies of A and A^T built
   SellMat sellA{}, sellT{};
+  MultiRhs mrhs{};                 // nrhs > 0 while a multi-right-hand-side solve runs
+  std::unique_ptr<MultiView> mview;
   // tiles
   int ntiles = 0;
   int* d_tile_start = nullptr;
@@ -423,21 +451,27 @@ unsigned long long pattern_key(const std::vector<int>& rowptr, const std::vector
 }
 
 // The three sparse products, on the CSR arrays with `lanes` lanes per row or
-// on the sliced-ELL copies (lanes == LANES_SELL).
+// on the sliced-ELL copies (lanes == LANES_SELL); during a solve with several
+// right-hand sides, on the sliced-ELL copies for all vectors at once.
 hipError_t spmv_a(const bc_ctx* c, hipStream_t st, int lanes, const double* x, double* y,
                   const OuterState& S, bool skip_done) {
+  if (c->mrhs.nrhs > 0)
+    return launch_spmv_sell_multi(st, c->sellA, c->mrhs, c->spmv32, x, y, S, skip_done);
   if (lanes == LANES_SELL) return launch_spmv_sell(st, c->sellA, c->spmv32, x, y, S, skip_done);
   return launch_spmv(lanes, st, c->d_rowptr, c->d_col, c->d_val, c->d_val32, c->spmv32, x, y, S,
                      skip_done);
 }
 hipError_t spmv_t(const bc_ctx* c, hipStream_t st, int lanes, const double* y, double* psi,
                   const double* p, const OuterState& S) {
+  if (c->mrhs.nrhs > 0)
+    return launch_spmvT_dot_sell_multi(st, c->sellT, c->mrhs, c->spmv32, y, psi, p, S);
   if (lanes == LANES_SELL) return launch_spmvT_dot_sell(st, c->sellT, c->spmv32, y, psi, p, S);
   return launch_spmvT_dot(lanes, st, c->d_tptr, c->d_trow, c->d_tval, c->d_tval32, c->spmv32, y,
                           psi, p, S);
 }
 hipError_t residual_a(const bc_ctx* c, hipStream_t st, int lanes, const double* x, const double* f,
                       double* s, const OuterState& S, const int* mask) {
+  if (c->mrhs.nrhs > 0) return launch_residual_sell_multi(st, c->sellA, c->mrhs, x, f, s, S, mask);
   if (lanes == LANES_SELL) return launch_residual_sell(st, c->sellA, x, f, s, S, mask);
   return launch_residual(lanes, st, c->d_rowptr, c->d_col, c->d_val, x, f, s, S, mask);
 }
@@ -1414,9 +1448,23 @@ bc_status block_solves(bc_ctx* c, const double* u, double* y, const int* done) {
     }
     BC_HIP(hipEventRecord(c->ev_proj[2 * c->ev_used], st));
   }
-  BC_HIP(launch_dense_apply(st, c->dense, c->mixed, u, y, done));
-  BC_HIP(launch_band_apply(st, c->band, c->mixed, u, y, done));
-  BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u, y, done));
+  if (c->mrhs.nrhs > 0) {
+    // several right-hand sides: each dense factor is read once for a chunk
+    // of vectors; banded and inner-CG blocks take the vectors one by one
+    const int nr = c->mrhs.nrhs, n1 = c->mrhs.n1;
+    int max_nt = 0;
+    for (long long m : c->dn_m_h) max_nt = std::max(max_nt, (int)((m + DT - 1) / DT));
+    BC_HIP(launch_dense_apply_multi(st, c->dense, c->mixed, u, y, done, nr, n1, max_nt));
+    for (int j = 0; j < nr; ++j) {
+      const size_t o = (size_t)j * n1;
+      BC_HIP(launch_band_apply(st, c->band, c->mixed, u + o, y + o, done ? done + j : nullptr));
+      BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u + o, y + o, done ? done + j : nullptr));
+    }
+  } else {
+    BC_HIP(launch_dense_apply(st, c->dense, c->mixed, u, y, done));
+    BC_HIP(launch_band_apply(st, c->band, c->mixed, u, y, done));
+    BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u, y, done));
+  }
   if (c->timing) {
     BC_HIP(hipEventRecord(c->ev_proj[2 * c->ev_used + 1], st));
     ++c->ev_used;
@@ -1679,7 +1727,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   // projections G divides replace_every, so replacements fall between groups.
   int G = std::max(1, o.check_every);
   if (c->mixed && o.replace_every > 0) G = std::gcd(G, o.replace_every);
-  const bool graphs = o.use_graph && c->inner.nblk == 0 && !c->graph_off;
+  const bool graphs = o.use_graph && c->inner.nblk == 0 && !c->graph_off && c->mrhs.nrhs == 0;
   std::vector<int> done(ns, 0), status(ns, 0), iters(ns, 0);
   std::vector<int> verified(ns, 0), replacements(ns, 0);
   int it = 0;
@@ -1916,6 +1964,140 @@ extern "C" bc_status bc_solve_batched(bc_ctx* c, const double* f, const double* 
     return BC_ERR_INVALID;
   }
   return solve_impl(c, f, x0, tol, maxit, x, stats);
+}
+
+namespace {
+
+// Exchanges the per-system state of the context with that of the view.
+void swap_view(bc_ctx* c, MultiView& v) {
+  using std::swap;
+  swap(c->nsys, v.nsys);
+  swap(c->n_total, v.n_total);
+  swap(c->sys_off, v.sys_off);
+  swap(c->normA_inf, v.normA_inf);
+  swap(c->d_perm, v.d_perm);
+  swap(c->ntiles, v.ntiles);
+  swap(c->d_tile_start, v.d_tile_start);
+  swap(c->d_tile_sys, v.d_tile_sys);
+  swap(c->d_sys_tile, v.d_sys_tile);
+  swap(c->d_done, v.d_done);
+  swap(c->d_zero_flags, v.d_zero_flags);
+  swap(c->d_iters, v.d_iters);
+  swap(c->d_status, v.d_status);
+  swap(c->d_pending, v.d_pending);
+  swap(c->d_mask, v.d_mask);
+  swap(c->d_restart, v.d_restart);
+  swap(c->d_thr, v.d_thr);
+  swap(c->d_rr, v.d_rr);
+  swap(c->d_hist, v.d_hist);
+  swap(c->d_part_a, v.d_part_a);
+  swap(c->d_part_b, v.d_part_b);
+  swap(c->d_part_c, v.d_part_c);
+  swap(c->d_part_d, v.d_part_d);
+  swap(c->d_part_e, v.d_part_e);
+  swap(c->d_part_f, v.d_part_f);
+  swap(c->d_part_g, v.d_part_g);
+  swap(c->d_final, v.d_final);
+  swap(c->d_normA, v.d_normA);
+  swap(c->d_finf, v.d_finf);
+  swap(c->d_r, v.d_r);
+  swap(c->d_p, v.d_p);
+  swap(c->d_psi, v.d_psi);
+  swap(c->d_s, v.d_s);
+  swap(c->d_u, v.d_u);
+  swap(c->d_y, v.d_y);
+  swap(c->d_f, v.d_f);
+}
+
+// The per-vector state of nrhs right-hand sides of the context's one system
+// (kept for the next call with the same nrhs).
+bc_status build_view(bc_ctx* c, int nrhs) {
+  if (!c->mview) c->mview.reset(new MultiView());
+  MultiView& v = *c->mview;
+  if (v.nrhs == nrhs) return BC_OK;
+  BC_HIP(hipStreamSynchronize(c->stream));
+  v.arena.release();
+  v.nrhs = 0;
+  hipStream_t st = c->stream;
+  const int n1 = c->n_total, T1 = c->ntiles;
+  std::vector<int> ts1(T1 + 1), perm1(n1);
+  BC_HIP(hipMemcpy(ts1.data(), c->d_tile_start, ts1.size() * sizeof(int), hipMemcpyDeviceToHost));
+  BC_HIP(hipMemcpy(perm1.data(), c->d_perm, perm1.size() * sizeof(int), hipMemcpyDeviceToHost));
+  const size_t n = (size_t)n1 * nrhs, T = (size_t)T1 * nrhs;
+  std::vector<int> tile_start(T + 1), tile_sys(T), sys_tile(nrhs + 1), perm(n), zeros(nrhs, 0);
+  for (int j = 0; j < nrhs; ++j) {
+    for (int t = 0; t < T1; ++t) {
+      tile_start[(size_t)j * T1 + t] = j * n1 + ts1[t];
+      tile_sys[(size_t)j * T1 + t] = j;
+    }
+    sys_tile[j] = j * T1;
+    for (int i = 0; i < n1; ++i) perm[(size_t)j * n1 + i] = perm1[i] + j * n1;
+  }
+  tile_start[T] = (int)n;
+  sys_tile[nrhs] = (int)T;
+  v.nsys = nrhs;
+  v.n_total = (int)n;
+  v.ntiles = (int)T;
+  v.sys_off.resize(nrhs + 1);
+  for (int j = 0; j <= nrhs; ++j) v.sys_off[j] = j * n1;
+  v.normA_inf.assign(nrhs, c->normA_inf[0]);
+  Arena& A = v.arena;
+  BC_TRY(A.upload(&v.d_perm, perm, st));
+  BC_TRY(A.upload(&v.d_tile_start, tile_start, st));
+  BC_TRY(A.upload(&v.d_tile_sys, tile_sys, st));
+  BC_TRY(A.upload(&v.d_sys_tile, sys_tile, st));
+  BC_TRY(A.upload(&v.d_done, zeros, st));
+  BC_TRY(A.upload(&v.d_zero_flags, zeros, st));
+  BC_TRY(A.upload(&v.d_iters, zeros, st));
+  BC_TRY(A.upload(&v.d_status, zeros, st));
+  BC_TRY(A.upload(&v.d_pending, zeros, st));
+  BC_TRY(A.upload(&v.d_mask, zeros, st));
+  BC_TRY(A.upload(&v.d_restart, zeros, st));
+  BC_TRY(A.alloc(&v.d_thr, nrhs));
+  BC_TRY(A.alloc(&v.d_rr, 2 * (size_t)nrhs));
+  BC_TRY(A.alloc(&v.d_hist, nrhs));
+  for (double** q : {&v.d_part_a, &v.d_part_b, &v.d_part_c, &v.d_part_d, &v.d_part_e, &v.d_part_f,
+                     &v.d_part_g})
+    BC_TRY(A.alloc(q, T));
+  BC_TRY(A.alloc(&v.d_final, 5 * (size_t)nrhs));
+  BC_TRY(A.upload(&v.d_normA, v.normA_inf, st));
+  BC_TRY(A.alloc(&v.d_finf, nrhs));
+  for (double** q : {&v.d_r, &v.d_p, &v.d_psi, &v.d_s, &v.d_u, &v.d_y, &v.d_f})
+    BC_TRY(A.alloc(q, n));
+  BC_HIP(hipStreamSynchronize(st));  // host staging vectors go out of scope
+  v.nrhs = nrhs;
+  return BC_OK;
+}
+
+}  // namespace
+
+extern "C" bc_status bc_solve_multi(bc_ctx* c, int32_t nrhs, const double* f, const double* x0,
+                                    double tol, int32_t maxit, double* x, bc_stats* stats) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  if (c->nsys != 1) {
+    bc_set_error("bc_solve_multi needs a one-system context (bc_setup)");
+    return BC_ERR_INVALID;
+  }
+  if (nrhs < 1 || (long long)nrhs * c->n_total > INT32_MAX) {
+    bc_set_error("bc_solve_multi: nrhs must be >= 1 and nrhs * n below 2^31");
+    return BC_ERR_INVALID;
+  }
+  if (!c->have_sell) {
+    bc_set_error("bc_solve_multi needs the sliced-ELL copies of A (bc_opts.spmv_lanes = -1 "
+                 "builds them whatever their padding)");
+    return BC_ERR_INVALID;
+  }
+  BC_TRY(build_view(c, nrhs));
+  const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start};
+  swap_view(c, *c->mview);
+  c->mrhs = m;
+  const bc_status rc = solve_impl(c, f, x0, tol, maxit, x, stats);
+  c->mrhs = MultiRhs{};
+  swap_view(c, *c->mview);
+  return rc;
 }
 
 extern "C" bc_status bc_cimmino(bc_ctx* c, const double* f, const double* x0, double omega,

@@ -198,6 +198,23 @@ hipError_t launch_spmvT_dot_sell(hipStream_t st, const SellMat& AT, bool mixed, 
                                  double* psi, const double* p, const OuterState& S);
 hipError_t launch_residual_sell(hipStream_t st, const SellMat& A, const double* x, const double* f,
                                 double* s, const OuterState& S, const int* mask);
+// Multiple right-hand sides of one system: nrhs vectors of n1 entries,
+// concatenated; the one-vector tiling is tile_start (ntiles1 + 1 offsets).
+// The OuterState passed with it is that of nrhs systems of ntiles1 tiles.
+struct MultiRhs {
+  int nrhs;
+  int n1;
+  int ntiles1;
+  const int* tile_start;
+};
+hipError_t launch_spmv_sell_multi(hipStream_t st, const SellMat& A, const MultiRhs& M, bool mixed,
+                                  const double* x, double* y, const OuterState& S, bool skip_done);
+hipError_t launch_spmvT_dot_sell_multi(hipStream_t st, const SellMat& AT, const MultiRhs& M,
+                                       bool mixed, const double* y, double* psi, const double* p,
+                                       const OuterState& S);
+hipError_t launch_residual_sell_multi(hipStream_t st, const SellMat& A, const MultiRhs& M,
+                                      const double* x, const double* f, double* s,
+                                      const OuterState& S, const int* mask);
 hipError_t launch_gather(hipStream_t st, const double* src, const int* idx, double* dst, int n);
 hipError_t launch_sqnorm_tiles(hipStream_t st, const double* v, double* part, const OuterState& S);
 hipError_t launch_set_thresholds(hipStream_t st, const double* part_f, double tol, const OuterState& S);
@@ -279,6 +296,14 @@ hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);
 hipError_t launch_dense_apply(hipStream_t st, const DenseBlocks& D, bool mixed, const double* u,
                               double* y, const int* done);
+// The same apply to nrhs vectors at once (vector j at u + j*n1, y + j*n1;
+// done indexed by j), in chunks whose z fits the LDS of one workgroup;
+// max_nt: the largest tiles-per-side of the dense blocks.  Every vector gets
+// the bits of launch_dense_apply.
+constexpr size_t DENSE_MULTI_LDS = 160 * 1024;
+hipError_t launch_dense_apply_multi(hipStream_t st, const DenseBlocks& D, bool mixed,
+                                    const double* u, double* y, const int* done, int nrhs, int n1,
+                                    int max_nt);
 
 // Banded blocks: rows of the block in reverse Cuthill-McKee order, so that the
 // scaled normal-equation matrix G = D A_i A_i^T D has half-bandwidth bw.  The

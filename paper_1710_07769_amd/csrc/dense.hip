@@ -343,6 +343,120 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
   }
 }
 
+// The same sweeps for NR right-hand sides at once (grid.y walks chunks of NR
+// of the nrhs vectors, vector j at offset j * n1).  Each L, LT and inverse
+// element is loaded once and used for the NR vectors, whose sums run in the
+// order of k_dense_apply, so every vector gets the bits of a one-vector
+// apply.  z of the NR vectors sits in dynamic LDS as zs[row][NR]; the
+// diagonal-tile steps of vector q run on wavefront q % NW.
+template <typename T, int NR>
+__global__ void __launch_bounds__(APPLY_THREADS)
+k_dense_apply_multi(DenseBlocks D, const double* __restrict__ u, double* __restrict__ y,
+                    const int* __restrict__ done, int nrhs, int n1) {
+  extern __shared__ __align__(16) unsigned char dyn[];
+  constexpr int NW = APPLY_THREADS / 64;
+  const int b = blockIdx.x;
+  const int m = D.m[b], nt = D.nt[b], row0 = D.row0[b];
+  const int j0 = blockIdx.y * NR;
+  bool act[NR];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    act[q] = j0 + q < nrhs && !(done && done[j0 + q]);
+    any = any || act[q];
+  }
+  if (!any) return;
+  T* zs = (T*)dyn;                                  // nt * DT rows of NR
+  T* part = zs + (size_t)nt * DT * NR;              // [NW][NR][DT]
+  T* accs = part + (size_t)NW * NR * DT;            // [NR][DT]
+  const T* L;
+  const T* LT;
+  const T* Dv;
+  if constexpr (sizeof(T) == 8) {
+    L = (const T*)(D.L + D.loff[b]);
+    LT = (const T*)(D.LT + D.loff[b]);
+    Dv = (const T*)(D.Dinv + D.doff[b]);
+  } else {
+    L = (const T*)(D.L32 + D.loff[b]);
+    LT = (const T*)(D.LT32 + D.loff[b]);
+    Dv = (const T*)(D.Dinv32 + D.doff[b]);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) atomicAdd(&D.applies[b], 1ull);
+  // forward: z = L^{-1} u
+  for (int i = 0; i < nt; ++i) {
+    T acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = (T)0;
+    for (int j = w; j < i; j += NW) {
+      const T* tile = L + ltile(i, j);
+      const T* zj = zs + (size_t)j * DT * NR;
+#pragma unroll 4
+      for (int c = 0; c < DT; ++c) {
+        const T l = tile[c * DT + lane];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] += l * zj[c * NR + q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) part[(w * NR + q) * DT + lane] = acc[q];
+    __syncthreads();
+    const int gi = i * DT + lane;
+    for (int q = w; q < NR; q += NW) {
+      const int jr = j0 + q;
+      T a = (gi < m && act[q]) ? (T)(u[(size_t)jr * n1 + row0 + gi] * D.dsc[row0 + gi]) : (T)0;
+      for (int qq = 0; qq < NW; ++qq) a -= part[(qq * NR + q) * DT + lane];
+      accs[q * DT + lane] = a;
+    }
+    __syncthreads();
+    for (int q = w; q < NR; q += NW) {
+      const T* inv = Dv + (long long)i * TSZ;
+      const T* aq = accs + q * DT;
+      T s = (T)0;
+#pragma unroll 8
+      for (int c = 0; c < DT; ++c) s += inv[c * DT + lane] * aq[c];
+      zs[(size_t)gi * NR + q] = s;
+    }
+    __syncthreads();
+  }
+  // backward: y = L^{-T} z, overwriting zs tile by tile from the end
+  for (int i = nt - 1; i >= 0; --i) {
+    T acc[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = (T)0;
+    for (int j = i + 1 + w; j < nt; j += NW) {
+      const T* tile = LT + uttile(nt, i, j);
+      const T* yj = zs + (size_t)j * DT * NR;
+#pragma unroll 4
+      for (int c = 0; c < DT; ++c) {
+        const T l = tile[c * DT + lane];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc[q] += l * yj[c * NR + q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) part[(w * NR + q) * DT + lane] = acc[q];
+    __syncthreads();
+    const int gi = i * DT + lane;
+    for (int q = w; q < NR; q += NW) {
+      T a = zs[(size_t)gi * NR + q];
+      for (int qq = 0; qq < NW; ++qq) a -= part[(qq * NR + q) * DT + lane];
+      accs[q * DT + lane] = a;
+    }
+    __syncthreads();
+    for (int q = w; q < NR; q += NW) {
+      const T* invT = Dv + (long long)(nt + i) * TSZ;
+      const T* aq = accs + q * DT;
+      T s = (T)0;
+#pragma unroll 8
+      for (int c = 0; c < DT; ++c) s += invT[c * DT + lane] * aq[c];
+      zs[(size_t)gi * NR + q] = s;
+      if (gi < m && act[q]) y[(size_t)(j0 + q) * n1 + row0 + gi] = (double)s * D.dsc[row0 + gi];
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gram(hipStream_t st, const DenseBlocks& D, const int4* tiles, int ntiles,
@@ -368,6 +482,49 @@ hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed)
   if (D.nblk == 0) return hipSuccess;
   hipLaunchKernelGGL(k_dense_finish, dim3(64, D.nblk), dim3(256), 0, st, D, (int)mixed);
   return hipGetLastError();
+}
+
+// Dynamic LDS of k_dense_apply_multi for NR vectors and blocks of up to
+// max_nt tiles.
+size_t dense_multi_lds(int nr, int max_nt, bool mixed) {
+  return (size_t)(max_nt + 5) * DT * nr * (mixed ? sizeof(float) : sizeof(double));
+}
+
+template <typename T, int NR>
+hipError_t launch_dense_multi_nr(hipStream_t st, const DenseBlocks& D, const double* u, double* y,
+                                 const int* done, int nrhs, int n1, size_t lds) {
+  const void* fn = (const void*)k_dense_apply_multi<T, NR>;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_dense_apply_multi<T, NR>), dim3(D.nblk, (nrhs + NR - 1) / NR),
+                     dim3(APPLY_THREADS), lds, st, D, u, y, done, nrhs, n1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dense_multi_t(hipStream_t st, const DenseBlocks& D, const double* u, double* y,
+                                const int* done, int nrhs, int n1, int max_nt) {
+  // the widest chunk (at most 8, and at most the next power of two of nrhs)
+  // whose LDS fits in one workgroup
+  int nr = 8;
+  while (nr > 1 && (nr / 2 >= nrhs || dense_multi_lds(nr, max_nt, sizeof(T) == 4) > DENSE_MULTI_LDS))
+    nr /= 2;
+  const size_t lds = dense_multi_lds(nr, max_nt, sizeof(T) == 4);
+  switch (nr) {
+    case 8: return launch_dense_multi_nr<T, 8>(st, D, u, y, done, nrhs, n1, lds);
+    case 4: return launch_dense_multi_nr<T, 4>(st, D, u, y, done, nrhs, n1, lds);
+    case 2: return launch_dense_multi_nr<T, 2>(st, D, u, y, done, nrhs, n1, lds);
+    default: return launch_dense_multi_nr<T, 1>(st, D, u, y, done, nrhs, n1, lds);
+  }
+}
+
+hipError_t launch_dense_apply_multi(hipStream_t st, const DenseBlocks& D, bool mixed,
+                                    const double* u, double* y, const int* done, int nrhs, int n1,
+                                    int max_nt) {
+  if (D.nblk == 0 || nrhs <= 0) return hipSuccess;
+  if (dense_multi_lds(1, max_nt, mixed) > DENSE_MULTI_LDS) return hipErrorInvalidValue;
+  return mixed ? launch_dense_multi_t<float>(st, D, u, y, done, nrhs, n1, max_nt)
+               : launch_dense_multi_t<double>(st, D, u, y, done, nrhs, n1, max_nt);
 }
 
 hipError_t launch_dense_apply(hipStream_t st, const DenseBlocks& D, bool mixed, const double* u,

@@ -202,6 +202,177 @@ k_residual_sell(SellMat A, const double* __restrict__ x, const double* __restric
   if (threadIdx.x == 0) S.part_c[t] = ss;
 }
 
+// The three sliced-ELL products for nrhs vectors at once (multiple right-hand
+// sides).  The vectors are concatenated, vector j at offset j * n1, and the
+// per-vector state in S is that of nrhs systems of ntiles1 tiles each (tile t
+// of vector j is j * ntiles1 + t).  Grid: ntiles1 x chunks of NR vectors; the
+// index and value loads of a batch of 8 entries serve the chunk's vectors,
+// and each vector sums its row in the stored order, so it gets the bits of
+// the one-vector kernels above.
+template <typename V, typename ACC, int NR>
+__device__ __forceinline__ void sell_rows_multi(const int* __restrict__ col,
+                                                const V* __restrict__ val,
+                                                const double* __restrict__ x, long long n1,
+                                                int j0, const bool (&act)[NR], long long e, int w,
+                                                ACC (&acc)[NR]) {
+#pragma unroll
+  for (int q = 0; q < NR; ++q) acc[q] = (ACC)0;
+  for (int k0 = 0; k0 < w; k0 += 8) {
+    const int nb = min(8, w - k0);
+    int c[8];
+    V v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      c[r] = r < nb ? col[e + (long long)(k0 + r) * 64] : 0;
+      v[r] = r < nb ? val[e + (long long)(k0 + r) * 64] : (V)0;
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      if (!act[q]) continue;
+      const double* xq = x + (long long)(j0 + q) * n1;
+      ACC xv[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) xv[r] = r < nb ? (ACC)xq[c[r]] : (ACC)0;
+#pragma unroll
+      for (int r = 0; r < 8; ++r)
+        if (r < nb) acc[q] += (ACC)v[r] * xv[r];
+    }
+  }
+}
+
+// Per-vector block sums of NR values, each summed like block_sum.
+template <int NR>
+__device__ __forceinline__ void block_sum_multi(double (&v)[NR], double* sh) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) v[q] = wave_sum_lane0(v[q]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) sh[q * nw + w] = v[q];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    double t = 0.0;
+    for (int i = 0; i < nw; ++i) t += sh[q * nw + i];
+    v[q] = t;
+  }
+}
+
+template <int NR>
+__device__ __forceinline__ bool chunk_active(int j0, int nrhs, const int* flags, bool skip_if_set,
+                                             bool (&act)[NR]) {
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    act[q] = j0 + q < nrhs && !(flags && (flags[j0 + q] != 0) == skip_if_set);
+    any = any || act[q];
+  }
+  return any;
+}
+
+template <bool MIXED, int NR>
+__global__ void __launch_bounds__(SELL_THREADS)
+k_spmv_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x, double* __restrict__ y,
+                  OuterState S, int skip_done) {
+  const int t = blockIdx.x, j0 = blockIdx.y * NR;
+  bool act[NR];
+  if (!chunk_active<NR>(j0, M.nrhs, skip_done ? S.done : nullptr, true, act)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = t * SELL_SLICES + wave;
+  const int i = M.tile_start[t] + wave * 64 + lane;
+  const long long e = A.ptr[sl] + lane;
+  const int w = A.wid[sl];
+  const bool row = i < M.tile_start[t + 1];
+  if constexpr (MIXED) {
+    float acc[NR];
+    sell_rows_multi<float, float, NR>(A.col, A.val32, x, M.n1, j0, act, e, w, acc);
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (act[q] && row) y[(long long)(j0 + q) * M.n1 + i] = (double)acc[q];
+  } else {
+    double acc[NR];
+    sell_rows_multi<double, double, NR>(A.col, A.val, x, M.n1, j0, act, e, w, acc);
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (act[q] && row) y[(long long)(j0 + q) * M.n1 + i] = acc[q];
+  }
+}
+
+template <bool MIXED, int NR>
+__global__ void __launch_bounds__(SELL_THREADS)
+k_spmvT_dot_sell_multi(SellMat AT, MultiRhs M, const double* __restrict__ y,
+                       double* __restrict__ psi, const double* __restrict__ p, OuterState S) {
+  __shared__ double sh[NR * SELL_SLICES];
+  const int t = blockIdx.x, j0 = blockIdx.y * NR;
+  bool act[NR];
+  if (!chunk_active<NR>(j0, M.nrhs, S.done, true, act)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = t * SELL_SLICES + wave;
+  const int j = M.tile_start[t] + wave * 64 + lane;
+  const long long e = AT.ptr[sl] + lane;
+  const int w = AT.wid[sl];
+  const bool row = j < M.tile_start[t + 1];
+  double acc[NR];
+  if constexpr (MIXED) {
+    float a32[NR];
+    sell_rows_multi<float, float, NR>(AT.col, AT.val32, y, M.n1, j0, act, e, w, a32);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] = (double)a32[q];
+  } else {
+    sell_rows_multi<double, double, NR>(AT.col, AT.val, y, M.n1, j0, act, e, w, acc);
+  }
+  double dot[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    dot[q] = 0.0;
+    const long long o = (long long)(j0 + q) * M.n1 + j;
+    if (act[q] && row) {
+      psi[o] = acc[q];
+      dot[q] = p[o] * acc[q];
+    }
+  }
+  block_sum_multi<NR>(dot, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (act[q]) S.part_a[(j0 + q) * M.ntiles1 + t] = dot[q];
+}
+
+template <int NR>
+__global__ void __launch_bounds__(SELL_THREADS)
+k_residual_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x,
+                      const double* __restrict__ f, double* __restrict__ s, OuterState S,
+                      const int* __restrict__ mask) {
+  __shared__ double sh[NR * SELL_SLICES];
+  const int t = blockIdx.x, j0 = blockIdx.y * NR;
+  bool act[NR];
+  if (!chunk_active<NR>(j0, M.nrhs, mask, false, act)) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int sl = t * SELL_SLICES + wave;
+  const int i = M.tile_start[t] + wave * 64 + lane;
+  const bool row = i < M.tile_start[t + 1];
+  double acc[NR];
+  sell_rows_multi<double, double, NR>(A.col, A.val, x, M.n1, j0, act, A.ptr[sl] + lane, A.wid[sl],
+                                      acc);
+  double ss[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    ss[q] = 0.0;
+    const long long o = (long long)(j0 + q) * M.n1 + i;
+    if (act[q] && row) {
+      const double v = f[o] - acc[q];
+      s[o] = v;
+      ss[q] = v * v;
+    }
+  }
+  block_sum_multi<NR>(ss, sh);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+      if (act[q]) S.part_c[(j0 + q) * M.ntiles1 + t] = ss[q];
+}
+
 // psi[j] = sum over column j of A of a_ij * y[i] (stored A^T), plus the
 // tile's partial of p . psi.
 template <int L, bool MIXED>
@@ -769,5 +940,43 @@ hipError_t launch_copy(hipStream_t st, const double* src, double* dst, int n) {
 hipError_t launch_zero(hipStream_t st, double* dst, int n) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_zero, dim3((n + 255) / 256), dim3(256), 0, st, dst, n);
+  return hipGetLastError();
+}
+
+// Chunk width of the multi-vector sparse products: 4 vectors (8 entries'
+// indices and values plus 4 accumulators stay in registers at 1024 threads).
+constexpr int SELL_MULTI_NR = 4;
+
+hipError_t launch_spmv_sell_multi(hipStream_t st, const SellMat& A, const MultiRhs& M, bool mixed,
+                                  const double* x, double* y, const OuterState& S, bool skip_done) {
+  const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
+  if (mixed)
+    hipLaunchKernelGGL((k_spmv_sell_multi<true, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0, st,
+                       A, M, x, y, S, (int)skip_done);
+  else
+    hipLaunchKernelGGL((k_spmv_sell_multi<false, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0, st,
+                       A, M, x, y, S, (int)skip_done);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmvT_dot_sell_multi(hipStream_t st, const SellMat& AT, const MultiRhs& M,
+                                       bool mixed, const double* y, double* psi, const double* p,
+                                       const OuterState& S) {
+  const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
+  if (mixed)
+    hipLaunchKernelGGL((k_spmvT_dot_sell_multi<true, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0,
+                       st, AT, M, y, psi, p, S);
+  else
+    hipLaunchKernelGGL((k_spmvT_dot_sell_multi<false, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0,
+                       st, AT, M, y, psi, p, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual_sell_multi(hipStream_t st, const SellMat& A, const MultiRhs& M,
+                                      const double* x, const double* f, double* s,
+                                      const OuterState& S, const int* mask) {
+  const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
+  hipLaunchKernelGGL((k_residual_sell_multi<SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0, st, A, M,
+                     x, f, s, S, mask);
   return hipGetLastError();
 }

@@ -1,0 +1,209 @@
+"""Several right-hand sides of one system (``bc_solve_multi``) on the GPU
+(needs an MI355X).
+
+Bars:
+* each right-hand side of a multi solve ends with the iteration count, status
+  and iterate bits of a ``bc_solve`` of that right-hand side alone on the same
+  context (sliced-ELL products forced with spmv_lanes = -1, so both take the
+  same product schedule); this holds for dense FP64 and FP32-apply factors,
+  banded factors and inner-CG blocks, for chunks that leave a ragged tail and
+  for right-hand sides that stop at different iterations;
+* against the oracle (Algorithm 2 per right-hand side, FP64): the iteration
+  count (a difference of one only as a near-tie of the stop decision) and, at
+  the oracle's count, the iterate within 1e-8 relative (FP64 factors).
+"""
+import numpy as np
+import pytest
+
+import paper_1710_07769_amd as bc
+import workloads
+from oracle import block_cimmino_cg
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    return torch.device("cuda:0")
+
+
+def banner(msg):
+    print("\n[case] " + msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def st27(N, K):
+    p = workloads.small_config5(N=N, K=K)
+    return p, workloads.blocks_to_part(workloads.contiguous_blocks(p.n, K))
+
+
+def check_multi_equals_single(dev, p, part, K, nrhs, seed, tol=1e-10, maxit=5000, F=None,
+                              **opts):
+    """Multi solve vs one bc_solve per right-hand side: same iterations,
+    statuses and bits.  Returns (F, X, stats)."""
+    if F is None:
+        F, _ = workloads.multi_rhs(p.A, nrhs, seed)
+    solver = bc.BlockCimmino(p.A, part, K, spmv_lanes=-1, **opts)
+    try:
+        Fd = torch.from_numpy(F).to(dev)
+        X, sts = solver.solve_multi(Fd, tol=tol, maxit=maxit)
+        X = X.cpu().numpy()
+        assert len(sts) == nrhs
+        for j in range(nrhs):
+            x1, st1 = solver.solve(Fd[j].contiguous(), tol=tol, maxit=maxit)
+            x1 = x1.cpu().numpy()
+            print("rhs %d: iterations multi=%d single=%d status %d/%d rel_res=%.2e"
+                  % (j, sts[j].iterations, st1.iterations, sts[j].status, st1.status,
+                     sts[j].rel_residual))
+            assert sts[j].iterations == st1.iterations
+            assert sts[j].status == st1.status
+            assert np.array_equal(X[j], x1), "rhs %d: max diff %.3e" % (j, np.abs(X[j] - x1).max())
+            assert sts[j].rel_residual == st1.rel_residual
+        return F, X, sts
+    finally:
+        solver.close()
+
+
+def test_multi_dense_fp64_matches_single_and_oracle(dev):
+    banner("bc_solve_multi st27-10 K=6 dense FP64, 5 right-hand sides")
+    p, part = st27(10, 6)
+    F, X, sts = check_multi_equals_single(dev, p, part, 6, 5, seed=11,
+                                          projection=bc.BC_PROJ_DENSE_CHOL)
+    A = p.A.to_scipy()
+    for j in (0, 3):
+        ref = block_cimmino_cg(A, F[j], part, 6, tol=1e-10)
+        print("rhs %d: oracle iterations %d" % (j, ref.iterations))
+        assert sts[j].status == bc.BC_OK and abs(sts[j].iterations - ref.iterations) <= 1
+        if sts[j].iterations != ref.iterations:
+            t = min(sts[j].iterations, ref.iterations)
+            assert abs(ref.history[t] - 1e-10) <= 1e-3 * 1e-10
+    # at the oracle's count, the iterates agree
+    solver = bc.BlockCimmino(p.A, part, 6, spmv_lanes=-1, projection=bc.BC_PROJ_DENSE_CHOL)
+    try:
+        ref0 = block_cimmino_cg(A, F[0], part, 6, tol=1e-10)
+        Xd, sts2 = solver.solve_multi(torch.from_numpy(F).to(dev), tol=0.0, maxit=ref0.iterations)
+        Xd = Xd.cpu().numpy()
+        for j in (0, 3):
+            refj = block_cimmino_cg(A, F[j], part, 6, tol=0.0, maxit=ref0.iterations)
+            assert sts2[j].iterations == ref0.iterations
+            err = rel(Xd[j], refj.x)
+            print("rhs %d at %d iterations: rel_err vs oracle %.3e" % (j, ref0.iterations, err))
+            assert err <= 1e-8
+    finally:
+        solver.close()
+
+
+@pytest.mark.parametrize("nrhs", [1, 2, 9])
+def test_multi_dense_fp32_applies_ragged_chunks(dev, nrhs):
+    banner("bc_solve_multi st27-10 K=6 FP32 dense applies, %d right-hand sides" % nrhs)
+    p, part = st27(10, 6)
+    check_multi_equals_single(dev, p, part, 6, nrhs, seed=12, projection=bc.BC_PROJ_DENSE_CHOL,
+                              precision=bc.BC_MIXED_PROJ)
+
+
+def test_multi_banded(dev):
+    banner("bc_solve_multi st27-8 K=8 banded FP64, 3 right-hand sides")
+    p, part = st27(8, 8)
+    check_multi_equals_single(dev, p, part, 8, 3, seed=13, projection=bc.BC_PROJ_BAND_CHOL)
+
+
+def test_multi_inner_cg(dev):
+    banner("bc_solve_multi cd3d-12 K=4 inner CG FP64, 2 right-hand sides")
+    p = workloads.small_config2(N=12, K=4)
+    part = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, 4))
+    check_multi_equals_single(dev, p, part, 4, 2, seed=14, projection=bc.BC_PROJ_INNER_CG)
+
+
+def test_multi_stops_independently(dev):
+    banner("bc_solve_multi: zero, exact and ordinary right-hand sides stop on their own")
+    p, part = st27(8, 4)
+    F, _ = workloads.multi_rhs(p.A, 4, 15)
+    F[1] = 0.0            # f = 0: converged before any iteration
+    F[2] = 1e-3 * F[3]    # a scaled copy: the same iterations as F[3]
+    F = np.ascontiguousarray(F)
+    _, X, sts = check_multi_equals_single(dev, p, part, 4, 4, seed=0, F=F,
+                                          projection=bc.BC_PROJ_DENSE_CHOL)
+    assert sts[1].iterations == 0 and sts[1].status == bc.BC_OK
+    assert float(np.abs(X[1]).max()) == 0.0
+    assert sts[0].iterations > 0 and sts[3].iterations > 0
+
+
+def test_multi_maxit_and_x0(dev):
+    banner("bc_solve_multi: maxit, tol = 0 and a starting guess")
+    p, part = st27(8, 4)
+    F, Xs = workloads.multi_rhs(p.A, 3, 16)
+    solver = bc.BlockCimmino(p.A, part, 4, spmv_lanes=-1, projection=bc.BC_PROJ_DENSE_CHOL)
+    try:
+        Fd = torch.from_numpy(F).to(dev)
+        X, sts = solver.solve_multi(Fd, tol=0.0, maxit=4)
+        assert all(s.iterations == 4 and s.status == bc.BC_NOT_CONVERGED for s in sts)
+        X0 = torch.from_numpy(np.ascontiguousarray(Xs)).to(dev)
+        X2, sts2 = solver.solve_multi(Fd, X0=X0, tol=1e-10)
+        assert all(s.iterations == 0 and s.status == bc.BC_OK for s in sts2)
+        assert np.array_equal(X2.cpu().numpy(), Xs)
+        # a different nrhs on the same context re-sizes the per-vector state
+        X3, sts3 = solver.solve_multi(Fd[:2].contiguous(), tol=0.0, maxit=4)
+        assert np.array_equal(X3.cpu().numpy(), X.cpu().numpy()[:2])
+        for j in range(3):
+            x1, st1 = solver.solve(Fd[j].contiguous(), tol=0.0, maxit=4)
+            assert np.array_equal(x1.cpu().numpy(), X.cpu().numpy()[j])
+    finally:
+        solver.close()
+
+
+def test_multi_rejects_bad_calls(dev):
+    banner("bc_solve_multi argument errors")
+    cases = [st27(6, 3) + (3,), st27(8, 4) + (4,)]
+    batched = bc.BlockCimminoBatched([(p.A, part, K) for p, part, K in cases],
+                                     projection=bc.BC_PROJ_DENSE_CHOL)
+    try:
+        n = batched.n
+        f = torch.zeros(2 * n, dtype=torch.float64, device=dev)
+        x = torch.empty_like(f)
+        with pytest.raises(bc.BCError):
+            bc.bc_solve_multi(batched.ctx, 2, f, None, 1e-10, 10, x)
+    finally:
+        batched.close()
+    p, part = st27(6, 3)
+    solver = bc.BlockCimmino(p.A, part, 3, spmv_lanes=-1, projection=bc.BC_PROJ_DENSE_CHOL)
+    try:
+        f = torch.zeros(p.n, dtype=torch.float64, device=dev)
+        x = torch.empty_like(f)
+        with pytest.raises(ValueError):
+            bc.bc_solve_multi(solver.ctx, 0, f, None, 1e-10, 10, x)
+        with pytest.raises(ValueError):
+            bc.bc_solve_multi(solver.ctx, 2, f, None, 1e-10, 10, x)
+        # the C entry point itself refuses nrhs < 1
+        import ctypes
+        rc = bc._lib.bc_solve_multi(solver.ctx, 0, ctypes.c_void_p(f.data_ptr()), None, 1e-10, 10,
+                                    ctypes.c_void_p(x.data_ptr()), None)
+        assert rc == bc.BC_ERR_INVALID
+    finally:
+        solver.close()
+
+
+def test_multi_fullsize_st27_100cubed(dev):
+    banner("bc_solve_multi st27-100 n=1e6 K=512 FP32 dense applies, 8 right-hand sides; "
+           "2 of them against bc_solve")
+    p = workloads.config5()
+    part = p.part()
+    F, _ = workloads.multi_rhs(p.A, 8, 17)
+    solver = bc.BlockCimmino(p.A, part, p.K, spmv_lanes=-1, projection=bc.BC_PROJ_DENSE_CHOL,
+                             precision=bc.BC_MIXED_PROJ)
+    try:
+        Fd = torch.from_numpy(F).to(dev)
+        X, sts = solver.solve_multi(Fd, tol=1e-10, maxit=2000)
+        print("iterations", [s.iterations for s in sts], "t_solve_ms %.1f" % sts[0].t_solve_ms)
+        assert all(s.status == bc.BC_OK and s.rel_residual <= 1e-10 * (1 + 1e-6) for s in sts)
+        for j in (0, 7):
+            x1, st1 = solver.solve(Fd[j].contiguous(), tol=1e-10, maxit=2000)
+            assert st1.iterations == sts[j].iterations
+            assert torch.equal(x1, X[j])
+    finally:
+        solver.close()

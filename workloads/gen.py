@@ -225,6 +225,21 @@ def powerlaw(n: int, rng: np.random.Generator, lmin=5, lmax=400, mean=20.0) -> C
 
 # ---------------------------------------------------------------- partitions
 
+def multi_rhs(A: Csr, nrhs: int, seed: int) -> tuple:
+    """nrhs right-hand sides F[j] = A @ Xstar[j] for one matrix (Section 3.5's
+    sequences of systems with one coefficient matrix): Xstar[0] is the vector
+    of ones of Section 3.1, the others are standard Gaussian vectors drawn
+    from default_rng(seed) one after another.  Returns (F, Xstar), each
+    (nrhs, n) float64, C order."""
+    rng = np.random.default_rng(seed)
+    X = np.empty((nrhs, A.n))
+    for j in range(nrhs):
+        X[j] = 1.0 if j == 0 else rng.standard_normal(A.n)
+    M = A.to_scipy()
+    F = np.stack([M @ X[j] for j in range(nrhs)]) if nrhs else np.empty((0, A.n))
+    return np.ascontiguousarray(F), X
+
+
 def contiguous_blocks(n: int, K: int) -> np.ndarray:
     """K contiguous blocks of near-equal size; the first n % K get one extra row."""
     q, r = divmod(n, K)
