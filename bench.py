@@ -35,7 +35,7 @@ MEASURED_TRAFFIC = {
              "profile": "profiles/k_inner_grp_f64_cd3d_64cubed_K32.md"},
     "cfg4": {"kernel": "k_band_apply<float, 20>", "bytes_per_launch": 2.569e+09,
              "profile": "profiles/k_band_apply_f32_cd2d_batch256_K8.md"},
-    "cfg5": {"kernel": "k_dense_apply<float>", "bytes_per_launch": 6.884e9,
+    "cfg5": {"kernel": "k_dense_apply<float, 4>", "bytes_per_launch": 7.803e+09,
              "profile": "profiles/k_dense_apply_f32_st27_100cubed_K512.md"},
 }
 
@@ -60,11 +60,11 @@ def parse():
                     help="also compare the spectrum of H (Lanczos through bc_project) and the "
                          "CG iteration count for contiguous and greedy rip_graph blocks of the "
                          "workload's matrix")
-    ap.add_argument("--nrhs", type=int, default=1,
+    ap.add_argument("--nrhs", type=int, default=None,
                     help="right-hand sides of the single-system workload solved together by "
                          "bc_solve_multi (vector 0: the workload's f, the others A times a "
                          "seeded Gaussian vector); value then counts the outer iterations of "
-                         "every right-hand side")
+                         "every right-hand side.  Without it: one bc_solve")
     ap.add_argument("--compare", action="store_true",
                     help="also time plain FP64 on the same matrices (per system, one after "
                          "another, for a batch) and report the time-to-tolerance ratio")
@@ -131,9 +131,9 @@ class Workload:
         self.nnz = sum(q.A.nnz for q in self.problems)
 
 
-def run_step(wl, f_dev, method="cg", partitioner="greedy", nrhs=1):
+def run_step(wl, f_dev, method="cg", partitioner="greedy", nrhs=None):
     """One pass of the whole path; returns a dict of phase times and stats.
-    With nrhs > 1, f_dev holds nrhs right-hand sides (nrhs x n)."""
+    With nrhs given, f_dev holds nrhs right-hand sides (nrhs x n) for bc_solve_multi."""
     import torch
     import paper_1710_07769_amd as bc
     out = {"rip_ms": 0.0, "rip_spgemm_ms": 0.0, "partition_ms": 0.0}
@@ -184,7 +184,7 @@ def run_step(wl, f_dev, method="cg", partitioner="greedy", nrhs=1):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sts = bc.bc_cimmino(ctx, f_dev, None, spec.omega_opt, wl.tol, 100000, x)
-        elif nrhs > 1:
+        elif nrhs is not None:
             t0 = time.perf_counter()
             sts = bc.bc_solve_multi(ctx, nrhs, f_dev, None, wl.tol, 10000, x)
         elif wl.batched:
@@ -351,9 +351,9 @@ def main():
     if args.method == "alg1" and wl.batched:
         raise SystemExit("--method alg1 takes a single-system workload")
     xstar = np.concatenate([q.xstar for q in wl.problems])
-    if args.nrhs > 1:
-        if wl.batched or args.method != "cg":
-            raise SystemExit("--nrhs takes a single-system workload and --method cg")
+    if args.nrhs is not None:
+        if wl.batched or args.method != "cg" or args.nrhs < 1:
+            raise SystemExit("--nrhs takes a single-system workload, --method cg and nrhs >= 1")
         import workloads as W
         q = wl.problems[0]
         F, Xs = W.multi_rhs(q.A, args.nrhs, seed=1000)
@@ -402,7 +402,7 @@ def main():
                    + ("; multilevel partitioner" if args.partitioner == "multilevel"
                       and wl.partition == "greedy-rip" else "")
                    + ("; %d right-hand sides solved together (bc_solve_multi)" % args.nrhs
-                      if args.nrhs > 1 else ""),
+                      if args.nrhs is not None else ""),
                    "n": wl.n, "nnz": wl.nnz,
                    "K": [q.K for q in wl.problems][0] if not wl.batched else 8,
                    "systems": len(wl.problems), "partition": wl.partition, "tol": wl.tol},
@@ -429,11 +429,11 @@ def main():
                      "bytes_per_launch": pbytes / max(launches, 1),
                      "traffic": (MEASURED_TRAFFIC[wl.name]["bytes_per_launch"]
                                  if wl.name in MEASURED_TRAFFIC and args.precision is None
-                                 and args.nrhs == 1 else None)},
+                                 and args.nrhs is None else None)},
     }
     if "cutsize" in runs[-1]:
         line["partition_cutsize"] = runs[-1]["cutsize"]
-    if args.nrhs > 1:
+    if args.nrhs is not None:
         line["nrhs"] = args.nrhs
         line["rhs_solves_per_s"] = args.nrhs / (line["time_to_tol_ms"] / 1e3)
     if args.method == "alg1":

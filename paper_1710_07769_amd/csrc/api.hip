@@ -360,6 +360,7 @@ struct bc_ctx {
   unsigned long long* d_inner_total = nullptr;
   std::vector<int> blk_m;
   std::vector<long long> in_nnz, in_m_h, dn_m_h;  // per inner / dense block sizes
+  int dense_max_nt = 0;                             // largest tiles per side of a dense block
 
   // captured group of outer iterations (factor-based projections only)
   hipGraphExec_t gexec = nullptr;
@@ -866,6 +867,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     dn_row0.push_back(blk_row0[b]);
     dn_m.push_back(m);
     c->dn_m_h.push_back(m);
+    c->dense_max_nt = std::max(c->dense_max_nt, nt);
     dn_nt.push_back(nt);
     dn_sys.push_back(blk_sys[b]);
     dn_loff.push_back(ltot);
@@ -1175,6 +1177,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
                        c->d_tptr, c->d_trow, c->d_tval));
     BC_HIP(launch_cholesky(st, D));
     BC_HIP(launch_dense_finish(st, D, c->mixed));
+    BC_HIP(prepare_dense_apply());
     std::vector<int> info(D.nblk);
     BC_HIP(hipMemcpyAsync(info.data(), pinfo, D.nblk * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
@@ -1452,16 +1455,14 @@ bc_status block_solves(bc_ctx* c, const double* u, double* y, const int* done) {
     // several right-hand sides: each dense factor is read once for a chunk
     // of vectors; banded and inner-CG blocks take the vectors one by one
     const int nr = c->mrhs.nrhs, n1 = c->mrhs.n1;
-    int max_nt = 0;
-    for (long long m : c->dn_m_h) max_nt = std::max(max_nt, (int)((m + DT - 1) / DT));
-    BC_HIP(launch_dense_apply_multi(st, c->dense, c->mixed, u, y, done, nr, n1, max_nt));
+    BC_HIP(launch_dense_apply_multi(st, c->dense, c->mixed, u, y, done, nr, n1, c->dense_max_nt));
     for (int j = 0; j < nr; ++j) {
       const size_t o = (size_t)j * n1;
       BC_HIP(launch_band_apply(st, c->band, c->mixed, u + o, y + o, done ? done + j : nullptr));
       BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u + o, y + o, done ? done + j : nullptr));
     }
   } else {
-    BC_HIP(launch_dense_apply(st, c->dense, c->mixed, u, y, done));
+    BC_HIP(launch_dense_apply(st, c->dense, c->mixed, u, y, done, c->dense_max_nt));
     BC_HIP(launch_band_apply(st, c->band, c->mixed, u, y, done));
     BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u, y, done));
   }
@@ -1614,7 +1615,7 @@ bc_status group_graph(bc_ctx* c, double* x, const OuterState& S, int G, bool* ra
     for (int q = 0; q < G && ok; ++q) {
       ok = spmv_a(c, st, c->lanes, c->d_p, c->d_u, S, true) == hipSuccess &&
            launch_stamp(st, c->d_stamps, 2 * q) == hipSuccess &&
-           launch_dense_apply(st, c->dense, c->mixed, c->d_u, c->d_y, c->d_done) == hipSuccess &&
+           launch_dense_apply(st, c->dense, c->mixed, c->d_u, c->d_y, c->d_done, c->dense_max_nt) == hipSuccess &&
            launch_band_apply(st, c->band, c->mixed, c->d_u, c->d_y, c->d_done) == hipSuccess &&
            launch_stamp(st, c->d_stamps, 2 * q + 1) == hipSuccess &&
            spmv_t(c, st, c->lanesT, c->d_y, c->d_psi, c->d_p, S) == hipSuccess &&

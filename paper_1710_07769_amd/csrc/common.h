@@ -294,12 +294,16 @@ struct DenseBlocks {
 };
 hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);
+// Lets the apply kernels use the full LDS of a workgroup; call before the
+// first apply (and outside stream capture).
+hipError_t prepare_dense_apply();
+// y_i = D L^{-T} L^{-1} D u_i on every dense block (done indexed by the
+// block's system); max_nt: the largest tiles-per-side of the dense blocks.
 hipError_t launch_dense_apply(hipStream_t st, const DenseBlocks& D, bool mixed, const double* u,
-                              double* y, const int* done);
-// The same apply to nrhs vectors at once (vector j at u + j*n1, y + j*n1;
-// done indexed by j), in chunks whose z fits the LDS of one workgroup;
-// max_nt: the largest tiles-per-side of the dense blocks.  Every vector gets
-// the bits of launch_dense_apply.
+                              double* y, const int* done, int max_nt);
+// The same apply to nrhs vectors of a one-system context at once (vector j at
+// u + j*n1, y + j*n1; done indexed by j), in chunks whose z fits the LDS of
+// one workgroup.  Every vector gets the bits it gets alone.
 constexpr size_t DENSE_MULTI_LDS = 160 * 1024;
 hipError_t launch_dense_apply_multi(hipStream_t st, const DenseBlocks& D, bool mixed,
                                     const double* u, double* y, const int* done, int nrhs, int n1,

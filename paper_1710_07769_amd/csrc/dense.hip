@@ -257,118 +257,90 @@ __global__ void k_dense_finish(DenseBlocks D, int mixed) {
 }
 
 // ------------------------------------------------------------- apply
-// y = L^{-T} L^{-1} u for one block per workgroup.  Forward sweep over tile
-// rows: acc_i = u_i - sum_{j<i} L_ij z_j (the j tiles are split over the
-// wavefronts; lane r owns row r, so each load reads one 512-byte column),
-// then z_i = Linv_i acc_i.  Backward sweep with the LT tiles and Linv_i^T.
+// y = D L^{-T} L^{-1} D u (D: the row scaling dsc, L L^T the Cholesky
+// factorization of the scaled Gram matrix) for one block per workgroup and up to NR vectors
+// at once (grid.y walks chunks of NR of the nrhs vectors, vector j at offset
+// j * n1).  Forward sweep over tile rows: acc_i = D u_i - sum_{j<i} L_ij z_j,
+// z_i = L_ii^{-1} acc_i; backward sweep with the transposed tiles and
+// L_ii^{-T}; z of the chunk's vectors stays in LDS.  Every tile product
+// (64x64 factor tile times 64 x NR vectors) runs on the matrix cores as
+// 16x16x4 MFMAs with the vectors as the N dimension (columns n >= NR are
+// zero).  Lane l loads a 4-vector of rows 4 (l % 16) .. + 3 of column
+// c0 + l / 16 of the factor tile (64 lanes read 4 whole columns); component
+// e of it is the A operand of the MFMA for the rows 4 i' + e, so the 4
+// MFMAs of a k-step cover the 64 rows and each factor element is read once.
+// Wave w takes the off-diagonal tiles j = w mod 4 of a tile row, the
+// partials are summed in wave order with the right-hand side, and wave w
+// computes the rows 4 i' + w of the diagonal-tile product.  Every output
+// element of an MFMA depends only on its own row and column, so a vector
+// gets the same bits whatever the chunk holds.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = flt4; };
+template <> struct Vec4<double> { using type = dbl4; };
+
 template <typename T>
-__global__ void __launch_bounds__(APPLY_THREADS)
-k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ y,
-              const int* __restrict__ done) {
-  __shared__ T zs[4096 + DT];
-  __shared__ T part[APPLY_THREADS / 64][DT];
-  __shared__ T accs[DT];
-  const int b = blockIdx.x;
-  if (done && done[D.sys[b]]) return;
-  const int m = D.m[b], nt = D.nt[b], row0 = D.row0[b];
-  const T* L;
-  const T* LT;
-  const T* Dv;
-  if constexpr (sizeof(T) == 8) {
-    L = (const T*)(D.L + D.loff[b]);
-    LT = (const T*)(D.LT + D.loff[b]);
-    Dv = (const T*)(D.Dinv + D.doff[b]);
-  } else {
-    L = (const T*)(D.L32 + D.loff[b]);
-    LT = (const T*)(D.LT32 + D.loff[b]);
-    Dv = (const T*)(D.Dinv32 + D.doff[b]);
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  constexpr int NW = APPLY_THREADS / 64;
-  if (threadIdx.x == 0) atomicAdd(&D.applies[b], 1ull);
-  // forward: z = L^{-1} u
-  for (int i = 0; i < nt; ++i) {
-    T acc = (T)0;
-    for (int j = w; j < i; j += NW) {
-      const T* tile = L + ltile(i, j);
-      const T* zj = zs + j * DT;
-#pragma unroll 8
-      for (int c = 0; c < DT; ++c) acc += tile[c * DT + lane] * zj[c];
-    }
-    part[w][lane] = acc;
-    __syncthreads();
-    if (w == 0) {
-      const int gi = i * DT + lane;
-      T a = gi < m ? (T)(u[row0 + gi] * D.dsc[row0 + gi]) : (T)0;
-      for (int q = 0; q < NW; ++q) a -= part[q][lane];
-      accs[lane] = a;
-    }
-    __syncthreads();
-    if (w == 0) {
-      const T* inv = Dv + (long long)i * TSZ;
-      T s = (T)0;
-#pragma unroll 8
-      for (int c = 0; c < DT; ++c) s += inv[c * DT + lane] * accs[c];
-      zs[i * DT + lane] = s;
-    }
-    __syncthreads();
-  }
-  // backward: y = L^{-T} z, overwriting zs tile by tile from the end
-  for (int i = nt - 1; i >= 0; --i) {
-    T acc = (T)0;
-    for (int j = i + 1 + w; j < nt; j += NW) {
-      const T* tile = LT + uttile(nt, i, j);
-      const T* yj = zs + j * DT;
-#pragma unroll 8
-      for (int c = 0; c < DT; ++c) acc += tile[c * DT + lane] * yj[c];
-    }
-    part[w][lane] = acc;
-    __syncthreads();
-    if (w == 0) {
-      T a = zs[i * DT + lane];
-      for (int q = 0; q < NW; ++q) a -= part[q][lane];
-      accs[lane] = a;
-    }
-    __syncthreads();
-    if (w == 0) {
-      const T* invT = Dv + (long long)(nt + i) * TSZ;
-      T s = (T)0;
-#pragma unroll 8
-      for (int c = 0; c < DT; ++c) s += invT[c * DT + lane] * accs[c];
-      zs[i * DT + lane] = s;
-      const int gi = i * DT + lane;
-      if (gi < m) y[row0 + gi] = (double)s * D.dsc[row0 + gi];
-    }
-    __syncthreads();
+__device__ __forceinline__ typename Vec4<T>::type mfma16(T a, T b, typename Vec4<T>::type c) {
+  if constexpr (sizeof(T) == 4) return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  else return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// Row (0..15) of a 16x16x4 MFMA result held in register v of lane l: the
+// FP32 form keeps rows 4 (l / 16) .. + 3 in a lane, the FP64 form rows
+// v * 4 + l / 16.  The column is l % 16 in both.
+template <typename T>
+__device__ __forceinline__ int mfma_row(int l, int v) {
+  return sizeof(T) == 4 ? 4 * (l >> 4) + v : 4 * v + (l >> 4);
+}
+
+// k-steps whose factor loads are issued together: the whole 64-column tile
+// (16 KiB per wave) in FP32, half of it in FP64
+template <typename T>
+constexpr int multi_u() { return sizeof(T) == 4 ? 16 : 8; }
+
+// acc[e] += tile (64x64, column-major) * Z (64 x NR, rows z[c * NR + n]) for
+// the rows 4 i' + e.
+template <typename T, int NR>
+__device__ __forceinline__ void tile_prod_mfma(const T* __restrict__ tile, const T* z,
+                                               typename Vec4<T>::type (&acc)[4], int l) {
+  using V = typename Vec4<T>::type;
+  constexpr int MULTI_U = multi_u<T>();
+  const int li = l & 15, lk = l >> 4;
+  const bool bn = li < NR;
+  for (int c0 = 0; c0 < DT; c0 += 4 * MULTI_U) {
+    V a[MULTI_U];
+    T b[MULTI_U];
+#pragma unroll
+    for (int u = 0; u < MULTI_U; ++u)
+      a[u] = *(const V*)(tile + (c0 + 4 * u + lk) * DT + 4 * li);
+#pragma unroll
+    for (int u = 0; u < MULTI_U; ++u) b[u] = bn ? z[(c0 + 4 * u + lk) * NR + li] : (T)0;
+#pragma unroll
+    for (int u = 0; u < MULTI_U; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] = mfma16<T>(a[u][e], b[u], acc[e]);
   }
 }
 
-// The same sweeps for NR right-hand sides at once (grid.y walks chunks of NR
-// of the nrhs vectors, vector j at offset j * n1).  Each L, LT and inverse
-// element is loaded once and used for the NR vectors, whose sums run in the
-// order of k_dense_apply, so every vector gets the bits of a one-vector
-// apply.  z of the NR vectors sits in dynamic LDS as zs[row][NR]; the
-// diagonal-tile steps of vector q run on wavefront q % NW.
 template <typename T, int NR>
 __global__ void __launch_bounds__(APPLY_THREADS)
-k_dense_apply_multi(DenseBlocks D, const double* __restrict__ u, double* __restrict__ y,
-                    const int* __restrict__ done, int nrhs, int n1) {
+k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ y,
+                    const int* __restrict__ done, int nrhs, int n1, int sys_done) {
+  using V = typename Vec4<T>::type;
   extern __shared__ __align__(16) unsigned char dyn[];
   constexpr int NW = APPLY_THREADS / 64;
+  static_assert(NW == 4, "one wave per MFMA row interleave");
   const int b = blockIdx.x;
   const int m = D.m[b], nt = D.nt[b], row0 = D.row0[b];
   const int j0 = blockIdx.y * NR;
-  bool act[NR];
+  // sys_done: one vector (of a batch of systems), stopped with the block's system
+  if (sys_done && done && done[D.sys[b]]) return;
+  if (sys_done) done = nullptr;
   bool any = false;
-#pragma unroll
-  for (int q = 0; q < NR; ++q) {
-    act[q] = j0 + q < nrhs && !(done && done[j0 + q]);
-    any = any || act[q];
-  }
+  for (int q = 0; q < NR; ++q) any = any || (j0 + q < nrhs && !(done && done[j0 + q]));
   if (!any) return;
   T* zs = (T*)dyn;                                  // nt * DT rows of NR
-  T* part = zs + (size_t)nt * DT * NR;              // [NW][NR][DT]
-  T* accs = part + (size_t)NW * NR * DT;            // [NR][DT]
+  T* part = zs + (size_t)nt * DT * NR;              // [NW][DT][NR]
+  T* accs = part + (size_t)NW * DT * NR;            // [DT][NR]
   const T* L;
   const T* LT;
   const T* Dv;
@@ -381,79 +353,68 @@ k_dense_apply_multi(DenseBlocks D, const double* __restrict__ u, double* __restr
     LT = (const T*)(D.LT32 + D.loff[b]);
     Dv = (const T*)(D.Dinv32 + D.doff[b]);
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = l & 15, lk = l >> 4;
   if (threadIdx.x == 0) atomicAdd(&D.applies[b], 1ull);
-  // forward: z = L^{-1} u
-  for (int i = 0; i < nt; ++i) {
-    T acc[NR];
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fwd = pass == 0;
+    for (int s = 0; s < nt; ++s) {
+      const int i = fwd ? s : nt - 1 - s;
+      // off-diagonal part of tile row i
+      V acc[4];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) acc[q] = (T)0;
-    for (int j = w; j < i; j += NW) {
-      const T* tile = L + ltile(i, j);
-      const T* zj = zs + (size_t)j * DT * NR;
-#pragma unroll 4
-      for (int c = 0; c < DT; ++c) {
-        const T l = tile[c * DT + lane];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] += l * zj[c * NR + q];
+      for (int e = 0; e < 4; ++e) acc[e] = V{};
+      if (fwd) {
+        for (int j = w; j < i; j += NW) tile_prod_mfma<T, NR>(L + ltile(i, j), zs + (size_t)j * DT * NR, acc, l);
+      } else {
+        for (int j = i + 1 + w; j < nt; j += NW)
+          tile_prod_mfma<T, NR>(LT + uttile(nt, i, j), zs + (size_t)j * DT * NR, acc, l);
       }
-    }
+      if (li < NR)
 #pragma unroll
-    for (int q = 0; q < NR; ++q) part[(w * NR + q) * DT + lane] = acc[q];
-    __syncthreads();
-    const int gi = i * DT + lane;
-    for (int q = w; q < NR; q += NW) {
-      const int jr = j0 + q;
-      T a = (gi < m && act[q]) ? (T)(u[(size_t)jr * n1 + row0 + gi] * D.dsc[row0 + gi]) : (T)0;
-      for (int qq = 0; qq < NW; ++qq) a -= part[(qq * NR + q) * DT + lane];
-      accs[q * DT + lane] = a;
-    }
-    __syncthreads();
-    for (int q = w; q < NR; q += NW) {
-      const T* inv = Dv + (long long)i * TSZ;
-      const T* aq = accs + q * DT;
-      T s = (T)0;
-#pragma unroll 8
-      for (int c = 0; c < DT; ++c) s += inv[c * DT + lane] * aq[c];
-      zs[(size_t)gi * NR + q] = s;
-    }
-    __syncthreads();
-  }
-  // backward: y = L^{-T} z, overwriting zs tile by tile from the end
-  for (int i = nt - 1; i >= 0; --i) {
-    T acc[NR];
+        for (int e = 0; e < 4; ++e)
 #pragma unroll
-    for (int q = 0; q < NR; ++q) acc[q] = (T)0;
-    for (int j = i + 1 + w; j < nt; j += NW) {
-      const T* tile = LT + uttile(nt, i, j);
-      const T* yj = zs + (size_t)j * DT * NR;
-#pragma unroll 4
-      for (int c = 0; c < DT; ++c) {
-        const T l = tile[c * DT + lane];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) acc[q] += l * yj[c * NR + q];
+          for (int v = 0; v < 4; ++v)
+            part[((size_t)w * DT + 4 * mfma_row<T>(l, v) + e) * NR + li] = acc[e][v];
+      __syncthreads();
+      // right-hand side of the diagonal tile: (scaled u or z) minus the partials
+      for (int q = threadIdx.x; q < DT * NR; q += APPLY_THREADS) {
+        const int r = q / NR, n = q - r * NR;
+        const int gi = i * DT + r;
+        T a;
+        if (fwd) {
+          const bool on = gi < m && j0 + n < nrhs && !(done && done[j0 + n]);
+          a = on ? (T)(u[(size_t)(j0 + n) * n1 + row0 + gi] * D.dsc[row0 + gi]) : (T)0;
+        } else {
+          a = zs[(size_t)gi * NR + n];
+        }
+        for (int ww = 0; ww < NW; ++ww) a -= part[((size_t)ww * DT + r) * NR + n];
+        accs[q] = a;
       }
-    }
+      __syncthreads();
+      // diagonal tile: rows 4 i' + w of (L_ii^{-1} or its transpose) * accs
+      const T* inv = Dv + (long long)(fwd ? i : nt + i) * TSZ;
+      V d = V{};
+#pragma unroll 4
+      for (int c0 = 0; c0 < DT; c0 += 4) {
+        const T a = inv[(c0 + lk) * DT + 4 * li + w];
+        const T bb = li < NR ? accs[(c0 + lk) * NR + li] : (T)0;
+        d = mfma16<T>(a, bb, d);
+      }
+      if (li < NR) {
+        const int n = li;
+        const bool on = j0 + n < nrhs && !(done && done[j0 + n]);
 #pragma unroll
-    for (int q = 0; q < NR; ++q) part[(w * NR + q) * DT + lane] = acc[q];
-    __syncthreads();
-    const int gi = i * DT + lane;
-    for (int q = w; q < NR; q += NW) {
-      T a = zs[(size_t)gi * NR + q];
-      for (int qq = 0; qq < NW; ++qq) a -= part[(qq * NR + q) * DT + lane];
-      accs[q * DT + lane] = a;
+        for (int v = 0; v < 4; ++v) {
+          const int r = 4 * mfma_row<T>(l, v) + w;
+          const int gi = i * DT + r;
+          zs[(size_t)gi * NR + n] = d[v];
+          if (!fwd && on && gi < m)
+            y[(size_t)(j0 + n) * n1 + row0 + gi] = (double)d[v] * D.dsc[row0 + gi];
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int q = w; q < NR; q += NW) {
-      const T* invT = Dv + (long long)(nt + i) * TSZ;
-      const T* aq = accs + q * DT;
-      T s = (T)0;
-#pragma unroll 8
-      for (int c = 0; c < DT; ++c) s += invT[c * DT + lane] * aq[c];
-      zs[(size_t)gi * NR + q] = s;
-      if (gi < m && act[q]) y[(size_t)(j0 + q) * n1 + row0 + gi] = (double)s * D.dsc[row0 + gi];
-    }
-    __syncthreads();
   }
 }
 
@@ -484,7 +445,7 @@ hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed)
   return hipGetLastError();
 }
 
-// Dynamic LDS of k_dense_apply_multi for NR vectors and blocks of up to
+// Dynamic LDS of k_dense_apply for NR vectors and blocks of up to
 // max_nt tiles.
 size_t dense_multi_lds(int nr, int max_nt, bool mixed) {
   return (size_t)(max_nt + 5) * DT * nr * (mixed ? sizeof(float) : sizeof(double));
@@ -492,49 +453,57 @@ size_t dense_multi_lds(int nr, int max_nt, bool mixed) {
 
 template <typename T, int NR>
 hipError_t launch_dense_multi_nr(hipStream_t st, const DenseBlocks& D, const double* u, double* y,
-                                 const int* done, int nrhs, int n1, size_t lds) {
-  const void* fn = (const void*)k_dense_apply_multi<T, NR>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_dense_apply_multi<T, NR>), dim3(D.nblk, (nrhs + NR - 1) / NR),
-                     dim3(APPLY_THREADS), lds, st, D, u, y, done, nrhs, n1);
+                                 const int* done, int nrhs, int n1, size_t lds, int sys_done) {
+  hipLaunchKernelGGL((k_dense_apply<T, NR>), dim3(D.nblk, (nrhs + NR - 1) / NR),
+                     dim3(APPLY_THREADS), lds, st, D, u, y, done, nrhs, n1, sys_done);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_dense_multi_t(hipStream_t st, const DenseBlocks& D, const double* u, double* y,
-                                const int* done, int nrhs, int n1, int max_nt) {
-  // the widest chunk (at most 8, and at most the next power of two of nrhs)
-  // whose LDS fits in one workgroup
-  int nr = 8;
-  while (nr > 1 && (nr / 2 >= nrhs || dense_multi_lds(nr, max_nt, sizeof(T) == 4) > DENSE_MULTI_LDS))
-    nr /= 2;
-  const size_t lds = dense_multi_lds(nr, max_nt, sizeof(T) == 4);
+                                const int* done, int nrhs, int n1, int max_nt, int sys_done) {
+  // chunk width: the widest of 16, 8 and 4 vectors (no wider than nrhs
+  // needs) whose LDS fits in one workgroup, so each factor is read as few
+  // times as possible (a narrower chunk at higher occupancy reads it more
+  // often and was measured slower)
+  const bool f32 = sizeof(T) == 4;
+  int nr = 16;
+  while (nr > 4 && (nr / 2 >= nrhs || dense_multi_lds(nr, max_nt, f32) > DENSE_MULTI_LDS)) nr /= 2;
+  const size_t lds = dense_multi_lds(nr, max_nt, f32);
   switch (nr) {
-    case 8: return launch_dense_multi_nr<T, 8>(st, D, u, y, done, nrhs, n1, lds);
-    case 4: return launch_dense_multi_nr<T, 4>(st, D, u, y, done, nrhs, n1, lds);
-    case 2: return launch_dense_multi_nr<T, 2>(st, D, u, y, done, nrhs, n1, lds);
-    default: return launch_dense_multi_nr<T, 1>(st, D, u, y, done, nrhs, n1, lds);
+    case 16: return launch_dense_multi_nr<T, 16>(st, D, u, y, done, nrhs, n1, lds, sys_done);
+    case 8: return launch_dense_multi_nr<T, 8>(st, D, u, y, done, nrhs, n1, lds, sys_done);
+    default: return launch_dense_multi_nr<T, 4>(st, D, u, y, done, nrhs, n1, lds, sys_done);
   }
+}
+
+// Allows every variant of the apply the full LDS of a workgroup (once per
+// process and device, outside any stream capture).
+hipError_t prepare_dense_apply() {
+  const void* fns[] = {(const void*)k_dense_apply<float, 4>, (const void*)k_dense_apply<float, 8>,
+                       (const void*)k_dense_apply<float, 16>, (const void*)k_dense_apply<double, 4>,
+                       (const void*)k_dense_apply<double, 8>, (const void*)k_dense_apply<double, 16>};
+  for (const void* fn : fns) {
+    const hipError_t e =
+        hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)DENSE_MULTI_LDS);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_dense_apply_multi(hipStream_t st, const DenseBlocks& D, bool mixed,
                                     const double* u, double* y, const int* done, int nrhs, int n1,
                                     int max_nt) {
   if (D.nblk == 0 || nrhs <= 0) return hipSuccess;
-  if (dense_multi_lds(1, max_nt, mixed) > DENSE_MULTI_LDS) return hipErrorInvalidValue;
-  return mixed ? launch_dense_multi_t<float>(st, D, u, y, done, nrhs, n1, max_nt)
-               : launch_dense_multi_t<double>(st, D, u, y, done, nrhs, n1, max_nt);
+  if (dense_multi_lds(4, max_nt, mixed) > DENSE_MULTI_LDS) return hipErrorInvalidValue;
+  return mixed ? launch_dense_multi_t<float>(st, D, u, y, done, nrhs, n1, max_nt, 0)
+               : launch_dense_multi_t<double>(st, D, u, y, done, nrhs, n1, max_nt, 0);
 }
 
 hipError_t launch_dense_apply(hipStream_t st, const DenseBlocks& D, bool mixed, const double* u,
-                              double* y, const int* done) {
+                              double* y, const int* done, int max_nt) {
   if (D.nblk == 0) return hipSuccess;
-  if (mixed)
-    hipLaunchKernelGGL(k_dense_apply<float>, dim3(D.nblk), dim3(APPLY_THREADS), 0, st, D, u, y,
-                       done);
-  else
-    hipLaunchKernelGGL(k_dense_apply<double>, dim3(D.nblk), dim3(APPLY_THREADS), 0, st, D, u, y,
-                       done);
-  return hipGetLastError();
+  if (dense_multi_lds(4, max_nt, mixed) > DENSE_MULTI_LDS) return hipErrorInvalidValue;
+  return mixed ? launch_dense_multi_t<float>(st, D, u, y, done, 1, 0, max_nt, 1)
+               : launch_dense_multi_t<double>(st, D, u, y, done, 1, 0, max_nt, 1);
 }

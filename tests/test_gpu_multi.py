@@ -3,11 +3,17 @@
 
 Bars:
 * each right-hand side of a multi solve ends with the iteration count, status
-  and iterate bits of a ``bc_solve`` of that right-hand side alone on the same
-  context (sliced-ELL products forced with spmv_lanes = -1, so both take the
-  same product schedule); this holds for dense FP64 and FP32-apply factors,
-  banded factors and inner-CG blocks, for chunks that leave a ragged tail and
-  for right-hand sides that stop at different iterations;
+  and iterate bits of a ``bc_solve_multi`` of that right-hand side alone
+  (the sliced-ELL products and the matrix-core dense sweeps give every vector
+  the same bits whatever else its chunk holds); this holds for dense FP64 and
+  FP32-apply factors, banded factors and inner-CG blocks, for chunks that
+  leave a ragged tail and for right-hand sides that stop at different
+  iterations;
+* against ``bc_solve`` of the same right-hand side (sliced-ELL products forced
+  with spmv_lanes = -1 on both): banded and inner-CG blocks take the same
+  kernels, so the bits agree; dense blocks use the one-vector sweeps there,
+  so the iteration count agrees within one (FP64) or two (FP32 applies) and
+  the iterates within 1e-9 (FP64) or 1e-6 (FP32 applies) relative;
 * against the oracle (Algorithm 2 per right-hand side, FP64): the iteration
   count (a difference of one only as a near-tie of the stop decision) and, at
   the oracle's count, the iterate within 1e-8 relative (FP64 factors).
@@ -43,10 +49,11 @@ def st27(N, K):
     return p, workloads.blocks_to_part(workloads.contiguous_blocks(p.n, K))
 
 
-def check_multi_equals_single(dev, p, part, K, nrhs, seed, tol=1e-10, maxit=5000, F=None,
-                              **opts):
-    """Multi solve vs one bc_solve per right-hand side: same iterations,
-    statuses and bits.  Returns (F, X, stats)."""
+def check_multi(dev, p, part, K, nrhs, seed, tol=1e-10, maxit=5000, F=None, single_exact=True,
+                single_bar=(0, 0.0), **opts):
+    """Multi solve against one-vector multi solves (same bits) and against one
+    bc_solve per right-hand side (same bits when single_exact, else within
+    single_bar = (iterations, relative error)).  Returns (F, X, stats)."""
     if F is None:
         F, _ = workloads.multi_rhs(p.A, nrhs, seed)
     solver = bc.BlockCimmino(p.A, part, K, spmv_lanes=-1, **opts)
@@ -56,25 +63,39 @@ def check_multi_equals_single(dev, p, part, K, nrhs, seed, tol=1e-10, maxit=5000
         X = X.cpu().numpy()
         assert len(sts) == nrhs
         for j in range(nrhs):
-            x1, st1 = solver.solve(Fd[j].contiguous(), tol=tol, maxit=maxit)
-            x1 = x1.cpu().numpy()
-            print("rhs %d: iterations multi=%d single=%d status %d/%d rel_res=%.2e"
-                  % (j, sts[j].iterations, st1.iterations, sts[j].status, st1.status,
-                     sts[j].rel_residual))
-            assert sts[j].iterations == st1.iterations
-            assert sts[j].status == st1.status
+            x1, st1 = solver.solve_multi(Fd[j:j + 1].contiguous(), tol=tol, maxit=maxit)
+            x1 = x1.cpu().numpy()[0]
+            xs, sts_ = solver.solve(Fd[j].contiguous(), tol=tol, maxit=maxit)
+            xs = xs.cpu().numpy()
+            print("rhs %d: iterations multi=%d alone=%d bc_solve=%d status %d/%d/%d rel_res=%.2e "
+                  "rel_diff_vs_bc_solve=%.2e"
+                  % (j, sts[j].iterations, st1[0].iterations, sts_.iterations, sts[j].status,
+                     st1[0].status, sts_.status, sts[j].rel_residual, rel(X[j], xs)))
+            assert sts[j].iterations == st1[0].iterations
+            assert sts[j].status == st1[0].status
             assert np.array_equal(X[j], x1), "rhs %d: max diff %.3e" % (j, np.abs(X[j] - x1).max())
-            assert sts[j].rel_residual == st1.rel_residual
+            assert sts[j].rel_residual == st1[0].rel_residual
+            assert sts[j].status == sts_.status
+            if single_exact:
+                assert sts[j].iterations == sts_.iterations
+                assert np.array_equal(X[j], xs)
+            else:
+                assert abs(sts[j].iterations - sts_.iterations) <= single_bar[0]
+                assert rel(X[j], xs) <= single_bar[1]
         return F, X, sts
     finally:
         solver.close()
 
 
+FP64_DENSE = dict(single_exact=False, single_bar=(1, 1e-9))
+FP32_DENSE = dict(single_exact=False, single_bar=(2, 1e-6))
+
+
 def test_multi_dense_fp64_matches_single_and_oracle(dev):
     banner("bc_solve_multi st27-10 K=6 dense FP64, 5 right-hand sides")
     p, part = st27(10, 6)
-    F, X, sts = check_multi_equals_single(dev, p, part, 6, 5, seed=11,
-                                          projection=bc.BC_PROJ_DENSE_CHOL)
+    F, X, sts = check_multi(dev, p, part, 6, 5, seed=11, projection=bc.BC_PROJ_DENSE_CHOL,
+                            **FP64_DENSE)
     A = p.A.to_scipy()
     for j in (0, 3):
         ref = block_cimmino_cg(A, F[j], part, 6, tol=1e-10)
@@ -99,25 +120,32 @@ def test_multi_dense_fp64_matches_single_and_oracle(dev):
         solver.close()
 
 
-@pytest.mark.parametrize("nrhs", [1, 2, 9])
+@pytest.mark.parametrize("nrhs", [1, 2, 9, 17])
 def test_multi_dense_fp32_applies_ragged_chunks(dev, nrhs):
     banner("bc_solve_multi st27-10 K=6 FP32 dense applies, %d right-hand sides" % nrhs)
     p, part = st27(10, 6)
-    check_multi_equals_single(dev, p, part, 6, nrhs, seed=12, projection=bc.BC_PROJ_DENSE_CHOL,
-                              precision=bc.BC_MIXED_PROJ)
+    check_multi(dev, p, part, 6, nrhs, seed=12, projection=bc.BC_PROJ_DENSE_CHOL,
+                precision=bc.BC_MIXED_PROJ, **FP32_DENSE)
+
+
+@pytest.mark.parametrize("nrhs", [3, 12])
+def test_multi_dense_fp64_chunks(dev, nrhs):
+    banner("bc_solve_multi st27-10 K=6 FP64 dense, %d right-hand sides" % nrhs)
+    p, part = st27(10, 6)
+    check_multi(dev, p, part, 6, nrhs, seed=18, projection=bc.BC_PROJ_DENSE_CHOL, **FP64_DENSE)
 
 
 def test_multi_banded(dev):
     banner("bc_solve_multi st27-8 K=8 banded FP64, 3 right-hand sides")
     p, part = st27(8, 8)
-    check_multi_equals_single(dev, p, part, 8, 3, seed=13, projection=bc.BC_PROJ_BAND_CHOL)
+    check_multi(dev, p, part, 8, 3, seed=13, projection=bc.BC_PROJ_BAND_CHOL)
 
 
 def test_multi_inner_cg(dev):
     banner("bc_solve_multi cd3d-12 K=4 inner CG FP64, 2 right-hand sides")
     p = workloads.small_config2(N=12, K=4)
     part = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, 4))
-    check_multi_equals_single(dev, p, part, 4, 2, seed=14, projection=bc.BC_PROJ_INNER_CG)
+    check_multi(dev, p, part, 4, 2, seed=14, projection=bc.BC_PROJ_INNER_CG)
 
 
 def test_multi_stops_independently(dev):
@@ -127,8 +155,8 @@ def test_multi_stops_independently(dev):
     F[1] = 0.0            # f = 0: converged before any iteration
     F[2] = 1e-3 * F[3]    # a scaled copy: the same iterations as F[3]
     F = np.ascontiguousarray(F)
-    _, X, sts = check_multi_equals_single(dev, p, part, 4, 4, seed=0, F=F,
-                                          projection=bc.BC_PROJ_DENSE_CHOL)
+    _, X, sts = check_multi(dev, p, part, 4, 4, seed=0, F=F, projection=bc.BC_PROJ_DENSE_CHOL,
+                            **FP64_DENSE)
     assert sts[1].iterations == 0 and sts[1].status == bc.BC_OK
     assert float(np.abs(X[1]).max()) == 0.0
     assert sts[0].iterations > 0 and sts[3].iterations > 0
@@ -151,8 +179,8 @@ def test_multi_maxit_and_x0(dev):
         X3, sts3 = solver.solve_multi(Fd[:2].contiguous(), tol=0.0, maxit=4)
         assert np.array_equal(X3.cpu().numpy(), X.cpu().numpy()[:2])
         for j in range(3):
-            x1, st1 = solver.solve(Fd[j].contiguous(), tol=0.0, maxit=4)
-            assert np.array_equal(x1.cpu().numpy(), X.cpu().numpy()[j])
+            x1, st1 = solver.solve_multi(Fd[j:j + 1].contiguous(), tol=0.0, maxit=4)
+            assert np.array_equal(x1.cpu().numpy()[0], X.cpu().numpy()[j])
     finally:
         solver.close()
 
@@ -190,7 +218,7 @@ def test_multi_rejects_bad_calls(dev):
 
 def test_multi_fullsize_st27_100cubed(dev):
     banner("bc_solve_multi st27-100 n=1e6 K=512 FP32 dense applies, 8 right-hand sides; "
-           "2 of them against bc_solve")
+           "2 of them alone and against bc_solve")
     p = workloads.config5()
     part = p.part()
     F, _ = workloads.multi_rhs(p.A, 8, 17)
@@ -202,8 +230,13 @@ def test_multi_fullsize_st27_100cubed(dev):
         print("iterations", [s.iterations for s in sts], "t_solve_ms %.1f" % sts[0].t_solve_ms)
         assert all(s.status == bc.BC_OK and s.rel_residual <= 1e-10 * (1 + 1e-6) for s in sts)
         for j in (0, 7):
-            x1, st1 = solver.solve(Fd[j].contiguous(), tol=1e-10, maxit=2000)
-            assert st1.iterations == sts[j].iterations
-            assert torch.equal(x1, X[j])
+            x1, st1 = solver.solve_multi(Fd[j:j + 1].contiguous(), tol=1e-10, maxit=2000)
+            assert st1[0].iterations == sts[j].iterations
+            assert torch.equal(x1[0], X[j])
+            xs, sts_ = solver.solve(Fd[j].contiguous(), tol=1e-10, maxit=2000)
+            print("rhs %d: bc_solve iterations %d, rel diff %.2e"
+                  % (j, sts_.iterations, rel(X[j].cpu().numpy(), xs.cpu().numpy())))
+            assert abs(sts_.iterations - sts[j].iterations) <= 2
+            assert rel(X[j].cpu().numpy(), xs.cpu().numpy()) <= 1e-6
     finally:
         solver.close()
