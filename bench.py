@@ -35,7 +35,7 @@ MEASURED_TRAFFIC = {
              "profile": "profiles/k_inner_grp_f64_cd3d_64cubed_K32.md"},
     "cfg4": {"kernel": "k_band_apply<float, 20>", "bytes_per_launch": 2.569e+09,
              "profile": "profiles/k_band_apply_f32_cd2d_batch256_K8.md"},
-    "cfg5": {"kernel": "k_dense_apply<float, 4>", "bytes_per_launch": 7.803e+09,
+    "cfg5": {"kernel": "k_dense_apply<float, 4>", "bytes_per_launch": 7.805e+09,
              "profile": "profiles/k_dense_apply_f32_st27_100cubed_K512.md"},
 }
 

@@ -171,8 +171,8 @@ bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, doubl
  * own CG recurrence and stops on its own, exactly as one bc_solve with it
  * would (same iterations and bits, given the same sparse-product schedule:
  * spmv_lanes = -1); the right-hand sides share every read of A, A^T and the
- * dense block factors: the sparse products take chunks of 4 vectors per
- * matrix read, the dense triangular sweeps chunks of up to 8 per factor read.
+ * dense block factors: the sparse products take chunks of 8 vectors per
+ * matrix read, the dense triangular sweeps chunks of up to 16 per factor read.
  * Banded and inner-CG blocks take the vectors one after another.
  * f, x0 (or NULL for zero), x: device float64[nrhs * n], vector j at
  * offset j * n (original row / column order, as bc_solve).  stats: host,

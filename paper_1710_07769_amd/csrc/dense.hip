@@ -298,7 +298,9 @@ template <typename T>
 constexpr int multi_u() { return sizeof(T) == 4 ? 16 : 8; }
 
 // acc[e] += tile (64x64, column-major) * Z (64 x NR, rows z[c * NR + n]) for
-// the rows 4 i' + e.
+// the rows 4 i' + e.  Lane l loads the 4-vector of rows 4 (l % 16) .. + 3 of
+// column c0 + 4 u + l / 16; the loads of a batch of U k-steps are issued
+// before its MFMAs.
 template <typename T, int NR>
 __device__ __forceinline__ void tile_prod_mfma(const T* __restrict__ tile, const T* z,
                                                typename Vec4<T>::type (&acc)[4], int l) {
@@ -356,16 +358,52 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = l & 15, lk = l >> 4;
   if (threadIdx.x == 0) atomicAdd(&D.applies[b], 1ull);
+  // The right-hand-side step of a tile row: thread t handles the entries
+  // q = t + 256 k (k < NR/4) of the 64 x NR tile, always of vector n = t % NR.
+  constexpr int QK = DT * NR / APPLY_THREADS;
+  static_assert(QK >= 1 && APPLY_THREADS % NR == 0, "entries per thread");
+  const int qn = threadIdx.x % NR;
+  const bool qon = j0 + qn < nrhs && !(done && done[j0 + qn]);
+  // the output rows of lane l in the diagonal-tile product, and whether
+  // its vector is written
+  const bool non = li < NR && j0 + li < nrhs && !(done && done[j0 + li]);
   for (int pass = 0; pass < 2; ++pass) {
     const bool fwd = pass == 0;
     for (int s = 0; s < nt; ++s) {
       const int i = fwd ? s : nt - 1 - s;
-      // off-diagonal part of tile row i
+      // Loads of this step that depend on nothing computed here are issued
+      // first, so that they arrive during the off-diagonal products: the A
+      // operands of the diagonal-tile product, the scaled right-hand side
+      // (forward) and the output scales (backward).
+      const T* inv = Dv + (long long)(fwd ? i : nt + i) * TSZ;
+      T ainv[DT / 4];
+#pragma unroll
+      for (int c = 0; c < DT / 4; ++c) ainv[c] = inv[(4 * c + lk) * DT + 4 * li + w];
+      T upre[QK];
+      if (fwd) {
+#pragma unroll
+        for (int k = 0; k < QK; ++k) {
+          const int gi = i * DT + (threadIdx.x + APPLY_THREADS * k) / NR;
+          upre[k] = (qon && gi < m) ? (T)(u[(size_t)(j0 + qn) * n1 + row0 + gi] * D.dsc[row0 + gi])
+                                    : (T)0;
+        }
+      }
+      double osc[4];
+      if (!fwd) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int gi = i * DT + 4 * mfma_row<T>(l, v) + w;
+          osc[v] = gi < m ? D.dsc[row0 + gi] : 0.0;
+        }
+      }
+      // off-diagonal part of tile row i: tiles j = w mod 4 (j < i forward,
+      // j > i backward)
       V acc[4];
 #pragma unroll
       for (int e = 0; e < 4; ++e) acc[e] = V{};
       if (fwd) {
-        for (int j = w; j < i; j += NW) tile_prod_mfma<T, NR>(L + ltile(i, j), zs + (size_t)j * DT * NR, acc, l);
+        for (int j = w; j < i; j += NW)
+          tile_prod_mfma<T, NR>(L + ltile(i, j), zs + (size_t)j * DT * NR, acc, l);
       } else {
         for (int j = i + 1 + w; j < nt; j += NW)
           tile_prod_mfma<T, NR>(LT + uttile(nt, i, j), zs + (size_t)j * DT * NR, acc, l);
@@ -378,39 +416,29 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
             part[((size_t)w * DT + 4 * mfma_row<T>(l, v) + e) * NR + li] = acc[e][v];
       __syncthreads();
       // right-hand side of the diagonal tile: (scaled u or z) minus the partials
-      for (int q = threadIdx.x; q < DT * NR; q += APPLY_THREADS) {
-        const int r = q / NR, n = q - r * NR;
-        const int gi = i * DT + r;
-        T a;
-        if (fwd) {
-          const bool on = gi < m && j0 + n < nrhs && !(done && done[j0 + n]);
-          a = on ? (T)(u[(size_t)(j0 + n) * n1 + row0 + gi] * D.dsc[row0 + gi]) : (T)0;
-        } else {
-          a = zs[(size_t)gi * NR + n];
-        }
-        for (int ww = 0; ww < NW; ++ww) a -= part[((size_t)ww * DT + r) * NR + n];
+#pragma unroll
+      for (int k = 0; k < QK; ++k) {
+        const int q = threadIdx.x + APPLY_THREADS * k;
+        const int r = q / NR;
+        T a = fwd ? upre[k] : zs[(size_t)(i * DT + r) * NR + qn];
+        for (int ww = 0; ww < NW; ++ww) a -= part[((size_t)ww * DT + r) * NR + qn];
         accs[q] = a;
       }
       __syncthreads();
       // diagonal tile: rows 4 i' + w of (L_ii^{-1} or its transpose) * accs
-      const T* inv = Dv + (long long)(fwd ? i : nt + i) * TSZ;
       V d = V{};
-#pragma unroll 4
-      for (int c0 = 0; c0 < DT; c0 += 4) {
-        const T a = inv[(c0 + lk) * DT + 4 * li + w];
-        const T bb = li < NR ? accs[(c0 + lk) * NR + li] : (T)0;
-        d = mfma16<T>(a, bb, d);
+#pragma unroll
+      for (int c = 0; c < DT / 4; ++c) {
+        const T bb = li < NR ? accs[(4 * c + lk) * NR + li] : (T)0;
+        d = mfma16<T>(ainv[c], bb, d);
       }
       if (li < NR) {
-        const int n = li;
-        const bool on = j0 + n < nrhs && !(done && done[j0 + n]);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int r = 4 * mfma_row<T>(l, v) + w;
           const int gi = i * DT + r;
-          zs[(size_t)gi * NR + n] = d[v];
-          if (!fwd && on && gi < m)
-            y[(size_t)(j0 + n) * n1 + row0 + gi] = (double)d[v] * D.dsc[row0 + gi];
+          zs[(size_t)gi * NR + li] = d[v];
+          if (!fwd && non && gi < m) y[(size_t)(j0 + li) * n1 + row0 + gi] = (double)d[v] * osc[v];
         }
       }
       __syncthreads();

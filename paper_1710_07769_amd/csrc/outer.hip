@@ -943,9 +943,10 @@ hipError_t launch_zero(hipStream_t st, double* dst, int n) {
   return hipGetLastError();
 }
 
-// Chunk width of the multi-vector sparse products: 4 vectors (8 entries'
-// indices and values plus 4 accumulators stay in registers at 1024 threads).
-constexpr int SELL_MULTI_NR = 4;
+// Chunk width of the multi-vector sparse products: 8 vectors (8 entries'
+// indices and values plus 8 accumulators stay within 76 VGPRs at 1024
+// threads, without spills).
+constexpr int SELL_MULTI_NR = 8;
 
 hipError_t launch_spmv_sell_multi(hipStream_t st, const SellMat& A, const MultiRhs& M, bool mixed,
                                   const double* x, double* y, const OuterState& S, bool skip_done) {
