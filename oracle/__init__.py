@@ -12,8 +12,9 @@ Contents (each function cites the passage of the paper it follows):
   seminormal equations (large inputs); Section 1, eqs. (iterscheme), (H),
   (Iterat).
 * :mod:`oracle.cimmino`   - Algorithm 2 (classical CG on H x = xi), the
-  normwise backward error of eq. (stopping), and Algorithm 1 (plain block
-  Cimmino with relaxation omega).
+  normwise backward error of eq. (stopping), Algorithm 1 (plain block
+  Cimmino with relaxation omega), and block CG on H for several right-hand
+  sides (Section 3.1).
 * :mod:`oracle.ripgraph`  - the row inner-product graph of Section 2.1 built
   from C = A A^T with the dense-column sparsification and integer edge
   weights of Section 2.3.
@@ -26,7 +27,8 @@ or reordering beyond what the definitions state.
 """
 from .projection import QRProjector, CSNEProjector, BlockProjections
 from .cimmino import (block_cimmino_cg, block_cimmino_plain, backward_error,
-                      CimminoResult, OK, NOT_CONVERGED, BREAKDOWN)
+                      CimminoResult, OK, NOT_CONVERGED, BREAKDOWN,
+                      block_cimmino_block_cg, orthonormal_directions, BlockCGResult)
 from .ripgraph import rip_graph, rip_rows, row_norms, sparsify_columns, RipGraph
 from .partition import (greedy_partition, multilevel_partition, cutsize, int_cut, ip_matrix,
                         imbalance, brute_force_min_cut, part_max_weight)
@@ -34,6 +36,7 @@ from .partition import (greedy_partition, multilevel_partition, cutsize, int_cut
 __all__ = [
     "QRProjector", "CSNEProjector", "BlockProjections",
     "block_cimmino_cg", "block_cimmino_plain", "backward_error", "CimminoResult",
+    "block_cimmino_block_cg", "orthonormal_directions", "BlockCGResult",
     "OK", "NOT_CONVERGED", "BREAKDOWN",
     "rip_graph", "rip_rows", "row_norms", "sparsify_columns", "RipGraph",
     "greedy_partition", "multilevel_partition", "cutsize", "int_cut", "ip_matrix", "imbalance",

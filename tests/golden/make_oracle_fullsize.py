@@ -8,7 +8,9 @@ residual, and the solution at 2000 seeded sample indices (the GPU side
 compares its iterate at the same iteration count on those entries).
 
 Run from the repository root:  python tests/golden/make_oracle_fullsize.py
-(several minutes of single-threaded CPU; config 2 dominates).
+(several minutes of single-threaded CPU; config 2 dominates).  With the
+argument cfg2-ml it only adds the hash of the oracle's multilevel partition of
+config 2's row inner-product graph (about 30 s).
 """
 import json
 import os
@@ -22,7 +24,7 @@ sys.path.insert(0, ROOT)
 
 import workloads  # noqa: E402
 from oracle import (block_cimmino_cg, rip_graph, greedy_partition,  # noqa: E402
-                    BlockProjections)
+                    multilevel_partition, BlockProjections)
 
 NSAMPLE = 2000
 OUT = os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")
@@ -55,6 +57,12 @@ def main():
         out["cfg2"] = run("cfg2", p.A, p.f, part, p.K)
         out["cfg2"]["partition_sha"] = int(np.sum(part.astype(np.int64) *
                                                   np.arange(1, p.n + 1, dtype=np.int64)) % (2**61 - 1))
+    if "cfg2-ml" in which:
+        p = workloads.config2()
+        part = multilevel_partition(rip_graph(p.A), p.K)
+        out.setdefault("cfg2", {})["partition_ml_sha"] = int(
+            np.sum(part.astype(np.int64) * np.arange(1, p.n + 1, dtype=np.int64)) % (2**61 - 1))
+        print("cfg2 multilevel partition hash", out["cfg2"]["partition_ml_sha"], flush=True)
     if "cfg3" in which:
         p = workloads.config3()
         out["cfg3"] = run("cfg3", p.A, p.f, p.part(), p.K)

@@ -116,6 +116,14 @@ def test_partition_cd3d_64cubed(dev, golden):
     assert partition_hash(part) == golden["cfg2"]["partition_sha"]
 
 
+def test_multilevel_partition_cd3d_64cubed(dev, golden):
+    banner("multilevel partition of the 64^3 convection-diffusion row graph, K=32: bit-exact")
+    p = config2()
+    g = bc.rip_graph(p.n, p.A.rowptr, p.A.col, p.A.val)
+    part = bc.bc_partition_multilevel(g, p.K)
+    assert partition_hash(part) == golden["cfg2"]["partition_ml_sha"]
+
+
 def test_solve_cd3d_64cubed_inner_cg(dev, golden):
     banner("FP64 inner-CG solve, 64^3 convection-diffusion, K=32 greedy partition")
     p = config2()
