@@ -185,6 +185,30 @@ bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, doubl
 bc_status bc_solve_multi(bc_ctx* ctx, int32_t nrhs, const double* f, const double* x0,
                          double tol, int32_t maxit, double* x, bc_stats* stats);
 
+/* Block CG on H X = Xi for nrhs right-hand sides of the one system of a
+ * bc_setup context: one Krylov space for all of them, the stabilized
+ * block-CG acceleration that Section 3.1 names for multiple right-hand sides
+ * (the paper itself uses Algorithm 2 per right-hand side).  Per iteration:
+ * Q = H P for the p <= nrhs search directions P (orthonormal columns),
+ * alpha = (P^T Q)^{-1} P^T R, X += P alpha, R -= Q alpha; the true residual
+ * f_j - A x_j of every column still running is tested (relative 2-norm
+ * <= tol, as bc_solve) and columns that meet it stop; then
+ * beta = -(P^T Q)^{-1} Q^T R and the next P is an orthonormal basis of
+ * R + P beta over the running columns, a direction whose part outside the
+ * span of those before it is below 1e-5 of its norm being dropped (repeated
+ * or dependent right-hand sides).  The products with H take all p
+ * directions at once (as bc_solve_multi); the p x p algebra runs on the host
+ * in FP64 between device reductions.  With FP32 projections (BC_MIXED,
+ * BC_MIXED_PROJ) R is recomputed from the FP64 true residual every
+ * replace_every iterations, R = A^T D^{-1} (f - A x), and the directions
+ * restart from it (stats.replacements counts these).  Arguments and layout as
+ * bc_solve_multi; stats[j].iterations counts the block iterations until
+ * column j stopped.  1 <= nrhs <= 16.  Returns the worst status;
+ * BC_ERR_BREAKDOWN if P^T Q is not positive definite or no direction is left
+ * while columns run (x holds the last iterate). */
+bc_status bc_solve_block(bc_ctx* ctx, int32_t nrhs, const double* f, const double* x0,
+                         double tol, int32_t maxit, double* x, bc_stats* stats);
+
 /* Algorithm 1 (plain block Cimmino, Section 1, eq. (iterscheme)):
  * x <- x + omega sum_i A_i^+ (f_i - A_i x), from x0 (device float64[n], or
  * NULL for zero), until ||f - A x||_2 <= tol ||f||_2 (the residual of the

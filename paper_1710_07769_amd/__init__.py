@@ -89,6 +89,8 @@ _SIGS = {
                              C.POINTER(bc_stats)]),
     "bc_solve_multi": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, C.c_int32, _P,
                                  C.POINTER(bc_stats)]),
+    "bc_solve_block": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, C.c_int32, _P,
+                                 C.POINTER(bc_stats)]),
     "bc_info": (C.c_int, [_P, _I64P, _I32P, _I32P, _I32P]),
     "bc_block_info": (C.c_int, [_P, _I32P, _I32P]),
     "bc_schedule": (C.c_int, [_P, _I32P, _I32P]),
@@ -231,6 +233,22 @@ def bc_solve_multi(ctx, nrhs: int, f, x0, tol: float, maxit: int, x) -> List[bc_
     s = _lib.bc_solve_multi(ctx, nrhs, _dev(f, "f"), None if x0 is None else _dev(x0, "x0"),
                             float(tol), int(maxit), _dev(x, "x"), st)
     _check(s, "bc_solve_multi", ok=(BC_OK, BC_NOT_CONVERGED, BC_ERR_BREAKDOWN))
+    return list(st)
+
+
+def bc_solve_block(ctx, nrhs: int, f, x0, tol: float, maxit: int, x) -> List[bc_stats]:
+    """Block CG on H for nrhs right-hand sides of one system (layout as
+    bc_solve_multi); one stats entry per right-hand side."""
+    nrhs = int(nrhs)
+    if nrhs < 1:
+        raise ValueError("nrhs must be >= 1")
+    for t, name in ((f, "f"), (x, "x")) + (() if x0 is None else ((x0, "x0"),)):
+        if t.numel() != nrhs * bc_info(ctx)["n_total"]:
+            raise ValueError("%s must hold nrhs * n entries" % name)
+    st = (bc_stats * nrhs)()
+    s = _lib.bc_solve_block(ctx, nrhs, _dev(f, "f"), None if x0 is None else _dev(x0, "x0"),
+                            float(tol), int(maxit), _dev(x, "x"), st)
+    _check(s, "bc_solve_block", ok=(BC_OK, BC_NOT_CONVERGED, BC_ERR_BREAKDOWN))
     return list(st)
 
 
@@ -377,6 +395,13 @@ class BlockCimmino:
         import torch
         X = torch.empty_like(F)
         return X, bc_solve_multi(self.ctx, F.shape[0], F, X0, tol, maxit, X)
+
+    def solve_block(self, F, X0=None, tol=1e-10, maxit=10000):
+        """Block CG on H for the rows of F (nrhs x n): X (nrhs x n) and one
+        stats entry per right-hand side."""
+        import torch
+        X = torch.empty_like(F)
+        return X, bc_solve_block(self.ctx, F.shape[0], F, X0, tol, maxit, X)
 
     def cimmino(self, f, omega, x0=None, tol=1e-10, maxit=10000):
         """Algorithm 1 on this context: x, per-system stats."""

@@ -287,6 +287,9 @@ struct MultiView {
   double *d_final = nullptr, *d_normA = nullptr, *d_finf = nullptr;
   double *d_r = nullptr, *d_p = nullptr, *d_psi = nullptr;
   double *d_s = nullptr, *d_u = nullptr, *d_y = nullptr, *d_f = nullptr;
+  // block CG only (allocated on its first call): the next directions Z,
+  // Gram partials and results, and the coefficient matrices of the updates
+  double *d_z = nullptr, *d_gpart = nullptr, *d_gout = nullptr, *d_coef = nullptr;
 };
 
 }  // namespace
@@ -2019,6 +2022,7 @@ bc_status build_view(bc_ctx* c, int nrhs) {
   BC_HIP(hipStreamSynchronize(c->stream));
   v.arena.release();
   v.nrhs = 0;
+  v.d_z = v.d_gpart = v.d_gout = v.d_coef = nullptr;
   hipStream_t st = c->stream;
   const int n1 = c->n_total, T1 = c->ntiles;
   std::vector<int> ts1(T1 + 1), perm1(n1);
@@ -2096,6 +2100,371 @@ extern "C" bc_status bc_solve_multi(bc_ctx* c, int32_t nrhs, const double* f, co
   swap_view(c, *c->mview);
   c->mrhs = m;
   const bc_status rc = solve_impl(c, f, x0, tol, maxit, x, stats);
+  c->mrhs = MultiRhs{};
+  swap_view(c, *c->mview);
+  return rc;
+}
+
+namespace {
+
+// ---- block CG on H (several right-hand sides, one Krylov space).  The small
+// dense algebra runs on the host in FP64; matrices are row-major.
+
+// M = L L^T from the lower triangle of the p x p matrix M; false if a pivot
+// is not positive and finite.
+bool chol_lower(const std::vector<double>& M, int p, std::vector<double>& L) {
+  L.assign((size_t)p * p, 0.0);
+  for (int j = 0; j < p; ++j) {
+    double d = M[(size_t)j * p + j];
+    for (int k = 0; k < j; ++k) d -= L[(size_t)j * p + k] * L[(size_t)j * p + k];
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    const double ljj = std::sqrt(d);
+    L[(size_t)j * p + j] = ljj;
+    for (int i = j + 1; i < p; ++i) {
+      double sum = M[(size_t)i * p + j];
+      for (int k = 0; k < j; ++k) sum -= L[(size_t)i * p + k] * L[(size_t)j * p + k];
+      L[(size_t)i * p + j] = sum / ljj;
+    }
+  }
+  return true;
+}
+
+// B <- (L L^T)^{-1} B for B of p rows and a columns.
+void chol_solve(const std::vector<double>& L, int p, std::vector<double>& B, int a) {
+  for (int c = 0; c < a; ++c) {
+    for (int i = 0; i < p; ++i) {
+      double sum = B[(size_t)i * a + c];
+      for (int k = 0; k < i; ++k) sum -= L[(size_t)i * p + k] * B[(size_t)k * a + c];
+      B[(size_t)i * a + c] = sum / L[(size_t)i * p + i];
+    }
+    for (int i = p - 1; i >= 0; --i) {
+      double sum = B[(size_t)i * a + c];
+      for (int k = i + 1; k < p; ++k) sum -= L[(size_t)k * p + i] * B[(size_t)k * a + c];
+      B[(size_t)i * a + c] = sum / L[(size_t)i * p + i];
+    }
+  }
+}
+
+// Orthonormal directions from the Gram matrix G (a x a) of the columns of Z:
+// the columns scaled to unit norm, a Cholesky factorization of their Gram
+// matrix column by column, a column whose pivot is at most drop left out.
+// Returns r and T (a x r) with Z T = Zn[:, kept] L^{-T}, orthonormal columns.
+int orth_from_gram(const std::vector<double>& G, int a, double drop, std::vector<double>& T) {
+  std::vector<double> d(a);
+  std::vector<int> kept;
+  for (int j = 0; j < a; ++j) {
+    d[j] = std::sqrt(std::max(G[(size_t)j * a + j], 0.0));
+    if (d[j] > 0.0) kept.push_back(j);
+  }
+  const int k = (int)kept.size();
+  auto gn = [&](int x, int y) {
+    return G[(size_t)kept[x] * a + kept[y]] / (d[kept[x]] * d[kept[y]]);
+  };
+  std::vector<double> L((size_t)k * k, 0.0), l;
+  std::vector<int> keep2;
+  for (int q = 0; q < k; ++q) {
+    const int r = (int)keep2.size();
+    l.assign(r, 0.0);
+    for (int i = 0; i < r; ++i) {
+      double sum = gn(keep2[i], q);
+      for (int m = 0; m < i; ++m) sum -= L[(size_t)i * k + m] * l[m];
+      l[i] = sum / L[(size_t)i * k + i];
+    }
+    double piv = gn(q, q);
+    for (int i = 0; i < r; ++i) piv -= l[i] * l[i];
+    if (piv > drop) {
+      for (int i = 0; i < r; ++i) L[(size_t)r * k + i] = l[i];
+      L[(size_t)r * k + r] = std::sqrt(piv);
+      keep2.push_back(q);
+    }
+  }
+  const int r = (int)keep2.size();
+  std::vector<double> Li((size_t)r * r, 0.0);  // L^{-1}, lower
+  for (int c = 0; c < r; ++c)
+    for (int i = c; i < r; ++i) {
+      double sum = i == c ? 1.0 : 0.0;
+      for (int m = c; m < i; ++m) sum -= L[(size_t)i * k + m] * Li[(size_t)m * r + c];
+      Li[(size_t)i * r + c] = sum / L[(size_t)i * k + i];
+    }
+  T.assign((size_t)a * r, 0.0);
+  for (int i = 0; i < r; ++i) {
+    const int col = kept[keep2[i]];
+    for (int c = 0; c < r; ++c) T[(size_t)col * r + c] = Li[(size_t)c * r + i] / d[col];
+  }
+  return r;
+}
+
+ColList cols(double* base, long long n1, const std::vector<int>& idx) {
+  ColList L{};
+  L.c = (int)idx.size();
+  for (size_t q = 0; q < idx.size(); ++q) L.v[q] = base + idx[q] * n1;
+  return L;
+}
+ColList cols_first(double* base, long long n1, int count) {
+  ColList L{};
+  L.c = count;
+  for (int q = 0; q < count; ++q) L.v[q] = base + q * n1;
+  return L;
+}
+ColList cat(const ColList& a, const ColList& b) {
+  ColList L = a;
+  for (int q = 0; q < b.c; ++q) L.v[a.c + q] = b.v[q];
+  L.c = a.c + b.c;
+  return L;
+}
+
+// Squared 2-norm of each of the nr vectors from per-(vector, tile) partials,
+// summed in tile order.
+bc_status vector_sq_norms(bc_ctx* c, const double* part, int nr, int T1, std::vector<double>& out) {
+  std::vector<double> h((size_t)nr * T1);
+  BC_HIP(hipMemcpyAsync(h.data(), part, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  BC_HIP(hipStreamSynchronize(c->stream));
+  out.assign(nr, 0.0);
+  for (int j = 0; j < nr; ++j)
+    for (int t = 0; t < T1; ++t) out[j] += h[(size_t)j * T1 + t];
+  return BC_OK;
+}
+
+// The block CG iteration of the oracle's block_cimmino_block_cg, on the view
+// of nrhs right-hand sides (context state swapped in; c->mrhs set).
+bc_status block_cg_impl(bc_ctx* c, const double* f, const double* x0, double tol, int maxit,
+                        double* x, bc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!f || !x || !(tol >= 0.0) || maxit < 0) {
+    bc_set_error("bc_solve_block: null f/x, negative tol or maxit");
+    return BC_ERR_INVALID;
+  }
+  const bc_opts& o = c->opts;
+  if (o.stop_rule != BC_STOP_REL2) {
+    bc_set_error("bc_solve_block stops on the relative residual only (stop_rule BC_STOP_REL2)");
+    return BC_ERR_INVALID;
+  }
+  MultiView& v = *c->mview;
+  hipStream_t st = c->stream;
+  const int nr = c->nsys, n = c->n_total;
+  const int n1 = c->mrhs.n1, T1 = c->mrhs.ntiles1;
+  const double drop = 1e-10;
+  if (!v.d_z) {
+    BC_TRY(v.arena.alloc(&v.d_z, (size_t)n));
+    BC_TRY(v.arena.alloc(&v.d_gpart, (size_t)BG_GROUPS * BG_PAIRS));
+    BC_TRY(v.arena.alloc(&v.d_gout, (size_t)BG_PAIRS));
+    BC_TRY(v.arena.alloc(&v.d_coef, (size_t)4 * BG_MAX * BG_MAX));
+    BC_HIP(prepare_block_gram());
+  }
+  double* coef_a = v.d_coef;
+  double* coef_ma = v.d_coef + BG_MAX * BG_MAX;
+  double* coef_b = v.d_coef + 2 * BG_MAX * BG_MAX;
+  double* coef_t = v.d_coef + 3 * BG_MAX * BG_MAX;
+  // the coefficient uploads come from host vectors that live until the
+  // stream is synchronised at the next readback
+  auto upload = [&](double* dst, const std::vector<double>& h) -> bc_status {
+    if (!h.empty())
+      BC_HIP(hipMemcpyAsync(dst, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    return BC_OK;
+  };
+  auto gram = [&](const ColList& L1, const ColList& L2, std::vector<double>& out) -> bc_status {
+    BC_HIP(launch_block_gram(st, L1, L2, n1, v.d_gpart, v.d_gout));
+    out.resize((size_t)L1.c * L2.c);
+    BC_HIP(hipMemcpyAsync(out.data(), v.d_gout, out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+    BC_HIP(hipStreamSynchronize(st));
+    return BC_OK;
+  };
+  BC_TRY(enter(c, o.stream));
+  OuterState S = c->outer(maxit, 0);
+  OuterState Sall = S;
+  Sall.done = c->d_zero_flags;
+  // f in block order, x = x0 (or 0), s = f - A x, ||f||^2 and ||s||^2 per vector
+  BC_HIP(launch_gather(st, f, c->d_perm, c->d_f, n));
+  if (x0) BC_HIP(launch_copy(st, x0, x, n)); else BC_HIP(launch_zero(st, x, n));
+  BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, Sall, nullptr));
+  BC_HIP(launch_sqnorm_tiles(st, c->d_f, c->d_part_f, Sall));
+  std::vector<double> ff, ss;
+  BC_TRY(vector_sq_norms(c, c->d_part_f, nr, T1, ff));
+  BC_TRY(vector_sq_norms(c, c->d_part_c, nr, T1, ss));
+  BC_HIP(hipMemsetAsync(c->d_inner_total, 0, sizeof(unsigned long long), st));
+  BC_TRY(reset_proj_counters(c));
+  c->timing = true;
+  std::vector<int> iters(nr, 0), status(nr, BC_NOT_CONVERGED), replacements(nr, 0), act;
+  for (int j = 0; j < nr; ++j) {
+    if (ff[j] == 0.0 || std::sqrt(ss[j]) <= tol * std::sqrt(ff[j])) status[j] = BC_OK;
+    else act.push_back(j);
+  }
+  std::vector<int> flags(nr);
+  // device flags per vector: 1 for the active vectors (or for the others)
+  auto set_flags = [&](int* dev, bool mark_active) -> bc_status {
+    for (int j = 0; j < nr; ++j) flags[j] = mark_active ? 0 : 1;
+    for (int j : act) flags[j] = mark_active ? 1 : 0;
+    BC_HIP(hipMemcpyAsync(dev, flags.data(), nr * sizeof(int), hipMemcpyHostToDevice, st));
+    BC_HIP(hipStreamSynchronize(st));  // flags is reused
+    return BC_OK;
+  };
+  std::vector<double> G, T, M, Lm, PQ, alpha, malpha, beta, QRn;
+  if (!act.empty()) {
+    // R = Xi - H X = A^T D^{-1} s for the active vectors (done marks the others)
+    BC_TRY(set_flags(c->d_done, false));
+    OuterState Sact = S;
+    Sact.done = c->d_done;
+    BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
+    BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, c->d_r, c->d_p, Sact));
+    // first directions: an orthonormal basis of the active columns of R
+    ColList Ract = cols(c->d_r, n1, act);
+    BC_TRY(gram(Ract, Ract, G));
+    int p = orth_from_gram(G, (int)act.size(), drop, T);
+    BC_TRY(upload(coef_t, T));
+    BC_HIP(launch_block_combine(st, Ract, cols_first(c->d_p, n1, p), ColList{}, coef_t, n1));
+    for (int t = 1; t <= maxit; ++t) {
+      if (p == 0) {
+        for (int j : act) status[j] = BC_ERR_BREAKDOWN;
+        break;
+      }
+      const int a = (int)act.size();
+      // Q = H P for the p directions
+      c->mrhs.nrhs = p;
+      BC_HIP(spmv_a(c, st, c->lanes, c->d_p, c->d_u, Sall, false));
+      const bc_status rs = block_solves(c, c->d_u, c->d_y, nullptr);
+      if (rs == BC_OK) BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, c->d_psi, c->d_p, Sall));
+      c->mrhs.nrhs = nr;
+      BC_TRY(rs);
+      const ColList P = cols_first(c->d_p, n1, p), Q = cols_first(c->d_psi, n1, p);
+      Ract = cols(c->d_r, n1, act);
+      // [P Q]^T [Q R_act]: M = P^T Q, P^T R, Q^T Q, Q^T R
+      BC_TRY(gram(cat(P, Q), cat(Q, Ract), PQ));
+      const int c2 = p + a;
+      M.assign((size_t)p * p, 0.0);
+      alpha.assign((size_t)p * a, 0.0);
+      for (int i = 0; i < p; ++i) {
+        for (int k = 0; k < p; ++k) M[(size_t)i * p + k] = PQ[(size_t)i * c2 + k];
+        for (int j = 0; j < a; ++j) alpha[(size_t)i * a + j] = PQ[(size_t)i * c2 + p + j];
+      }
+      if (!chol_lower(M, p, Lm)) {
+        for (int j : act) status[j] = BC_ERR_BREAKDOWN;
+        break;
+      }
+      chol_solve(Lm, p, alpha, a);
+      malpha.resize(alpha.size());
+      for (size_t e = 0; e < alpha.size(); ++e) malpha[e] = -alpha[e];
+      BC_TRY(upload(coef_a, alpha));
+      BC_TRY(upload(coef_ma, malpha));
+      const ColList Xact = cols(x, n1, act);
+      BC_HIP(launch_block_combine(st, P, Xact, Xact, coef_a, n1));
+      BC_HIP(launch_block_combine(st, Q, Ract, Ract, coef_ma, n1));
+      // true residuals of the active vectors and the stop test
+      BC_TRY(set_flags(c->d_mask, true));
+      BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, Sall, c->d_mask));
+      BC_TRY(vector_sq_norms(c, c->d_part_c, nr, T1, ss));
+      harvest_proj_events(c);
+      std::vector<int> still, pos;  // pos: index of each remaining vector in act
+      for (int q = 0; q < a; ++q) {
+        const int j = act[q];
+        iters[j] = t;
+        if (std::sqrt(ss[j]) <= tol * std::sqrt(ff[j])) {
+          status[j] = BC_OK;
+        } else {
+          still.push_back(j);
+          pos.push_back(q);
+        }
+      }
+      act = still;
+      if (act.empty()) break;
+      const int a2 = (int)act.size();
+      if (c->mixed && o.replace_every > 0 && t % o.replace_every == 0) {
+        // FP32 projections: the recursive R drifts from Xi - H X by the
+        // rounding of the FP32 operator, so every replace_every iterations R
+        // is recomputed from the true residual, R = A^T D^{-1} s, and the
+        // iteration restarts with directions from it
+        BC_TRY(set_flags(c->d_done, false));
+        OuterState Sact = S;
+        Sact.done = c->d_done;
+        BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
+        BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, c->d_r, c->d_psi, Sact));
+        Ract = cols(c->d_r, n1, act);
+        BC_TRY(gram(Ract, Ract, G));
+        p = orth_from_gram(G, a2, drop, T);
+        BC_TRY(upload(coef_t, T));
+        BC_HIP(launch_block_combine(st, Ract, cols_first(c->d_p, n1, p), ColList{}, coef_t, n1));
+        for (int j : act) replacements[j]++;
+        continue;
+      }
+      // Q^T R after the update = Q^T R - (Q^T Q) alpha; beta = -M^{-1} Q^T R
+      QRn.assign((size_t)p * a2, 0.0);
+      for (int i = 0; i < p; ++i)
+        for (int q = 0; q < a2; ++q) {
+          double sum = PQ[(size_t)(p + i) * c2 + p + pos[q]];
+          for (int k = 0; k < p; ++k)
+            sum -= PQ[(size_t)(p + i) * c2 + k] * alpha[(size_t)k * a + pos[q]];
+          QRn[(size_t)i * a2 + q] = sum;
+        }
+      chol_solve(Lm, p, QRn, a2);
+      beta.resize(QRn.size());
+      for (size_t e = 0; e < QRn.size(); ++e) beta[e] = -QRn[e];
+      // Z = R_act + P beta, then its orthonormal basis as the next directions
+      Ract = cols(c->d_r, n1, act);
+      const ColList Z = cols_first(v.d_z, n1, a2);
+      BC_TRY(upload(coef_b, beta));
+      BC_HIP(launch_block_combine(st, P, Z, Ract, coef_b, n1));
+      BC_TRY(gram(Z, Z, G));
+      p = orth_from_gram(G, a2, drop, T);
+      BC_TRY(upload(coef_t, T));
+      BC_HIP(launch_block_combine(st, Z, cols_first(c->d_p, n1, p), ColList{}, coef_t, n1));
+    }
+  }
+  unsigned long long inner_total = 0;
+  BC_HIP(hipMemcpyAsync(&inner_total, c->d_inner_total, sizeof(inner_total), hipMemcpyDeviceToHost, st));
+  BC_HIP(hipStreamSynchronize(st));
+  harvest_proj_events(c);
+  c->timing = false;
+  double pbytes = 0.0;
+  BC_TRY(proj_bytes(c, &pbytes));
+  {
+    int* err = inner_err_flag();
+    int h = 0;
+    BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
+    if (h) {
+      bc_set_error("inner CG workgroups timed out waiting for each other");
+      return BC_ERR_DEVICE;
+    }
+  }
+  const double t_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats)
+    BC_TRY(fill_stats(c, x, Sall, iters, status, replacements, t_ms, pbytes, inner_total, stats));
+  BC_TRY(leave(c, o.stream));
+  int worst = BC_OK;
+  for (int j = 0; j < nr; ++j) {
+    const int sv = status[j];
+    if (sv < 0 && (worst >= 0 || sv < worst)) worst = sv;
+    else if (sv > 0 && worst == BC_OK) worst = sv;
+  }
+  return (bc_status)worst;
+}
+
+}  // namespace
+
+extern "C" bc_status bc_solve_block(bc_ctx* c, int32_t nrhs, const double* f, const double* x0,
+                                    double tol, int32_t maxit, double* x, bc_stats* stats) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  if (c->nsys != 1) {
+    bc_set_error("bc_solve_block needs a one-system context (bc_setup)");
+    return BC_ERR_INVALID;
+  }
+  if (nrhs < 1 || nrhs > BG_MAX / 2 || (long long)nrhs * c->n_total > INT32_MAX) {
+    bc_set_error("bc_solve_block: nrhs must be in [1, 16] and nrhs * n below 2^31");
+    return BC_ERR_INVALID;
+  }
+  if (!c->have_sell) {
+    bc_set_error("bc_solve_block needs the sliced-ELL copies of A (bc_opts.spmv_lanes = -1 "
+                 "builds them whatever their padding)");
+    return BC_ERR_INVALID;
+  }
+  BC_TRY(build_view(c, nrhs));
+  const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start};
+  swap_view(c, *c->mview);
+  c->mrhs = m;
+  const bc_status rc = block_cg_impl(c, f, x0, tol, maxit, x, stats);
   c->mrhs = MultiRhs{};
   swap_view(c, *c->mview);
   return rc;

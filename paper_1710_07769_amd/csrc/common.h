@@ -207,6 +207,26 @@ struct MultiRhs {
   int ntiles1;
   const int* tile_start;
 };
+// Block CG on H: products of short lists of n-vectors (column k at v[k]).
+constexpr int BG_MAX = 32;       // columns per list (16 for combine outputs)
+constexpr int BG_ROWS = 128;     // rows per Gram tile
+constexpr int BG_LD = BG_ROWS + 1;  // LDS column stride of a Gram tile
+constexpr int BG_THREADS = 256;
+constexpr int BG_PAIRS = 1024;   // c1 * c2 at most
+constexpr int BG_GROUPS = 512;   // Gram workgroups (partials per pair)
+struct ColList {
+  double* v[BG_MAX];
+  int c;
+};
+// Lets the Gram kernel stage two full lists (once, before its first use).
+hipError_t prepare_block_gram();
+// out[a * c2 + b] = L1_a . L2_b (device, c1*c2 doubles); part: BG_GROUPS * c1 * c2.
+hipError_t launch_block_gram(hipStream_t st, const ColList& L1, const ColList& L2, int n,
+                             double* part, double* out);
+// out_j = base_j + sum_k in_k coef[k * out.c + j] (base.c = 0: no base term;
+// base may list the output vectors themselves).
+hipError_t launch_block_combine(hipStream_t st, const ColList& in, const ColList& out,
+                                const ColList& base, const double* coef, int n);
 hipError_t launch_spmv_sell_multi(hipStream_t st, const SellMat& A, const MultiRhs& M, bool mixed,
                                   const double* x, double* y, const OuterState& S, bool skip_done);
 hipError_t launch_spmvT_dot_sell_multi(hipStream_t st, const SellMat& AT, const MultiRhs& M,

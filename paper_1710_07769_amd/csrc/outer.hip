@@ -373,6 +373,94 @@ k_residual_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x,
       if (act[q]) S.part_c[(j0 + q) * M.ntiles1 + t] = ss[q];
 }
 
+// ---- block CG on H: tall-skinny products of a few vectors of length n.
+// Gram: G[a][b] = V1_a . V2_b for the columns of two lists.  A fixed number
+// of workgroups walk the 128-row tiles (tile t by workgroup t mod groups);
+// each stages the tile's columns in LDS and sums its pairs over the rows in
+// order, then writes one partial per pair; k_block_gram_reduce adds the
+// partials of a pair in workgroup order.  The order of every sum is fixed by
+// n and the list sizes, so the result is reproducible.
+__global__ void __launch_bounds__(BG_THREADS)
+k_block_gram(ColList L1, ColList L2, int n, double* __restrict__ part) {
+  extern __shared__ double gsh[];  // c1 + c2 columns of BG_LD (odd: no bank conflicts)
+  const int c1 = L1.c, c2 = L2.c, np = c1 * c2;
+  const int tid = threadIdx.x, r = tid % BG_ROWS, h = tid / BG_ROWS;
+  static_assert(BG_THREADS == 2 * BG_ROWS, "two columns per staging pass");
+  double acc[BG_PAIRS / BG_THREADS];
+#pragma unroll
+  for (int k = 0; k < BG_PAIRS / BG_THREADS; ++k) acc[k] = 0.0;
+  const int ntl = (n + BG_ROWS - 1) / BG_ROWS;
+  for (int tl = blockIdx.x; tl < ntl; tl += gridDim.x) {
+    const int r0 = tl * BG_ROWS;
+    const bool in = r0 + r < n;
+    __syncthreads();
+#pragma unroll
+    for (int cc = 0; cc < BG_MAX; cc += 2) {
+      const int col = cc + h;
+      if (cc < c1) {
+        const double* v = h ? L1.v[cc + 1] : L1.v[cc];
+        if (col < c1) gsh[col * BG_LD + r] = in ? v[r0 + r] : 0.0;
+      }
+      if (cc < c2) {
+        const double* v = h ? L2.v[cc + 1] : L2.v[cc];
+        if (col < c2) gsh[(c1 + col) * BG_LD + r] = in ? v[r0 + r] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < BG_PAIRS / BG_THREADS; ++k) {
+      const int pr = tid + k * BG_THREADS;
+      if (pr < np) {
+        const double* x = gsh + (pr / c2) * BG_LD;
+        const double* y = gsh + (c1 + pr % c2) * BG_LD;
+        double sum = acc[k];
+        for (int q = 0; q < BG_ROWS; ++q) sum += x[q] * y[q];
+        acc[k] = sum;
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < BG_PAIRS / BG_THREADS; ++k) {
+    const int pr = tid + k * BG_THREADS;
+    if (pr < np) part[(size_t)blockIdx.x * np + pr] = acc[k];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_block_gram_reduce(const double* __restrict__ part, int groups, int np, double* __restrict__ out) {
+  __shared__ double sh[4];
+  const int pr = blockIdx.x;
+  double sum = 0.0;
+  for (int g = threadIdx.x; g < groups; g += blockDim.x) sum += part[(size_t)g * np + pr];
+  sum = block_sum(sum, sh);
+  if (threadIdx.x == 0) out[pr] = sum;
+}
+
+// out_j = base_j + sum_k in_k * coef[k][j] (coef row-major, ci x co; base may
+// be the output itself, or absent), one row per thread, k in order.
+__global__ void __launch_bounds__(256)
+k_block_combine(ColList in, ColList outl, ColList base, const double* __restrict__ coef, int n) {
+  __shared__ double cs[BG_MAX * BG_MAX / 2];
+  const int ci = in.c, co = outl.c;
+  for (int e = threadIdx.x; e < ci * co; e += blockDim.x) cs[e] = coef[e];
+  __syncthreads();
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double v[BG_MAX];
+#pragma unroll
+  for (int k = 0; k < BG_MAX; ++k) v[k] = k < ci ? in.v[k][row] : 0.0;
+#pragma unroll
+  for (int j = 0; j < BG_MAX / 2; ++j) {
+    if (j < co) {
+      double sum = base.c > j ? base.v[j][row] : 0.0;
+#pragma unroll
+      for (int k = 0; k < BG_MAX; ++k)
+        if (k < ci) sum += v[k] * cs[k * co + j];
+      outl.v[j][row] = sum;
+    }
+  }
+}
+
 // psi[j] = sum over column j of A of a_ij * y[i] (stored A^T), plus the
 // tile's partial of p . psi.
 template <int L, bool MIXED>
@@ -979,5 +1067,32 @@ hipError_t launch_residual_sell_multi(hipStream_t st, const SellMat& A, const Mu
   const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
   hipLaunchKernelGGL((k_residual_sell_multi<SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0, st, A, M,
                      x, f, s, S, mask);
+  return hipGetLastError();
+}
+
+hipError_t prepare_block_gram() {
+  return hipFuncSetAttribute((const void*)k_block_gram, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)(BG_LD * 2 * BG_MAX * sizeof(double)));
+}
+
+hipError_t launch_block_gram(hipStream_t st, const ColList& L1, const ColList& L2, int n,
+                             double* part, double* out) {
+  const int np = L1.c * L2.c;
+  if (np == 0) return hipSuccess;
+  if (L1.c > BG_MAX || L2.c > BG_MAX || np > BG_PAIRS) return hipErrorInvalidValue;
+  const int ntl = (n + BG_ROWS - 1) / BG_ROWS;
+  const int groups = ntl < BG_GROUPS ? ntl : BG_GROUPS;
+  const size_t lds = (size_t)BG_LD * (L1.c + L2.c) * sizeof(double);
+  hipLaunchKernelGGL(k_block_gram, dim3(groups), dim3(BG_THREADS), lds, st, L1, L2, n, part);
+  hipLaunchKernelGGL(k_block_gram_reduce, dim3(np), dim3(256), 0, st, part, groups, np, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_block_combine(hipStream_t st, const ColList& in, const ColList& out,
+                                const ColList& base, const double* coef, int n) {
+  if (out.c == 0) return hipSuccess;
+  if (in.c > BG_MAX || out.c > BG_MAX / 2 || base.c > BG_MAX / 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_block_combine, dim3((n + 255) / 256), dim3(256), 0, st, in, out, base, coef,
+                     n);
   return hipGetLastError();
 }
