@@ -49,10 +49,12 @@ def parse():
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed", "mixed-proj"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=20)
-    ap.add_argument("--method", default="cg", choices=["cg", "alg1"],
-                    help="cg: Algorithm 2 (default); alg1: Algorithm 1 (plain block Cimmino) "
+    ap.add_argument("--method", default="cg", choices=["cg", "alg1", "block"],
+                    help="cg: Algorithm 2 (default; with --nrhs, one CG per right-hand side "
+                         "through bc_solve_multi); alg1: Algorithm 1 (plain block Cimmino) "
                          "with omega = 2 / (lambda_min + lambda_max) of H estimated by Lanczos "
-                         "through bc_project before the timed solve")
+                         "through bc_project before the timed solve; block: block CG on H for "
+                         "the --nrhs right-hand sides (bc_solve_block)")
     ap.add_argument("--partitioner", default="greedy", choices=["greedy", "multilevel"],
                     help="partitioner of the rip_graph workloads (the configurations name the "
                          "greedy one)")
@@ -184,6 +186,9 @@ def run_step(wl, f_dev, method="cg", partitioner="greedy", nrhs=None):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             sts = bc.bc_cimmino(ctx, f_dev, None, spec.omega_opt, wl.tol, 100000, x)
+        elif method == "block":
+            t0 = time.perf_counter()
+            sts = bc.bc_solve_block(ctx, nrhs, f_dev, None, wl.tol, 10000, x)
         elif nrhs is not None:
             t0 = time.perf_counter()
             sts = bc.bc_solve_multi(ctx, nrhs, f_dev, None, wl.tol, 10000, x)
@@ -351,9 +356,12 @@ def main():
     if args.method == "alg1" and wl.batched:
         raise SystemExit("--method alg1 takes a single-system workload")
     xstar = np.concatenate([q.xstar for q in wl.problems])
+    if args.method == "block" and args.nrhs is None:
+        raise SystemExit("--method block needs --nrhs")
     if args.nrhs is not None:
-        if wl.batched or args.method != "cg" or args.nrhs < 1:
-            raise SystemExit("--nrhs takes a single-system workload, --method cg and nrhs >= 1")
+        if wl.batched or args.method == "alg1" or args.nrhs < 1:
+            raise SystemExit("--nrhs takes a single-system workload, --method cg or block and "
+                             "nrhs >= 1")
         import workloads as W
         q = wl.problems[0]
         F, Xs = W.multi_rhs(q.A, args.nrhs, seed=1000)
@@ -401,7 +409,9 @@ def main():
                                           if args.method == "alg1" else "")
                    + ("; multilevel partitioner" if args.partitioner == "multilevel"
                       and wl.partition == "greedy-rip" else "")
-                   + ("; %d right-hand sides solved together (bc_solve_multi)" % args.nrhs
+                   + ("; %d right-hand sides solved together (%s)"
+                      % (args.nrhs, "bc_solve_block, block CG" if args.method == "block"
+                         else "bc_solve_multi")
                       if args.nrhs is not None else ""),
                    "n": wl.n, "nnz": wl.nnz,
                    "K": [q.K for q in wl.problems][0] if not wl.batched else 8,
