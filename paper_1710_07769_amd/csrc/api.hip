@@ -1455,13 +1455,13 @@ bc_status block_solves(bc_ctx* c, const double* u, double* y, const int* done) {
     BC_HIP(hipEventRecord(c->ev_proj[2 * c->ev_used], st));
   }
   if (c->mrhs.nrhs > 0) {
-    // several right-hand sides: each dense factor is read once for a chunk
-    // of vectors; banded and inner-CG blocks take the vectors one by one
+    // several right-hand sides: each dense or banded factor is read once
+    // for a chunk of vectors; inner-CG blocks take the vectors one by one
     const int nr = c->mrhs.nrhs, n1 = c->mrhs.n1;
     BC_HIP(launch_dense_apply_multi(st, c->dense, c->mixed, u, y, done, nr, n1, c->dense_max_nt));
+    BC_HIP(launch_band_apply_multi(st, c->band, c->mixed, u, y, done, nr, n1));
     for (int j = 0; j < nr; ++j) {
       const size_t o = (size_t)j * n1;
-      BC_HIP(launch_band_apply(st, c->band, c->mixed, u + o, y + o, done ? done + j : nullptr));
       BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u + o, y + o, done ? done + j : nullptr));
     }
   } else {

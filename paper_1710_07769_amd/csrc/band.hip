@@ -16,6 +16,7 @@
 #include "common.h"
 
 #include <cmath>
+#include <utility>
 #include <vector>
 
 std::vector<int> band_nvp_buckets(const BandBlocks& B, size_t elem);
@@ -182,8 +183,11 @@ __device__ __forceinline__ double lane_bcast<double>(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// The computation of one tile of a sweep for lane l (row p): the off-tile
-// part against the window, then the in-tile column sweep; returns w_p.
+// The computation of one tile of a sweep for lane l (row p) and NR vectors
+// (window q at yw + 256 q): the off-tile part against the window, then the
+// in-tile column sweep; leaves w_p of each vector in acc.  The band entries
+// are read once for the NR vectors, whose independent broadcast-and-FMA
+// chains of the column sweep interleave.
 // The window slots of the tile's rows are zero (they held rows 256 back, no
 // longer referenced) and slots of rows below 0 are zero from the start of the
 // sweep, so in-tile and out-of-matrix columns contribute nothing and the
@@ -193,9 +197,9 @@ __device__ __forceinline__ double lane_bcast<double>(double v, int lane) {
 // diagonal slot, so a step is a multiply, a broadcast and an FMA; lane l's
 // value stops changing after step l, and rows past m have a zero pivot
 // reciprocal.
-template <typename T>
-__device__ __forceinline__ T band_tile(const T* buf, const T* yw, T acc, T dp, int p, int l, int bw,
-                                       int ld) {
+template <typename T, int NR>
+__device__ __forceinline__ void band_tile(const T* buf, const T* yw, T (&acc)[NR], T dp, int p,
+                                          int l, int bw, int ld) {
   // The entry indices of the column sweep are the same for every tile; an
   // opaque copy of the lane index keeps the compiler from holding all 64 of
   // them in registers across the tile loop (recomputing them is cheap).
@@ -203,24 +207,30 @@ __device__ __forceinline__ T band_tile(const T* buf, const T* yw, T acc, T dp, i
   const int kb = p - bw;
   int d0 = 0;
   for (; d0 + 8 <= bw; d0 += 8) {
-    T v[8], yk[8];
+    T v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      v[i] = buf[(d0 + i) * 64 + l];
-      yk[i] = yw[(kb + d0 + i) & 255];
+    for (int i = 0; i < 8; ++i) v[i] = buf[(d0 + i) * 64 + l];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      T yk[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) yk[i] = yw[q * 256 + ((kb + d0 + i) & 255)];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[q] -= v[i] * yk[i];
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc -= v[i] * yk[i];
   }
   if (d0 < bw) {
-    T v[8], yk[8];
+    T v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      v[i] = buf[min(d0 + i, ld - 1) * 64 + l];
-      yk[i] = yw[(kb + d0 + i) & 255];
+    for (int i = 0; i < 8; ++i) v[i] = buf[min(d0 + i, ld - 1) * 64 + l];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      T yk[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) yk[i] = yw[q * 256 + ((kb + d0 + i) & 255)];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[q] -= (d0 + i < bw) ? v[i] * yk[i] : (T)0;
     }
-#pragma unroll
-    for (int i = 0; i < 8; ++i) acc -= (d0 + i < bw) ? v[i] * yk[i] : (T)0;
   }
 #pragma unroll
   for (int j0 = 0; j0 < 64; j0 += 8) {
@@ -231,12 +241,15 @@ __device__ __forceinline__ T band_tile(const T* buf, const T* yw, T acc, T dp, i
       e[i] = buf[((unsigned)dd <= (unsigned)bw ? dd : bw) * 64 + l];
     }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const T s = lane_bcast<T>(acc * dp, j0 + i);
-      acc -= e[i] * s;
-    }
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const T s = lane_bcast<T>(acc[q] * dp, j0 + i);
+        acc[q] -= e[i] * s;
+      }
   }
-  return acc * dp;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) acc[q] *= dp;
 }
 
 // One wave per block; lane l owns row p = i0 + l of the current 64-row tile.
@@ -276,20 +289,31 @@ __device__ __forceinline__ void wave_sync() {
 #define BC_LOAD(S, q) if constexpr (NVP > q) S##q = src_[((q) < npre ? (q) : 0) * 64 + l];
 #define BC_STORE(S, q) if constexpr (NVP > q) dst_[((q) < npre ? (q) : 0) * 64 + l] = S##q;
 
-template <typename T, int NVP>
+template <typename T, int NVP, int NR>
 __global__ void __launch_bounds__(64)
 k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
-             const int* __restrict__ done) {
+             const int* __restrict__ done, int nrhs, int n1, int sys_done) {
   extern __shared__ float4 lds4[];
   const int blk = blockIdx.x;
-  if (done && done[B.sys[blk]]) return;
+  // vectors j0 .. j0 + NR - 1 of the nrhs at offsets j * n1; sys_done: one
+  // vector of a batch of systems, stopped with the block's system
+  const int j0 = blockIdx.y * NR;
+  if (sys_done && done && done[B.sys[blk]]) return;
+  bool act[NR];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    act[q] = j0 + q < nrhs && !(!sys_done && done && done[j0 + q]);
+    any = any || act[q];
+  }
+  if (!any) return;
   const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk], row0 = B.row0[blk];
   const int nt = (m + 63) >> 6;
   const int l = threadIdx.x;
   T* stage = (T*)lds4;                         // band of the current tile, 64*ld
-  T* yw = stage + 64 * B.ldmax;                // solved values, circular, 256
-  double* ra = (double*)(yw + 256);            // staged right-hand side of the tile
-  double* rs = ra + 64;                        // staged output scale
+  T* yw = stage + 64 * B.ldmax;                // solved values, circular, 256 per vector
+  double* ra = (double*)(yw + 256 * NR);       // staged right-hand sides of the tile, 64 per vector
+  double* rs = ra + 64 * NR;                   // staged output scale
   T* rd = (T*)(rs + 64);                       // staged pivot reciprocal
   constexpr int VT = 16 / (int)sizeof(T);
   const int nv = ld / VT;          // 16-byte vectors per lane per tile
@@ -308,8 +332,13 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
     dv = (const T*)(B.dinv32 + row0);
   }
   const double* dsc = B.dsc + row0;
-  double* yb = y + row0;
   const int total = 2 * nt;
+  // vector q's right-hand side and output (vectors past nrhs read vector j0;
+  // inactive vectors write nothing)
+  auto ub = [&](int q) -> const double* {
+    return u + (size_t)(j0 + q < nrhs ? j0 + q : j0) * n1 + row0;
+  };
+  auto yb = [&](int q) -> double* { return y + (size_t)(j0 + q < nrhs ? j0 + q : j0) * n1 + row0; };
   // band of tile idx (clamped into the sequence, so any idx is in bounds)
   auto chunk = [&](int idx) -> const float4* {
     idx = min(idx, total - 1);
@@ -325,8 +354,8 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
     const int pc = min((bwd ? idx - nt : idx) * 64 + l, m - 1);
     return bwd ? m - 1 - pc : pc;
   };
-  auto rhs_src = [&](int idx, int r) -> const double* {
-    return min(idx, total - 1) >= nt ? yb + r : u + row0 + r;
+  auto rhs_src = [&](int idx, int q, int r) -> const double* {
+    return min(idx, total - 1) >= nt ? yb(q) + r : ub(q) + r;
   };
   // prologue: tile 0 staged, tile 1 in set A
   {
@@ -334,16 +363,18 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
     float4* dst = (float4*)stage;
     for (int q = 0; q < nv; ++q) dst[q * 64 + l] = src[q * 64 + l];
     const int r = rhs_row(0);
-    ra[l] = u[row0 + r] * dsc[r];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) ra[q * 64 + l] = ub(q)[r] * dsc[r];
     rd[l] = dv[r];
   }
   BC_LIST(BC_DECL, pa)
   BC_LIST(BC_DECL, pb)
-  double xa_a, xa_s, xb_a, xb_s;
+  double xa_a[NR], xb_a[NR], xa_s, xb_s;
   T xa_d, xb_d;
   {
     const int r = rhs_row(1);
-    xa_a = *rhs_src(1, r);
+#pragma unroll
+    for (int q = 0; q < NR; ++q) xa_a[q] = *rhs_src(1, q, r);
     xa_s = dsc[r];
     xa_d = dv[r];
     const float4* src_ = chunk(1);
@@ -365,43 +396,49 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
         __syncthreads();                                                                 \
       }                                                                                  \
       const int r = rhs_row(idx);                                                        \
-      ra[l] = yb[r];                                                                     \
+      _Pragma("unroll") for (int q = 0; q < NR; ++q) ra[q * 64 + l] = yb(q)[r];          \
       rs[l] = dsc[r];                                                                    \
       rd[l] = dv[r];                                                                     \
     }                                                                                    \
     if (t == 0) {                                                                        \
-      _Pragma("unroll") for (int q = 0; q < 4; ++q) yw[q * 64 + l] = (T)0;              \
+      _Pragma("unroll") for (int q = 0; q < 4 * NR; ++q) yw[q * 64 + l] = (T)0;          \
     }                                                                                    \
-    yw[p & 255] = (T)0;                                                                  \
+    _Pragma("unroll") for (int q = 0; q < NR; ++q) yw[q * 256 + (p & 255)] = (T)0;       \
     wave_sync();                                                                         \
-    T acc = p < m ? (T)ra[l] : (T)0;                                                     \
+    T acc[NR];                                                                           \
+    _Pragma("unroll") for (int q = 0; q < NR; ++q) acc[q] = p < m ? (T)ra[q * 64 + l] : (T)0; \
     const T dp = p < m ? rd[l] : (T)0;                                                   \
     const double sc = rs[l];                                                             \
     /* prefetch tile idx+2: right-hand side first, then band */                         \
     {                                                                                    \
       const int r = rhs_row(idx + 2);                                                    \
-      XN##_a = *rhs_src(idx + 2, r);                                                     \
+      _Pragma("unroll") for (int q = 0; q < NR; ++q) XN##_a[q] = *rhs_src(idx + 2, q, r); \
       XN##_s = dsc[r];                                                                   \
       XN##_d = dv[r];                                                                    \
       const float4* src_ = chunk(idx + 2);                                               \
       BC_LIST(BC_LOAD, NXT)                                                              \
     }                                                                                    \
-    const T w = band_tile<T>(stage, yw, acc, dp, p, l, bw, ld);                          \
+    band_tile<T, NR>(stage, yw, acc, dp, p, l, bw, ld);                                  \
     wave_sync(); /* every lane is done with the stage and the window */                 \
-    yw[p & 255] = w;                                                                     \
+    _Pragma("unroll") for (int q = 0; q < NR; ++q) yw[q * 256 + (p & 255)] = acc[q];     \
     if (idx + 1 < total) {                                                               \
       /* stage tile idx+1 (the one wait for HBM per tile) */                            \
       float4* dst_ = (float4*)stage;                                                     \
       BC_LIST(BC_STORE, CUR)                                                             \
       const float4* nsrc = chunk(idx + 1);                                               \
       for (int q = npre; q < nv; ++q) dst_[q * 64 + l] = nsrc[q * 64 + l];               \
-      ra[l] = (idx + 1 >= nt) ? XC##_a : XC##_a * XC##_s;                                \
+      _Pragma("unroll") for (int q = 0; q < NR; ++q)                                     \
+        ra[q * 64 + l] = (idx + 1 >= nt) ? XC##_a[q] : XC##_a[q] * XC##_s;              \
       rs[l] = XC##_s;                                                                    \
       rd[l] = XC##_d;                                                                    \
     }                                                                                    \
     if (p < m) {                                                                         \
-      if (!bwd) yb[p] = (double)w;                                                       \
-      else yb[m - 1 - p] = (double)w * sc;                                               \
+      _Pragma("unroll") for (int q = 0; q < NR; ++q) {                                   \
+        if (act[q]) {                                                                    \
+          if (!bwd) yb(q)[p] = (double)acc[q];                                           \
+          else yb(q)[m - 1 - p] = (double)acc[q] * sc;                                   \
+        }                                                                                \
+      }                                                                                  \
     }                                                                                    \
     wave_sync();                                                                         \
   }
@@ -418,26 +455,72 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
 #undef BC_LOAD
 #undef BC_STORE
 
+// Compute units of the current device (read once).
+int device_cus() {
+  static int cus = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+    return n;
+  }();
+  return cus;
+}
+
+// Dynamic LDS of the sweep for NR vectors: stage, NR windows, NR staged
+// right-hand sides, output scales and pivot reciprocals.
+template <typename T>
+size_t band_apply_lds(const BandBlocks& B, int nr) {
+  return (size_t)(64 * B.ldmax + 256 * nr) * sizeof(T) + 64 * nr * sizeof(double) +
+         64 * (sizeof(double) + sizeof(T));
+}
+
+template <typename T, int NR>
+hipError_t launch_apply_nr(hipStream_t st, const BandBlocks& B, const double* u, double* y,
+                           const int* done, int nrhs, int n1, int sys_done, int nvp) {
+  const size_t lds = band_apply_lds<T>(B, NR);
+  const dim3 grid(B.nblk, (nrhs + NR - 1) / NR);
+#define BC_LAUNCH(V)                                                                       \
+  hipLaunchKernelGGL((k_band_apply<T, V, NR>), grid, dim3(64), lds, st, B, u, y, done, nrhs, \
+                     n1, sys_done)
+  if constexpr (NR == 1) {
+    if (nvp == 4) BC_LAUNCH(4);
+    else if (nvp == 8) BC_LAUNCH(8);
+    else if (nvp == 12) BC_LAUNCH(12);
+    else if (nvp == 20) BC_LAUNCH(20);
+    else if (nvp == 16) BC_LAUNCH(16);
+    else if (nvp == 24) BC_LAUNCH(24);
+    else BC_LAUNCH(32);
+  } else {
+    // the multi-vector sweeps use register sets of at most BAND_MULTI_NVP
+    if (nvp <= 4) BC_LAUNCH(4);
+    else if (nvp <= 8) BC_LAUNCH(8);
+    else BC_LAUNCH(BAND_MULTI_NVP);
+  }
+#undef BC_LAUNCH
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_apply_t(hipStream_t st, const BandBlocks& B, const double* u, double* y,
-                          const int* done) {
-  const size_t lds = (size_t)(64 * B.ldmax + 256) * sizeof(T) + 64 * (2 * sizeof(double) + sizeof(T));
+                          const int* done, int nrhs, int n1, int sys_done) {
   const int nvp = B.nvp > 0 ? B.nvp : band_nvp_buckets(B, sizeof(T)).back();
-  if (nvp == 4)
-    hipLaunchKernelGGL((k_band_apply<T, 4>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
-  else if (nvp == 8)
-    hipLaunchKernelGGL((k_band_apply<T, 8>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
-  else if (nvp == 12)
-    hipLaunchKernelGGL((k_band_apply<T, 12>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
-  else if (nvp == 20)
-    hipLaunchKernelGGL((k_band_apply<T, 20>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
-  else if (nvp == 16)
-    hipLaunchKernelGGL((k_band_apply<T, 16>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
-  else if (nvp == 24)
-    hipLaunchKernelGGL((k_band_apply<T, 24>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
-  else
-    hipLaunchKernelGGL((k_band_apply<T, 32>), dim3(B.nblk), dim3(64), lds, st, B, u, y, done);
-  return hipGetLastError();
+  if (nrhs == 1) return launch_apply_nr<T, 1>(st, B, u, y, done, nrhs, n1, sys_done, nvp);
+  // Several vectors: one wave per block and chunk of 1, 4 or 8 vectors.  A
+  // wave is bound by the latency of its column sweeps, and a second wave on
+  // a SIMD slows both about as much as running after it, so the time is
+  // about (rounds of one wave per SIMD) x (the chunk's cost), the chunks of
+  // 1, 4 and 8 vectors costing about 1 : 2.6 : 3.7 (measured on the 27-point
+  // 100^3 blocks).  The cheapest is taken (the narrower on a tie).
+  const long long simds = 4LL * device_cus();
+  auto cost = [&](int nr, double w) {
+    const long long waves = (long long)B.nblk * ((nrhs + nr - 1) / nr);
+    return (double)((waves + simds - 1) / simds) * w;
+  };
+  const double c1 = cost(1, 1.0), c4 = cost(4, 2.6), c8 = cost(8, 3.7);
+  if (c1 <= c4 && c1 <= c8) return launch_apply_nr<T, 1>(st, B, u, y, done, nrhs, n1, sys_done, nvp);
+  if (c4 <= c8) return launch_apply_nr<T, 4>(st, B, u, y, done, nrhs, n1, sys_done, nvp);
+  return launch_apply_nr<T, 8>(st, B, u, y, done, nrhs, n1, sys_done, nvp);
 }
 
 }  // namespace
@@ -486,13 +569,18 @@ std::vector<int> band_nvp_buckets(const BandBlocks& B, size_t elem) {
 // capture is a plain kernel launch).
 template <typename T>
 hipError_t prepare_apply_t(const BandBlocks& B) {
-  const int lds = (int)((64 * B.ldmax + 256) * sizeof(T) + 64 * (2 * sizeof(double) + sizeof(T)));
-  const void* fns[] = {(const void*)k_band_apply<T, 4>,  (const void*)k_band_apply<T, 8>,
-                       (const void*)k_band_apply<T, 12>, (const void*)k_band_apply<T, 16>,
-                       (const void*)k_band_apply<T, 20>, (const void*)k_band_apply<T, 24>,
-                       (const void*)k_band_apply<T, 32>};
-  for (const void* fn : fns) {
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const int l1 = (int)band_apply_lds<T>(B, 1), l4 = (int)band_apply_lds<T>(B, 4);
+  const int l8 = (int)band_apply_lds<T>(B, 8);
+  const std::pair<const void*, int> fns[] = {
+      {(const void*)k_band_apply<T, 4, 1>, l1},  {(const void*)k_band_apply<T, 8, 1>, l1},
+      {(const void*)k_band_apply<T, 12, 1>, l1}, {(const void*)k_band_apply<T, 16, 1>, l1},
+      {(const void*)k_band_apply<T, 20, 1>, l1}, {(const void*)k_band_apply<T, 24, 1>, l1},
+      {(const void*)k_band_apply<T, 32, 1>, l1}, {(const void*)k_band_apply<T, 4, 4>, l4},
+      {(const void*)k_band_apply<T, 8, 4>, l4},  {(const void*)k_band_apply<T, 12, 4>, l4},
+      {(const void*)k_band_apply<T, 4, 8>, l8},  {(const void*)k_band_apply<T, 8, 8>, l8},
+      {(const void*)k_band_apply<T, 12, 8>, l8}};
+  for (const auto& f : fns) {
+    hipError_t e = hipFuncSetAttribute(f.first, hipFuncAttributeMaxDynamicSharedMemorySize, f.second);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -506,7 +594,15 @@ hipError_t prepare_band_apply(const BandBlocks& B, bool mixed) {
 hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, const double* u,
                              double* y, const int* done) {
   if (B.nblk == 0) return hipSuccess;
-  return mixed ? launch_apply_t<float>(st, B, u, y, done) : launch_apply_t<double>(st, B, u, y, done);
+  return mixed ? launch_apply_t<float>(st, B, u, y, done, 1, 0, 1)
+               : launch_apply_t<double>(st, B, u, y, done, 1, 0, 1);
+}
+
+hipError_t launch_band_apply_multi(hipStream_t st, const BandBlocks& B, bool mixed,
+                                   const double* u, double* y, const int* done, int nrhs, int n1) {
+  if (B.nblk == 0 || nrhs <= 0) return hipSuccess;
+  return mixed ? launch_apply_t<float>(st, B, u, y, done, nrhs, n1, 0)
+               : launch_apply_t<double>(st, B, u, y, done, nrhs, n1, 0);
 }
 
 std::vector<int> band_apply_candidates(const BandBlocks& B, bool mixed) {

@@ -365,4 +365,10 @@ hipError_t launch_band_finish(hipStream_t st, const BandBlocks& B, bool mixed);
 hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, const double* u,
                              double* y, const int* done);
 hipError_t prepare_band_apply(const BandBlocks& B, bool mixed);
+// The same sweeps for nrhs vectors of a one-system context at once (vector j
+// at u + j*n1, y + j*n1; done indexed by j): chunks of up to 8 vectors per
+// wave read each band once.  Every vector gets the bits of launch_band_apply.
+constexpr int BAND_MULTI_NVP = 12;  // prefetch register set of the multi-vector sweeps
+hipError_t launch_band_apply_multi(hipStream_t st, const BandBlocks& B, bool mixed,
+                                   const double* u, double* y, const int* done, int nrhs, int n1);
 std::vector<int> band_apply_candidates(const BandBlocks& B, bool mixed);
