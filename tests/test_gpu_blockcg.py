@@ -152,6 +152,24 @@ def test_block_cg_fp32_applies_and_x0(dev):
         solver.close()
 
 
+def test_block_cg_fp32_products(dev):
+    banner("bc_solve_block st27-10 K=6 FP32 sparse products and dense applies, 5 right-hand "
+           "sides")
+    p, part = st27(10, 6)
+    F, Xs = workloads.multi_rhs(p.A, 5, 27)
+    solver = bc.BlockCimmino(p.A, part, 6, spmv_lanes=-1, projection=bc.BC_PROJ_DENSE_CHOL,
+                             precision=bc.BC_MIXED)
+    try:
+        X, sts = solver.solve_block(torch.from_numpy(F).to(dev), tol=1e-10)
+        print("iterations", [s.iterations for s in sts],
+              "replacements", [s.replacements for s in sts])
+        assert all(s.status == bc.BC_OK and s.rel_residual <= 1e-10 * (1 + 1e-6) for s in sts)
+        for j in range(5):
+            assert rel(X[j].cpu().numpy(), Xs[j]) <= 1e-6
+    finally:
+        solver.close()
+
+
 def test_block_cg_rejects_bad_calls(dev):
     banner("bc_solve_block argument errors")
     p, part = st27(6, 3)

@@ -148,6 +148,32 @@ def test_multi_inner_cg(dev):
     check_multi(dev, p, part, 4, 2, seed=14, projection=bc.BC_PROJ_INNER_CG)
 
 
+def test_multi_inner_cg_mixed_restarts(dev):
+    banner("bc_solve_multi powerlaw-6000 K=4 FP32 products and inner CG (restarts every 20), "
+           "3 right-hand sides")
+    p = workloads.small_config3(n=6000, K=4)
+    part = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, 4))
+    F, X, sts = check_multi(dev, p, part, 4, 3, seed=31, projection=bc.BC_PROJ_INNER_CG,
+                            precision=bc.BC_MIXED)
+    assert all(s.status == bc.BC_OK and s.replacements > 0 for s in sts)
+
+
+def test_multi_backward_error_stop_rule(dev):
+    banner("bc_solve_multi with the paper's backward-error stop rule, st27-10 K=6, 3 right-hand "
+           "sides")
+    p, part = st27(10, 6)
+    F, X, sts = check_multi(dev, p, part, 6, 3, seed=32, tol=1e-12,
+                            projection=bc.BC_PROJ_DENSE_CHOL, stop_rule=bc.BC_STOP_BACKWARD_ERR,
+                            **FP64_DENSE)
+    A = p.A.to_scipy()
+    for j in range(3):
+        ref = block_cimmino_cg(A, F[j], part, 6, tol=1e-12, stop="backward")
+        print("rhs %d: iterations %d oracle %d backward error %.2e"
+              % (j, sts[j].iterations, ref.iterations, sts[j].backward_err))
+        assert sts[j].status == bc.BC_OK and sts[j].backward_err < 1e-12
+        assert abs(sts[j].iterations - ref.iterations) <= 1
+
+
 def test_multi_stops_independently(dev):
     banner("bc_solve_multi: zero, exact and ordinary right-hand sides stop on their own")
     p, part = st27(8, 4)
