@@ -376,54 +376,74 @@ k_residual_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x,
 // ---- block CG on H: tall-skinny products of a few vectors of length n.
 // Gram: G[a][b] = V1_a . V2_b for the columns of two lists.  A fixed number
 // of workgroups walk the 128-row tiles (tile t by workgroup t mod groups);
-// each stages the tile's columns in LDS and sums its pairs over the rows in
-// order, then writes one partial per pair; k_block_gram_reduce adds the
-// partials of a pair in workgroup order.  The order of every sum is fixed by
-// n and the list sizes, so the result is reproducible.
+// each stages the tile's columns in LDS, and wave w accumulates the 16x16
+// block (w / 2, w % 2) of G over the tile's rows on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: A[i][k] = V1_i at row k from lane i + 16k, B[k][j]
+// = V2_j at row k from lane j + 16k, D[i][j] in register r of lane j + 16g
+// with i = 4r + g), K = 4 rows per step.  Each workgroup writes one partial
+// per entry; k_block_gram_reduce adds the partials in workgroup order.  The
+// order of every sum is fixed by n and the list sizes, so the result is
+// reproducible.
+typedef double dbl4v __attribute__((ext_vector_type(4)));
+
 __global__ void __launch_bounds__(BG_THREADS)
 k_block_gram(ColList L1, ColList L2, int n, double* __restrict__ part) {
   extern __shared__ double gsh[];  // c1 + c2 columns of BG_LD (odd: no bank conflicts)
   const int c1 = L1.c, c2 = L2.c, np = c1 * c2;
   const int tid = threadIdx.x, r = tid % BG_ROWS, h = tid / BG_ROWS;
   static_assert(BG_THREADS == 2 * BG_ROWS, "two columns per staging pass");
-  double acc[BG_PAIRS / BG_THREADS];
-#pragma unroll
-  for (int k = 0; k < BG_PAIRS / BG_THREADS; ++k) acc[k] = 0.0;
+  static_assert(BG_THREADS == 4 * 64 && BG_MAX == 32, "four waves, one 16x16 block each");
+  // h is uniform per wave (waves 0-1: h = 0, waves 2-3: h = 1)
+  const int w = tid >> 6, l = tid & 63;
+  const int bi = w >> 1, bj = w & 1;
+  const int i = bi * 16 + (l & 15), j = bj * 16 + (l & 15), kq = l >> 4;
+  const bool live = bi * 16 < c1 && bj * 16 < c2;   // this wave's block holds entries
+  dbl4v acc = {0.0, 0.0, 0.0, 0.0};
   const int ntl = (n + BG_ROWS - 1) / BG_ROWS;
+  // Thread (r, h) stages row r of the columns 2q + h of both lists.  The
+  // values of a tile are loaded into registers one tile ahead, so the loads
+  // of the next tile are in flight while the matrix cores work on this one.
+  double va[BG_MAX / 2], vb[BG_MAX / 2];
+  auto load = [&](int tl) {
+    const int row = tl * BG_ROWS + r;
+    const bool in = tl < ntl && row < n;
+#pragma unroll
+    for (int q = 0; q < BG_MAX / 2; ++q) {
+      const int col = 2 * q + h;
+      const double* v1 = h ? L1.v[2 * q + 1] : L1.v[2 * q];
+      const double* v2 = h ? L2.v[2 * q + 1] : L2.v[2 * q];
+      va[q] = (in && col < c1) ? v1[row] : 0.0;
+      vb[q] = (in && col < c2) ? v2[row] : 0.0;
+    }
+  };
+  load(blockIdx.x);
   for (int tl = blockIdx.x; tl < ntl; tl += gridDim.x) {
-    const int r0 = tl * BG_ROWS;
-    const bool in = r0 + r < n;
     __syncthreads();
 #pragma unroll
-    for (int cc = 0; cc < BG_MAX; cc += 2) {
-      const int col = cc + h;
-      if (cc < c1) {
-        const double* v = h ? L1.v[cc + 1] : L1.v[cc];
-        if (col < c1) gsh[col * BG_LD + r] = in ? v[r0 + r] : 0.0;
-      }
-      if (cc < c2) {
-        const double* v = h ? L2.v[cc + 1] : L2.v[cc];
-        if (col < c2) gsh[(c1 + col) * BG_LD + r] = in ? v[r0 + r] : 0.0;
-      }
+    for (int q = 0; q < BG_MAX / 2; ++q) {
+      const int col = 2 * q + h;
+      if (col < c1) gsh[col * BG_LD + r] = va[q];
+      if (col < c2) gsh[(c1 + col) * BG_LD + r] = vb[q];
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < BG_PAIRS / BG_THREADS; ++k) {
-      const int pr = tid + k * BG_THREADS;
-      if (pr < np) {
-        const double* x = gsh + (pr / c2) * BG_LD;
-        const double* y = gsh + (c1 + pr % c2) * BG_LD;
-        double sum = acc[k];
-        for (int q = 0; q < BG_ROWS; ++q) sum += x[q] * y[q];
-        acc[k] = sum;
+    load(tl + gridDim.x);
+    if (live) {
+      const double* xa = gsh + (i < c1 ? i : 0) * BG_LD;
+      const double* xb = gsh + (c1 + (j < c2 ? j : 0)) * BG_LD;
+#pragma unroll 8
+      for (int k0 = 0; k0 < BG_ROWS; k0 += 4) {
+        const double a = i < c1 ? xa[k0 + kq] : 0.0;
+        const double b = j < c2 ? xb[k0 + kq] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
       }
     }
   }
+  if (live)
 #pragma unroll
-  for (int k = 0; k < BG_PAIRS / BG_THREADS; ++k) {
-    const int pr = tid + k * BG_THREADS;
-    if (pr < np) part[(size_t)blockIdx.x * np + pr] = acc[k];
-  }
+    for (int q = 0; q < 4; ++q) {
+      const int ii = bi * 16 + 4 * q + kq;
+      if (ii < c1 && j < c2) part[(size_t)blockIdx.x * np + ii * c2 + j] = acc[q];
+    }
 }
 
 __global__ void __launch_bounds__(256)
