@@ -35,6 +35,7 @@ struct DBuf {
 // two systems of a batch, so per-system sums are sums over a tile range.
 constexpr int TILE = 1024;
 constexpr int VEC_THREADS = 256;
+static_assert(TILE % VEC_THREADS == 0, "a tile is a whole number of rows per thread");
 // Dense projection tile edge (tiles of the packed lower-triangular factor).
 constexpr int DT = 64;
 

@@ -560,6 +560,22 @@ k_update_xrs(double* __restrict__ x, double* __restrict__ r, double* __restrict_
   const int sys = S.tile_sys[t];
   if (S.done[sys]) return;
   const int it = S.iters[sys] + 1;  // this iteration of the system (k_book advances the count)
+  // The tile's vector entries do not depend on alpha: they are loaded first,
+  // so that their latency overlaps the reduction of p.psi below.
+  constexpr int PER = TILE / VEC_THREADS;
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  double xv[PER], pv[PER], rv[PER], qv[PER], sv[PER], uv[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = i0 + threadIdx.x + k * VEC_THREADS;
+    const bool in = i < i1;
+    xv[k] = in ? x[i] : 0.0;
+    pv[k] = in ? p[i] : 0.0;
+    rv[k] = in ? r[i] : 0.0;
+    qv[k] = in ? psi[i] : 0.0;
+    sv[k] = in ? s[i] : 0.0;
+    uv[k] = in ? u[i] : 0.0;
+  }
   if (threadIdx.x < 64) {
     const double ppsi = sys_sum_wave(S.part_a, S.sys_tile[sys], S.sys_tile[sys + 1]);
     if (threadIdx.x == 0) {
@@ -579,19 +595,22 @@ k_update_xrs(double* __restrict__ x, double* __restrict__ r, double* __restrict_
     return;
   }
   const double alpha = alpha_sh;
-  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
   double rr = 0.0, ss = 0.0, smax = 0.0, xsum = 0.0;
-  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) {
-    const double xi = x[i] + alpha * p[i];
-    x[i] = xi;
-    xsum += fabs(xi);
-    const double ri = r[i] - alpha * psi[i];
-    r[i] = ri;
-    rr += ri * ri;
-    const double si = s[i] - alpha * u[i];
-    s[i] = si;
-    ss += si * si;
-    smax = fmax(smax, fabs(si));
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = i0 + threadIdx.x + k * VEC_THREADS;
+    if (i < i1) {
+      const double xi = xv[k] + alpha * pv[k];
+      x[i] = xi;
+      xsum += fabs(xi);
+      const double ri = rv[k] - alpha * qv[k];
+      r[i] = ri;
+      rr += ri * ri;
+      const double si = sv[k] - alpha * uv[k];
+      s[i] = si;
+      ss += si * si;
+      smax = fmax(smax, fabs(si));
+    }
   }
   rr = block_sum(rr, sh);
   ss = block_sum(ss, sh);
@@ -620,6 +639,16 @@ k_update_p(double* __restrict__ p, const double* __restrict__ r, OuterState S) {
   const int sys = S.tile_sys[t];
   if (S.done[sys]) return;
   const int it = S.iters[sys] + 1;
+  // entries first (they do not depend on beta), as in k_update_xrs
+  constexpr int PER = TILE / VEC_THREADS;
+  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
+  double rv[PER], pv[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = i0 + threadIdx.x + k * VEC_THREADS;
+    rv[k] = i < i1 ? r[i] : 0.0;
+    pv[k] = i < i1 ? p[i] : 0.0;
+  }
   if (threadIdx.x < 64) {
     const int a = S.sys_tile[sys], b = S.sys_tile[sys + 1];
     const double rrn = sys_sum_wave(S.part_b, a, b);
@@ -645,8 +674,11 @@ k_update_p(double* __restrict__ p, const double* __restrict__ r, OuterState S) {
   }
   __syncthreads();
   const double beta = beta_sh;
-  const int i0 = S.tile_start[t], i1 = S.tile_start[t + 1];
-  for (int i = i0 + threadIdx.x; i < i1; i += VEC_THREADS) p[i] = r[i] + beta * p[i];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int i = i0 + threadIdx.x + k * VEC_THREADS;
+    if (i < i1) p[i] = rv[k] + beta * pv[k];
+  }
 }
 
 // Stop test on the FP64 true residual (partials of s.s in part_c from
