@@ -2076,26 +2076,38 @@ bc_status build_view(bc_ctx* c, int nrhs) {
 
 }  // namespace
 
-extern "C" bc_status bc_solve_multi(bc_ctx* c, int32_t nrhs, const double* f, const double* x0,
-                                    double tol, int32_t maxit, double* x, bc_stats* stats) {
+namespace {
+
+// Checks shared by the entry points for several right-hand sides of one
+// system, then the per-vector state for nrhs of them.
+bc_status multi_begin(bc_ctx* c, int32_t nrhs, const char* who, int max_nrhs) {
   if (!c) {
     bc_set_error("ctx is null");
     return BC_ERR_INVALID;
   }
   if (c->nsys != 1) {
-    bc_set_error("bc_solve_multi needs a one-system context (bc_setup)");
+    bc_set_error(std::string(who) + " needs a one-system context (bc_setup)");
     return BC_ERR_INVALID;
   }
-  if (nrhs < 1 || (long long)nrhs * c->n_total > INT32_MAX) {
-    bc_set_error("bc_solve_multi: nrhs must be >= 1 and nrhs * n below 2^31");
+  if (nrhs < 1 || nrhs > max_nrhs || (long long)nrhs * c->n_total > INT32_MAX) {
+    bc_set_error(std::string(who) + ": nrhs must be in [1, " + std::to_string(max_nrhs) +
+                 "] and nrhs * n below 2^31");
     return BC_ERR_INVALID;
   }
   if (!c->have_sell) {
-    bc_set_error("bc_solve_multi needs the sliced-ELL copies of A (bc_opts.spmv_lanes = -1 "
-                 "builds them whatever their padding)");
+    bc_set_error(std::string(who) +
+                 " needs the sliced-ELL copies of A (bc_opts.spmv_lanes = -1 builds them "
+                 "whatever their padding)");
     return BC_ERR_INVALID;
   }
-  BC_TRY(build_view(c, nrhs));
+  return build_view(c, nrhs);
+}
+
+}  // namespace
+
+extern "C" bc_status bc_solve_multi(bc_ctx* c, int32_t nrhs, const double* f, const double* x0,
+                                    double tol, int32_t maxit, double* x, bc_stats* stats) {
+  BC_TRY(multi_begin(c, nrhs, "bc_solve_multi", INT32_MAX));
   const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start};
   swap_view(c, *c->mview);
   c->mrhs = m;
@@ -2443,24 +2455,7 @@ bc_status block_cg_impl(bc_ctx* c, const double* f, const double* x0, double tol
 
 extern "C" bc_status bc_solve_block(bc_ctx* c, int32_t nrhs, const double* f, const double* x0,
                                     double tol, int32_t maxit, double* x, bc_stats* stats) {
-  if (!c) {
-    bc_set_error("ctx is null");
-    return BC_ERR_INVALID;
-  }
-  if (c->nsys != 1) {
-    bc_set_error("bc_solve_block needs a one-system context (bc_setup)");
-    return BC_ERR_INVALID;
-  }
-  if (nrhs < 1 || nrhs > BG_MAX / 2 || (long long)nrhs * c->n_total > INT32_MAX) {
-    bc_set_error("bc_solve_block: nrhs must be in [1, 16] and nrhs * n below 2^31");
-    return BC_ERR_INVALID;
-  }
-  if (!c->have_sell) {
-    bc_set_error("bc_solve_block needs the sliced-ELL copies of A (bc_opts.spmv_lanes = -1 "
-                 "builds them whatever their padding)");
-    return BC_ERR_INVALID;
-  }
-  BC_TRY(build_view(c, nrhs));
+  BC_TRY(multi_begin(c, nrhs, "bc_solve_block", BG_MAX / 2));
   const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start};
   swap_view(c, *c->mview);
   c->mrhs = m;
