@@ -170,6 +170,26 @@ def test_block_cg_fp32_products(dev):
         solver.close()
 
 
+def test_block_cg_sixteen_columns(dev):
+    banner("bc_solve_block st27-8 K=4 dense FP64, 16 right-hand sides (32-column Gram lists); "
+           "maxit = 0")
+    p, part = st27(8, 4)
+    F, _ = workloads.multi_rhs(p.A, 16, 28)
+    X, sts, ref = check_vs_oracle(dev, p, part, 4, F, fixed=(1, 3),
+                                  projection=bc.BC_PROJ_DENSE_CHOL)
+    print("block iterations", [s.iterations for s in sts])
+    solver = bc.BlockCimmino(p.A, part, 4, spmv_lanes=-1, projection=bc.BC_PROJ_DENSE_CHOL)
+    try:
+        Fd = torch.from_numpy(F).to(dev)
+        X0 = torch.zeros_like(Fd)
+        X0[3] = 1.0
+        X1, st1 = solver.solve_block(Fd, X0=X0, tol=1e-10, maxit=0)
+        assert all(s.iterations == 0 and s.status == bc.BC_NOT_CONVERGED for s in st1)
+        assert torch.equal(X1, X0)
+    finally:
+        solver.close()
+
+
 def test_block_cg_rejects_bad_calls(dev):
     banner("bc_solve_block argument errors")
     p, part = st27(6, 3)
