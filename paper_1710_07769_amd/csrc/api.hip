@@ -1181,6 +1181,11 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     BC_HIP(launch_cholesky(st, D));
     BC_HIP(launch_dense_finish(st, D, c->mixed));
     BC_HIP(prepare_dense_apply());
+    D.err = inner_err_flag();  // allocated here, outside any stream capture
+    if (!D.err) {
+      bc_set_error("device error flag could not be allocated");
+      return BC_ERR_NOMEM;
+    }
     std::vector<int> info(D.nblk);
     BC_HIP(hipMemcpyAsync(info.data(), pinfo, D.nblk * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
@@ -1552,7 +1557,8 @@ extern "C" bc_status bc_project(bc_ctx* c, const double* v, double* Hv) {
   int h = 0;
   BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
   if (h) {
-    bc_set_error("inner CG workgroups timed out waiting for each other");
+    bc_set_error("a device wait timed out (inner CG workgroups or dense sweep waves); the "
+                   "result is invalid");
     return BC_ERR_DEVICE;
   }
   return BC_OK;
@@ -1848,7 +1854,8 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
     int h = 0;
     BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
     if (h) {
-      bc_set_error("inner CG workgroups timed out waiting for each other");
+      bc_set_error("a device wait timed out (inner CG workgroups or dense sweep waves); the "
+                   "result is invalid");
       return BC_ERR_DEVICE;
     }
   }
@@ -1928,7 +1935,8 @@ bc_status cimmino_impl(bc_ctx* c, const double* f, const double* x0, double omeg
     int h = 0;
     BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
     if (h) {
-      bc_set_error("inner CG workgroups timed out waiting for each other");
+      bc_set_error("a device wait timed out (inner CG workgroups or dense sweep waves); the "
+                   "result is invalid");
       return BC_ERR_DEVICE;
     }
   }
@@ -2433,7 +2441,8 @@ bc_status block_cg_impl(bc_ctx* c, const double* f, const double* x0, double tol
     int h = 0;
     BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
     if (h) {
-      bc_set_error("inner CG workgroups timed out waiting for each other");
+      bc_set_error("a device wait timed out (inner CG workgroups or dense sweep waves); the "
+                   "result is invalid");
       return BC_ERR_DEVICE;
     }
   }

@@ -312,6 +312,7 @@ struct DenseBlocks {
   double* gdiag;           // diagonal of every block's Gram matrix (permuted row index)
   unsigned long long* applies; // per block running count of applications
   const double* dsc;       // per permuted row 1/||a_r||_2 (see InnerBlocks)
+  int* err;                // set to 1 when a wave of a sweep gave up waiting (result invalid)
 };
 hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);

@@ -446,6 +446,192 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
   }
 }
 
+// The same sweeps with tile rows owned by waves, for chunks whose LDS leaves
+// room for one workgroup per CU only (where the lockstep sweep above would
+// leave the CU idle at every barrier).  Wave w computes the rows k = w mod 4
+// from start to end (its off-diagonal tiles in order, then the diagonal-tile
+// product for all 64 rows) and publishes each finished row with an LDS flag.
+// A wave reading z_j (y_j) first waits for that flag; since every row needs
+// the one before it, rows finish in order, and the loads of a tile are issued
+// before the wait for the row they multiply, so one wave streams its factor
+// tiles while another finishes its diagonal product.  The waits are bounded
+// by the wall clock; a wave that gives up sets *D.err (the result is then
+// invalid).
+constexpr unsigned long long DENSE_WAIT_LIMIT = 200000000ull;  // wall-clock ticks (2 s)
+
+// Orders the LDS accesses of the lanes of one wave (they execute in program
+// order; the fences keep the compiler from moving accesses across).
+__device__ __forceinline__ void dense_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Waits until a row of the current sweep is published (its flag >= 1).
+__device__ __forceinline__ void wait_row(const int* flag, unsigned long long t0, int* err,
+                                         bool& ok) {
+  while (ok && __hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < 1) {
+    if (wall_clock64() - t0 > DENSE_WAIT_LIMIT) {
+      if ((threadIdx.x & 63) == 0) atomicExch(err, 1);
+      ok = false;
+    } else {
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+}
+
+// Publishes a row of the current sweep after the LDS writes of every lane of
+// the wave.
+__device__ __forceinline__ void publish_row(int* flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  if ((threadIdx.x & 63) == 0)
+    __hip_atomic_store(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <typename T, int NR>
+__global__ void __launch_bounds__(APPLY_THREADS)
+k_dense_apply_rows(DenseBlocks D, const double* __restrict__ u, double* __restrict__ y,
+              const int* __restrict__ done, int nrhs, int n1, int sys_done) {
+  using V = typename Vec4<T>::type;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  constexpr int NW = APPLY_THREADS / 64;
+  constexpr int U = multi_u<T>();
+  const unsigned long long t0 = wall_clock64();
+  const int b = blockIdx.x;
+  const int m = D.m[b], nt = D.nt[b], row0 = D.row0[b];
+  const int j0 = blockIdx.y * NR;
+  // sys_done: one vector (of a batch of systems), stopped with the block's system
+  if (sys_done && done && done[D.sys[b]]) return;
+  if (sys_done) done = nullptr;
+  bool any = false;
+  for (int q = 0; q < NR; ++q) any = any || (j0 + q < nrhs && !(done && done[j0 + q]));
+  if (!any) return;
+  T* zs = (T*)dyn;                                  // nt * DT rows of NR
+  T* wsc = zs + (size_t)nt * DT * NR;               // per wave: DT rows of NR
+  int* flags = (int*)(wsc + (size_t)NW * DT * NR);  // 2 * nt: forward, backward
+  const T* L;
+  const T* LT;
+  const T* Dv;
+  if constexpr (sizeof(T) == 8) {
+    L = (const T*)(D.L + D.loff[b]);
+    LT = (const T*)(D.LT + D.loff[b]);
+    Dv = (const T*)(D.Dinv + D.doff[b]);
+  } else {
+    L = (const T*)(D.L32 + D.loff[b]);
+    LT = (const T*)(D.LT32 + D.loff[b]);
+    Dv = (const T*)(D.Dinv32 + D.doff[b]);
+  }
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = l & 15, lk = l >> 4;
+  const bool bn = li < NR;                                           // column holds a vector
+  const bool on = bn && j0 + li < nrhs && !(done && done[j0 + li]);  // ... that is written
+  T* my = wsc + (size_t)w * DT * NR;
+  for (int e = threadIdx.x; e < 2 * nt; e += APPLY_THREADS) flags[e] = 0;
+  if (threadIdx.x == 0) atomicAdd(&D.applies[b], 1ull);
+  __syncthreads();
+  bool ok = true;
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fwd = pass == 0;
+    int* fl = flags + (fwd ? 0 : nt);
+    // rows known to be finished: forward j <= ready, backward j >= ready
+    int ready = fwd ? -1 : nt;
+    const int nown = (nt - w + NW - 1) / NW;  // rows owned by this wave
+    for (int s = 0; s < nown; ++s) {
+      const int k = fwd ? w + NW * s : w + NW * (nown - 1 - s);
+      const int gk = k * DT;
+      // loads that depend on nothing of this sweep: the right-hand side of
+      // the row (forward) and the output scales, issued first in FP32 (in
+      // FP64 their registers would cost occupancy; they are loaded at use)
+      constexpr bool PRE = sizeof(T) == 4;
+      double ru[16], rd[16];
+      auto load_rhs = [&]() {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int gi = gk + 4 * mfma_row<T>(l, v) + e;
+            const bool in = gi < m;
+            rd[4 * e + v] = in ? D.dsc[row0 + gi] : 0.0;
+            ru[4 * e + v] = (fwd && in && on) ? u[(size_t)(j0 + li) * n1 + row0 + gi] : 0.0;
+          }
+      };
+      if constexpr (PRE) load_rhs();
+      // off-diagonal tiles: forward j = 0 .. k-1, backward j = nt-1 .. k+1,
+      // in the order their rows finish
+      V acc[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[e] = V{};
+      const int nj = fwd ? k : nt - 1 - k;
+      for (int q = 0; q < nj; ++q) {
+        const int j = fwd ? q : nt - 1 - q;
+        const T* tile = fwd ? L + ltile(k, j) : LT + uttile(nt, k, j);
+        const T* zj = zs + (size_t)j * DT * NR;
+        for (int c0 = 0; c0 < DT; c0 += 4 * U) {
+          V a[U];
+#pragma unroll
+          for (int uu = 0; uu < U; ++uu)
+            a[uu] = *(const V*)(tile + (c0 + 4 * uu + lk) * DT + 4 * li);
+          if (c0 == 0 && (fwd ? j > ready : j < ready)) {
+            wait_row(fl + j, t0, D.err, ok);
+            ready = j;
+          }
+          T bz[U];
+#pragma unroll
+          for (int uu = 0; uu < U; ++uu) bz[uu] = bn ? zj[(c0 + 4 * uu + lk) * NR + li] : (T)0;
+#pragma unroll
+          for (int uu = 0; uu < U; ++uu)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = mfma16<T>(a[uu][e], bz[uu], acc[e]);
+        }
+      }
+      // a = (D u_k, or z_k) - acc; its rows are re-read as B operands
+      // through the wave's LDS scratch
+      if constexpr (!PRE) load_rhs();
+      if (bn) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 4 * mfma_row<T>(l, v) + e;
+            const T base = fwd ? (T)(ru[4 * e + v] * rd[4 * e + v]) : zs[(size_t)(gk + r) * NR + li];
+            my[r * NR + li] = base - acc[e][v];
+          }
+      }
+      dense_wave_sync();
+      // diagonal tile: (L_kk^{-1} or its transpose) times a, all 64 rows
+      const T* inv = Dv + (long long)(fwd ? k : nt + k) * TSZ;
+      T bq[DT / 4];
+#pragma unroll
+      for (int c = 0; c < DT / 4; ++c) bq[c] = bn ? my[(4 * c + lk) * NR + li] : (T)0;
+      V d[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d[e] = V{};
+#pragma unroll
+      for (int c = 0; c < DT / 4; ++c) {
+        const V iv = *(const V*)(inv + (4 * c + lk) * DT + 4 * li);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[e] = mfma16<T>(iv[e], bq[c], d[e]);
+      }
+      if (bn) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int r = 4 * mfma_row<T>(l, v) + e;
+            const int gi = gk + r;
+            zs[(size_t)gi * NR + li] = d[e][v];
+            if (!fwd && on && gi < m)
+              y[(size_t)(j0 + li) * n1 + row0 + gi] = (double)d[e][v] * rd[4 * e + v];
+          }
+      }
+      publish_row(fl + k);
+      dense_wave_sync();  // the scratch is reused by the next row
+    }
+    __syncthreads();  // every forward row is in before the backward sweep
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gram(hipStream_t st, const DenseBlocks& D, const int4* tiles, int ntiles,
@@ -474,16 +660,33 @@ hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed)
 }
 
 // Dynamic LDS of k_dense_apply for NR vectors and blocks of up to
-// max_nt tiles.
+// max_nt tiles (z, the partials of the 4 waves and the diagonal right-hand
+// side), and of k_dense_apply_rows (z, one 64-row scratch per wave and
+// 2 * max_nt row flags).
 size_t dense_multi_lds(int nr, int max_nt, bool mixed) {
   return (size_t)(max_nt + 5) * DT * nr * (mixed ? sizeof(float) : sizeof(double));
 }
+size_t dense_rows_lds(int nr, int max_nt, bool mixed) {
+  return (size_t)(max_nt + APPLY_THREADS / 64) * DT * nr * (mixed ? sizeof(float) : sizeof(double)) +
+         2 * (size_t)max_nt * sizeof(int);
+}
 
+// The lockstep sweep while two workgroups fit on a CU; the row-owned sweep
+// when only one does (measured on the 27-point 100^3 blocks: 16 FP32
+// vectors per chunk 2.51 -> 1.54 ms, while with two workgroups per CU the
+// lockstep sweep stays 4% ahead).
 template <typename T, int NR>
 hipError_t launch_dense_multi_nr(hipStream_t st, const DenseBlocks& D, const double* u, double* y,
-                                 const int* done, int nrhs, int n1, size_t lds, int sys_done) {
-  hipLaunchKernelGGL((k_dense_apply<T, NR>), dim3(D.nblk, (nrhs + NR - 1) / NR),
-                     dim3(APPLY_THREADS), lds, st, D, u, y, done, nrhs, n1, sys_done);
+                                 const int* done, int nrhs, int n1, int max_nt, int sys_done) {
+  const bool f32 = sizeof(T) == 4;
+  const dim3 grid(D.nblk, (nrhs + NR - 1) / NR);
+  const size_t lds = dense_multi_lds(NR, max_nt, f32);
+  if (lds <= DENSE_MULTI_LDS / 2)
+    hipLaunchKernelGGL((k_dense_apply<T, NR>), grid, dim3(APPLY_THREADS), lds, st, D, u, y, done,
+                       nrhs, n1, sys_done);
+  else
+    hipLaunchKernelGGL((k_dense_apply_rows<T, NR>), grid, dim3(APPLY_THREADS),
+                       dense_rows_lds(NR, max_nt, f32), st, D, u, y, done, nrhs, n1, sys_done);
   return hipGetLastError();
 }
 
@@ -497,20 +700,22 @@ hipError_t launch_dense_multi_t(hipStream_t st, const DenseBlocks& D, const doub
   const bool f32 = sizeof(T) == 4;
   int nr = 16;
   while (nr > 4 && (nr / 2 >= nrhs || dense_multi_lds(nr, max_nt, f32) > DENSE_MULTI_LDS)) nr /= 2;
-  const size_t lds = dense_multi_lds(nr, max_nt, f32);
   switch (nr) {
-    case 16: return launch_dense_multi_nr<T, 16>(st, D, u, y, done, nrhs, n1, lds, sys_done);
-    case 8: return launch_dense_multi_nr<T, 8>(st, D, u, y, done, nrhs, n1, lds, sys_done);
-    default: return launch_dense_multi_nr<T, 4>(st, D, u, y, done, nrhs, n1, lds, sys_done);
+    case 16: return launch_dense_multi_nr<T, 16>(st, D, u, y, done, nrhs, n1, max_nt, sys_done);
+    case 8: return launch_dense_multi_nr<T, 8>(st, D, u, y, done, nrhs, n1, max_nt, sys_done);
+    default: return launch_dense_multi_nr<T, 4>(st, D, u, y, done, nrhs, n1, max_nt, sys_done);
   }
 }
 
 // Allows every variant of the apply the full LDS of a workgroup (once per
 // process and device, outside any stream capture).
 hipError_t prepare_dense_apply() {
-  const void* fns[] = {(const void*)k_dense_apply<float, 4>, (const void*)k_dense_apply<float, 8>,
-                       (const void*)k_dense_apply<float, 16>, (const void*)k_dense_apply<double, 4>,
-                       (const void*)k_dense_apply<double, 8>, (const void*)k_dense_apply<double, 16>};
+  const void* fns[] = {(const void*)k_dense_apply<float, 4>,       (const void*)k_dense_apply<float, 8>,
+                       (const void*)k_dense_apply<float, 16>,      (const void*)k_dense_apply<double, 4>,
+                       (const void*)k_dense_apply<double, 8>,      (const void*)k_dense_apply<double, 16>,
+                       (const void*)k_dense_apply_rows<float, 4>,  (const void*)k_dense_apply_rows<float, 8>,
+                       (const void*)k_dense_apply_rows<float, 16>, (const void*)k_dense_apply_rows<double, 4>,
+                       (const void*)k_dense_apply_rows<double, 8>, (const void*)k_dense_apply_rows<double, 16>};
   for (const void* fn : fns) {
     const hipError_t e =
         hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)DENSE_MULTI_LDS);
