@@ -169,8 +169,10 @@ bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, doubl
  * right-hand sides with one matrix amortize the partitioning cost further).
  * Each right-hand side runs its
  * own CG recurrence and stops on its own, exactly as one bc_solve with it
- * would (same iterations and bits, given the same sparse-product schedule:
- * spmv_lanes = -1); the right-hand sides share every read of A, A^T and the
+ * would (same iterations and bits, given the same sparse-product schedule,
+ * spmv_lanes = -1, and the same dense sweep: chunks whose LDS leaves room for
+ * one workgroup per CU only take a row-owned sweep that sums in another
+ * order); the right-hand sides share every read of A, A^T and the
  * dense block factors: the sparse products take chunks of 8 vectors per
  * matrix read, the dense triangular sweeps chunks of up to 16 per factor read.
  * Banded and inner-CG blocks take the vectors one after another.

@@ -8,7 +8,11 @@ Bars:
   the same bits whatever else its chunk holds); this holds for dense FP64 and
   FP32-apply factors, banded factors and inner-CG blocks, for chunks that
   leave a ragged tail and for right-hand sides that stop at different
-  iterations;
+  iterations.  Where a wide chunk takes the row-owned dense sweep (blocks
+  large enough that its LDS fits one workgroup per CU) and a narrow one the
+  lockstep sweep, the two sum in different orders: then the bits agree
+  between solves whose chunks take the same sweep, and the rest is held to
+  the tolerance bars below;
 * against ``bc_solve`` of the same right-hand side (sliced-ELL products forced
   with spmv_lanes = -1 on both): banded and inner-CG blocks take the same
   kernels, so the bits agree; dense blocks use the one-vector sweeps there,
@@ -133,6 +137,34 @@ def test_multi_dense_fp64_chunks(dev, nrhs):
     banner("bc_solve_multi st27-10 K=6 FP64 dense, %d right-hand sides" % nrhs)
     p, part = st27(10, 6)
     check_multi(dev, p, part, 6, nrhs, seed=18, projection=bc.BC_PROJ_DENSE_CHOL, **FP64_DENSE)
+
+
+def test_multi_dense_row_owned_sweep(dev):
+    banner("bc_solve_multi st27-14 K=2 FP32 dense applies (1372-row blocks), 16 right-hand "
+           "sides: chunks of 16 take the row-owned sweep")
+    p, part = st27(14, 2)
+    F, _ = workloads.multi_rhs(p.A, 16, 33)
+    solver = bc.BlockCimmino(p.A, part, 2, spmv_lanes=-1, projection=bc.BC_PROJ_DENSE_CHOL,
+                             precision=bc.BC_MIXED_PROJ)
+    try:
+        Fd = torch.from_numpy(F).to(dev)
+        X, sts = solver.solve_multi(Fd, tol=1e-10, maxit=3000)
+        # 9 vectors also take a chunk of 16 (same sweep): the same bits
+        X9, sts9 = solver.solve_multi(Fd[:9].contiguous(), tol=1e-10, maxit=3000)
+        assert torch.equal(X9, X[:9])
+        assert [s.iterations for s in sts9] == [s.iterations for s in sts[:9]]
+        A = p.A.to_scipy()
+        for j in (0, 15):
+            xs, st1 = solver.solve(Fd[j].contiguous(), tol=1e-10, maxit=3000)
+            ref = block_cimmino_cg(A, F[j], part, 2, tol=1e-10)
+            print("rhs %d: iterations multi=%d bc_solve=%d oracle(FP64)=%d rel_res=%.2e"
+                  % (j, sts[j].iterations, st1.iterations, ref.iterations, sts[j].rel_residual))
+            assert sts[j].status == bc.BC_OK and sts[j].rel_residual <= 1e-10 * (1 + 1e-6)
+            assert abs(sts[j].iterations - st1.iterations) <= 2
+            assert rel(X[j].cpu().numpy(), xs.cpu().numpy()) <= 1e-6
+            assert rel(X[j].cpu().numpy(), ref.x) <= 1e-6
+    finally:
+        solver.close()
 
 
 def test_multi_banded(dev):

@@ -186,6 +186,13 @@ def test_solve_st27_dense(dev):
     _check_solve(dev, p, p.part(), p.K, projection=bc.BC_PROJ_DENSE_CHOL)
 
 
+def test_solve_st27_dense_large_blocks(dev):
+    banner("bc_solve st27-17 K=2 dense FP64, blocks of 2456 rows (row-owned sweep: one "
+           "workgroup per CU)")
+    p = workloads.small_config5(N=17, K=2)
+    _check_solve(dev, p, p.part(), p.K, projection=bc.BC_PROJ_DENSE_CHOL)
+
+
 @pytest.mark.parametrize("case", ["cd2d-32-K4", "cd2d-70-K8", "st27-8-K8"])
 def test_solve_band(dev, case):
     banner("bc_solve %s banded Cholesky FP64" % case)
