@@ -59,6 +59,7 @@ typedef enum {
 enum { BC_FP64 = 0, BC_MIXED = 1, BC_MIXED_PROJ = 2 };
 enum { BC_PROJ_AUTO = 0, BC_PROJ_DENSE_CHOL = 1, BC_PROJ_INNER_CG = 2, BC_PROJ_BAND_CHOL = 3 };
 enum { BC_STOP_REL2 = 0, BC_STOP_BACKWARD_ERR = 1 };
+enum { BC_GATHER_AUTO = 0, BC_GATHER_SEPARATE = 1, BC_GATHER_INTERLEAVED = 2 };
 
 typedef struct {
   int32_t precision;      /* BC_FP64 (default); BC_MIXED: FP32 sparse products
@@ -101,6 +102,18 @@ typedef struct {
                              iterations (gcd of check_every and, with FP32
                              projections, replace_every) are captured once in
                              a hipGraph and replayed; 0: plain stream launches */
+  int32_t multi_gather;   /* layout of the gathered vectors in the sparse
+                             products of bc_solve_multi / bc_solve_block:
+                             BC_GATHER_SEPARATE: each vector of a chunk of 8
+                             gathered on its own; BC_GATHER_INTERLEAVED: the
+                             chunk first copied vector-minor, one 64-byte
+                             gather per index for the 8; BC_GATHER_AUTO
+                             (default): per copy (A, A^T) at setup,
+                             interleaved when the separate gathers of one
+                             64-row slice touch at least twice the 64-byte
+                             segments that the interleaved ones do (scattered
+                             columns).  Both sum in the same order: the
+                             choice changes time, never bits */
   void* stream;           /* caller's hipStream_t; NULL = null stream */
 } bc_opts;
 
@@ -174,8 +187,9 @@ bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, doubl
  * one workgroup per CU only take a row-owned sweep that sums in another
  * order); the right-hand sides share every read of A, A^T and the
  * dense block factors: the sparse products take chunks of 8 vectors per
- * matrix read, the dense triangular sweeps chunks of up to 16 per factor read.
- * Banded and inner-CG blocks take the vectors one after another.
+ * matrix read (bc_opts.multi_gather), the dense triangular sweeps chunks of
+ * up to 16 per factor read, the banded ones chunks of 1, 4 or 8 per band
+ * read.  Inner-CG blocks take the vectors one after another.
  * f, x0 (or NULL for zero), x: device float64[nrhs * n], vector j at
  * offset j * n (original row / column order, as bc_solve).  stats: host,
  * nrhs entries, may be NULL.  Needs the sliced-ELL copies of A

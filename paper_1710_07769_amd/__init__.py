@@ -38,6 +38,7 @@ BC_FP64, BC_MIXED, BC_MIXED_PROJ = 0, 1, 2
 BC_PROJ_AUTO, BC_PROJ_DENSE_CHOL, BC_PROJ_INNER_CG, BC_PROJ_BAND_CHOL = 0, 1, 2, 3
 KIND_DENSE, KIND_INNER, KIND_BAND = 0, 1, 2
 BC_STOP_REL2, BC_STOP_BACKWARD_ERR = 0, 1
+BC_GATHER_AUTO, BC_GATHER_SEPARATE, BC_GATHER_INTERLEAVED = 0, 1, 2
 
 
 class bc_opts(C.Structure):
@@ -45,7 +46,8 @@ class bc_opts(C.Structure):
                 ("inner_tol", C.c_double), ("inner_maxit", C.c_int32),
                 ("inner_groups", C.c_int32), ("replace_every", C.c_int32),
                 ("stop_rule", C.c_int32), ("check_every", C.c_int32),
-                ("spmv_lanes", C.c_int32), ("use_graph", C.c_int32), ("stream", C.c_void_p)]
+                ("spmv_lanes", C.c_int32), ("use_graph", C.c_int32),
+                ("multi_gather", C.c_int32), ("stream", C.c_void_p)]
 
 
 class bc_stats(C.Structure):

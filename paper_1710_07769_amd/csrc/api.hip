@@ -51,6 +51,7 @@ extern "C" void bc_opts_default(bc_opts* o) {
   o->check_every = 8;
   o->spmv_lanes = 0;
   o->use_graph = 1;
+  o->multi_gather = BC_GATHER_AUTO;
   o->stream = nullptr;
 }
 
@@ -255,6 +256,33 @@ bool build_sell(const std::vector<int>& rp, const std::vector<int>& ci, const st
   return true;
 }
 
+// Gather layout of the multi-vector products over one sliced-ELL copy.  A
+// chunk of 8 vectors gathered separately reads, per entry column of a slice,
+// 8 x (distinct 64-byte segments among the 64 column indices); interleaved it
+// reads one 64-byte segment per distinct index.  Interleave when the first
+// is at least twice the second over the whole matrix (scattered columns, as
+// in reverse Cuthill-McKee order); with contiguous neighbours the two are
+// equal and the interleaving copy would be pure overhead.
+int gather_interleaved(const std::vector<long long>& ptr, const std::vector<int>& wid,
+                       const std::vector<int>& col, const bc_opts& o) {
+  if (o.multi_gather != BC_GATHER_AUTO) return o.multi_gather == BC_GATHER_INTERLEAVED;
+  long long seg = 0, idx = 0;
+  int c[64], g[64];
+  const size_t stride = std::max<size_t>(1, ptr.size() / 4096);  // a sample of slices
+  for (size_t sl = 0; sl < ptr.size(); sl += stride)
+    for (int k = 0; k < wid[sl]; ++k) {
+      for (int l = 0; l < 64; ++l) {
+        c[l] = col[(size_t)(ptr[sl] + 64LL * k + l)];
+        g[l] = c[l] >> 3;
+      }
+      std::sort(c, c + 64);
+      std::sort(g, g + 64);
+      idx += std::unique(c, c + 64) - c;
+      seg += std::unique(g, g + 64) - g;
+    }
+  return 8 * seg >= 2 * idx;
+}
+
 struct SysIn {
   int32_t n;
   const int32_t* rowptr;
@@ -287,6 +315,8 @@ struct MultiView {
   double *d_final = nullptr, *d_normA = nullptr, *d_finf = nullptr;
   double *d_r = nullptr, *d_p = nullptr, *d_psi = nullptr;
   double *d_s = nullptr, *d_u = nullptr, *d_y = nullptr, *d_f = nullptr;
+  // the sparse products' input, interleaved per chunk of 8 vectors
+  double* d_il = nullptr;
   // block CG only (allocated on its first call): the next directions Z,
   // Gram partials and results, and the coefficient matrices of the updates
   double *d_z = nullptr, *d_gpart = nullptr, *d_gout = nullptr, *d_coef = nullptr;
@@ -916,8 +946,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
         BC_TRY(A.upload(&pwt, wt, st));
         BC_TRY(A.upload(&pct, ct, st));
         BC_TRY(A.upload(&pvt, vt, st));
-        c->sellA = SellMat{ppa, pwa, pca, pva, nullptr};
-        c->sellT = SellMat{ppt, pwt, pct, pvt, nullptr};
+        c->sellA = SellMat{ppa, pwa, pca, pva, nullptr, gather_interleaved(pa, wa, ca, o)};
+        c->sellT = SellMat{ppt, pwt, pct, pvt, nullptr, gather_interleaved(pt, wt, ct, o)};
         if (c->spmv32) {
           std::vector<float> a32(va.begin(), va.end()), t32(vt.begin(), vt.end());
           float *pa32, *pt32;
@@ -1346,6 +1376,7 @@ extern "C" bc_status bc_setup_batched(bc_ctx** ctx, int32_t nsys, const int32_t*
                opts->inner_tol < 0.0 || opts->inner_maxit < 1 || opts->dense_max_m < 0 ||
                opts->stop_rule < 0 || opts->stop_rule > 1 || opts->spmv_lanes < LANES_SELL ||
                opts->use_graph < 0 || opts->use_graph > 1 ||
+               opts->multi_gather < BC_GATHER_AUTO || opts->multi_gather > BC_GATHER_INTERLEAVED ||
                (opts->spmv_lanes > 0 && (opts->spmv_lanes & (opts->spmv_lanes - 1))) ||
                opts->spmv_lanes > 64)) {
     bc_set_error("invalid option value");
@@ -2030,7 +2061,7 @@ bc_status build_view(bc_ctx* c, int nrhs) {
   BC_HIP(hipStreamSynchronize(c->stream));
   v.arena.release();
   v.nrhs = 0;
-  v.d_z = v.d_gpart = v.d_gout = v.d_coef = nullptr;
+  v.d_z = v.d_gpart = v.d_gout = v.d_coef = v.d_il = nullptr;
   hipStream_t st = c->stream;
   const int n1 = c->n_total, T1 = c->ntiles;
   std::vector<int> ts1(T1 + 1), perm1(n1);
@@ -2077,6 +2108,10 @@ bc_status build_view(bc_ctx* c, int nrhs) {
   BC_TRY(A.alloc(&v.d_finf, nrhs));
   for (double** q : {&v.d_r, &v.d_p, &v.d_psi, &v.d_s, &v.d_u, &v.d_y, &v.d_f})
     BC_TRY(A.alloc(q, n));
+  if (c->sellA.il || c->sellT.il) {
+    const size_t nch = (size_t)(nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR;
+    BC_TRY(A.alloc(&v.d_il, nch * SELL_MULTI_NR * n1));
+  }
   BC_HIP(hipStreamSynchronize(st));  // host staging vectors go out of scope
   v.nrhs = nrhs;
   return BC_OK;
@@ -2116,7 +2151,7 @@ bc_status multi_begin(bc_ctx* c, int32_t nrhs, const char* who, int max_nrhs) {
 extern "C" bc_status bc_solve_multi(bc_ctx* c, int32_t nrhs, const double* f, const double* x0,
                                     double tol, int32_t maxit, double* x, bc_stats* stats) {
   BC_TRY(multi_begin(c, nrhs, "bc_solve_multi", INT32_MAX));
-  const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start};
+  const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start, c->mview->d_il};
   swap_view(c, *c->mview);
   c->mrhs = m;
   const bc_status rc = solve_impl(c, f, x0, tol, maxit, x, stats);
@@ -2465,7 +2500,7 @@ bc_status block_cg_impl(bc_ctx* c, const double* f, const double* x0, double tol
 extern "C" bc_status bc_solve_block(bc_ctx* c, int32_t nrhs, const double* f, const double* x0,
                                     double tol, int32_t maxit, double* x, bc_stats* stats) {
   BC_TRY(multi_begin(c, nrhs, "bc_solve_block", BG_MAX / 2));
-  const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start};
+  const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start, c->mview->d_il};
   swap_view(c, *c->mview);
   c->mrhs = m;
   const bc_status rc = block_cg_impl(c, f, x0, tol, maxit, x, stats);

@@ -81,6 +81,7 @@ struct SellMat {
   const int* col;
   const double* val;
   const float* val32;     // FP32 copy for FP32 products, else null
+  int il;                 // multi-vector products gather an interleaved copy
 };
 // `lanes` value that selects the sliced-ELL kernels
 constexpr int LANES_SELL = -1;
@@ -207,7 +208,11 @@ struct MultiRhs {
   int n1;
   int ntiles1;
   const int* tile_start;
+  double* il;  // scratch for the gathered input, interleaved per chunk of vectors
 };
+// Vectors per chunk of the multi-vector sparse products: one 64-byte gather
+// per index of the interleaved input; il holds ceil(nrhs / 8) * 8 * n1 doubles.
+constexpr int SELL_MULTI_NR = 8;
 // Block CG on H: products of short lists of n-vectors (column k at v[k]).
 constexpr int BG_MAX = 32;       // columns per list (16 for combine outputs)
 constexpr int BG_ROWS = 128;     // rows per Gram tile

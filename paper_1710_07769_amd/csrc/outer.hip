@@ -205,10 +205,14 @@ k_residual_sell(SellMat A, const double* __restrict__ x, const double* __restric
 // The three sliced-ELL products for nrhs vectors at once (multiple right-hand
 // sides).  The vectors are concatenated, vector j at offset j * n1, and the
 // per-vector state in S is that of nrhs systems of ntiles1 tiles each (tile t
-// of vector j is j * ntiles1 + t).  Grid: ntiles1 x chunks of NR vectors; the
-// index and value loads of a batch of 8 entries serve the chunk's vectors,
-// and each vector sums its row in the stored order, so it gets the bits of
-// the one-vector kernels above.
+// of vector j is j * ntiles1 + t).  Grid: ntiles1 x chunks of NR vectors.  The
+// index and value loads of a batch of entries serve the chunk's vectors, and
+// each vector sums its row in the stored order, so it gets the bits of the
+// one-vector kernels above.  The gathered vectors are read either where they
+// are (sell_rows_multi: NR gathers per index) or, when the matrix copy's
+// columns are scattered (SellMat::il), from a copy made first into M.il with
+// the chunk's NR values of index c side by side (sell_rows_multi_il: one
+// 64-byte gather per index).
 template <typename V, typename ACC, int NR>
 __device__ __forceinline__ void sell_rows_multi(const int* __restrict__ col,
                                                 const V* __restrict__ val,
@@ -238,6 +242,56 @@ __device__ __forceinline__ void sell_rows_multi(const int* __restrict__ col,
         if (r < nb) acc[q] += (ACC)v[r] * xv[r];
     }
   }
+}
+
+typedef double dbl4m __attribute__((ext_vector_type(4)));
+template <typename V, typename ACC, int NR>
+__device__ __forceinline__ void sell_rows_multi_il(const int* __restrict__ col,
+                                                   const V* __restrict__ val,
+                                                   const double* __restrict__ xil, long long e,
+                                                   int w, ACC (&acc)[NR]) {
+  static_assert(NR % 4 == 0, "whole 32-byte vectors per index");
+  constexpr int B = 4;  // entries per batch: B * NR gathered doubles in flight
+#pragma unroll
+  for (int q = 0; q < NR; ++q) acc[q] = (ACC)0;
+  for (int k0 = 0; k0 < w; k0 += B) {
+    const int nb = min(B, w - k0);
+    V v[B];
+    dbl4m xv[B][NR / 4];
+#pragma unroll
+    for (int r = 0; r < B; ++r) {
+      const int c = r < nb ? col[e + (long long)(k0 + r) * 64] : 0;
+      v[r] = r < nb ? val[e + (long long)(k0 + r) * 64] : (V)0;
+#pragma unroll
+      for (int h = 0; h < NR / 4; ++h)
+        xv[r][h] = r < nb ? *(const dbl4m*)(xil + (long long)c * NR + 4 * h)
+                          : dbl4m{0.0, 0.0, 0.0, 0.0};
+    }
+#pragma unroll
+    for (int r = 0; r < B; ++r)
+#pragma unroll
+      for (int q = 0; q < NR; ++q)
+        if (r < nb) acc[q] += (ACC)v[r] * (ACC)xv[r][q / 4][q % 4];
+  }
+}
+
+// dst[(chunk * n1 + i) * NR + q] = src[(chunk * NR + q) * n1 + i] (zero past
+// nrhs): the chunks' vectors interleaved for the gathers above.
+template <int NR>
+__global__ void __launch_bounds__(256)
+k_interleave(const double* __restrict__ src, double* __restrict__ dst, int n1, int nrhs) {
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (i >= n1) return;
+  double v[NR];
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    const int j = ch * NR + q;
+    v[q] = j < nrhs ? src[(long long)j * n1 + i] : 0.0;
+  }
+  dbl4m* d = (dbl4m*)(dst + ((long long)ch * n1 + i) * NR);
+#pragma unroll
+  for (int h = 0; h < NR / 4; ++h) d[h] = dbl4m{v[4 * h], v[4 * h + 1], v[4 * h + 2], v[4 * h + 3]};
 }
 
 // Per-vector block sums of NR values, each summed like block_sum.
@@ -271,7 +325,7 @@ __device__ __forceinline__ bool chunk_active(int j0, int nrhs, const int* flags,
   return any;
 }
 
-template <bool MIXED, int NR>
+template <bool MIXED, bool IL, int NR>
 __global__ void __launch_bounds__(SELL_THREADS)
 k_spmv_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x, double* __restrict__ y,
                   OuterState S, int skip_done) {
@@ -284,22 +338,25 @@ k_spmv_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x, double* _
   const long long e = A.ptr[sl] + lane;
   const int w = A.wid[sl];
   const bool row = i < M.tile_start[t + 1];
+  const double* xil = M.il + (long long)blockIdx.y * M.n1 * NR;
   if constexpr (MIXED) {
     float acc[NR];
-    sell_rows_multi<float, float, NR>(A.col, A.val32, x, M.n1, j0, act, e, w, acc);
+    if constexpr (IL) sell_rows_multi_il<float, float, NR>(A.col, A.val32, xil, e, w, acc);
+    else sell_rows_multi<float, float, NR>(A.col, A.val32, x, M.n1, j0, act, e, w, acc);
 #pragma unroll
     for (int q = 0; q < NR; ++q)
       if (act[q] && row) y[(long long)(j0 + q) * M.n1 + i] = (double)acc[q];
   } else {
     double acc[NR];
-    sell_rows_multi<double, double, NR>(A.col, A.val, x, M.n1, j0, act, e, w, acc);
+    if constexpr (IL) sell_rows_multi_il<double, double, NR>(A.col, A.val, xil, e, w, acc);
+    else sell_rows_multi<double, double, NR>(A.col, A.val, x, M.n1, j0, act, e, w, acc);
 #pragma unroll
     for (int q = 0; q < NR; ++q)
       if (act[q] && row) y[(long long)(j0 + q) * M.n1 + i] = acc[q];
   }
 }
 
-template <bool MIXED, int NR>
+template <bool MIXED, bool IL, int NR>
 __global__ void __launch_bounds__(SELL_THREADS)
 k_spmvT_dot_sell_multi(SellMat AT, MultiRhs M, const double* __restrict__ y,
                        double* __restrict__ psi, const double* __restrict__ p, OuterState S) {
@@ -314,13 +371,16 @@ k_spmvT_dot_sell_multi(SellMat AT, MultiRhs M, const double* __restrict__ y,
   const int w = AT.wid[sl];
   const bool row = j < M.tile_start[t + 1];
   double acc[NR];
+  const double* yil = M.il + (long long)blockIdx.y * M.n1 * NR;
   if constexpr (MIXED) {
     float a32[NR];
-    sell_rows_multi<float, float, NR>(AT.col, AT.val32, y, M.n1, j0, act, e, w, a32);
+    if constexpr (IL) sell_rows_multi_il<float, float, NR>(AT.col, AT.val32, yil, e, w, a32);
+    else sell_rows_multi<float, float, NR>(AT.col, AT.val32, y, M.n1, j0, act, e, w, a32);
 #pragma unroll
     for (int q = 0; q < NR; ++q) acc[q] = (double)a32[q];
   } else {
-    sell_rows_multi<double, double, NR>(AT.col, AT.val, y, M.n1, j0, act, e, w, acc);
+    if constexpr (IL) sell_rows_multi_il<double, double, NR>(AT.col, AT.val, yil, e, w, acc);
+    else sell_rows_multi<double, double, NR>(AT.col, AT.val, y, M.n1, j0, act, e, w, acc);
   }
   double dot[NR];
 #pragma unroll
@@ -339,7 +399,7 @@ k_spmvT_dot_sell_multi(SellMat AT, MultiRhs M, const double* __restrict__ y,
       if (act[q]) S.part_a[(j0 + q) * M.ntiles1 + t] = dot[q];
 }
 
-template <int NR>
+template <bool IL, int NR>
 __global__ void __launch_bounds__(SELL_THREADS)
 k_residual_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x,
                       const double* __restrict__ f, double* __restrict__ s, OuterState S,
@@ -353,8 +413,12 @@ k_residual_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x,
   const int i = M.tile_start[t] + wave * 64 + lane;
   const bool row = i < M.tile_start[t + 1];
   double acc[NR];
-  sell_rows_multi<double, double, NR>(A.col, A.val, x, M.n1, j0, act, A.ptr[sl] + lane, A.wid[sl],
-                                      acc);
+  if constexpr (IL)
+    sell_rows_multi_il<double, double, NR>(A.col, A.val, M.il + (long long)blockIdx.y * M.n1 * NR,
+                                           A.ptr[sl] + lane, A.wid[sl], acc);
+  else
+    sell_rows_multi<double, double, NR>(A.col, A.val, x, M.n1, j0, act, A.ptr[sl] + lane,
+                                        A.wid[sl], acc);
   double ss[NR];
 #pragma unroll
   for (int q = 0; q < NR; ++q) {
@@ -1086,30 +1150,56 @@ hipError_t launch_zero(hipStream_t st, double* dst, int n) {
 // Chunk width of the multi-vector sparse products: 8 vectors (8 entries'
 // indices and values plus 8 accumulators stay within 76 VGPRs at 1024
 // threads, without spills).
-constexpr int SELL_MULTI_NR = 8;
+
+// The gathered input of a multi-vector product, interleaved per chunk.
+hipError_t interleave_input(hipStream_t st, const MultiRhs& M, const double* src) {
+  const dim3 grid((M.n1 + 255) / 256, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
+  hipLaunchKernelGGL(k_interleave<SELL_MULTI_NR>, grid, dim3(256), 0, st, src, M.il, M.n1, M.nrhs);
+  return hipGetLastError();
+}
+
+template <bool MIXED, bool IL>
+void spmv_multi_t(hipStream_t st, const SellMat& A, const MultiRhs& M, const double* x, double* y,
+                  const OuterState& S, bool skip_done) {
+  const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
+  hipLaunchKernelGGL((k_spmv_sell_multi<MIXED, IL, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0,
+                     st, A, M, x, y, S, (int)skip_done);
+}
 
 hipError_t launch_spmv_sell_multi(hipStream_t st, const SellMat& A, const MultiRhs& M, bool mixed,
                                   const double* x, double* y, const OuterState& S, bool skip_done) {
-  const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
-  if (mixed)
-    hipLaunchKernelGGL((k_spmv_sell_multi<true, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0, st,
-                       A, M, x, y, S, (int)skip_done);
-  else
-    hipLaunchKernelGGL((k_spmv_sell_multi<false, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0, st,
-                       A, M, x, y, S, (int)skip_done);
+  if (A.il) {
+    const hipError_t ei = interleave_input(st, M, x);
+    if (ei != hipSuccess) return ei;
+    if (mixed) spmv_multi_t<true, true>(st, A, M, x, y, S, skip_done);
+    else spmv_multi_t<false, true>(st, A, M, x, y, S, skip_done);
+  } else {
+    if (mixed) spmv_multi_t<true, false>(st, A, M, x, y, S, skip_done);
+    else spmv_multi_t<false, false>(st, A, M, x, y, S, skip_done);
+  }
   return hipGetLastError();
+}
+
+template <bool MIXED, bool IL>
+void spmvT_multi_t(hipStream_t st, const SellMat& AT, const MultiRhs& M, const double* y,
+                   double* psi, const double* p, const OuterState& S) {
+  const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
+  hipLaunchKernelGGL((k_spmvT_dot_sell_multi<MIXED, IL, SELL_MULTI_NR>), grid, dim3(SELL_THREADS),
+                     0, st, AT, M, y, psi, p, S);
 }
 
 hipError_t launch_spmvT_dot_sell_multi(hipStream_t st, const SellMat& AT, const MultiRhs& M,
                                        bool mixed, const double* y, double* psi, const double* p,
                                        const OuterState& S) {
-  const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
-  if (mixed)
-    hipLaunchKernelGGL((k_spmvT_dot_sell_multi<true, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0,
-                       st, AT, M, y, psi, p, S);
-  else
-    hipLaunchKernelGGL((k_spmvT_dot_sell_multi<false, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0,
-                       st, AT, M, y, psi, p, S);
+  if (AT.il) {
+    const hipError_t ei = interleave_input(st, M, y);
+    if (ei != hipSuccess) return ei;
+    if (mixed) spmvT_multi_t<true, true>(st, AT, M, y, psi, p, S);
+    else spmvT_multi_t<false, true>(st, AT, M, y, psi, p, S);
+  } else {
+    if (mixed) spmvT_multi_t<true, false>(st, AT, M, y, psi, p, S);
+    else spmvT_multi_t<false, false>(st, AT, M, y, psi, p, S);
+  }
   return hipGetLastError();
 }
 
@@ -1117,8 +1207,15 @@ hipError_t launch_residual_sell_multi(hipStream_t st, const SellMat& A, const Mu
                                       const double* x, const double* f, double* s,
                                       const OuterState& S, const int* mask) {
   const dim3 grid(M.ntiles1, (M.nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR);
-  hipLaunchKernelGGL((k_residual_sell_multi<SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0, st, A, M,
-                     x, f, s, S, mask);
+  if (A.il) {
+    const hipError_t ei = interleave_input(st, M, x);
+    if (ei != hipSuccess) return ei;
+    hipLaunchKernelGGL((k_residual_sell_multi<true, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0,
+                       st, A, M, x, f, s, S, mask);
+  } else {
+    hipLaunchKernelGGL((k_residual_sell_multi<false, SELL_MULTI_NR>), grid, dim3(SELL_THREADS), 0,
+                       st, A, M, x, f, s, S, mask);
+  }
   return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ def test_defaults_and_status_strings():
     assert o.precision == bc.BC_FP64 and o.projection == bc.BC_PROJ_AUTO
     assert o.dense_max_m == 4096 and o.inner_tol == 1e-12 and o.replace_every == 20
     assert o.stop_rule == bc.BC_STOP_REL2 and o.use_graph == 1 and o.spmv_lanes == 0
+    assert o.multi_gather == bc.BC_GATHER_AUTO
     for s in (0, 1, -1, -2, -3, -4, -5):
         assert bc.status_str(s) not in ("", "unknown status")
 
@@ -65,6 +66,9 @@ def test_setup_validation_without_device():
     badrp = A.rowptr.copy(); badrp[10] = badrp[11] + 1
     _expect_invalid(lambda: bc.bc_setup(p.n, badrp, A.col, A.val, p.K, part, stream=False))
     _expect_invalid(lambda: bc.rip_graph(p.n, A.rowptr, bad_col, A.val, stream=False))
+    for bad in (-1, 3):
+        _expect_invalid(lambda: bc.bc_setup(p.n, A.rowptr, A.col, A.val, p.K, part,
+                                            bc.make_opts(multi_gather=bad), stream=False))
 
 
 @pytest.mark.parametrize("maker,K", [(workloads.config1, 4), (lambda: workloads.small_config2(N=12, K=6), 6),

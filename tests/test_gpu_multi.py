@@ -173,6 +173,42 @@ def test_multi_banded(dev):
     check_multi(dev, p, part, 8, 3, seed=13, projection=bc.BC_PROJ_BAND_CHOL)
 
 
+@pytest.mark.parametrize("gather", [bc.BC_GATHER_SEPARATE, bc.BC_GATHER_INTERLEAVED])
+def test_multi_gather_layouts(dev, gather):
+    banner("bc_solve_multi st27-10 K=6, 11 right-hand sides (chunks of 8 + 3), FP32 sparse "
+           "products, gather layout %d: dense FP32 applies, then banded" % gather)
+    p, part = st27(10, 6)
+    check_multi(dev, p, part, 6, 11, seed=41, multi_gather=gather, precision=bc.BC_MIXED,
+                projection=bc.BC_PROJ_DENSE_CHOL, **FP32_DENSE)
+    check_multi(dev, p, part, 6, 11, seed=42, multi_gather=gather,
+                projection=bc.BC_PROJ_BAND_CHOL)
+
+
+def test_gather_layouts_same_bits(dev):
+    banner("separate against interleaved gathers: bc_solve_multi (banded, 11 right-hand "
+           "sides, FP64 and FP32 products) and bc_solve_block (dense, 5)")
+    p, part = st27(10, 6)
+    F, _ = workloads.multi_rhs(p.A, 11, 43)
+    Fd = torch.from_numpy(F).to(dev)
+
+    def run(gather, method, nr, **opts):
+        s = bc.BlockCimmino(p.A, part, 6, spmv_lanes=-1, multi_gather=gather, **opts)
+        try:
+            X, sts = getattr(s, method)(Fd[:nr].contiguous(), tol=1e-10, maxit=2000)
+            return X.cpu().numpy(), [(t.iterations, t.status) for t in sts]
+        finally:
+            s.close()
+    for method, nr, opts in (
+            ("solve_multi", 11, dict(projection=bc.BC_PROJ_BAND_CHOL)),
+            ("solve_multi", 11, dict(projection=bc.BC_PROJ_BAND_CHOL, precision=bc.BC_MIXED)),
+            ("solve_block", 5, dict(projection=bc.BC_PROJ_DENSE_CHOL))):
+        Xs, ss = run(bc.BC_GATHER_SEPARATE, method, nr, **opts)
+        Xi, si = run(bc.BC_GATHER_INTERLEAVED, method, nr, **opts)
+        print(method, opts, "iterations", [t[0] for t in ss])
+        assert ss == si and all(t[1] == bc.BC_OK for t in ss)
+        assert np.array_equal(Xs, Xi)
+
+
 def test_multi_inner_cg(dev):
     banner("bc_solve_multi cd3d-12 K=4 inner CG FP64, 2 right-hand sides")
     p = workloads.small_config2(N=12, K=4)
