@@ -109,11 +109,11 @@ typedef struct {
                              chunk first copied vector-minor, one 64-byte
                              gather per index for the 8; BC_GATHER_AUTO
                              (default): per copy (A, A^T) at setup,
-                             interleaved when the separate gathers of one
-                             64-row slice touch at least twice the 64-byte
-                             segments that the interleaved ones do (scattered
-                             columns).  Both sum in the same order: the
-                             choice changes time, never bits */
+                             interleaved when the separate gathers of a
+                             64-row slice touch at least 4.5 times the
+                             64-byte segments that the interleaved ones do
+                             (scattered columns).  Both sum in the same
+                             order: the choice changes time, never bits */
   void* stream;           /* caller's hipStream_t; NULL = null stream */
 } bc_opts;
 
