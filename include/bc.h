@@ -189,7 +189,11 @@ bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, doubl
  * dense block factors: the sparse products take chunks of 8 vectors per
  * matrix read (bc_opts.multi_gather), the dense triangular sweeps chunks of
  * up to 16 per factor read, the banded ones chunks of 1, 4 or 8 per band
- * read.  Inner-CG blocks take the vectors one after another.
+ * read.  Inner-CG blocks run all vectors in one launch of the
+ * one-workgroup-per-block kernel when bc_solve uses that kernel too
+ * (bc_opts.inner_groups resolving to 1) or when blocks x vectors reach the
+ * compute units; otherwise they take the vectors one after another with the
+ * grouped kernel of bc_solve (then the same bits as bc_solve).
  * f, x0 (or NULL for zero), x: device float64[nrhs * n], vector j at
  * offset j * n (original row / column order, as bc_solve).  stats: host,
  * nrhs entries, may be NULL.  Needs the sliced-ELL copies of A

@@ -318,6 +318,8 @@ struct MultiView {
   double *d_s = nullptr, *d_u = nullptr, *d_y = nullptr, *d_f = nullptr;
   // the sparse products' input, interleaved per chunk of 8 vectors
   double* d_il = nullptr;
+  // inner CG of all vectors in one launch: residual and support scratch
+  double *d_inner_r = nullptr, *d_inner_t = nullptr;
   // block CG only (allocated on its first call): the next directions Z,
   // Gram partials and results, and the coefficient matrices of the updates
   double *d_z = nullptr, *d_gpart = nullptr, *d_gout = nullptr, *d_coef = nullptr;
@@ -387,6 +389,7 @@ struct bc_ctx {
   // blocks
   int nblk = 0;
   InnerBlocks inner{};
+  int inner_sup_total = 0;         // support positions over the inner-CG blocks
   DenseBlocks dense{};
   BandBlocks band{};
   std::vector<long long> bd_m_h, bd_bw_h;  // per banded block rows and half-bandwidth
@@ -1018,6 +1021,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     B.rowptr = c->d_rowptr; B.loc = ploc; B.val = c->d_val; B.val32 = c->d_val32;
     B.btptr = pbp; B.btrow = pbr; B.btval = pbv;
     const int sup_total = (int)btptr.size() - 1;
+    c->inner_sup_total = sup_total;
     if (c->mixed) {
       std::vector<float> b32(btval.begin(), btval.end());
       float* pb32;
@@ -1493,11 +1497,17 @@ bc_status block_solves(bc_ctx* c, const double* u, double* y, const int* done) {
   }
   if (c->mrhs.nrhs > 0) {
     // several right-hand sides: each dense or banded factor is read once
-    // for a chunk of vectors; inner-CG blocks take the vectors one by one
+    // for a chunk of vectors; inner-CG blocks take all vectors in one launch
+    // of the single-workgroup kernel, or else one vector after another
     const int nr = c->mrhs.nrhs, n1 = c->mrhs.n1;
     BC_HIP(launch_dense_apply_multi(st, c->dense, c->mixed, u, y, done, nr, n1, c->dense_max_nt));
     BC_HIP(launch_band_apply_multi(st, c->band, c->mixed, u, y, done, nr, n1));
-    for (int j = 0; j < nr; ++j) {
+    bool taken = false;
+    MultiView* mv = c->mview.get();
+    BC_HIP(launch_inner_cg_multi(st, c->inner, c->mixed, u, y, done, nr, n1, c->inner_sup_total,
+                                 mv ? mv->d_inner_r : nullptr, mv ? mv->d_inner_t : nullptr,
+                                 &taken));
+    for (int j = 0; j < nr && !taken; ++j) {
       const size_t o = (size_t)j * n1;
       BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u + o, y + o, done ? done + j : nullptr));
     }
@@ -2062,7 +2072,7 @@ bc_status build_view(bc_ctx* c, int nrhs) {
   BC_HIP(hipStreamSynchronize(c->stream));
   v.arena.release();
   v.nrhs = 0;
-  v.d_z = v.d_gpart = v.d_gout = v.d_coef = v.d_il = nullptr;
+  v.d_z = v.d_gpart = v.d_gout = v.d_coef = v.d_il = v.d_inner_r = v.d_inner_t = nullptr;
   hipStream_t st = c->stream;
   const int n1 = c->n_total, T1 = c->ntiles;
   std::vector<int> ts1(T1 + 1), perm1(n1);
@@ -2109,6 +2119,10 @@ bc_status build_view(bc_ctx* c, int nrhs) {
   BC_TRY(A.alloc(&v.d_finf, nrhs));
   for (double** q : {&v.d_r, &v.d_p, &v.d_psi, &v.d_s, &v.d_u, &v.d_y, &v.d_f})
     BC_TRY(A.alloc(q, n));
+  if (c->inner.nblk > 0) {
+    BC_TRY(A.alloc(&v.d_inner_r, (size_t)nrhs * n1));
+    BC_TRY(A.alloc(&v.d_inner_t, (size_t)nrhs * std::max(1, c->inner_sup_total)));
+  }
   if (c->sellA.il || c->sellT.il) {
     const size_t nch = (size_t)(nrhs + SELL_MULTI_NR - 1) / SELL_MULTI_NR;
     BC_TRY(A.alloc(&v.d_il, nch * SELL_MULTI_NR * n1));

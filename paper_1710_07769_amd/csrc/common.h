@@ -298,6 +298,9 @@ struct InnerBlocks {
 };
 hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, const double* u,
                            double* y, const int* done);
+hipError_t launch_inner_cg_multi(hipStream_t st, const InnerBlocks& B, bool mixed,
+                                 const double* u, double* y, const int* done, int nrhs, int n1,
+                                 int sup_total, void* rs, void* ts, bool* taken);
 
 // Dense blocks: packed lower-triangular tiles of L (column-major 64x64 tiles)
 struct DenseBlocks {

@@ -107,18 +107,26 @@ __device__ __forceinline__ void two_slices8(const IX* __restrict__ idx, const T*
 
 // LDS layout: q (qcap), t (tcap, if resident), then the slice descriptors
 // (offset of every row slice and column slice, and their widths).
+// Several right-hand sides of a one-system context: blockIdx.y = j picks
+// vector j, whose u, y and residual scratch sit at offset j * vs and whose
+// support scratch (when t is not in LDS) at j * tstr; done[sys + j] is its
+// flag.  One vector: gridDim.y = 1, vs = tstr = 0.
 template <typename T, typename IX, int RPT, bool TLDS>
 __global__ void __launch_bounds__(WG_THREADS)
 k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
-             const int* __restrict__ done, int qcap, int tcap, int dcap) {
+             const int* __restrict__ done, int qcap, int tcap, int dcap, long long vs,
+             long long tstr) {
   extern __shared__ double lds_d[];
   __shared__ double sh[WG_THREADS / 64];
   const int b = blockIdx.x;
-  if (done && done[B.sys[b]]) return;
+  const int j = blockIdx.y;
+  if (done && done[B.sys[b] + j]) return;
   const int row0 = B.row0[b], m = B.m[b];
   const int sup0 = B.sup0[b], ns = B.nsup[b];
+  u += (long long)j * vs;
+  y += (long long)j * vs;
   T* qs = reinterpret_cast<T*>(lds_d);
-  T* ts = TLDS ? qs + qcap : Vec<T>::t(B) + sup0;
+  T* ts = TLDS ? qs + qcap : Vec<T>::t(B) + (long long)j * tstr + sup0;
   long long* dptr = reinterpret_cast<long long*>(qs + qcap + (TLDS ? tcap : 0));
   int* dw = reinterpret_cast<int*>(dptr + dcap);
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -129,7 +137,7 @@ k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y
   const T* __restrict__ tval = sel_val<T>(B.t_val, B.t_val32);
   const int nsa = (m + 63) >> 6, nst = (ns + 63) >> 6;
   constexpr int NW = WG_THREADS / 64;
-  T* __restrict__ rg = Vec<T>::r(B) + row0;   // residual of the block
+  T* __restrict__ rg = Vec<T>::r(B) + (long long)j * vs + row0;   // residual of the block
   double* __restrict__ yg = y + row0;          // iterate of the block
   // slice descriptors: row slices at [0, nsa), column slices at [nsa, nsa + nst)
   for (int s = threadIdx.x; s < nsa + nst; s += WG_THREADS) {
@@ -238,31 +246,40 @@ k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y
   __syncthreads();
   for (int i = threadIdx.x; i < m; i += WG_THREADS) yg[i] *= dsc[i];
   if (threadIdx.x == 0) {
-    B.iters[b] = it;
+    if (j == 0) B.iters[b] = it;
     atomicAdd(B.total, (unsigned long long)it);
     atomicAdd(&B.blk_total[b], (unsigned long long)it);
   }
 }
 
+// Vectors of one launch of the single-workgroup kernel: nv, at strides vs
+// (rows) and tstr (support positions).
+struct VecSet {
+  int nv;
+  long long vs, tstr;
+};
+
 template <typename T, typename IX, int RPT>
 hipError_t launch_sell(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
-                       const int* done, int qcap, int tcap, int dcap, bool tlds, size_t lds) {
+                       const int* done, int qcap, int tcap, int dcap, bool tlds, size_t lds,
+                       const VecSet& V) {
   const void* fn = tlds ? (const void*)k_inner_sell<T, IX, RPT, true>
                         : (const void*)k_inner_sell<T, IX, RPT, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
+  const dim3 grid(B.nblk, V.nv);
   if (tlds)
-    hipLaunchKernelGGL((k_inner_sell<T, IX, RPT, true>), dim3(B.nblk), dim3(WG_THREADS), lds, st,
-                       B, u, y, done, qcap, tcap, dcap);
+    hipLaunchKernelGGL((k_inner_sell<T, IX, RPT, true>), grid, dim3(WG_THREADS), lds, st, B, u, y,
+                       done, qcap, tcap, dcap, V.vs, V.tstr);
   else
-    hipLaunchKernelGGL((k_inner_sell<T, IX, RPT, false>), dim3(B.nblk), dim3(WG_THREADS), lds, st,
-                       B, u, y, done, qcap, tcap, dcap);
+    hipLaunchKernelGGL((k_inner_sell<T, IX, RPT, false>), grid, dim3(WG_THREADS), lds, st, B, u,
+                       y, done, qcap, tcap, dcap, V.vs, V.tstr);
   return hipGetLastError();
 }
 
 template <typename T, typename IX>
 hipError_t launch_sell_rows(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
-                            const int* done) {
+                            const int* done, const VecSet& V = VecSet{1, 0, 0}) {
   const int rpt = (B.max_m + WG_THREADS - 1) / WG_THREADS;
   // element counts rounded so that the descriptor array stays 8-byte aligned
   const int qcap = (B.max_m + 1) / 2 * 2;
@@ -272,12 +289,12 @@ hipError_t launch_sell_rows(hipStream_t st, const InnerBlocks& B, const double* 
   const size_t lds_budget = 160 * 1024 - (WG_THREADS / 64) * sizeof(double) - 256;
   const bool tlds = (size_t)(qcap + tcap) * sizeof(T) + dbytes <= lds_budget;
   const size_t lds = (size_t)(qcap + (tlds ? tcap : 0)) * sizeof(T) + dbytes;
-  if (rpt <= 4) return launch_sell<T, IX, 4>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
-  if (rpt <= 8) return launch_sell<T, IX, 8>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
-  if (rpt <= 9) return launch_sell<T, IX, 9>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
-  if (rpt <= 10) return launch_sell<T, IX, 10>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
-  if (rpt <= 12) return launch_sell<T, IX, 12>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
-  return launch_sell<T, IX, 16>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds);
+  if (rpt <= 4) return launch_sell<T, IX, 4>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 8) return launch_sell<T, IX, 8>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 9) return launch_sell<T, IX, 9>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 10) return launch_sell<T, IX, 10>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 12) return launch_sell<T, IX, 12>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  return launch_sell<T, IX, 16>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
 }
 
 // ------------------------------------------------------------------------
@@ -772,6 +789,48 @@ hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, con
                  : launch_sell_rows<double, uint16_t>(st, B, u, y, done);
   return mixed ? launch_sell_rows<float, int>(st, B, u, y, done)
                : launch_sell_rows<double, int>(st, B, u, y, done);
+}
+
+// nrhs vectors of a one-system context in one launch of the single-workgroup
+// kernel (grid blocks x vectors), with per-vector residual scratch rs
+// (nrhs * n1 values) and support scratch ts (nrhs * sup_total values), both
+// of the inner precision.  Taken when the blocks use that kernel anyway
+// (groups = 1: the same bits as one vector at a time) or when blocks x
+// vectors reach the CUs, where concurrent single-workgroup solves beat the
+// grouped ones run one vector after another; *taken = false leaves the
+// vectors to the caller.
+hipError_t launch_inner_cg_multi(hipStream_t st, const InnerBlocks& B, bool mixed,
+                                 const double* u, double* y, const int* done, int nrhs, int n1,
+                                 int sup_total, void* rs, void* ts, bool* taken) {
+  *taken = false;
+  if (B.nblk == 0) {
+    *taken = true;
+    return hipSuccess;
+  }
+  static const int ncu = [] {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
+      n = 256;
+    return n;
+  }();
+  if (!rs || !ts || nrhs < 1 || nrhs > 65535) return hipSuccess;
+  if (B.groups > 1 && (long long)nrhs * B.nblk < ncu) return hipSuccess;
+  InnerBlocks Bm = B;
+  if (mixed) {
+    Bm.ri32 = static_cast<float*>(rs);
+    Bm.t32 = static_cast<float*>(ts);
+  } else {
+    Bm.ri = static_cast<double*>(rs);
+    Bm.t = static_cast<double*>(ts);
+  }
+  const VecSet V{nrhs, (long long)n1, (long long)sup_total};
+  *taken = true;
+  if (B.idx16)
+    return mixed ? launch_sell_rows<float, uint16_t>(st, Bm, u, y, done, V)
+                 : launch_sell_rows<double, uint16_t>(st, Bm, u, y, done, V);
+  return mixed ? launch_sell_rows<float, int>(st, Bm, u, y, done, V)
+               : launch_sell_rows<double, int>(st, Bm, u, y, done, V);
 }
 
 int inner_grp_max_resident(bool mixed, int max_m) {

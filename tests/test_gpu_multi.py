@@ -15,7 +15,11 @@ Bars:
   the tolerance bars below;
 * against ``bc_solve`` of the same right-hand side (sliced-ELL products forced
   with spmv_lanes = -1 on both): banded and inner-CG blocks take the same
-  kernels, so the bits agree; dense blocks use the one-vector sweeps there,
+  kernels, so the bits agree (inner CG with several workgroups per block in
+  ``bc_solve`` but enough vectors x blocks to fill the CUs runs the
+  one-workgroup kernel for all vectors at once: then the bits agree with a
+  one-workgroup context and the iterates with ``bc_solve`` to 1e-9);
+  dense blocks use the one-vector sweeps there,
   so the iteration count agrees within one (FP64) or two (FP32 applies) and
   the iterates within 1e-9 (FP64) or 1e-6 (FP32 applies) relative;
 * against the oracle (Algorithm 2 per right-hand side, FP64): the iteration
@@ -214,6 +218,42 @@ def test_multi_inner_cg(dev):
     p = workloads.small_config2(N=12, K=4)
     part = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, 4))
     check_multi(dev, p, part, 4, 2, seed=14, projection=bc.BC_PROJ_INNER_CG)
+
+
+def test_multi_inner_cg_one_launch(dev):
+    banner("bc_solve_multi cd3d-16 K=8 inner CG FP64, 32 right-hand sides: blocks x vectors "
+           "fill the CUs, so all vectors run in one single-workgroup launch")
+    p = workloads.small_config2(N=16, K=8)
+    part = workloads.blocks_to_part(workloads.contiguous_blocks(p.n, 8))
+    F, _ = workloads.multi_rhs(p.A, 32, 44)
+    Fd = torch.from_numpy(F).to(dev)
+    grouped = bc.BlockCimmino(p.A, part, 8, spmv_lanes=-1, projection=bc.BC_PROJ_INNER_CG)
+    single = bc.BlockCimmino(p.A, part, 8, spmv_lanes=-1, projection=bc.BC_PROJ_INNER_CG,
+                             inner_groups=1)
+    try:
+        X, sts = grouped.solve_multi(Fd, tol=1e-10)
+        X1, sts1 = single.solve_multi(Fd, tol=1e-10)
+        X = X.cpu().numpy()
+        # the same kernel either way: the same bits, also against bc_solve with one
+        # workgroup per block
+        assert np.array_equal(X, X1.cpu().numpy())
+        assert [s.iterations for s in sts] == [s.iterations for s in sts1]
+        for j in (0, 7, 31):
+            xs, st = single.solve(Fd[j].contiguous(), tol=1e-10)
+            assert st.iterations == sts[j].iterations and np.array_equal(X[j], xs.cpu().numpy())
+        # against the grouped kernel one vector at a time: the same iterates up to rounding
+        for j in range(32):
+            xg, stg = grouped.solve(Fd[j].contiguous(), tol=1e-10)
+            assert sts[j].status == bc.BC_OK and sts[j].rel_residual <= 1e-10 * (1 + 1e-6)
+            assert abs(stg.iterations - sts[j].iterations) <= 1
+            assert rel(X[j], xg.cpu().numpy()) <= 1e-9
+        ref = block_cimmino_cg(p.A.to_scipy(), F[5], part, 8, tol=1e-10)
+        print("iterations", [s.iterations for s in sts][:8], "oracle rhs 5:", ref.iterations)
+        assert abs(sts[5].iterations - ref.iterations) <= 1
+        assert rel(X[5], ref.x) <= 1e-8
+    finally:
+        grouped.close()
+        single.close()
 
 
 def test_multi_inner_cg_mixed_restarts(dev):
