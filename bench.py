@@ -157,7 +157,9 @@ def run_step(wl, f_dev, method="cg", partitioner="greedy", nrhs=None):
             part = q.part()
         parts.append(part)
     t0 = time.perf_counter()
-    opts = bc.make_opts(**wl.opts)
+    # several right-hand sides run on the sliced-ELL copies of A, built here
+    # whatever their padding
+    opts = bc.make_opts(**(dict(wl.opts, spmv_lanes=-1) if nrhs is not None else wl.opts))
     if wl.batched:
         ctx = bc.bc_setup_batched([(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, pt)
                                    for q, pt in zip(wl.problems, parts)], opts)
