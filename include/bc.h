@@ -201,8 +201,8 @@ bc_status bc_solve_batched(bc_ctx* ctx, const double* f, const double* x0, doubl
  * hipGraph capture.  The per-vector state (8 n-vectors per right-hand side)
  * is allocated on the first call with a given nrhs and kept until another
  * nrhs or bc_destroy.  Returns the worst status, as bc_solve_batched;
- * BC_ERR_INVALID for a batched context, nrhs < 1, nrhs > 524280 (65535
- * chunks of 8) or nrhs * n >= 2^31. */
+ * BC_ERR_INVALID for a batched context, nrhs < 1, nrhs > 262140 (65535
+ * chunks of 4, the narrowest chunk of the dense sweeps) or nrhs * n >= 2^31. */
 bc_status bc_solve_multi(bc_ctx* ctx, int32_t nrhs, const double* f, const double* x0,
                          double tol, int32_t maxit, double* x, bc_stats* stats);
 

@@ -2165,8 +2165,9 @@ bc_status multi_begin(bc_ctx* c, int32_t nrhs, const char* who, int max_nrhs) {
 
 extern "C" bc_status bc_solve_multi(bc_ctx* c, int32_t nrhs, const double* f, const double* x0,
                                     double tol, int32_t maxit, double* x, bc_stats* stats) {
-  // the multi-vector products take one grid row per chunk of vectors
-  BC_TRY(multi_begin(c, nrhs, "bc_solve_multi", 65535 * SELL_MULTI_NR));
+  // the multi-vector kernels take one grid row per chunk of vectors, the
+  // narrowest chunk being 4 (dense sweeps of the largest blocks)
+  BC_TRY(multi_begin(c, nrhs, "bc_solve_multi", 65535 * 4));
   const MultiRhs m{nrhs, c->n_total, c->ntiles, c->d_tile_start, c->mview->d_il};
   swap_view(c, *c->mview);
   c->mrhs = m;

@@ -346,8 +346,8 @@ def test_multi_rejects_bad_calls(dev):
         rc = bc._lib.bc_solve_multi(solver.ctx, 0, ctypes.c_void_p(f.data_ptr()), None, 1e-10, 10,
                                     ctypes.c_void_p(x.data_ptr()), None)
         assert rc == bc.BC_ERR_INVALID
-        # and more vectors than 65535 chunks of 8 (checked before any buffer is read)
-        rc = bc._lib.bc_solve_multi(solver.ctx, 65535 * 8 + 1, ctypes.c_void_p(f.data_ptr()),
+        # and more vectors than 65535 chunks of 4 (checked before any buffer is read)
+        rc = bc._lib.bc_solve_multi(solver.ctx, 65535 * 4 + 1, ctypes.c_void_p(f.data_ptr()),
                                     None, 1e-10, 10, ctypes.c_void_p(x.data_ptr()), None)
         assert rc == bc.BC_ERR_INVALID
     finally:
