@@ -4,6 +4,7 @@ from __future__ import annotations
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
@@ -31,13 +32,16 @@ def _run(cmd):
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    for src in HIP_SOURCES:
-        obj = os.path.join(BUILD, src + ".o")
-        out = _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
-        if verbose and out.strip():
-            print(out)
-        objs.append(obj)
+    objs = [os.path.join(BUILD, src + ".o") for src in HIP_SOURCES]
+    jobs = max(1, min(len(HIP_SOURCES), int(os.environ.get("MAX_JOBS", "0")) or os.cpu_count() or 1))
+    # the HIP sources compile independently: one hipcc per source, in parallel
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        outs = list(ex.map(lambda so: _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, so[0]),
+                                            "-o", so[1]]), zip(HIP_SOURCES, objs)))
+    if verbose:
+        for out in outs:
+            if out.strip():
+                print(out)
     for src in CXX_SOURCES:
         obj = os.path.join(BUILD, src + ".o")
         _run(["g++", "-O2", "-std=c++17", "-fPIC", "-c", os.path.join(CSRC, src), "-o", obj])

@@ -1235,10 +1235,10 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   BandBlocks& Bd = c->band;
   Bd = BandBlocks{};
   {
-    std::vector<int> bd_row0, bd_m, bd_bw, bd_ld, bd_sys;
-    std::vector<long long> bd_off;
-    long long btot = 0;
-    int ldmax = 0;
+    std::vector<int> bd_row0, bd_m, bd_bw, bd_ld, bd_sys, bd_sld;
+    std::vector<long long> bd_off, bd_soff;
+    long long btot = 0, stot = 0;
+    int ldmax = 0, sldmax = 0;
     for (int b = 0; b < c->nblk; ++b) {
       if (kind[b] != KIND_BAND) continue;
       const int m = blk_m[b], W = (bandw[b] + 1 + 3) / 4 * 4;
@@ -1252,6 +1252,12 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       c->bd_m_h.push_back(m);
       c->bd_bw_h.push_back(bandw[b]);
       btot += (long long)((m + 63) / 64) * 64 * W;
+      // slot layout: as many slots per row as the band layout
+      const int S = W;
+      sldmax = std::max(sldmax, S);
+      bd_sld.push_back(S);
+      bd_soff.push_back(stot);
+      stot += (long long)((m + 63) / 64) * 64 * S;
     }
     Bd.nblk = (int)bd_m.size();
     if (Bd.nblk > 0) {
@@ -1267,19 +1273,38 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       BC_TRY(A.upload(&pinfo, iz, st));
       Bd.row0 = p0; Bd.m = p1; Bd.bw = p2; Bd.ld = p4; Bd.sys = p3; Bd.off = po; Bd.info = pinfo;
       Bd.ldmax = ldmax;
+      {
+        int* ps;
+        long long* pso;
+        BC_TRY(A.upload(&ps, bd_sld, st));
+        BC_TRY(A.upload(&pso, bd_soff, st));
+        Bd.sld = ps;
+        Bd.soff = pso;
+        Bd.sldmax = sldmax;
+      }
       Bd.dsc = d_dsc;
       unsigned long long* pap;
       BC_TRY(A.alloc(&pap, Bd.nblk));
       BC_HIP(hipMemsetAsync(pap, 0, Bd.nblk * sizeof(unsigned long long), st));
       Bd.applies = pap;
       BC_TRY(A.alloc(&Bd.L, btot));
-      BC_TRY(A.alloc(&Bd.dinv, n));
       if (c->mixed) {
-        BC_TRY(A.alloc(&Bd.L32, btot));
-        BC_TRY(A.alloc(&Bd.R32, btot));
-        BC_TRY(A.alloc(&Bd.dinv32, n));
+        BC_TRY(A.alloc(&Bd.SL32, stot));
+        BC_TRY(A.alloc(&Bd.SR32, stot));
       } else {
-        BC_TRY(A.alloc(&Bd.R, btot));
+        BC_TRY(A.alloc(&Bd.SL, stot));
+        BC_TRY(A.alloc(&Bd.SR, stot));
+      }
+      {
+        // sweeps of the blocks with the most work are launched first
+        std::vector<int> ord(Bd.nblk);
+        for (int b = 0; b < Bd.nblk; ++b) ord[b] = b;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+          return (long long)bd_m[x] * bd_sld[x] > (long long)bd_m[y] * bd_sld[y];
+        });
+        int* pord;
+        BC_TRY(A.upload(&pord, ord, st));
+        Bd.order = pord;
       }
       BC_HIP(launch_band_gram(st, Bd, c->d_rowptr, c->d_col, c->d_val, c->d_tptr, c->d_trow, c->d_tval));
       BC_HIP(launch_band_cholesky(st, Bd));
@@ -1294,42 +1319,6 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
         }
       BC_HIP(launch_band_finish(st, Bd, c->mixed));
       BC_HIP(prepare_band_apply(Bd, c->mixed));
-      // Prefetch register-set size of the sweeps, chosen by timing each
-      // candidate on these blocks (the arithmetic does not depend on it).
-      {
-        BC_HIP(hipMemsetAsync(c->d_u, 0, (size_t)n * sizeof(double), st));
-        const std::vector<int> cand = band_apply_candidates(Bd, c->mixed);
-        hipEvent_t e0, e1;
-        BC_HIP(hipEventCreate(&e0));
-        BC_HIP(hipEventCreate(&e1));
-        float best = 1e30f;
-        int pick = cand.back();
-        bc_status rc = BC_OK;
-        for (int v : cand) {
-          Bd.nvp = v;
-          float ms = 0.f;
-          if (launch_band_apply(st, Bd, c->mixed, c->d_u, c->d_y, nullptr) != hipSuccess ||
-              hipEventRecord(e0, st) != hipSuccess ||
-              launch_band_apply(st, Bd, c->mixed, c->d_u, c->d_y, nullptr) != hipSuccess ||
-              launch_band_apply(st, Bd, c->mixed, c->d_u, c->d_y, nullptr) != hipSuccess ||
-              hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-              hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            rc = BC_ERR_DEVICE;
-            break;
-          }
-          if (ms < best) {
-            best = ms;
-            pick = v;
-          }
-        }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        if (rc != BC_OK) {
-          bc_set_error("banded sweep tuning failed");
-          return rc;
-        }
-        Bd.nvp = pick;
-      }
     }
   }
   if (o.spmv_lanes == 0) BC_TRY(autotune_lanes(c, pattern_key(rowptr, col, n, c->spmv32)));

@@ -5,21 +5,20 @@
 // eq. (H): y_i = (A_i A_i^T)^{-1} u_i) is banded with a small half-bandwidth
 // bw, and so is its Cholesky factor (a banded matrix factors without fill
 // outside its band).  Setup forms G in the band storage (k_band_gram),
-// factors it in FP64 in place (k_band_chol) and derives the reversed
-// transpose and the FP32 copies (k_band_finish).  Each projection then runs
-// two banded triangular sweeps (k_band_apply): L z = D u and L^T w = z, y = D w.
+// factors it in FP64 in place (k_band_chol) and writes the factor and its
+// reversed transpose in the slot layout of the sweeps (k_band_slots), FP64 or
+// rounded once to FP32.  Each projection then runs two banded triangular
+// sweeps (k_band_sweep): L z = D u and L^T w = z, y = D w.
 //
-// Storage (see BandBlocks): per 64-row tile, diagonal-major, entry d of local
-// row p at tile*64*ld + d*64 + p%64, column p - bw + d (ld = bw+1 rounded up
-// to a multiple of 4).  Lanes of a wave own consecutive rows, so every band
-// access of the sweeps is coalesced, and a tile is one contiguous chunk.
+// Band storage (see BandBlocks): per 64-row tile, diagonal-major, entry d of
+// local row p at tile*64*ld + d*64 + p%64, column p - bw + d (ld = bw+1
+// rounded up to a multiple of 4).  Lanes of a wave own consecutive rows, so
+// every access is coalesced, and a tile is one contiguous chunk.
 #include "common.h"
 
 #include <cmath>
 #include <utility>
 #include <vector>
-
-std::vector<int> band_nvp_buckets(const BandBlocks& B, size_t elem);
 
 namespace {
 
@@ -123,178 +122,323 @@ k_band_chol(BandBlocks B) {
   }
 }
 
-// ---------------------------------------------------------------- finish
-// Reversed transpose R[p][d] = L[m-1-p+bw-d][d] (zero outside the matrix and
-// for d >= bw), 1/L_pp, and the FP32 copies (diagonal zero).  Grid: (tiles,
-// blocks).  k_band_zero_diag then clears the diagonal of the FP64 factor, so
-// that every copy the sweeps read has a zero diagonal.
-__global__ void __launch_bounds__(256)
-k_band_finish(BandBlocks B, int mixed) {
-  const int blk = blockIdx.y;
-  const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk], row0 = B.row0[blk];
-  const int nt = (m + 63) >> 6;
-  const long long off = B.off[blk];
-  const double* L = B.L + off;
-  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
-    for (int e = threadIdx.x; e < 64 * ld; e += blockDim.x) {
-      const int d = e >> 6, p = t * 64 + (e & 63);
-      const long long at = band_at(p, d, ld);
-      double r = 0.0;
-      const int k = p - bw + d;          // column of R, reversed row of L
-      const int src = m - 1 - k;         // row of L holding R[p][k]
-      if (d < bw && p < m && k >= 0 && src < m) r = L[band_at(src, d, ld)];
-      // the sweeps take 1/L_pp from dinv; their copies keep a zero diagonal
-      if (mixed) {
-        B.L32[off + at] = d == bw ? 0.f : (float)L[at];
-        B.R32[off + at] = (float)r;
-      } else {
-        B.R[off + at] = r;
-      }
-      if (d == bw && p < m) {
-        const double iv = 1.0 / L[at];
-        B.dinv[row0 + p] = iv;
-        if (mixed) B.dinv32[row0 + p] = (float)iv;
-      }
-    }
-  }
+// ------------------------------------------------------------ slot layout
+// The sweeps read each factor F (L, or its reversed transpose R) in a slot
+// layout.  A 64-row tile is cut into sub-tiles of q rows, q the largest power
+// of two with q <= min(ld, 64) (q = 64 once bw >= 63).  Slot s of local row p
+// (lane l = p % 64, l' = l % q) holds the coefficient of the value of row
+// p - s:
+//   s <= l':  X[l'][l'-s], X the inverse of the sub-tile's lower-triangular
+//             q x q diagonal block of F (rows past m: X = I);
+//   s >  l':  F[p][p-s], an entry left of the sub-tile (zero outside the band).
+// One sub-tile of the sweep F z = b is then
+//   a_p = b_p - sum_{s > l'} F[p][p-s] z_{p-s}   (rows already solved)
+//   z_p = sum_{s <= l'} X[l'][l'-s] a_{p-s}       (the sub-tile's block inverse)
+// and both are the same loop over slots against values indexed by p - s.  In
+// the band layout row p keeps l'+1 entries of F inside its sub-tile (diagonal
+// included); in the slot layout it keeps the l'+1 entries of row l' of X, so
+// the two layouts hold the same number of entries (q <= ld keeps every entry
+// of X inside the row's ld slots).
+//
+// Slots are grouped in 16-byte vectors of VT = 16 / sizeof(element) slots:
+// slot s of lane l sits at tile*64*ld + (s/VT)*64*VT + l*VT + s%VT, so a wave
+// loads VT slots of its 64 rows with one coalesced 1 KiB access.
+//
+// Reversed transpose: R[p][k] = L[m-1-k][m-1-p], so the backward sweep
+// L^T w = z is the forward sweep R w' = z' on reversed vectors.
+
+// Sub-tile height of a block's sweeps.
+__device__ __forceinline__ int band_subtile(int ld) {
+  int q = 64;
+  while (q > ld) q >>= 1;
+  return q;
 }
 
-__global__ void __launch_bounds__(256)
-k_band_zero_diag(BandBlocks B) {
-  const int blk = blockIdx.y;
-  const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk];
-  double* L = B.L + B.off[blk];
-  for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < m; p += gridDim.x * blockDim.x)
-    L[band_at(p, bw, ld)] = 0.0;
+// One 64-thread workgroup per (tile, block, factor): the tile's block-diagonal
+// of sub-tile blocks is inverted in FP64 by forward substitution, one column
+// per thread, and every slot of the tile is written (FP64, or rounded once to
+// FP32).
+template <typename TF>
+__global__ void __launch_bounds__(64)
+k_band_slots(BandBlocks B, TF* __restrict__ outL, TF* __restrict__ outR) {
+  __shared__ double Tb[64][65];
+  __shared__ double Xb[64][65];
+  const int blk = blockIdx.y, rev = blockIdx.z;
+  const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk], sld = B.sld[blk];
+  const int nt = (m + 63) >> 6;
+  const double* L = B.L + B.off[blk];
+  TF* out = (rev ? outR : outL) + B.soff[blk];
+  const int l = threadIdx.x, q = band_subtile(sld);
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    const int i0 = t * 64;
+    // row l of the block diagonal of sub-tile blocks
+    for (int b = 0; b < 64; ++b) {
+      double v = 0.0;
+      if (i0 + l >= m) {
+        v = l == b ? 1.0 : 0.0;
+      } else if (b <= l && l - b <= bw && l / q == b / q) {
+        v = rev ? L[band_at(m - 1 - i0 - b, bw - (l - b), ld)] : L[band_at(i0 + l, bw - (l - b), ld)];
+      }
+      Tb[l][b] = v;
+    }
+    __syncthreads();
+    // column l of X: T x = e_l
+    double x[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      double s = i == l ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) s -= Tb[i][k] * x[k];
+      x[i] = s / Tb[i][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 64; ++i) Xb[i][l] = x[i];
+    __syncthreads();
+    const int p = i0 + l;
+    constexpr int VT = 16 / (int)sizeof(TF);
+    TF* o = out + (long long)t * 64 * sld + l * VT;
+    for (int s = 0; s < sld; ++s) {
+      double v = 0.0;
+      if (s <= l % q) {
+        v = Xb[l][l - s];
+      } else if (p < m && s <= bw && p - s >= 0) {
+        v = rev ? L[band_at(m - 1 - p + s, bw - s, ld)] : L[band_at(p, bw - s, ld)];
+      }
+      o[(s / VT) * 64 * VT + s % VT] = (TF)v;
+    }
+    __syncthreads();
+  }
 }
 
 // ----------------------------------------------------------------- apply
-template <typename T>
-__device__ __forceinline__ T lane_bcast(T v, int lane);
-template <>
-__device__ __forceinline__ float lane_bcast<float>(float v, int lane) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-template <>
-__device__ __forceinline__ double lane_bcast<double>(double v, int lane) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
+// k_band_sweep: one workgroup of four waves per block (and chunk of NR
+// vectors); lane l owns row p = i0 + l of the current tile, and wave w owns
+// the slot vectors 4i + w (i < NV).  Per sub-tile, with the waves' partial
+// sums exchanged through LDS:
+//   phase 1: each wave sums its slots against its window of solved values
+//            (z of rows p - s; rows of the tile not yet solved read 0);
+//            barrier; every wave forms a = b - (sum of the four partials), in
+//            wave order, on the sub-tile's rows (0 elsewhere);
+//   phase 2: each wave sums its slots s < q against [0 x 64 | a] (a of row
+//            p - s, zero outside the sub-tile); barrier; every wave forms z,
+//            in wave order, and writes the sub-tile's rows to its own window;
+//            wave 0 stores them.
+// Every wave thus holds the same z, and the only cross-wave traffic is the
+// two partial-sum exchanges.  The window keeps each value twice, 256 rows
+// apart, so that the reads of rows p - s need no wrap-around.  The slots and
+// right-hand sides of tile t+2 are loaded into registers while tile t is
+// computed (three register sets in rotation, issued in tile order).  The forward sweep (slots of L,
+// right-hand side D u) and the backward sweep (slots of R, right-hand side
+// the reversed forward result, output scaled by D) run one after the other.
+// Blocks are taken in decreasing order of work (B.order), so the long chains
+// of the largest blocks start first.
+constexpr int SWEEP_WAVES = 4;
 
-// The computation of one tile of a sweep for lane l (row p) and NR vectors
-// (window q at yw + 256 q): the off-tile part against the window, then the
-// in-tile column sweep; leaves w_p of each vector in acc.  The band entries
-// are read once for the NR vectors, whose independent broadcast-and-FMA
-// chains of the column sweep interleave.
-// The window slots of the tile's rows are zero (they held rows 256 back, no
-// longer referenced) and slots of rows below 0 are zero from the start of the
-// sweep, so in-tile and out-of-matrix columns contribute nothing and the
-// batches of 8 need no mask; only the tail batch is masked.  All LDS reads
-// of a batch are issued before its arithmetic.  In the column sweep, entries
-// outside the band of row p (including j >= l) are read from the zero
-// diagonal slot, so a step is a multiply, a broadcast and an FMA; lane l's
-// value stops changing after step l, and rows past m have a zero pivot
-// reciprocal.
-template <typename T, int NR>
-__device__ __forceinline__ void band_tile(const T* buf, const T* yw, T (&acc)[NR], T dp, int p,
-                                          int l, int bw, int ld) {
-  // The entry indices of the column sweep are the same for every tile; an
-  // opaque copy of the lane index keeps the compiler from holding all 64 of
-  // them in registers across the tile loop (recomputing them is cheap).
-  asm volatile("" : "+v"(l));
-  const int kb = p - bw;
-  int d0 = 0;
-  for (; d0 + 8 <= bw; d0 += 8) {
-    T v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = buf[(d0 + i) * 64 + l];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      T yk[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) yk[i] = yw[q * 256 + ((kb + d0 + i) & 255)];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) acc[q] -= v[i] * yk[i];
-    }
-  }
-  if (d0 < bw) {
-    T v[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = buf[min(d0 + i, ld - 1) * 64 + l];
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      T yk[8];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) yk[i] = yw[q * 256 + ((kb + d0 + i) & 255)];
-#pragma unroll
-      for (int i = 0; i < 8; ++i) acc[q] -= (d0 + i < bw) ? v[i] * yk[i] : (T)0;
-    }
-  }
-#pragma unroll
-  for (int j0 = 0; j0 < 64; j0 += 8) {
-    T e[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int dd = bw - l + j0 + i;  // entry of row p for column i0 + j
-      e[i] = buf[((unsigned)dd <= (unsigned)bw ? dd : bw) * 64 + l];
-    }
-#pragma unroll
-    for (int i = 0; i < 8; ++i)
-#pragma unroll
-      for (int q = 0; q < NR; ++q) {
-        const T s = lane_bcast<T>(acc[q] * dp, j0 + i);
-        acc[q] -= e[i] * s;
-      }
-  }
-#pragma unroll
-  for (int q = 0; q < NR; ++q) acc[q] *= dp;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename TF, int NV, int NR>
+struct SweepSet {
+  TF cf[NV * (16 / sizeof(TF))];
+  double ra[NR];
+  double sc;
+};
+
+// Barrier that orders only LDS: the global loads of the prefetch stay in
+// flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// One wave per block; lane l owns row p = i0 + l of the current 64-row tile.
-// The tiles of the forward sweep (factor L, right-hand side D u) and then of
-// the backward sweep (factor R, right-hand side the reversed forward result)
-// are processed in one sequence.  The band of a tile (64*ld contiguous
-// values) and its right-hand side are loaded two tiles ahead into one of two
-// named register sets and written to the (single) LDS stage at the end of the
-// tile before their use, so each load has two tiles of compute to arrive
-// (the first two backward tiles need the forward result and load their
-// right-hand side after the forward sweep instead).  Per tile: the off-tile
-// part acc -= sum_{k < i0} F[p][k] w[k] reads the stage against the solved
-// values kept in a 256-entry circular window (bw <= BAND_MAX < 192, so rows
-// i0-bw..i0-1 are all still there); the in-tile triangle is a column sweep:
-// at step j, w_j = acc_j / F_jj is broadcast from lane j and the lanes below
-// it subtract F[p][i0+j] w_j.
-
-// Ordering point for the one-wave workgroup of k_band_apply: LDS operations
-// of a wave execute in program order, so a compiler barrier with
-// wavefront-scope fences orders the lanes' LDS accesses without the
-// memory-counter waits of a workgroup barrier (which would also wait for the
-// prefetch loads in flight and for the global stores of the last tile).
+// Ordering point for one wave's own LDS accesses (LDS operations of a wave
+// execute in program order).
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-#define BC_LIST(M, S)                                                                   \
-  M(S, 0) M(S, 1) M(S, 2) M(S, 3) M(S, 4) M(S, 5) M(S, 6) M(S, 7) M(S, 8) M(S, 9)        \
-  M(S, 10) M(S, 11) M(S, 12) M(S, 13) M(S, 14) M(S, 15) M(S, 16) M(S, 17) M(S, 18)       \
-  M(S, 19) M(S, 20) M(S, 21) M(S, 22) M(S, 23) M(S, 24) M(S, 25) M(S, 26) M(S, 27)       \
-  M(S, 28) M(S, 29) M(S, 30) M(S, 31)
-#define BC_DECL(S, q) float4 S##q;
-// vectors q >= npre re-read / re-write vector 0 (in bounds, idempotent), so
-// the loads and stores of a set carry no predicate
-#define BC_LOAD(S, q) if constexpr (NVP > q) S##q = src_[((q) < npre ? (q) : 0) * 64 + l];
-#define BC_STORE(S, q) if constexpr (NVP > q) dst_[((q) < npre ? (q) : 0) * 64 + l] = S##q;
+template <typename TA>
+constexpr size_t sweep_lds(int nr) {
+  // per wave and vector: window 2 x 256 + [zeros | a] 128; per vector and wave: two partials 64
+  return (size_t)SWEEP_WAVES * nr * (512 + 128 + 2 * 64) * sizeof(TA);
+}
 
-template <typename T, int NVP, int NR>
-__global__ void __launch_bounds__(64)
-k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
-             const int* __restrict__ done, int nrhs, int n1, int sys_done) {
-  extern __shared__ float4 lds4[];
-  const int blk = blockIdx.x;
+// The tiles of one sweep (BWD: the backward sweep, slots of R, right-hand
+// side the reversed forward result, output scaled by D).
+template <bool BWD, typename TF, typename TA, int NV, int NR>
+__device__ __forceinline__ void band_sweep_run(const TF* __restrict__ F0, const double* __restrict__ dsc,
+                                               const double* const (&src)[NR], double* const (&dst)[NR],
+                                               const bool (&act)[NR], TA* win, TA* za, TA* p1, TA* p2,
+                                               int m, int ld, int w, int l) {
+  constexpr int VT = 16 / (int)sizeof(TF);
+  constexpr int SMAX = 4 * NV * VT;  // bound of the slots a wave holds
+  constexpr int GI = NR == 1 ? 4 : 2;  // slot vectors whose LDS reads issue together
+  const int nt = (m + 63) >> 6;
+  const int qh = band_subtile(ld), qlog = __builtin_ctz(qh), nsub = 64 >> qlog;
+  using Set = SweepSet<TF, NV, NR>;
+  auto load = [&](Set& S, int t) {
+    // A buffer resource over exactly the tile's slots: vectors past its ld
+    // are out of range and read as zero, so every wave multiplies all NV of
+    // its vectors, in and past the block's band alike, with no mask.  A tile
+    // past the last one has an empty range (its set is never used).
+    const int nrec = t < nt ? 64 * ld * (int)sizeof(TF) : 0;
+    t = min(t, nt - 1);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(F0 + (long long)t * 64 * ld), (short)0, nrec, 0x00020000);
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (w * 64 + l) * 16, i * 4096, 0);
+      __builtin_memcpy(&S.cf[i * VT], &v, 16);
+    }
+    const int pc = min(t * 64 + l, m - 1);
+    const int r = BWD ? m - 1 - pc : pc;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) S.ra[q] = src[q][r];
+    S.sc = dsc[r];
+    // The sets are issued in tile order and never reordered: the compiler's
+    // wait counts take a set as complete only once every set issued before
+    // it is, so a later set issued first would make every tile wait for the
+    // set of the tile after it.
+    __builtin_amdgcn_sched_barrier(0);
+  };
+  // one sub-tile: the rows with mine set take a and z (q = 64: every row)
+  auto substep = [&](const Set& S, const TA (&b)[NR], TA (&zp)[NR], int p, bool mine) {
+    wave_sync();
+    // phase 1: this wave's slots against the solved values; win1 points at
+    // row p - SMAX of the doubled window
+    const TA* win1 = win + (p & 255) + 256 - SMAX;
+    TA part[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) part[q] = (TA)0;
+    // (the reads of a group of GI vectors are issued together, then
+    // multiplied in slot order)
+#pragma unroll
+    for (int g = 0; g < NV; g += GI) {
+      TA wv[GI * VT][NR];
+#pragma unroll
+      for (int i = g; i < g + GI && i < NV; ++i)
+#pragma unroll
+        for (int e = 0; e < VT; ++e)
+#pragma unroll
+          for (int q = 0; q < NR; ++q)
+            wv[(i - g) * VT + e][q] = win1[q * 512 + SMAX - ((4 * i + w) * VT + e)];
+#pragma unroll
+      for (int i = g; i < g + GI && i < NV; ++i)
+#pragma unroll
+        for (int e = 0; e < VT; ++e)
+#pragma unroll
+          for (int q = 0; q < NR; ++q) part[q] += (TA)S.cf[i * VT + e] * wv[(i - g) * VT + e][q];
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) p1[(w * NR + q) * 64 + l] = part[q];
+    lds_barrier();
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const TA* P = p1 + q * 64 + l;
+      const TA sum = ((P[0] + P[NR * 64]) + P[2 * NR * 64]) + P[3 * NR * 64];
+      za[q * 128 + 64 + l] = mine && p < m ? b[q] - sum : (TA)0;
+    }
+    wave_sync();
+    // phase 2: this wave's slots inside the sub-tile against a
+#pragma unroll
+    for (int q = 0; q < NR; ++q) part[q] = (TA)0;
+    // (vectors i < 16 / VT hold every slot below 64; a slot at or past q
+    // reads a row before the sub-tile, which is 0 in [0 x 64 | a])
+    constexpr int NV2 = NV < 16 / VT ? NV : 16 / VT;
+#pragma unroll
+    for (int g = 0; g < NV2; g += GI) {
+      TA wv[GI * VT][NR];
+#pragma unroll
+      for (int i = g; i < g + GI && i < NV2; ++i)
+#pragma unroll
+        for (int e = 0; e < VT; ++e)
+#pragma unroll
+          for (int q = 0; q < NR; ++q)
+            wv[(i - g) * VT + e][q] = za[q * 128 + 64 + l - ((4 * i + w) * VT + e)];
+#pragma unroll
+      for (int i = g; i < g + GI && i < NV2; ++i)
+#pragma unroll
+        for (int e = 0; e < VT; ++e)
+#pragma unroll
+          for (int q = 0; q < NR; ++q) part[q] += (TA)S.cf[i * VT + e] * wv[(i - g) * VT + e][q];
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) p2[(w * NR + q) * 64 + l] = part[q];
+    lds_barrier();
+    if (mine) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const TA* P = p2 + q * 64 + l;
+        zp[q] = ((P[0] + P[NR * 64]) + P[2 * NR * 64]) + P[3 * NR * 64];
+        win[q * 512 + (p & 255)] = zp[q];
+        win[q * 512 + (p & 255) + 256] = zp[q];
+      }
+    }
+  };
+  auto tile = [&](int t, const Set& S) {
+    const int p = t * 64 + l;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      win[q * 512 + (p & 255)] = (TA)0;
+      win[q * 512 + (p & 255) + 256] = (TA)0;
+    }
+    TA b[NR], zp[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) b[q] = BWD ? (TA)S.ra[q] : (TA)(S.ra[q] * S.sc);
+    // The first sub-tile is outside the loop, so every path through the tile
+    // has used the set; the loop holds no global store (a loop with stores
+    // and no loads makes the compiler wait for every load in flight, the
+    // prefetch included, before entering it).
+    substep(S, b, zp, p, (l >> qlog) == 0);
+    for (int k = 1; k < nsub; ++k) substep(S, b, zp, p, (l >> qlog) == k);
+    if (w == 0 && p < m) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        if (act[q]) {
+          if (!BWD) dst[q][p] = (double)zp[q];
+          else dst[q][m - 1 - p] = (double)zp[q] * S.sc;
+        }
+      }
+    }
+  };
+  // rows before the first tile read 0
+#pragma unroll
+  for (int q = 0; q < NR; ++q)
+#pragma unroll
+    for (int k = 0; k < 8; ++k) win[q * 512 + k * 64 + l] = (TA)0;
+  // Three register sets in rotation: tile t is computed while the sets of
+  // tiles t+1 and t+2 are in flight.
+  Set S0, S1, S2;
+  load(S0, 0);
+  load(S1, 1);
+  for (int t = 0; t < nt; t += 3) {
+    load(S2, t + 2);
+    tile(t, S0);
+    if (t + 1 >= nt) break;
+    load(S0, t + 3);
+    tile(t + 1, S1);
+    if (t + 2 >= nt) break;
+    load(S1, t + 4);
+    tile(t + 2, S2);
+  }
+}
+
+template <typename TF, typename TA, int NV, int NR>
+__global__ void __launch_bounds__(256, 2)
+k_band_sweep(BandBlocks B, const TF* __restrict__ FL, const TF* __restrict__ FR,
+             const double* __restrict__ u, double* __restrict__ y, const int* __restrict__ done,
+             int nrhs, int n1, int sys_done) {
+  extern __shared__ double sweep_lds_mem[];
+  // the wave index is uniform: slot bounds and branches on it stay scalar
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+  TA* lbase = (TA*)sweep_lds_mem;
+  TA* win = lbase + w * NR * 512;                                   // own windows, 2 x 256 per vector
+  TA* za = lbase + SWEEP_WAVES * NR * 512 + w * NR * 128;           // own [0 x 64 | a], per vector
+  TA* p1 = lbase + SWEEP_WAVES * NR * 640;                          // [wave][vector][64]
+  TA* p2 = p1 + SWEEP_WAVES * NR * 64;
+  const int blk = B.order[blockIdx.x];
   // vectors j0 .. j0 + NR - 1 of the nrhs at offsets j * n1; sys_done: one
   // vector of a batch of systems, stopped with the block's system
   const int j0 = blockIdx.y * NR;
@@ -307,220 +451,68 @@ k_band_apply(BandBlocks B, const double* __restrict__ u, double* __restrict__ y,
     any = any || act[q];
   }
   if (!any) return;
-  const int m = B.m[blk], bw = B.bw[blk], ld = B.ld[blk], row0 = B.row0[blk];
-  const int nt = (m + 63) >> 6;
-  const int l = threadIdx.x;
-  T* stage = (T*)lds4;                         // band of the current tile, 64*ld
-  T* yw = stage + 64 * B.ldmax;                // solved values, circular, 256 per vector
-  double* ra = (double*)(yw + 256 * NR);       // staged right-hand sides of the tile, 64 per vector
-  double* rs = ra + 64 * NR;                   // staged output scale
-  T* rd = (T*)(rs + 64);                       // staged pivot reciprocal
-  constexpr int VT = 16 / (int)sizeof(T);
-  const int nv = ld / VT;          // 16-byte vectors per lane per tile
-  const int npre = min(nv, NVP);   // of which prefetched
-  if (l == 0) atomicAdd(&B.applies[blk], 1ull);
-  const T* Fl;
-  const T* Fr;
-  const T* dv;
-  if constexpr (sizeof(T) == 8) {
-    Fl = (const T*)(B.L + B.off[blk]);
-    Fr = (const T*)(B.R + B.off[blk]);
-    dv = (const T*)(B.dinv + row0);
-  } else {
-    Fl = (const T*)(B.L32 + B.off[blk]);
-    Fr = (const T*)(B.R32 + B.off[blk]);
-    dv = (const T*)(B.dinv32 + row0);
-  }
-  const double* dsc = B.dsc + row0;
-  const int total = 2 * nt;
-  // vector q's right-hand side and output (vectors past nrhs read vector j0;
-  // inactive vectors write nothing)
-  auto ub = [&](int q) -> const double* {
-    return u + (size_t)(j0 + q < nrhs ? j0 + q : j0) * n1 + row0;
-  };
-  auto yb = [&](int q) -> double* { return y + (size_t)(j0 + q < nrhs ? j0 + q : j0) * n1 + row0; };
-  // band of tile idx (clamped into the sequence, so any idx is in bounds)
-  auto chunk = [&](int idx) -> const float4* {
-    idx = min(idx, total - 1);
-    const bool bwd = idx >= nt;
-    const int t = bwd ? idx - nt : idx;
-    return (const float4*)((bwd ? Fr : Fl) + (long long)t * 64 * ld);
-  };
-  // row whose right-hand side, output scale and pivot lane l loads for tile
-  // idx, clamped into the block so the loads carry no predicate
-  auto rhs_row = [&](int idx) -> int {
-    idx = min(idx, total - 1);
-    const int bwd = idx >= nt;
-    const int pc = min((bwd ? idx - nt : idx) * 64 + l, m - 1);
-    return bwd ? m - 1 - pc : pc;
-  };
-  auto rhs_src = [&](int idx, int q, int r) -> const double* {
-    return min(idx, total - 1) >= nt ? yb(q) + r : ub(q) + r;
-  };
-  // prologue: tile 0 staged, tile 1 in set A
-  {
-    const float4* src = chunk(0);
-    float4* dst = (float4*)stage;
-    for (int q = 0; q < nv; ++q) dst[q * 64 + l] = src[q * 64 + l];
-    const int r = rhs_row(0);
+  const int m = B.m[blk], ld = B.sld[blk], row0 = B.row0[blk];
+  if (threadIdx.x == 0) atomicAdd(&B.applies[blk], 1ull);
+  // vectors past nrhs read vector j0; inactive vectors write nothing
+  const double* ub[NR];
+  double* yb[NR];
 #pragma unroll
-    for (int q = 0; q < NR; ++q) ra[q * 64 + l] = ub(q)[r] * dsc[r];
-    rd[l] = dv[r];
+  for (int q = 0; q < NR; ++q) {
+    const size_t o = (size_t)(j0 + q < nrhs ? j0 + q : j0) * n1 + row0;
+    ub[q] = u + o;
+    yb[q] = y + o;
   }
-  BC_LIST(BC_DECL, pa)
-  BC_LIST(BC_DECL, pb)
-  double xa_a[NR], xb_a[NR], xa_s, xb_s;
-  T xa_d, xb_d;
-  {
-    const int r = rhs_row(1);
+  // [0 x 64 | a]: the zero half is written once
 #pragma unroll
-    for (int q = 0; q < NR; ++q) xa_a[q] = *rhs_src(1, q, r);
-    xa_s = dsc[r];
-    xa_d = dv[r];
-    const float4* src_ = chunk(1);
-    BC_LIST(BC_LOAD, pa)
-  }
-  wave_sync();
-
-  // One tile: CUR holds tile idx+1 (loaded one tile ago), NXT receives tile
-  // idx+2.
-#define BC_TILE(CUR, XC, NXT, XN)                                                         \
-  {                                                                                      \
-    const bool bwd = idx >= nt;                                                          \
-    const int t = bwd ? idx - nt : idx;                                                  \
-    const int i0 = t * 64, p = i0 + l;                                                   \
-    if (idx == nt || idx == nt + 1) {                                                    \
-      /* the first backward tiles start from the forward result of all lanes */         \
-      if (idx == nt) {                                                                   \
-        __threadfence_block();                                                           \
-        __syncthreads();                                                                 \
-      }                                                                                  \
-      const int r = rhs_row(idx);                                                        \
-      _Pragma("unroll") for (int q = 0; q < NR; ++q) ra[q * 64 + l] = yb(q)[r];          \
-      rs[l] = dsc[r];                                                                    \
-      rd[l] = dv[r];                                                                     \
-    }                                                                                    \
-    if (t == 0) {                                                                        \
-      _Pragma("unroll") for (int q = 0; q < 4 * NR; ++q) yw[q * 64 + l] = (T)0;          \
-    }                                                                                    \
-    _Pragma("unroll") for (int q = 0; q < NR; ++q) yw[q * 256 + (p & 255)] = (T)0;       \
-    wave_sync();                                                                         \
-    T acc[NR];                                                                           \
-    _Pragma("unroll") for (int q = 0; q < NR; ++q) acc[q] = p < m ? (T)ra[q * 64 + l] : (T)0; \
-    const T dp = p < m ? rd[l] : (T)0;                                                   \
-    const double sc = rs[l];                                                             \
-    /* prefetch tile idx+2: right-hand side first, then band */                         \
-    {                                                                                    \
-      const int r = rhs_row(idx + 2);                                                    \
-      _Pragma("unroll") for (int q = 0; q < NR; ++q) XN##_a[q] = *rhs_src(idx + 2, q, r); \
-      XN##_s = dsc[r];                                                                   \
-      XN##_d = dv[r];                                                                    \
-      const float4* src_ = chunk(idx + 2);                                               \
-      BC_LIST(BC_LOAD, NXT)                                                              \
-    }                                                                                    \
-    band_tile<T, NR>(stage, yw, acc, dp, p, l, bw, ld);                                  \
-    wave_sync(); /* every lane is done with the stage and the window */                 \
-    _Pragma("unroll") for (int q = 0; q < NR; ++q) yw[q * 256 + (p & 255)] = acc[q];     \
-    if (idx + 1 < total) {                                                               \
-      /* stage tile idx+1 (the one wait for HBM per tile) */                            \
-      float4* dst_ = (float4*)stage;                                                     \
-      BC_LIST(BC_STORE, CUR)                                                             \
-      const float4* nsrc = chunk(idx + 1);                                               \
-      for (int q = npre; q < nv; ++q) dst_[q * 64 + l] = nsrc[q * 64 + l];               \
-      _Pragma("unroll") for (int q = 0; q < NR; ++q)                                     \
-        ra[q * 64 + l] = (idx + 1 >= nt) ? XC##_a[q] : XC##_a[q] * XC##_s;              \
-      rs[l] = XC##_s;                                                                    \
-      rd[l] = XC##_d;                                                                    \
-    }                                                                                    \
-    if (p < m) {                                                                         \
-      _Pragma("unroll") for (int q = 0; q < NR; ++q) {                                   \
-        if (act[q]) {                                                                    \
-          if (!bwd) yb(q)[p] = (double)acc[q];                                           \
-          else yb(q)[m - 1 - p] = (double)acc[q] * sc;                                   \
-        }                                                                                \
-      }                                                                                  \
-    }                                                                                    \
-    wave_sync();                                                                         \
-  }
-
-  for (int idx = 0; idx < total; ++idx) {
-    BC_TILE(pa, xa, pb, xb)
-    if (++idx >= total) break;
-    BC_TILE(pb, xb, pa, xa)
-  }
-#undef BC_TILE
-}
-#undef BC_LIST
-#undef BC_DECL
-#undef BC_LOAD
-#undef BC_STORE
-
-// Compute units of the current device (read once).
-int device_cus() {
-  static int cus = [] {
-    int dev = 0, n = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1)
-      n = 256;
-    return n;
-  }();
-  return cus;
+  for (int q = 0; q < NR; ++q) za[q * 128 + l] = (TA)0;
+  band_sweep_run<false, TF, TA, NV, NR>(FL + B.soff[blk], B.dsc + row0, ub, yb, act, win, za, p1,
+                                        p2, m, ld, w, l);
+  // the backward sweep starts from the forward result of every row
+  __threadfence_block();
+  __syncthreads();
+  band_sweep_run<true, TF, TA, NV, NR>(FR + B.soff[blk], B.dsc + row0, yb, yb, act, win, za, p1, p2,
+                                       m, ld, w, l);
 }
 
-// Dynamic LDS of the sweep for NR vectors: stage, NR windows, NR staged
-// right-hand sides, output scales and pivot reciprocals.
-template <typename T>
-size_t band_apply_lds(const BandBlocks& B, int nr) {
-  return (size_t)(64 * B.ldmax + 256 * nr) * sizeof(T) + 64 * nr * sizeof(double) +
-         64 * (sizeof(double) + sizeof(T));
+// Register-set sizes (16-byte slot vectors per wave) the sweeps are built
+// for: the widest band (ld = 128) takes 16 vectors in FP64, 8 in FP32.
+constexpr int SWEEP_NV[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16};
+
+template <typename TF, typename TA, int NR, int K = 0>
+const void* sweep_kernel(int nv) {
+  if constexpr (K + 1 < (int)(sizeof(SWEEP_NV) / sizeof(int)) &&
+                (sizeof(TF) == 8 || SWEEP_NV[K] < 8)) {
+    if (nv > SWEEP_NV[K]) return sweep_kernel<TF, TA, NR, K + 1>(nv);
+  }
+  return (const void*)k_band_sweep<TF, TA, SWEEP_NV[K], NR>;
 }
 
-template <typename T, int NR>
-hipError_t launch_apply_nr(hipStream_t st, const BandBlocks& B, const double* u, double* y,
-                           const int* done, int nrhs, int n1, int sys_done, int nvp) {
-  const size_t lds = band_apply_lds<T>(B, NR);
+template <typename TF, typename TA, int NR>
+hipError_t launch_sweep_nr(hipStream_t st, const BandBlocks& B, const TF* FL, const TF* FR,
+                           const double* u, double* y, const int* done, int nrhs, int n1,
+                           int sys_done) {
+  const size_t lds = sweep_lds<TA>(NR);
   const dim3 grid(B.nblk, (nrhs + NR - 1) / NR);
-#define BC_LAUNCH(V)                                                                       \
-  hipLaunchKernelGGL((k_band_apply<T, V, NR>), grid, dim3(64), lds, st, B, u, y, done, nrhs, \
-                     n1, sys_done)
-  if constexpr (NR == 1) {
-    if (nvp == 4) BC_LAUNCH(4);
-    else if (nvp == 8) BC_LAUNCH(8);
-    else if (nvp == 12) BC_LAUNCH(12);
-    else if (nvp == 20) BC_LAUNCH(20);
-    else if (nvp == 16) BC_LAUNCH(16);
-    else if (nvp == 24) BC_LAUNCH(24);
-    else BC_LAUNCH(32);
-  } else {
-    // the multi-vector sweeps use register sets of at most BAND_MULTI_NVP
-    if (nvp <= 4) BC_LAUNCH(4);
-    else if (nvp <= 8) BC_LAUNCH(8);
-    else BC_LAUNCH(BAND_MULTI_NVP);
-  }
-#undef BC_LAUNCH
-  return hipGetLastError();
+  // slot vectors per wave: the widest block's slots / VT over four waves
+  const int nv = (B.sldmax * (int)sizeof(TF) / 16 + 3) / 4;
+  void* args[] = {(void*)&B, (void*)&FL, (void*)&FR, (void*)&u, (void*)&y, (void*)&done,
+                  (void*)&nrhs, (void*)&n1, (void*)&sys_done};
+  return hipLaunchKernel(sweep_kernel<TF, TA, NR>(nv), grid, dim3(64 * SWEEP_WAVES), args, lds, st);
 }
 
-template <typename T>
-hipError_t launch_apply_t(hipStream_t st, const BandBlocks& B, const double* u, double* y,
-                          const int* done, int nrhs, int n1, int sys_done) {
-  const int nvp = B.nvp > 0 ? B.nvp : band_nvp_buckets(B, sizeof(T)).back();
-  if (nrhs == 1) return launch_apply_nr<T, 1>(st, B, u, y, done, nrhs, n1, sys_done, nvp);
-  // Several vectors: one wave per block and chunk of 1, 4 or 8 vectors.  A
-  // wave is bound by the latency of its column sweeps, and a second wave on
-  // a SIMD slows both about as much as running after it, so the time is
-  // about (rounds of one wave per SIMD) x (the chunk's cost), the chunks of
-  // 1, 4 and 8 vectors costing about 1 : 2.6 : 3.7 (measured on the 27-point
-  // 100^3 blocks).  The cheapest is taken (the narrower on a tie).
-  const long long simds = 4LL * device_cus();
-  auto cost = [&](int nr, double w) {
-    const long long waves = (long long)B.nblk * ((nrhs + nr - 1) / nr);
-    return (double)((waves + simds - 1) / simds) * w;
-  };
-  const double c1 = cost(1, 1.0), c4 = cost(4, 2.6), c8 = cost(8, 3.7);
-  if (c1 <= c4 && c1 <= c8) return launch_apply_nr<T, 1>(st, B, u, y, done, nrhs, n1, sys_done, nvp);
-  if (c4 <= c8) return launch_apply_nr<T, 4>(st, B, u, y, done, nrhs, n1, sys_done, nvp);
-  return launch_apply_nr<T, 8>(st, B, u, y, done, nrhs, n1, sys_done, nvp);
+template <typename TF, typename TA>
+hipError_t launch_sweep_t(hipStream_t st, const BandBlocks& B, const TF* FL, const TF* FR,
+                          const double* u, double* y, const int* done, int nrhs, int n1,
+                          int sys_done) {
+  // several vectors: chunks of 4 read each factor once per chunk
+  if (nrhs == 1) return launch_sweep_nr<TF, TA, 1>(st, B, FL, FR, u, y, done, nrhs, n1, sys_done);
+  return launch_sweep_nr<TF, TA, 4>(st, B, FL, FR, u, y, done, nrhs, n1, sys_done);
+}
+
+hipError_t launch_sweep(hipStream_t st, const BandBlocks& B, bool mixed, const double* u, double* y,
+                        const int* done, int nrhs, int n1, int sys_done) {
+  return mixed ? launch_sweep_t<float, float>(st, B, B.SL32, B.SR32, u, y, done, nrhs, n1, sys_done)
+               : launch_sweep_t<double, double>(st, B, B.SL, B.SR, u, y, done, nrhs, n1, sys_done);
 }
 
 }  // namespace
@@ -545,66 +537,35 @@ hipError_t launch_band_cholesky(hipStream_t st, const BandBlocks& B) {
 
 hipError_t launch_band_finish(hipStream_t st, const BandBlocks& B, bool mixed) {
   if (B.nblk == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_band_finish, dim3(32, B.nblk), dim3(256), 0, st, B, (int)mixed);
-  if (!mixed) hipLaunchKernelGGL(k_band_zero_diag, dim3(4, B.nblk), dim3(256), 0, st, B);
+  const dim3 grid(64, B.nblk, 2);
+  if (mixed)
+    hipLaunchKernelGGL(k_band_slots<float>, grid, dim3(64), 0, st, B, B.SL32, B.SR32);
+  else
+    hipLaunchKernelGGL(k_band_slots<double>, grid, dim3(64), 0, st, B, B.SL, B.SR);
   return hipGetLastError();
 }
 
-// Register-set sizes (16-byte vectors per lane and tile) worth trying for
-// these blocks: every instantiated size up to the first one that holds a
-// whole tile of the widest band.
-std::vector<int> band_nvp_buckets(const BandBlocks& B, size_t elem) {
-  static const int sizes[] = {4, 8, 12, 16, 20, 24, 32};
-  const int nvmax = B.ldmax * (int)elem / 16;
-  std::vector<int> out;
-  for (int v : sizes) {
-    out.push_back(v);
-    if (v >= nvmax) break;
-  }
-  return out;
-}
-
-// Raises the dynamic LDS limit of every sweep instantiation to what the
-// widest band needs (set once at setup, so that a launch inside a stream
-// capture is a plain kernel launch).
-template <typename T>
-hipError_t prepare_apply_t(const BandBlocks& B) {
-  const int l1 = (int)band_apply_lds<T>(B, 1), l4 = (int)band_apply_lds<T>(B, 4);
-  const int l8 = (int)band_apply_lds<T>(B, 8);
-  const std::pair<const void*, int> fns[] = {
-      {(const void*)k_band_apply<T, 4, 1>, l1},  {(const void*)k_band_apply<T, 8, 1>, l1},
-      {(const void*)k_band_apply<T, 12, 1>, l1}, {(const void*)k_band_apply<T, 16, 1>, l1},
-      {(const void*)k_band_apply<T, 20, 1>, l1}, {(const void*)k_band_apply<T, 24, 1>, l1},
-      {(const void*)k_band_apply<T, 32, 1>, l1}, {(const void*)k_band_apply<T, 4, 4>, l4},
-      {(const void*)k_band_apply<T, 8, 4>, l4},  {(const void*)k_band_apply<T, 12, 4>, l4},
-      {(const void*)k_band_apply<T, 4, 8>, l8},  {(const void*)k_band_apply<T, 8, 8>, l8},
-      {(const void*)k_band_apply<T, 12, 8>, l8}};
-  for (const auto& f : fns) {
-    hipError_t e = hipFuncSetAttribute(f.first, hipFuncAttributeMaxDynamicSharedMemorySize, f.second);
+// Raises the dynamic LDS limit of the multi-vector sweeps (set once at setup,
+// so that a launch inside a stream capture is a plain kernel launch).
+hipError_t prepare_band_apply(const BandBlocks& B, bool mixed) {
+  if (B.nblk == 0) return hipSuccess;
+  const int l4 = (int)(mixed ? sweep_lds<float>(4) : sweep_lds<double>(4));
+  for (int nv : SWEEP_NV) {
+    const void* f = mixed ? sweep_kernel<float, float, 4>(nv) : sweep_kernel<double, double, 4>(nv);
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, l4);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
 }
 
-hipError_t prepare_band_apply(const BandBlocks& B, bool mixed) {
-  if (B.nblk == 0) return hipSuccess;
-  return mixed ? prepare_apply_t<float>(B) : prepare_apply_t<double>(B);
-}
-
 hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, const double* u,
                              double* y, const int* done) {
   if (B.nblk == 0) return hipSuccess;
-  return mixed ? launch_apply_t<float>(st, B, u, y, done, 1, 0, 1)
-               : launch_apply_t<double>(st, B, u, y, done, 1, 0, 1);
+  return launch_sweep(st, B, mixed, u, y, done, 1, 0, 1);
 }
 
 hipError_t launch_band_apply_multi(hipStream_t st, const BandBlocks& B, bool mixed,
                                    const double* u, double* y, const int* done, int nrhs, int n1) {
   if (B.nblk == 0 || nrhs <= 0) return hipSuccess;
-  return mixed ? launch_apply_t<float>(st, B, u, y, done, nrhs, n1, 0)
-               : launch_apply_t<double>(st, B, u, y, done, nrhs, n1, 0);
-}
-
-std::vector<int> band_apply_candidates(const BandBlocks& B, bool mixed) {
-  return band_nvp_buckets(B, mixed ? sizeof(float) : sizeof(double));
+  return launch_sweep(st, B, mixed, u, y, done, nrhs, n1, 0);
 }

@@ -345,10 +345,13 @@ hipError_t launch_dense_apply_multi(hipStream_t st, const DenseBlocks& D, bool m
 // of local row p, i.e. L[p][p - bw + d], is at off + (p/64)*64*ld + d*64 +
 // p%64, with ld = bw+1 rounded up to a multiple of 4 (entries left of column
 // 0, entries d > bw and rows past m are zero; a tile is 64*ld contiguous
-// values, a multiple of 16 bytes).  R is the reversed transpose,
-// R[p][k] = L[m-1-k][m-1-p], in the same layout, so the backward sweep with
-// L^T is a forward sweep with R on reversed vectors.
+// values, a multiple of 16 bytes).  The sweeps read L and its reversed
+// transpose R[p][k] = L[m-1-k][m-1-p] (the backward sweep with L^T is a
+// forward sweep with R on reversed vectors) in a slot layout of the same size
+// that puts the inverse of each tile's diagonal block in place of the
+// in-tile entries (band.hip).
 constexpr int BAND_MAX = 127;  // largest half-bandwidth (LDS window of the factorization)
+
 struct BandBlocks {
   int nblk;
   const int* row0;
@@ -356,14 +359,15 @@ struct BandBlocks {
   const int* bw;           // half-bandwidth per block
   const int* ld;           // stored entries per row (bw+1 rounded up to a multiple of 4)
   int ldmax;               // largest ld
-  int nvp;                 // 16-byte vectors per lane of a prefetch register set (0 = default)
+  const int* order;        // blocks by decreasing m * sld: launch order of the sweeps
   const int* sys;
-  const long long* off;    // element offset of the block's tiles
-  double* L;               // Gram matrix on entry to the factorization, FP64 factor after
-  double* R;               // FP64 reversed transpose (FP64 projections only)
-  float* L32; float* R32;  // FP32 copies (FP32 projections only)
-  double* dinv;            // per permuted row: 1 / L[p][p]
-  float* dinv32;
+  const long long* off;    // element offset of the block's tiles in the band layout
+  const int* sld;          // slots per row in the slot layout of the sweeps (>= ld)
+  const long long* soff;   // element offset of the block's tiles in the slot layout
+  int sldmax;              // largest sld
+  double* L;               // Gram matrix on entry to the factorization, FP64 factor after (band layout)
+  double* SL; double* SR;  // slot layout of L and of its reversed transpose (FP64 projections)
+  float* SL32; float* SR32;// the same rounded to FP32 (FP32 projections)
   int* info;               // per block: 0 ok, j+1 = first pivot at or below m*eps*G_jj
   unsigned long long* applies; // per block running count of applications
   const double* dsc;       // per permuted row 1/||a_r||_2 (see InnerBlocks)
@@ -376,9 +380,8 @@ hipError_t launch_band_apply(hipStream_t st, const BandBlocks& B, bool mixed, co
                              double* y, const int* done);
 hipError_t prepare_band_apply(const BandBlocks& B, bool mixed);
 // The same sweeps for nrhs vectors of a one-system context at once (vector j
-// at u + j*n1, y + j*n1; done indexed by j): chunks of up to 8 vectors per
-// wave read each band once.  Every vector gets the bits of launch_band_apply.
-constexpr int BAND_MULTI_NVP = 12;  // prefetch register set of the multi-vector sweeps
+// at u + j*n1, y + j*n1; done indexed by j): chunks of 4 vectors per
+// workgroup read each factor once.  Every vector gets the bits of
+// launch_band_apply.
 hipError_t launch_band_apply_multi(hipStream_t st, const BandBlocks& B, bool mixed,
                                    const double* u, double* y, const int* done, int nrhs, int n1);
-std::vector<int> band_apply_candidates(const BandBlocks& B, bool mixed);
