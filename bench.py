@@ -2,13 +2,20 @@
 """Benchmark of the CG-accelerated block Cimmino path on one MI355X.
 
 One step is one pass of the whole path over the workload:
-row inner-product graph (GPU) -> greedy partition (host C++) -> setup
-(permutation, transposes, dense factors on the GPU) -> solve to a relative
-true residual of 1e-10 (GPU).  The headline `value` is outer CG iterations
-per second of the solve phase (inputs resident in HBM); time-to-tolerance
-and the other phases are reported beside it.
+row inner-product graph (GPU; rip_graph-partitioned workloads only) ->
+partition (host C++) -> setup (permutation, transposes, factors on the GPU) ->
+solve to a relative true residual of 1e-10 (GPU).  The headline `value` is
+outer CG iterations per second of the solve phase (inputs resident in HBM;
+for a batch, the iterations of all systems); time-to-tolerance and the other
+phases are reported beside it.
 
-Usage: python bench.py [--steps K] [--warmup W] [--workload cfg2|cfg1|cfg3|cfg4|cfg5|cfg5-rip|cfg5-band]
+The default workload is the batch of 256 2D convection-diffusion systems
+(sides 48..256, 8 blocks each) in plain FP64, all systems in one batched
+solve; the same run also solves the batch with FP32 projections (FP64 outer
+CG) and reports both times to tolerance and their ratio.
+
+Usage: python bench.py [--steps K] [--warmup W]
+                       [--workload cfg4|cfg1|cfg2|cfg3|cfg5|cfg5-rip|cfg5-band]
 """
 from __future__ import annotations
 
@@ -26,18 +33,37 @@ sys.path.insert(0, ROOT)
 METRIC = "outer Cimmino iters/s + time-to-1e-10 residual; % HBM roofline; mixed vs FP64"
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes per dispatch of the dominant projection kernel, from separate
-# rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this same command (default
-# precision of the workload), scaled by the factors a plain 1 GiB copy gives
-# (FETCH x2.0, WRITE x1.0).  An entry is removed whenever its kernel changes.
-MEASURED_TRAFFIC = {
-    "cfg2": {"kernel": "k_inner_grp<double>", "bytes_per_launch": 1.166e+10,
-             "profile": "profiles/k_inner_grp_f64_cd3d_64cubed_K32.md"},
-    "cfg4": {"kernel": "k_band_apply<float, 20>", "bytes_per_launch": 2.569e+09,
-             "profile": "profiles/k_band_apply_f32_cd2d_batch256_K8.md"},
-    "cfg5": {"kernel": "k_dense_apply<float, 4>", "bytes_per_launch": 7.805e+09,
-             "profile": "profiles/k_dense_apply_f32_st27_100cubed_K512.md"},
+# Counter summaries of the dominant projection kernel per workload (HBM
+# bytes per dispatch from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE runs of this
+# script, scaled by a plain copy's counts).  Each summary records the SHA-256
+# of the kernel's source file; the traffic is reported only while that source
+# is unchanged.
+TRAFFIC_PROFILES = {
+    ("cfg4", "fp64"): "profiles/k_band_sweep_f64_cd2d_batch256_K8.md",
+    ("cfg4", "mixed-proj"): "profiles/k_band_sweep_f32_cd2d_batch256_K8.md",
 }
+
+
+def measured_traffic(workload, precision):
+    """(bytes per dispatch, profile path) from the workload's counter
+    summary, or (None, reason) when there is none or its kernel changed."""
+    import hashlib
+    import re
+    path = TRAFFIC_PROFILES.get((workload, precision))
+    if path is None:
+        return None, "no counter summary for this workload"
+    full = os.path.join(ROOT, path)
+    if not os.path.exists(full):
+        return None, path + " missing"
+    text = open(full).read()
+    m_src = re.search(r"^source: (\S+) sha256 ([0-9a-f]{64})$", text, re.M)
+    m_val = re.search(r"^traffic_bytes_per_dispatch: ([0-9.eE+-]+)$", text, re.M)
+    if not (m_src and m_val):
+        return None, path + " has no machine-readable traffic line"
+    src = os.path.join(ROOT, m_src.group(1))
+    if not os.path.exists(src) or hashlib.sha256(open(src, "rb").read()).hexdigest() != m_src.group(2):
+        return None, "kernel source changed since " + path
+    return float(m_val.group(1)), path
 
 
 def parse():
@@ -45,10 +71,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--workload", default="cfg4")
     ap.add_argument("--precision", default=None, choices=[None, "fp64", "mixed", "mixed-proj"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=20)
+    ap.add_argument("--cpu-iters", type=int, default=10,
+                    help="outer iterations of each oracle solve in the CPU baseline sample")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32-projection solve of a batched workload")
     ap.add_argument("--method", default="cg", choices=["cg", "alg1", "block"],
                     help="cg: Algorithm 2 (default; with --nrhs, one CG per right-hand side "
                          "through bc_solve_multi); alg1: Algorithm 1 (plain block Cimmino) "
@@ -101,10 +130,9 @@ class Workload:
         elif name == "cfg4":
             self.problems, self.partition = W.config4(), "contiguous"
             self.batched = True
-            self.opts = {"precision": bc.BC_MIXED_PROJ}
+            self.opts = {"precision": bc.BC_FP64}
             self.desc = ("256 x cd2d sides 48..256, K=8 each, batched, projection kind per "
-                         "block by the byte model (banded FP64 Cholesky, FP32 applies), "
-                         "FP64 sparse products and outer CG")
+                         "block by the byte model (banded FP64 Cholesky), plain FP64")
         elif name in ("cfg5", "cfg5-rip"):
             p = W.config5()
             self.problems = [p]
@@ -128,6 +156,11 @@ class Workload:
             self.opts["precision"] = bc.BC_MIXED
         elif precision == "mixed-proj":
             self.opts["precision"] = bc.BC_MIXED_PROJ
+        if name == "cfg4" and self.opts["precision"] != bc.BC_FP64:
+            self.desc = self.desc.replace("plain FP64", "FP32 applies, FP64 sparse products "
+                                                        "and outer CG")
+        self.precision = {bc.BC_FP64: "fp64", bc.BC_MIXED: "mixed",
+                          bc.BC_MIXED_PROJ: "mixed-proj"}[self.opts.get("precision", bc.BC_FP64)]
         self.mixed = self.opts.get("precision", 0) in (bc.BC_MIXED, bc.BC_MIXED_PROJ)
         self.n = sum(q.n for q in self.problems)
         self.nnz = sum(q.A.nnz for q in self.problems)
@@ -205,6 +238,7 @@ def run_step(wl, f_dev, method="cg", partitioner="greedy", nrhs=None):
     finally:
         bc.bc_destroy(ctx)
     out["iterations"] = sum(s.iterations for s in sts)
+    out["sys_iters"] = [int(s.iterations) for s in sts]
     out["max_iterations"] = max(s.iterations for s in sts)
     out["status"] = max(abs(s.status) for s in sts)
     out["rel_residual"] = max(s.rel_residual for s in sts)
@@ -255,34 +289,133 @@ def spectrum_study(wl, f_dev, steps=60):
     return out
 
 
-def cpu_baseline(wl, iters, omega=None):
-    """The oracle timed on the host cores on a bounded sample of the workload:
-    its projection setup for the whole system, then the first `iters` outer
-    iterations of its Algorithm 2 (tol = 0), or of its Algorithm 1 with
-    relaxation `omega` when that is given."""
-    import workloads as W
-    from oracle import (BlockProjections, block_cimmino_cg, block_cimmino_plain, rip_graph,
-                        greedy_partition)
-    q = wl.problems[0]
-    if wl.partition == "greedy-rip":
-        part = greedy_partition(rip_graph(q.A), q.K)
-    else:
-        part = q.part()
+def _oracle_sample_worker(args):
+    """One oracle solve of the CPU baseline (a process of its own): the
+    oracle's projection setup, then `iters` outer iterations of Algorithm 2
+    (tol = 0), or of Algorithm 1 with relaxation `omega`.  The iteration
+    phase starts at a barrier shared by all workers so that the sample's
+    wall time covers iterations running side by side."""
+    q, part, iters, omega, barrier = args
+    from oracle import BlockProjections, block_cimmino_cg, block_cimmino_plain
     A = q.A.to_scipy()
     t0 = time.perf_counter()
     B = BlockProjections(A, part, q.K)
     t1 = time.perf_counter()
+    if barrier is not None:
+        barrier.wait()
+    t2 = time.perf_counter()
     if omega is None:
         block_cimmino_cg(A, q.f, part, q.K, tol=0.0, maxit=iters, proj=B)
     else:
         block_cimmino_plain(A, q.f, part, q.K, omega=omega, tol=0.0, maxit=iters, proj=B)
-    t2 = time.perf_counter()
-    return {"value": iters / (t2 - t1), "unit": "outer iters/s", "cores": 1, "kind": "oracle",
+    t3 = time.perf_counter()
+    return {"name": q.name, "setup_s": t1 - t0, "start": t2, "end": t3, "iters": iters}
+
+
+def _pool_init():
+    # one thread per worker process: the workers are the parallelism
+    os.environ["OMP_NUM_THREADS"] = "1"
+    os.environ["OPENBLAS_NUM_THREADS"] = "1"
+    os.environ["MKL_NUM_THREADS"] = "1"
+
+
+def cpu_baseline(wl, iters, omega=None, sys_iters=None):
+    """The oracle timed on the host cores on a bounded sample of the workload.
+
+    A batch: one oracle solve per worker process, one worker per host core
+    (at most 16), on systems spread evenly over the batch's sizes, all
+    iterating at once.  Each sampled system's time per outer iteration
+    (measured with all workers running) stands for the batch's systems
+    nearest to it in size; the batch's CPU time is then the sum, over its
+    systems, of the outer iterations the GPU solve took (`sys_iters`) times
+    that per-iteration time, spread over the cores, and value = the batch's
+    outer iterations over that time.  One system: the oracle's own solve,
+    its BLAS on every host core.  Each solve is the oracle's projection setup
+    (reported separately) and then its first `iters` outer iterations."""
+    import multiprocessing as mp
+    from oracle import rip_graph, greedy_partition
+    cores = max(1, min(len(os.sched_getaffinity(0)), 16))
+    if wl.batched:
+        cores = min(cores, len(wl.problems))
+        order = np.argsort([q.n for q in wl.problems], kind="stable")
+        pick = [int(order[int(round(i * (len(order) - 1) / max(cores - 1, 1)))])
+                for i in range(cores)]
+        qs = [wl.problems[i] for i in pick]
+        ctx = mp.get_context("spawn")
+        with ctx.Manager() as mgr:
+            barrier = mgr.Barrier(len(qs))
+            with ctx.Pool(len(qs), initializer=_pool_init) as pool:
+                res = pool.map(_oracle_sample_worker,
+                               [(q, q.part(), iters, omega, barrier) for q in qs])
+        wall = max(r["end"] for r in res) - min(r["start"] for r in res)
+        per_it = np.array([(r["end"] - r["start"]) / r["iters"] for r in res])
+        ns = np.array([q.n for q in qs], dtype=float)
+        its = np.asarray(sys_iters if sys_iters is not None else [iters] * len(wl.problems),
+                         dtype=float)
+        near = [int(np.argmin(np.abs(ns - q.n))) for q in wl.problems]
+        cpu_s = float(np.sum(its * per_it[near])) / len(qs)
+        sides = sorted(int(round(np.sqrt(q.n))) for q in qs)
+        return {"value": float(its.sum()) / cpu_s, "unit": "outer iters/s", "cores": len(qs),
+                "kind": "oracle",
+                "sample": "%d of the %d systems (grid sides %s), one oracle process per host "
+                          "core (1 BLAS thread each): projection setup (%.1f s mean), then %d "
+                          "outer CG iterations each, all started together (%.1f s until the "
+                          "last finished); scaled to the whole batch: each system's outer "
+                          "iterations in the GPU solve (%d in all) at the per-iteration time of "
+                          "the sampled system nearest in size, over %d cores = %.0f s; %d host "
+                          "cores visible"
+                          % (len(qs), len(wl.problems), ",".join(map(str, sides)),
+                             float(np.mean([r["setup_s"] for r in res])), iters, wall,
+                             int(its.sum()), len(qs), cpu_s, len(os.sched_getaffinity(0)))}
+    q = wl.problems[0]
+    part = greedy_partition(rip_graph(q.A), q.K) if wl.partition == "greedy-rip" else q.part()
+    r = _oracle_sample_worker((q, part, iters, omega, None))
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    except Exception:  # threadpoolctl missing: report the process's own view
+        blas = 1
+    return {"value": iters / (r["end"] - r["start"]), "unit": "outer iters/s", "cores": blas,
+            "kind": "oracle",
             "sample": "%s: oracle projection setup (%.1f s, seminormal equations with SuperLU / "
-                      "LAPACK per block) then its first %d %s iterations (%.1f s); "
-                      "single-threaded SciPy; %d host cores visible"
-                      % (q.name, t1 - t0, iters, "outer CG" if omega is None else
-                         "Algorithm 1", t2 - t1, len(os.sched_getaffinity(0)))}
+                      "LAPACK per block) then its first %d %s iterations (%.1f s); BLAS on %d "
+                      "threads (SuperLU itself is sequential); %d host cores visible"
+                      % (q.name, r["setup_s"], iters, "outer CG" if omega is None else
+                         "Algorithm 1", r["end"] - r["start"], blas,
+                         len(os.sched_getaffinity(0)))}
+
+
+def mixed_batched(wl, f_dev, reps=3):
+    """The same batch solved with FP32 projections (FP64 outer CG): setup
+    once, one untimed solve, then `reps` timed solves (median)."""
+    import torch
+    import paper_1710_07769_amd as bc
+    opts = dict(wl.opts, precision=bc.BC_MIXED_PROJ)
+    ctx = bc.bc_setup_batched([(q.n, q.A.rowptr, q.A.col, q.A.val, q.K, q.part())
+                               for q in wl.problems], bc.make_opts(**opts))
+    try:
+        x = torch.empty_like(f_dev)
+        times, its = [], []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = bc.bc_solve_batched(ctx, f_dev, None, wl.tol, 10000, x)
+            torch.cuda.synchronize()
+            if r > 0:
+                times.append((time.perf_counter() - t0) * 1e3)
+            its.append(int(max(st.iterations for st in sts)))
+            print("[bench] FP32 projections, batched: %.1f ms, %d iterations (slowest system)"
+                  % ((time.perf_counter() - t0) * 1e3, its[-1]), file=sys.stderr, flush=True)
+        res = max(st.rel_residual for st in sts)
+        proj_ms = sts[0].t_proj_ms
+        launches = sts[0].proj_launches
+        pbytes = sts[0].proj_bytes
+    finally:
+        bc.bc_destroy(ctx)
+    return {"time_to_tol_ms": float(np.median(times)), "iterations_max": its[-1],
+            "rel_residual": res,
+            "projection_avg_launch_ms": proj_ms / max(launches, 1),
+            "projection_bytes_per_launch": pbytes / max(launches, 1)}
 
 
 def fp64_comparison(wl, f_dev, t_config_ms):
@@ -439,10 +572,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "avg_launch_ms": proj_ms / max(launches, 1),
                      "bytes_per_launch": pbytes / max(launches, 1),
-                     "traffic": (MEASURED_TRAFFIC[wl.name]["bytes_per_launch"]
-                                 if wl.name in MEASURED_TRAFFIC and args.precision is None
-                                 and args.nrhs is None else None)},
+                     "timing": "wall-clock stamp kernels on the library stream around each "
+                               "projection launch (the solve replays captured graphs, inside "
+                               "which events cannot be timed)",
+                     "traffic": None},
     }
+    traffic, tsrc = (measured_traffic(wl.name, wl.precision) if args.nrhs is None
+                     and args.method == "cg" else (None, "not profiled"))
+    line["roofline"]["traffic"] = traffic
+    line["roofline"]["traffic_source"] = tsrc
     if "cutsize" in runs[-1]:
         line["partition_cutsize"] = runs[-1]["cutsize"]
     if args.nrhs is not None:
@@ -457,10 +595,18 @@ def main():
         line["spectrum_study"] = spectrum_study(wl, f)
     if args.compare:
         line["fp64_comparison"] = fp64_comparison(wl, f, line["time_to_tol_ms"])
-    if not args.no_cpu_baseline and not wl.batched:
+    if wl.batched and not args.no_mixed and wl.precision == "fp64" and args.method == "cg":
+        # the precision pattern on the same matrices, batched against batched
+        mb = mixed_batched(wl, f)
+        mb["speedup_vs_fp64_batched"] = line["time_to_tol_ms"] / mb["time_to_tol_ms"]
+        mb["mode"] = ("bc_solve_batched with FP32 banded applies (FP64 factorization, sparse "
+                      "products, outer CG scalars and true-residual replacement)")
+        line["mixed_batched"] = mb
+    if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(
-            wl, args.cpu_iters, line["spectrum"]["omega"] if args.method == "alg1" else None)
+            wl, args.cpu_iters, line["spectrum"]["omega"] if args.method == "alg1" else None,
+            runs[-1]["sys_iters"] if wl.batched else None)
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
