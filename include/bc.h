@@ -259,6 +259,18 @@ bc_status bc_schedule(const bc_ctx* ctx, int32_t* lanes_a, int32_t* lanes_at);
  * host arrays of bc_info's nblocks entries, either may be NULL. */
 bc_status bc_block_info(const bc_ctx* ctx, int32_t* kind, int32_t* bandwidth);
 
+/* Bound of the device waits of a context, in seconds of wall clock (default
+ * 2).  Two kernels wait for other parts of the GPU: the inner CG, whose
+ * workgroups of one block meet at barriers in global memory, and the dense
+ * sweep whose waves publish finished rows to each other.  A wait that passes
+ * the bound stops its kernel, which then exits normally, and the call
+ * (bc_project or a solve) returns BC_ERR_DEVICE with a message in
+ * bc_last_error: its result is invalid, and the next call on the context
+ * starts clean.  seconds = 0 makes every such wait give up at its first check
+ * (a test of that path); negative or non-finite values return
+ * BC_ERR_INVALID. */
+bc_status bc_set_wait_limit(bc_ctx* ctx, double seconds);
+
 /* Releases the context and all its device memory.  NULL is allowed. */
 void bc_destroy(bc_ctx* ctx);
 

@@ -96,6 +96,7 @@ _SIGS = {
     "bc_info": (C.c_int, [_P, _I64P, _I32P, _I32P, _I32P]),
     "bc_block_info": (C.c_int, [_P, _I32P, _I32P]),
     "bc_schedule": (C.c_int, [_P, _I32P, _I32P]),
+    "bc_set_wait_limit": (C.c_int, [_P, C.c_double]),
     "bc_destroy": (None, [_P]),
     "rip_opts_default": (None, [C.POINTER(rip_opts)]),
     "rip_graph": (C.c_int, [C.c_int32, _I32P, _I32P, _DP, C.POINTER(rip_opts),
@@ -286,6 +287,10 @@ def bc_schedule(ctx):
     a, t = C.c_int32(), C.c_int32()
     _check(_lib.bc_schedule(ctx, C.byref(a), C.byref(t)), "bc_schedule")
     return a.value, t.value
+
+
+def bc_set_wait_limit(ctx, seconds: float) -> None:
+    _check(_lib.bc_set_wait_limit(ctx, float(seconds)), "bc_set_wait_limit")
 
 
 def bc_destroy(ctx):

@@ -69,7 +69,6 @@ hipError_t launch_gram(hipStream_t st, const DenseBlocks& D, const int4* tiles, 
                        const int* trow, const double* tval);
 int inner_max_resident_groups(bool mixed);
 int inner_grp_max_resident(bool mixed, int max_m);
-int* inner_err_flag();
 hipError_t rip_launch_prescale(hipStream_t st, int n, long long nnz, const int* rowptr,
                                double* aval, const int* trow, double* tval, double* nrm,
                                int* zero_row);
@@ -398,6 +397,11 @@ struct bc_ctx {
   std::vector<int> blk_m;
   std::vector<long long> in_nnz, in_m_h, dn_m_h;  // per inner / dense block sizes
   int dense_max_nt = 0;                             // largest tiles per side of a dense block
+
+  // Wait-error word of the bounded device waits (inner-CG workgroups, dense
+  // sweep waves): cleared at the start of each call, read at its end.
+  int* d_err = nullptr;
+  unsigned long long wait_ticks = 0;  // bound of a wait in device wall-clock ticks (set at setup)
 
   // captured group of outer iterations (factor-based projections only)
   hipGraphExec_t gexec = nullptr;
@@ -917,6 +921,15 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   // ---- device state
   hipStream_t st = c->stream;
   Arena& A = c->arena;
+  {
+    std::vector<int> ez(1, 0);
+    BC_TRY(A.upload(&c->d_err, ez, st));
+    int dev = 0, khz = 0;
+    BC_HIP(hipGetDevice(&dev));
+    BC_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    c->wall_khz = khz > 0 ? khz : 100000;
+    c->wait_ticks = (unsigned long long)(2.0 * c->wall_khz * 1e3);  // 2 s
+  }
   BC_TRY(A.upload(&c->d_perm, perm, st));
   BC_TRY(A.upload(&c->d_rowptr, rowptr, st));
   BC_TRY(A.upload(&c->d_col, col, st));
@@ -1166,6 +1179,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     unsigned* pbar;
     BC_TRY(A.upload(&pbar, bz, st));
     B.bar = pbar;
+    B.err = c->d_err;
+    B.wait_ticks = c->wait_ticks;
     std::vector<int> iz(B.nblk, 0);
     int* pit;
     BC_TRY(A.upload(&pit, iz, st));
@@ -1216,11 +1231,8 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     BC_HIP(launch_cholesky(st, D));
     BC_HIP(launch_dense_finish(st, D, c->mixed));
     BC_HIP(prepare_dense_apply());
-    D.err = inner_err_flag();  // allocated here, outside any stream capture
-    if (!D.err) {
-      bc_set_error("device error flag could not be allocated");
-      return BC_ERR_NOMEM;
-    }
+    D.err = c->d_err;
+    D.wait_ticks = c->wait_ticks;
     std::vector<int> info(D.nblk);
     BC_HIP(hipMemcpyAsync(info.data(), pinfo, D.nblk * sizeof(int), hipMemcpyDeviceToHost, st));
     BC_HIP(hipStreamSynchronize(st));
@@ -1455,6 +1467,21 @@ extern "C" bc_status bc_schedule(const bc_ctx* c, int32_t* lanes_a, int32_t* lan
   return BC_OK;
 }
 
+extern "C" bc_status bc_set_wait_limit(bc_ctx* c, double seconds) {
+  if (!c || !(seconds >= 0.0) || !std::isfinite(seconds) || seconds > 1e9) {
+    bc_set_error("bc_set_wait_limit: null context or seconds not in [0, 1e9]");
+    return BC_ERR_INVALID;
+  }
+  c->wait_ticks = (unsigned long long)(seconds * c->wall_khz * 1e3);
+  c->inner.wait_ticks = c->wait_ticks;
+  c->dense.wait_ticks = c->wait_ticks;
+  if (c->gexec) {  // the captured iterations hold the old bound
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  return BC_OK;
+}
+
 extern "C" bc_status bc_block_info(const bc_ctx* c, int32_t* kind, int32_t* bandwidth) {
   if (!c) {
     bc_set_error("ctx is null");
@@ -1527,6 +1554,42 @@ void harvest_proj_events(bc_ctx* c) {
   c->ev_used = 0;
 }
 
+__global__ void k_zero_words(unsigned* __restrict__ p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
+// Clears the context's wait-error word at the start of a call (a kernel, not
+// a memset: the caller's stream may be under capture).
+bc_status clear_wait_error(bc_ctx* c) {
+  hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, c->stream, (unsigned*)c->d_err, 1LL);
+  BC_HIP(hipGetLastError());
+  return BC_OK;
+}
+
+// BC_ERR_DEVICE if a bounded device wait gave up during the call.  The
+// inner-CG barrier epochs and tagged partials then start again from zero, so
+// that workgroups that stopped at different barriers meet again at the next
+// call.
+bc_status check_wait_error(bc_ctx* c) {
+  int h = 0;
+  BC_HIP(hipMemcpyAsync(&h, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  BC_HIP(hipStreamSynchronize(c->stream));
+  if (!h) return BC_OK;
+  if (c->inner.nblk) {
+    hipLaunchKernelGGL(k_zero_words, dim3(64), dim3(256), 0, c->stream, c->inner.bar,
+                       32LL * c->inner.nblk);
+    hipLaunchKernelGGL(k_zero_words, dim3(64), dim3(256), 0, c->stream, (unsigned*)c->inner.xp,
+                       2LL * 2 * 64 * c->inner.nblk);
+    BC_HIP(hipGetLastError());
+    BC_HIP(hipStreamSynchronize(c->stream));
+  }
+  bc_set_error("a device wait gave up (inner-CG workgroups of a block or dense sweep waves did "
+               "not meet within the wait limit); the result is invalid");
+  return BC_ERR_DEVICE;
+}
+
 // Algorithmic bytes of all projection launches counted by the device counters.
 bc_status proj_bytes(bc_ctx* c, double* out) {
   const double w = c->mixed ? 4.0 : 8.0;
@@ -1577,22 +1640,16 @@ extern "C" bc_status bc_project(bc_ctx* c, const double* v, double* Hv) {
     return BC_ERR_INVALID;
   }
   BC_TRY(enter(c, c->opts.stream));
+  BC_TRY(clear_wait_error(c));
   OuterState S = c->outer(0, 0);
   S.done = c->d_zero_flags;
   hipStream_t st = c->stream;
   BC_HIP(spmv_a(c, st, c->lanes, v, c->d_u, S, false));
   BC_TRY(block_solves(c, c->d_u, c->d_y, nullptr));
   BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, Hv, v, S));
+  const bc_status werr = check_wait_error(c);
   BC_TRY(leave(c, c->opts.stream));
-  int* err = inner_err_flag();
-  int h = 0;
-  BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
-  if (h) {
-    bc_set_error("a device wait timed out (inner CG workgroups or dense sweep waves); the "
-                   "result is invalid");
-    return BC_ERR_DEVICE;
-  }
-  return BC_OK;
+  return werr;
 }
 
 // ------------------------------------------------------------------- solve
@@ -1748,6 +1805,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
     return BC_ERR_INVALID;
   }
   BC_TRY(enter(c, o.stream));
+  BC_TRY(clear_wait_error(c));
   OuterState S = c->outer(maxit, backward ? 1 : 0);
   S.tol_bw = tol;
   // f in block order, x = x0 (or 0), s = f - A x
@@ -1880,21 +1938,15 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   BC_TRY(proj_bytes(c, &pbytes));
   for (int s2 = 0; s2 < ns; ++s2)
     if (!done[s2]) status[s2] = BC_NOT_CONVERGED;
-  {
-    int* err = inner_err_flag();
-    int h = 0;
-    BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
-    if (h) {
-      bc_set_error("a device wait timed out (inner CG workgroups or dense sweep waves); the "
-                   "result is invalid");
-      return BC_ERR_DEVICE;
-    }
-  }
+  // a wait that gave up invalidates the result; the stats and the stream
+  // order are still completed before the error is returned
+  const bc_status werr = check_wait_error(c);
   const double t_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats)
     BC_TRY(fill_stats(c, x, S, iters, status, replacements, t_ms, pbytes, inner_total, stats));
   BC_TRY(leave(c, o.stream));
+  if (werr != BC_OK) return werr;
   int worst = BC_OK;
   for (int s2 = 0; s2 < ns; ++s2) {
     const int v = status[s2];
@@ -1923,6 +1975,7 @@ bc_status cimmino_impl(bc_ctx* c, const double* f, const double* x0, double omeg
   hipStream_t st = c->stream;
   const int n = c->n_total, ns = c->nsys;
   BC_TRY(enter(c, o.stream));
+  BC_TRY(clear_wait_error(c));
   OuterState S = c->outer(maxit, 0);
   BC_HIP(launch_gather(st, f, c->d_perm, c->d_f, n));
   if (x0) BC_HIP(launch_copy(st, x0, x, n)); else BC_HIP(launch_zero(st, x, n));
@@ -1961,21 +2014,15 @@ bc_status cimmino_impl(bc_ctx* c, const double* f, const double* x0, double omeg
   BC_TRY(proj_bytes(c, &pbytes));
   for (int s2 = 0; s2 < ns; ++s2)
     if (!done[s2]) status[s2] = BC_NOT_CONVERGED;
-  {
-    int* err = inner_err_flag();
-    int h = 0;
-    BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
-    if (h) {
-      bc_set_error("a device wait timed out (inner CG workgroups or dense sweep waves); the "
-                   "result is invalid");
-      return BC_ERR_DEVICE;
-    }
-  }
+  // a wait that gave up invalidates the result; the stats and the stream
+  // order are still completed before the error is returned
+  const bc_status werr = check_wait_error(c);
   const double t_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats)
     BC_TRY(fill_stats(c, x, S, iters, status, replacements, t_ms, pbytes, inner_total, stats));
   BC_TRY(leave(c, o.stream));
+  if (werr != BC_OK) return werr;
   int worst = BC_OK;
   for (int s2 = 0; s2 < ns; ++s2) {
     const int v = status[s2];
@@ -2332,6 +2379,7 @@ bc_status block_cg_impl(bc_ctx* c, const double* f, const double* x0, double tol
     return BC_OK;
   };
   BC_TRY(enter(c, o.stream));
+  BC_TRY(clear_wait_error(c));
   OuterState S = c->outer(maxit, 0);
   OuterState Sall = S;
   Sall.done = c->d_zero_flags;
@@ -2477,21 +2525,15 @@ bc_status block_cg_impl(bc_ctx* c, const double* f, const double* x0, double tol
   c->timing = false;
   double pbytes = 0.0;
   BC_TRY(proj_bytes(c, &pbytes));
-  {
-    int* err = inner_err_flag();
-    int h = 0;
-    BC_HIP(hipMemcpy(&h, err, sizeof(int), hipMemcpyDeviceToHost));
-    if (h) {
-      bc_set_error("a device wait timed out (inner CG workgroups or dense sweep waves); the "
-                   "result is invalid");
-      return BC_ERR_DEVICE;
-    }
-  }
+  // a wait that gave up invalidates the result; the stats and the stream
+  // order are still completed before the error is returned
+  const bc_status werr = check_wait_error(c);
   const double t_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats)
     BC_TRY(fill_stats(c, x, Sall, iters, status, replacements, t_ms, pbytes, inner_total, stats));
   BC_TRY(leave(c, o.stream));
+  if (werr != BC_OK) return werr;
   int worst = BC_OK;
   for (int j = 0; j < nr; ++j) {
     const int sv = status[j];

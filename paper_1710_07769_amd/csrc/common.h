@@ -279,6 +279,9 @@ struct InnerBlocks {
   // Sliced ELL copies (slices of 64 rows / 64 support columns; entry k of
   // lane l of slice s at ptr[s] + 64 k + l; padding has index 0, value 0)
   unsigned long long* trace; // optional phase timestamps (block 0), null when off
+  int* err;                // the context's wait-error word: set to 1 when a workgroup gave up
+                           // waiting for the others of its block (the result is then invalid)
+  unsigned long long wait_ticks;  // bound of a wait, 100 MHz wall-clock ticks (0: give up at once)
   const double* dsc;       // per permuted row 1/||a_r||_2: the projections solve the
                            // scaled normal equations (D A_i A_i^T D) z = D u, y = D z
   int sell;                // 1 if built
@@ -320,7 +323,9 @@ struct DenseBlocks {
   double* gdiag;           // diagonal of every block's Gram matrix (permuted row index)
   unsigned long long* applies; // per block running count of applications
   const double* dsc;       // per permuted row 1/||a_r||_2 (see InnerBlocks)
-  int* err;                // set to 1 when a wave of a sweep gave up waiting (result invalid)
+  int* err;                // the context's wait-error word: set to 1 when a wave of a sweep
+                           // gave up waiting (the result is then invalid)
+  unsigned long long wait_ticks;  // bound of a wait, 100 MHz wall-clock ticks (0: give up at once)
 };
 hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);

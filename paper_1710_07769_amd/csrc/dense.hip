@@ -455,9 +455,8 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
 // the one before it, rows finish in order, and the loads of a tile are issued
 // before the wait for the row they multiply, so one wave streams its factor
 // tiles while another finishes its diagonal product.  The waits are bounded
-// by the wall clock; a wave that gives up sets *D.err (the result is then
-// invalid).
-constexpr unsigned long long DENSE_WAIT_LIMIT = 200000000ull;  // wall-clock ticks (2 s)
+// by the wall clock (D.wait_ticks); a wave that gives up sets *D.err (the
+// result is then invalid).
 
 // Orders the LDS accesses of the lanes of one wave (they execute in program
 // order; the fences keep the compiler from moving accesses across).
@@ -469,9 +468,11 @@ __device__ __forceinline__ void dense_wave_sync() {
 
 // Waits until a row of the current sweep is published (its flag >= 1).
 __device__ __forceinline__ void wait_row(const int* flag, unsigned long long t0, int* err,
-                                         bool& ok) {
-  while (ok && __hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < 1) {
-    if (wall_clock64() - t0 > DENSE_WAIT_LIMIT) {
+                                         unsigned long long ticks, bool& ok) {
+  // ticks == 0 gives up at the first check
+  while (ok && (ticks == 0 ||
+                __hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < 1)) {
+    if (wall_clock64() - t0 > ticks) {
       if ((threadIdx.x & 63) == 0) atomicExch(err, 1);
       ok = false;
     } else {
@@ -573,7 +574,7 @@ k_dense_apply_rows(DenseBlocks D, const double* __restrict__ u, double* __restri
           for (int uu = 0; uu < U; ++uu)
             a[uu] = *(const V*)(tile + (c0 + 4 * uu + lk) * DT + 4 * li);
           if (c0 == 0 && (fwd ? j > ready : j < ready)) {
-            wait_row(fl + j, t0, D.err, ok);
+            wait_row(fl + j, t0, D.err, D.wait_ticks, ok);
             ready = j;
           }
           T bz[U];

@@ -23,8 +23,6 @@ namespace {
 
 constexpr int IN_THREADS = 512;
 constexpr int NXCD = 8;
-// about 2 s of the 100 MHz constant clock
-constexpr unsigned long long WAIT_LIMIT = 200000000ull;
 
 template <typename T>
 struct Vec;
@@ -342,6 +340,7 @@ struct FlagBar {
   unsigned epoch;
   int g, groups;
   bool fenced;       // full agent-scope fences (workgroups not on one XCC)
+  unsigned long long ticks;  // wait bound (0: give up at the first check)
 };
 
 __device__ __forceinline__ bool flag_barrier(FlagBar& fb, int* err) {
@@ -361,8 +360,8 @@ __device__ __forceinline__ bool flag_barrier(FlagBar& fb, int* err) {
                              ? __hip_atomic_load(&fb.flags[threadIdx.x], __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT)
                              : fb.epoch;
-      if (__all((int)(v - fb.epoch) >= 0)) break;
-      if (wall_clock64() - t0 > WAIT_LIMIT) {
+      if (fb.ticks != 0 && __all((int)(v - fb.epoch) >= 0)) break;
+      if (wall_clock64() - t0 > fb.ticks) {
         ok = 0;
         if (threadIdx.x == 0) atomicExch(err, 1);
         break;
@@ -395,7 +394,8 @@ __device__ __forceinline__ void put_tagged(unsigned long long* p, double v, unsi
 // Waits (bounded) for the two tagged values at p and p + 2 of epoch ep on
 // every lane of the wavefront where `active` (the others pass).
 __device__ __forceinline__ bool get_tagged2(const unsigned long long* p, bool active, unsigned ep,
-                                            double& a, double& b, int* err) {
+                                            double& a, double& b, int* err,
+                                            unsigned long long ticks) {
   const unsigned long long idle = (unsigned long long)ep << 32;
   const unsigned long long t0 = wall_clock64();
   while (true) {
@@ -405,12 +405,12 @@ __device__ __forceinline__ bool get_tagged2(const unsigned long long* p, bool ac
       v[q] = active ? __hip_atomic_load(p + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : idle;
     const bool here = (unsigned)(v[0] >> 32) == ep && (unsigned)(v[1] >> 32) == ep &&
                       (unsigned)(v[2] >> 32) == ep && (unsigned)(v[3] >> 32) == ep;
-    if (__all(here)) {
+    if (ticks != 0 && __all(here)) {
       a = __builtin_bit_cast(double, (v[1] << 32) | (v[0] & 0xffffffffull));
       b = __builtin_bit_cast(double, (v[3] << 32) | (v[2] & 0xffffffffull));
       return true;
     }
-    if (wall_clock64() - t0 > WAIT_LIMIT) {
+    if (wall_clock64() - t0 > ticks) {
       if ((threadIdx.x & 63) == 0) atomicExch(err, 1);
       return false;
     }
@@ -479,7 +479,7 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   constexpr bool DEFER = RPT <= 2;
   __shared__ double gd_sh[2];
   __shared__ int fail_sh;
-  FlagBar fb{B.bar + (size_t)b * 32, 0u, g, G, false};
+  FlagBar fb{B.bar + (size_t)b * 32, 0u, g, G, false, B.wait_ticks};
   if (threadIdx.x == 0) {
     fb.epoch = __hip_atomic_load(&fb.flags[g], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // placement check: publish this workgroup's XCC and whether it matches
@@ -636,7 +636,7 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
       if (wave == 0) {
         double pgq = 0.0, pdq = 0.0;
         bool okp = true;
-        okp = get_tagged2(xpe + (lane < G ? lane : 0) * 4, lane < G, E, pgq, pdq, err);
+        okp = get_tagged2(xpe + (lane < G ? lane : 0) * 4, lane < G, E, pgq, pdq, err, B.wait_ticks);
         if (lane >= G) pgq = pdq = 0.0;
         if (fb.fenced) __threadfence();
         double gsum = 0.0, dsum = 0.0;
@@ -761,22 +761,10 @@ hipError_t launch_grp(hipStream_t st, const InnerBlocks& B, const double* u, dou
 
 }  // namespace
 
-// Device-side error flag of the inner CG (wait timeouts); allocated once per process.
-static int* g_inner_err = nullptr;
-
-int* inner_err_flag() {
-  if (!g_inner_err) {
-    if (hipMalloc(&g_inner_err, sizeof(int)) != hipSuccess) return nullptr;
-    if (hipMemset(g_inner_err, 0, sizeof(int)) != hipSuccess) return nullptr;
-  }
-  return g_inner_err;
-}
-
 hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, const double* u,
                            double* y, const int* done) {
   if (B.nblk == 0) return hipSuccess;
-  int* err = inner_err_flag();
-  if (!err) return hipErrorOutOfMemory;
+  int* err = B.err;
   if (B.groups > 1) {
     if (B.idx16)
       return mixed ? launch_grp<float, uint16_t>(st, B, u, y, done, err)

@@ -69,6 +69,7 @@ def test_setup_validation_without_device():
     for bad in (-1, 3):
         _expect_invalid(lambda: bc.bc_setup(p.n, A.rowptr, A.col, A.val, p.K, part,
                                             bc.make_opts(multi_gather=bad), stream=False))
+    _expect_invalid(lambda: bc.bc_set_wait_limit(None, 1.0))
 
 
 @pytest.mark.parametrize("maker,K", [(workloads.config1, 4), (lambda: workloads.small_config2(N=12, K=6), 6),
