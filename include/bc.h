@@ -170,6 +170,22 @@ bc_status bc_project(bc_ctx* ctx, const double* v, double* Hv);
 bc_status bc_solve(bc_ctx* ctx, const double* f, const double* x0, double tol,
                    int32_t maxit, double* x, bc_stats* stats);
 
+/* bc_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture nearby, tight serving loops, harnesses that forbid
+ * hipMalloc): the same Algorithm 2 on the same kernels with no allocation at
+ * call time.  Its seven work vectors of n_total doubles live in a static
+ * device array of 256 MiB (held by every GPU the library runs on until the
+ * process ends) instead of the context's own; the outer iterations are
+ * plain launches (no captured graph) and no timing events are created, so
+ * bc_stats.t_proj_ms and proj_launches are 0.  Results are bit for bit those
+ * of bc_solve (also for batched contexts; the call takes one system or a
+ * batch like bc_solve_batched, with stats holding nsys entries).  Returns
+ * BC_ERR_INVALID when 7 * n_total * 8 bytes exceed the array (n_total above
+ * 4,793,490 rows).  All contexts on one GPU share the array: calls that
+ * overlap on one GPU (other host threads) race. */
+bc_status bc_solve_noalloc(bc_ctx* ctx, const double* f, const double* x0, double tol,
+                           int32_t maxit, double* x, bc_stats* stats);
+
 /* Batched form of bc_solve: f, x0, x are concatenated device vectors; stats
  * (host, may be NULL) has nsys entries.  Each system stops on its own; the
  * call returns the worst status over the systems. */

@@ -87,6 +87,7 @@ _SIGS = {
     "bc_project": (C.c_int, [_P, _P, _P]),
     "bc_solve": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
     "bc_solve_batched": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
+    "bc_solve_noalloc": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, C.POINTER(bc_stats)]),
     "bc_cimmino": (C.c_int, [_P, _P, _P, C.c_double, C.c_double, C.c_int32, _P,
                              C.POINTER(bc_stats)]),
     "bc_solve_multi": (C.c_int, [_P, C.c_int32, _P, _P, C.c_double, C.c_int32, _P,
@@ -219,6 +220,15 @@ def bc_solve_batched(ctx, f, x0, tol: float, maxit: int, x) -> List[bc_stats]:
     s = _lib.bc_solve_batched(ctx, _dev(f, "f"), None if x0 is None else _dev(x0, "x0"),
                               float(tol), int(maxit), _dev(x, "x"), st)
     _check(s, "bc_solve_batched", ok=(BC_OK, BC_NOT_CONVERGED, BC_ERR_BREAKDOWN))
+    return list(st)
+
+
+def bc_solve_noalloc(ctx, f, x0, tol: float, maxit: int, x) -> List[bc_stats]:
+    ns = bc_info(ctx)["nsys"]
+    st = (bc_stats * ns)()
+    s = _lib.bc_solve_noalloc(ctx, _dev(f, "f"), None if x0 is None else _dev(x0, "x0"),
+                              float(tol), int(maxit), _dev(x, "x"), st)
+    _check(s, "bc_solve_noalloc", ok=(BC_OK, BC_NOT_CONVERGED, BC_ERR_BREAKDOWN))
     return list(st)
 
 

@@ -338,6 +338,7 @@ struct bc_ctx {
   double t_proj_ms = 0.0;           // harvested projection time of the current solve
   int proj_launches = 0;
   bool timing = false;
+  bool noalloc = false;  // solve without any allocation (bc_solve_noalloc): no graphs, no events
   bool mixed = false;     // FP32 projections (BC_MIXED or BC_MIXED_PROJ)
   bool spmv32 = false;    // FP32 sparse products (BC_MIXED)
   int nsys = 0;
@@ -1816,7 +1817,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   BC_HIP(launch_set_thresholds(st, c->d_part_f, backward ? 0.0 : tol, S));
   BC_HIP(hipMemsetAsync(c->d_inner_total, 0, sizeof(unsigned long long), st));
   BC_TRY(reset_proj_counters(c));
-  c->timing = true;
+  c->timing = !c->noalloc;
   // r = sum_i A_i^+ (f_i - A_i x0) = A^T D^{-1} s ; p = r
   BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
   BC_HIP(spmv_t(c, st, c->lanesT, c->d_y, c->d_r, c->d_p, S));
@@ -1826,7 +1827,8 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   // projections G divides replace_every, so replacements fall between groups.
   int G = std::max(1, o.check_every);
   if (c->mixed && o.replace_every > 0) G = std::gcd(G, o.replace_every);
-  const bool graphs = o.use_graph && c->inner.nblk == 0 && !c->graph_off && c->mrhs.nrhs == 0;
+  const bool graphs = o.use_graph && c->inner.nblk == 0 && !c->graph_off && c->mrhs.nrhs == 0 &&
+                      !c->noalloc;
   std::vector<int> done(ns, 0), status(ns, 0), iters(ns, 0);
   std::vector<int> verified(ns, 0), replacements(ns, 0);
   int it = 0;
@@ -2045,6 +2047,86 @@ extern "C" bc_status bc_solve(bc_ctx* c, const double* f, const double* x0, doub
     return BC_ERR_INVALID;
   }
   return solve_impl(c, f, x0, tol, maxit, x, stats);
+}
+
+// ------------------------------------------------ solve without allocation
+// The seven work vectors of the outer iteration (f in block order, r, p, psi,
+// s, u = A p, y) live in this file-scope array during bc_solve_noalloc
+// instead of the context's own vectors; every GPU the library runs on holds
+// its copy until the process ends.  Host code takes its address per device
+// with hipGetSymbolAddress (the name itself is not a device address on the
+// host).
+constexpr size_t SCRATCH_BYTES = 256ull << 20;
+constexpr int SCRATCH_VECTORS = 7;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::unordered_map<int, double*> g_scratch_ptr;  // device id -> address of its scratch
+
+bc_status scratch_of_device(double** out) {
+  int dev = 0;
+  BC_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it == g_scratch_ptr.end()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      bc_set_error(std::string("bc_solve_noalloc: address of the static scratch: ") +
+                   hipGetErrorString(e));
+      return BC_ERR_DEVICE;
+    }
+    it = g_scratch_ptr.emplace(dev, (double*)ptr).first;
+  }
+  *out = it->second;
+  return BC_OK;
+}
+
+}  // namespace
+
+extern "C" bc_status bc_solve_noalloc(bc_ctx* c, const double* f, const double* x0, double tol,
+                                      int32_t maxit, double* x, bc_stats* stats) {
+  if (!c) {
+    bc_set_error("ctx is null");
+    return BC_ERR_INVALID;
+  }
+  if (c->mrhs.nrhs > 0) {
+    bc_set_error("bc_solve_noalloc: context is inside a solve with several right-hand sides");
+    return BC_ERR_INVALID;
+  }
+  const size_t need = (size_t)SCRATCH_VECTORS * (size_t)c->n_total * sizeof(double);
+  if (need > SCRATCH_BYTES) {
+    bc_set_error("bc_solve_noalloc: " + std::to_string(SCRATCH_VECTORS) + " vectors of " +
+                 std::to_string(c->n_total) + " rows need " + std::to_string(need) +
+                 " bytes, more than the " + std::to_string(SCRATCH_BYTES) +
+                 "-byte static scratch (at most " +
+                 std::to_string(SCRATCH_BYTES / (SCRATCH_VECTORS * sizeof(double))) + " rows)");
+    return BC_ERR_INVALID;
+  }
+  double* base = nullptr;
+  BC_TRY(scratch_of_device(&base));
+  const size_t n = (size_t)c->n_total;
+  // what the solve reads before writing must start at zero: clear the whole
+  // part it uses (a kernel, no memset)
+  {
+    const long long words = (long long)(need / sizeof(unsigned));
+    hipLaunchKernelGGL(k_zero_words, dim3((unsigned)std::min<long long>((words + 255) / 256, 4096)),
+                       dim3(256), 0, c->stream, (unsigned*)base, words);
+    BC_HIP(hipGetLastError());
+  }
+  double** vecs[SCRATCH_VECTORS] = {&c->d_f, &c->d_r, &c->d_p, &c->d_psi, &c->d_s, &c->d_u, &c->d_y};
+  double* saved[SCRATCH_VECTORS];
+  for (int q = 0; q < SCRATCH_VECTORS; ++q) {
+    saved[q] = *vecs[q];
+    *vecs[q] = base + q * n;
+  }
+  c->noalloc = true;
+  const bc_status rc = solve_impl(c, f, x0, tol, maxit, x, stats);
+  c->noalloc = false;
+  for (int q = 0; q < SCRATCH_VECTORS; ++q) *vecs[q] = saved[q];
+  return rc;
 }
 
 extern "C" bc_status bc_solve_batched(bc_ctx* c, const double* f, const double* x0, double tol,
