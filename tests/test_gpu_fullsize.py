@@ -27,6 +27,7 @@ import pytest
 import paper_1710_07769_amd as bc
 import workloads
 from oracle import rip_rows
+from _bars import counts_match
 
 pytestmark = pytest.mark.gpu
 
@@ -82,12 +83,19 @@ def partition_hash(part):
     return int(np.sum(part.astype(np.int64) * np.arange(1, n + 1, dtype=np.int64)) % (2**61 - 1))
 
 
+def history_at(ref):
+    """The oracle's relative true residual after t iterations, for the last
+    iterations of its solve (stored by make_oracle_fullsize.py)."""
+    tail = ref["history_tail"]
+    return lambda t: tail[str(t)]
+
+
 def check_fp64_count_and_iterate(dev, solver, f, ref, tol=1e-10):
     x, st = solver.solve(f, tol=tol, maxit=20000)
     assert st.status == bc.BC_OK and st.rel_residual <= tol * (1 + 1e-6)
-    d = st.iterations - ref["iterations"]
     print("iterations gpu=%d oracle=%d" % (st.iterations, ref["iterations"]))
-    assert abs(d) <= 1, "iteration counts differ by %d" % d
+    counts_match(st.iterations, ref["iterations"], history_at(ref), tol)
+    # iterates compared at the oracle's count
     x2, st2 = solver.solve(f, tol=0.0, maxit=ref["iterations"])
     err = sample_err(x2.cpu().numpy(), ref)
     print("sampled error at equal count: %.3e" % err)
@@ -215,8 +223,10 @@ def test_batch256_cd2d(dev, golden, precision):
             print("system %d (n=%d): iterations gpu=%d oracle=%d sampled err=%.2e"
                   % (k, probs[k].n, sts[k].iterations, ref["iterations"], err))
             if precision == "fp64":
-                assert abs(sts[k].iterations - ref["iterations"]) <= 1
-                assert err <= 1e-8
+                # iterates compared only at equal counts
+                if counts_match(sts[k].iterations, ref["iterations"], history_at(ref), 1e-10,
+                                "system %d" % k):
+                    assert err <= 1e-8
             else:
                 assert err <= 1e-6
     finally:

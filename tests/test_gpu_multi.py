@@ -31,7 +31,8 @@ import pytest
 
 import paper_1710_07769_amd as bc
 import workloads
-from oracle import block_cimmino_cg
+from _bars import counts_match
+from oracle import backward_error, block_cimmino_cg
 
 pytestmark = pytest.mark.gpu
 
@@ -47,6 +48,13 @@ def dev():
 def banner(msg):
     print("\n[case] " + msg, flush=True)
 
+
+
+def backward_error_at(A, f, part, K, t):
+    """The oracle's normwise backward error (eq. (stopping)) after t
+    iterations of Algorithm 2."""
+    r = block_cimmino_cg(A, f, part, K, tol=0.0, maxit=t)
+    return backward_error(A, r.x, f)
 
 def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
@@ -108,10 +116,8 @@ def test_multi_dense_fp64_matches_single_and_oracle(dev):
     for j in (0, 3):
         ref = block_cimmino_cg(A, F[j], part, 6, tol=1e-10)
         print("rhs %d: oracle iterations %d" % (j, ref.iterations))
-        assert sts[j].status == bc.BC_OK and abs(sts[j].iterations - ref.iterations) <= 1
-        if sts[j].iterations != ref.iterations:
-            t = min(sts[j].iterations, ref.iterations)
-            assert abs(ref.history[t] - 1e-10) <= 1e-3 * 1e-10
+        assert sts[j].status == bc.BC_OK
+        counts_match(sts[j].iterations, ref.iterations, lambda t: ref.history[t], 1e-10)
     # at the oracle's count, the iterates agree
     solver = bc.BlockCimmino(p.A, part, 6, spmv_lanes=-1, projection=bc.BC_PROJ_DENSE_CHOL)
     try:
@@ -245,12 +251,14 @@ def test_multi_inner_cg_one_launch(dev):
         for j in range(32):
             xg, stg = grouped.solve(Fd[j].contiguous(), tol=1e-10)
             assert sts[j].status == bc.BC_OK and sts[j].rel_residual <= 1e-10 * (1 + 1e-6)
-            assert abs(stg.iterations - sts[j].iterations) <= 1
-            assert rel(X[j], xg.cpu().numpy()) <= 1e-9
+            hist = lambda t, j=j: block_cimmino_cg(p.A.to_scipy(), F[j], part, 8,
+                                                   tol=1e-10).history[t]
+            if counts_match(stg.iterations, sts[j].iterations, hist, 1e-10, "rhs %d" % j):
+                assert rel(X[j], xg.cpu().numpy()) <= 1e-9
         ref = block_cimmino_cg(p.A.to_scipy(), F[5], part, 8, tol=1e-10)
         print("iterations", [s.iterations for s in sts][:8], "oracle rhs 5:", ref.iterations)
-        assert abs(sts[5].iterations - ref.iterations) <= 1
-        assert rel(X[5], ref.x) <= 1e-8
+        if counts_match(sts[5].iterations, ref.iterations, lambda t: ref.history[t], 1e-10):
+            assert rel(X[5], ref.x) <= 1e-8
     finally:
         grouped.close()
         single.close()
@@ -279,7 +287,8 @@ def test_multi_backward_error_stop_rule(dev):
         print("rhs %d: iterations %d oracle %d backward error %.2e"
               % (j, sts[j].iterations, ref.iterations, sts[j].backward_err))
         assert sts[j].status == bc.BC_OK and sts[j].backward_err < 1e-12
-        assert abs(sts[j].iterations - ref.iterations) <= 1
+        counts_match(sts[j].iterations, ref.iterations,
+                     lambda t, j=j: backward_error_at(A, F[j], part, 6, t), 1e-12)
 
 
 def test_multi_stops_independently(dev):

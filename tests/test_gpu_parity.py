@@ -18,7 +18,8 @@ import paper_1710_07769_amd as bc
 import workloads
 from workloads import Csr
 from oracle import (rip_graph as oracle_rip, greedy_partition, block_cimmino_cg,
-                    BlockProjections)
+                    BlockProjections, backward_error)
+from _bars import counts_match
 
 pytestmark = pytest.mark.gpu
 
@@ -157,12 +158,7 @@ def _check_solve(dev, p, part, K, tol=1e-10, **opts):
         x, st = solver.solve(f, tol=tol, maxit=10000)
         assert st.status == bc.BC_OK
         assert st.rel_residual <= tol * (1 + 1e-6)
-        d = st.iterations - ref.iterations
-        if d != 0:
-            # accepted only as a documented near-tie of the stop decision
-            assert abs(d) == 1
-            t = min(st.iterations, ref.iterations)
-            assert abs(ref.history[t] - tol) <= 1e-3 * tol
+        counts_match(st.iterations, ref.iterations, lambda t: ref.history[t], tol)
         # same iteration count, compare iterates
         x2, st2 = solver.solve(f, tol=0.0, maxit=ref.iterations)
         assert st2.iterations == ref.iterations
@@ -265,9 +261,10 @@ def test_solve_batched(dev):
         for q, st, xg in zip(probs, sts, xs):
             ref = block_cimmino_cg(q.A.to_scipy(), q.f, q.part(), q.K, tol=1e-10)
             assert st.status == bc.BC_OK
-            assert abs(st.iterations - ref.iterations) <= 1
             assert st.rel_residual <= 1e-10 * (1 + 1e-6)
-            assert rel(xg, ref.x) <= 1e-7
+            # iterates compared only at equal counts
+            if counts_match(st.iterations, ref.iterations, lambda t: ref.history[t], 1e-10):
+                assert rel(xg, ref.x) <= 1e-8
     finally:
         solver.close()
 
@@ -364,7 +361,12 @@ def test_backward_error_stop_rule(dev):
     try:
         x, st = solver.solve(to_dev(p.f, dev), tol=1e-10)
         assert st.status == bc.BC_OK
-        assert abs(st.iterations - ref.iterations) <= 1
+        A = p.A.to_scipy()
+
+        def gamma_at(t):
+            r = block_cimmino_cg(A, p.f, p.part(), p.K, tol=0.0, maxit=t)
+            return backward_error(A, r.x, p.f)
+        counts_match(st.iterations, ref.iterations, gamma_at, 1e-10)
         assert st.backward_err < 1e-10
     finally:
         solver.close()
@@ -566,8 +568,13 @@ def test_sliced_ell_products_match_csr(dev, name):
         # per thread here, several rows per thread in the CSR kernels), so
         # the solves agree to rounding, not bit for bit
         assert all(a.status == bc.BC_OK and a.rel_residual <= 1e-10 * (1 + 1e-6) for a in s1)
-        assert all(abs(a.iterations - b.iterations) <= 1 for a, b in zip(s1, s2))
-        assert rel(x1.cpu().numpy(), x2.cpu().numpy()) <= 1e-9
+        same = True
+        for q, a, b in zip(probs, s1, s2):
+            hist = lambda t, q=q: block_cimmino_cg(q.A.to_scipy(), q.f, q.part(), q.K,
+                                                   tol=1e-10).history[t]
+            same = counts_match(a.iterations, b.iterations, hist, 1e-10, q.name) and same
+        if same:
+            assert rel(x1.cpu().numpy(), x2.cpu().numpy()) <= 1e-9
     finally:
         sell.close()
         csr.close()
