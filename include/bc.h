@@ -356,8 +356,25 @@ bc_status bc_partition_greedy(int32_t n, const int64_t* rowptr, const int32_t* c
  *     weight: part k (k < K-1) grows until it weighs ceil(remaining weight /
  *     parts left), leaving at least one vertex for each later part.
  *  3. At every level from the coarsest to the original graph (after
- *     projecting the parts down), the refinement sweeps of
- *     bc_partition_greedy with vertex weights, W_max as there.
+ *     projecting the parts down), at most `passes` Fiduccia-Mattheyses
+ *     passes with vertex weights and W_max as in bc_partition_greedy.  In a
+ *     pass every vertex starts unlocked, and conn(v, q) is the total edge
+ *     weight from v to part q.  A max-priority queue holds (key, v), larger
+ *     key first, ties to the lower v, where key(v) is the largest
+ *     conn(v, q) - conn(v, part[v]) over the parts q != part[v] that v
+ *     touches; it starts with every vertex that touches another part.  A
+ *     popped entry is skipped if v is locked or key(v) has changed.  Else
+ *     v (in part a) moves to the touched part q != a of largest gain
+ *     conn(v, q) - conn(v, a), ties to the lower q, among parts with
+ *     W[q] + w(v) <= W_max, provided W[a] > w(v); if there is none the
+ *     entry is dropped and v stays unlocked.  The gain may be negative.  A
+ *     moved vertex is locked, the move logged with the running sum of
+ *     gains, and each unlocked neighbour u (in adjacency order) that
+ *     touches another part is pushed again with its current key(u).  The
+ *     pass ends when the queue is empty or 64 moves in a row have not
+ *     raised the best running sum; the moves after the best prefix (the
+ *     shortest on ties) are undone, last first.  No further pass runs after
+ *     one whose best running sum is 0.
  * Arguments and errors as bc_partition_greedy. */
 bc_status bc_partition_multilevel(int32_t n, const int64_t* rowptr, const int32_t* col,
                                   const int64_t* wgt, int32_t K, int32_t passes, int32_t* part);

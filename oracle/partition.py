@@ -149,31 +149,115 @@ def _grow_weighted(G: _Graph, K: int) -> np.ndarray:
     return part
 
 
-def _refine_weighted(G: _Graph, K: int, wmax: int, passes: int, part: np.ndarray) -> None:
-    """Refinement sweeps of greedy_partition with vertex weights (in place)."""
+FM_STALL = 64
+
+
+def _fm_conn(G: _Graph, part, v):
+    """conn(v, q): total edge weight from v to part q, for the parts v touches."""
+    to = {}
+    for e in range(G.rowptr[v], G.rowptr[v + 1]):
+        q = int(part[G.col[e]])
+        to[q] = to.get(q, 0) + int(G.wgt[e])
+    return to
+
+
+def _fm_key(to, a):
+    """The largest conn(v, q) - conn(v, a) over touched parts q != a, the
+    part of v (None when v touches no other part)."""
+    inside = to.get(a, 0)
+    gains = [to[q] - inside for q in to if q != a]
+    return max(gains) if gains else None
+
+
+def _refine_fm(G: _Graph, K: int, wmax: int, passes: int, part: np.ndarray,
+               stall_limit: int = FM_STALL, trace=None) -> None:
+    """Fiduccia-Mattheyses refinement with vertex weights (in place).
+
+    Each pass: every vertex unlocked; a max-priority queue of (key, vertex)
+    (larger key first, ties to the lower vertex) over the vertices that touch
+    another part.  A popped entry is skipped when its vertex is locked or its
+    key is no longer current.  Otherwise the vertex moves to the touched part
+    q != a of largest gain conn(v,q) - conn(v,a) (ties to the lower q) among
+    those that stay within W_max, provided part a keeps some weight; with no
+    such part the entry is dropped and the vertex stays unlocked.  A move may
+    have a negative gain.  The mover is locked, the move logged with the
+    running sum of gains, and every unlocked neighbour (adjacency order) is
+    pushed again with its new key.  The pass ends when the queue is empty or
+    FM_STALL moves in a row have not raised the best running sum; the moves
+    after the best prefix (the shortest one on ties) are undone in reverse
+    order.  Passes stop early after one whose best running sum is 0.
+    ``trace``, if a list, receives (pass, vertex, from, to, gain) for every
+    move made, undone or not."""
     W = np.zeros(K, dtype=np.int64)
     np.add.at(W, part, G.vw)
-    for _ in range(passes):
+    for pass_no in range(passes):
+        locked = np.zeros(G.n, dtype=bool)
+        conn = [_fm_conn(G, part, v) for v in range(G.n)]
+        heap = []
         for v in range(G.n):
+            key = _fm_key(conn[v], int(part[v]))
+            if key is not None:
+                heap.append((-key, v))
+        heapq.heapify(heap)
+        log = []
+        cum = best = 0
+        best_len = 0
+        stall = 0
+        while heap and stall < stall_limit:
+            negk, v = heapq.heappop(heap)
+            if locked[v]:
+                continue
             a = int(part[v])
+            to = conn[v]
+            key = _fm_key(to, a)
+            if key is None or key != -negk:
+                continue
             if W[a] <= G.vw[v]:
                 continue
-            to = {}
-            for e in range(G.rowptr[v], G.rowptr[v + 1]):
-                q = int(part[G.col[e]])
-                to[q] = to.get(q, 0) + int(G.wgt[e])
             inside = to.get(a, 0)
-            best_q, best_gain = -1, 0
+            q_best, g_best = -1, None
             for q in sorted(to):
                 if q == a or W[q] + G.vw[v] > wmax:
                     continue
                 gain = to[q] - inside
-                if gain > best_gain:
-                    best_q, best_gain = q, gain
-            if best_q >= 0:
-                part[v] = best_q
-                W[a] -= G.vw[v]
-                W[best_q] += G.vw[v]
+                if g_best is None or gain > g_best:
+                    q_best, g_best = q, gain
+            if q_best < 0:
+                continue
+            part[v] = q_best
+            W[a] -= G.vw[v]
+            W[q_best] += G.vw[v]
+            locked[v] = True
+            log.append((v, a))
+            if trace is not None:
+                trace.append((pass_no, v, a, q_best, g_best))
+            cum += g_best
+            if cum > best:
+                best, best_len, stall = cum, len(log), 0
+            else:
+                stall += 1
+            # the neighbours' connections follow the move; then each
+            # unlocked neighbour is queued with its new key
+            nbrs = range(G.rowptr[v], G.rowptr[v + 1])
+            for e in nbrs:
+                cu, w = conn[int(G.col[e])], int(G.wgt[e])
+                cu[a] -= w
+                if cu[a] == 0:
+                    del cu[a]
+                cu[q_best] = cu.get(q_best, 0) + w
+            for e in nbrs:
+                u = int(G.col[e])
+                if not locked[u]:
+                    ku = _fm_key(conn[u], int(part[u]))
+                    if ku is not None:
+                        heapq.heappush(heap, (-ku, u))
+        for v, a in reversed(log[best_len:]):
+            q = int(part[v])
+            part[v] = a
+            W[q] -= G.vw[v]
+            W[a] += G.vw[v]
+        if best == 0:
+            break
 
 
 def _coarsen(G: _Graph, maxvw: int):
@@ -229,7 +313,8 @@ def _coarsen(G: _Graph, maxvw: int):
 def multilevel_partition(g, K: int, passes: int = 2) -> np.ndarray:
     """Deterministic multilevel K-way partition (heavy-edge coarsening while
     the graph has more than 30 K vertices, weighted greedy growth on the
-    coarsest graph, refinement sweeps at every level on the way back);
+    coarsest graph, at most ``passes`` FM passes at every level on the way
+    back, see _refine_fm);
     returns int32 part[n].  The same specification as the library's host
     implementation, written independently."""
     n = g.n
@@ -248,10 +333,10 @@ def multilevel_partition(g, K: int, passes: int = 2) -> np.ndarray:
         levels.append(C)
         maps.append(cmap)
     part = _grow_weighted(levels[-1], K)
-    _refine_weighted(levels[-1], K, wmax, passes, part)
+    _refine_fm(levels[-1], K, wmax, passes, part)
     for lvl in range(len(levels) - 2, -1, -1):
         part = part[maps[lvl]]
-        _refine_weighted(levels[lvl], K, wmax, passes, part)
+        _refine_fm(levels[lvl], K, wmax, passes, part)
     return part.astype(np.int32)
 
 

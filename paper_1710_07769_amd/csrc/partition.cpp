@@ -275,41 +275,116 @@ void grow(const Level& L, int32_t K, std::vector<int32_t>& p) {
     if (p[v] == -1) p[v] = K - 1;
 }
 
-// refinement passes of bc_partition_greedy with vertex weights
+// Fiduccia-Mattheyses refinement with vertex weights (the rule is stated in
+// include/bc.h under bc_partition_multilevel, step 3).
+constexpr int FM_STALL = 64;
+
+struct FmState {
+  const Level& L;
+  const std::vector<int32_t>& p;
+  std::vector<int64_t> to;      // conn(v, q), cleared after use
+  std::vector<int32_t> seen;    // parts v touches, ascending after conn()
+  FmState(const Level& L_, const std::vector<int32_t>& p_, int32_t K) : L(L_), p(p_), to(K, 0) {}
+  // fills to[]/seen for v; returns whether v touches another part and sets key
+  bool conn(int32_t v, int64_t& key) {
+    seen.clear();
+    for (int64_t e = L.rowptr[v]; e < L.rowptr[v + 1]; ++e) {
+      const int32_t q = p[L.col[e]];
+      if (to[q] == 0) seen.push_back(q);
+      to[q] += L.wgt[e];
+    }
+    std::sort(seen.begin(), seen.end());
+    const int32_t a = p[v];
+    bool any = false;
+    for (int32_t q : seen) {
+      if (q == a) continue;
+      const int64_t g = to[q] - to[a];
+      if (!any || g > key) key = g;
+      any = true;
+    }
+    return any;
+  }
+  void clear() {
+    for (int32_t q : seen) to[q] = 0;
+  }
+};
+
 void refine(const Level& L, int32_t K, int64_t wmax, int32_t passes, std::vector<int32_t>& p) {
   const int32_t n = L.n;
-  std::vector<int64_t> W(K, 0), to(K, 0);
+  std::vector<int64_t> W(K, 0);
   for (int32_t v = 0; v < n; ++v) W[p[v]] += L.vw[v];
-  std::vector<int32_t> seen;
+  FmState st(L, p, K);
+  // (key, vertex): larger key first, then lower vertex
+  using Item = std::pair<int64_t, int32_t>;
+  auto cmp = [](const Item& x, const Item& y) {
+    if (x.first != y.first) return x.first < y.first;
+    return x.second > y.second;
+  };
+  std::vector<uint8_t> locked(n);
+  std::vector<std::pair<int32_t, int32_t>> log;  // (vertex, part it left)
   for (int32_t pass = 0; pass < passes; ++pass) {
+    std::fill(locked.begin(), locked.end(), 0);
+    std::vector<Item> init;
     for (int32_t v = 0; v < n; ++v) {
+      int64_t key = 0;
+      if (st.conn(v, key)) init.emplace_back(key, v);
+      st.clear();
+    }
+    std::priority_queue<Item, std::vector<Item>, decltype(cmp)> heap(cmp, std::move(init));
+    log.clear();
+    int64_t cum = 0, best = 0;
+    size_t best_len = 0;
+    int stall = 0;
+    while (!heap.empty() && stall < FM_STALL) {
+      const Item it = heap.top();
+      heap.pop();
+      const int32_t v = it.second;
+      if (locked[v]) continue;
+      int64_t key = 0;
+      const bool any = st.conn(v, key);
       const int32_t a = p[v];
-      if (W[a] <= L.vw[v]) continue;
-      seen.clear();
-      for (int64_t e = L.rowptr[v]; e < L.rowptr[v + 1]; ++e) {
-        const int32_t q = p[L.col[e]];
-        if (to[q] == 0) seen.push_back(q);
-        to[q] += L.wgt[e];
-      }
-      std::sort(seen.begin(), seen.end());
-      const int64_t inside = to[a];
-      int32_t best = -1;
-      int64_t best_gain = 0;
-      for (int32_t q : seen) {
-        if (q == a || W[q] + L.vw[v] > wmax) continue;
-        const int64_t gain = to[q] - inside;
-        if (gain > best_gain) {
-          best = q;
-          best_gain = gain;
+      int32_t q_best = -1;
+      int64_t g_best = 0;
+      if (any && key == it.first && W[a] > L.vw[v]) {
+        for (int32_t q : st.seen) {
+          if (q == a || W[q] + L.vw[v] > wmax) continue;
+          const int64_t g = st.to[q] - st.to[a];
+          if (q_best < 0 || g > g_best) {
+            q_best = q;
+            g_best = g;
+          }
         }
       }
-      for (int32_t q : seen) to[q] = 0;
-      if (best >= 0) {
-        p[v] = best;
-        W[a] -= L.vw[v];
-        W[best] += L.vw[v];
+      st.clear();
+      if (q_best < 0) continue;
+      p[v] = q_best;
+      W[a] -= L.vw[v];
+      W[q_best] += L.vw[v];
+      locked[v] = 1;
+      log.emplace_back(v, a);
+      cum += g_best;
+      if (cum > best) {
+        best = cum;
+        best_len = log.size();
+        stall = 0;
+      } else {
+        ++stall;
+      }
+      for (int64_t e = L.rowptr[v]; e < L.rowptr[v + 1]; ++e) {
+        const int32_t u = L.col[e];
+        if (locked[u]) continue;
+        int64_t ku = 0;
+        if (st.conn(u, ku)) heap.push(Item(ku, u));
+        st.clear();
       }
     }
+    for (size_t i = log.size(); i > best_len; --i) {
+      const int32_t v = log[i - 1].first, a = log[i - 1].second;
+      W[p[v]] -= L.vw[v];
+      W[a] += L.vw[v];
+      p[v] = a;
+    }
+    if (best == 0) break;
   }
 }
 

@@ -100,6 +100,22 @@ def test_library_multilevel_partitioner_matches_oracle(maker, K):
         assert np.array_equal(ref, got), passes
 
 
+def test_library_multilevel_on_a_64_vertex_path():
+    # one coarsening level (pairs), growth of 16 weight-2 coarse vertices,
+    # FM passes that gain nothing at either level: the halves (the oracle's
+    # hand-traced case)
+    n = 64
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    col = []
+    for v in range(n):
+        col += [u for u in (v - 1, v + 1) if 0 <= u < n]
+        rowptr[v + 1] = len(col)
+    wgt = np.ones(len(col), dtype=np.int64)
+    from oracle.ripgraph import RipGraph
+    g = RipGraph(n, rowptr, np.array(col, dtype=np.int32), wgt.astype(np.float64), wgt)
+    assert bc.bc_partition_multilevel(g, 2).tolist() == [0] * 32 + [1] * 32
+
+
 def test_partitioner_rejects_bad_graphs():
     g = oracle_rip(workloads.config1().A)
     with pytest.raises(bc.BCError):

@@ -156,13 +156,14 @@ def test_refinement_moves_positive_gain():
 # ------------------------------------------------------------- multilevel
 
 from oracle import multilevel_partition  # noqa: E402
-from oracle.partition import _coarsen, _Graph  # noqa: E402
+from oracle.partition import _coarsen, _Graph, _refine_fm  # noqa: E402
 
 
 @pytest.mark.parametrize("seed,n,K", [(0, 8, 2), (1, 9, 3), (3, 12, 3)])
 def test_multilevel_small_graph_is_greedy_and_not_below_brute_force(seed, n, K):
     # n <= 30 K: no coarsening; the weighted growth with unit weights is the
-    # greedy growth, so the two partitioners coincide
+    # greedy growth, and W_max = n / K leaves no room for a move, so neither
+    # refinement moves a vertex and the two partitioners coincide
     rng = np.random.default_rng(seed)
     W = np.triu(rng.integers(0, 4, (n, n)) * (rng.random((n, n)) < 0.5), 1)
     g = graph_from_dense(W + W.T)
@@ -223,3 +224,155 @@ def test_multilevel_on_stencil_graph_is_balanced():
     print("cut greedy %.3f multilevel %.3f contiguous %.3f"
           % (cutsize(g, greedy_partition(g, p.K)), cutsize(g, part), cutsize(g, contiguous)))
     assert cutsize(g, part) <= cutsize(g, contiguous)
+
+
+def _weighted_graph(n, edges, vw=None, order=None):
+    """_Graph from undirected (i, j, w) edges; ``order`` may give a vertex's
+    adjacency in a chosen order (default ascending)."""
+    adj = {v: {} for v in range(n)}
+    for i, j, w in edges:
+        adj[i][j] = w
+        adj[j][i] = w
+    rowptr, col, wgt = [0], [], []
+    for v in range(n):
+        nb = (order or {}).get(v, sorted(adj[v]))
+        assert sorted(nb) == sorted(adj[v])
+        col += nb
+        wgt += [adj[v][u] for u in nb]
+        rowptr.append(len(col))
+    vw = np.ones(n, dtype=np.int64) if vw is None else np.asarray(vw, dtype=np.int64)
+    return _Graph(n, np.array(rowptr, dtype=np.int64), np.array(col, dtype=np.int64),
+                  np.array(wgt, dtype=np.int64), vw)
+
+
+def test_coarsen_hand_traced():
+    # Vertex 0 lists neighbour 2 before 1 and both edges weigh 5: the tie
+    # goes to the lower index, 0-1.  Vertex 2 then takes 3 (0 and 1 are
+    # matched).  Vertex 4 cannot take 5 (weights 2 + 2 > 3), and takes 7
+    # (edge 4) over 8 (edge 1).  Vertex 5 takes 6; vertex 8 finds only a
+    # matched neighbour and stays single.  Coarse vertices in order of their
+    # lower fine vertex: {0,1} {2,3} {4,7} {5,6} {8}.  Coarse edges:
+    # c0-c1 = 5 (0-2) + 2 (1-2) + 1 (1-3) = 8; c1-c2 = 4 (3-4);
+    # c2-c3 = 4 (4-5) + 2 (7-6) = 6; c2-c4 = 1 (4-8); 0-1, 2-3, 4-7 and 5-6
+    # are internal and dropped.
+    edges = [(0, 1, 5), (0, 2, 5), (1, 2, 2), (1, 3, 1), (2, 3, 3), (3, 4, 4), (4, 5, 4),
+             (4, 7, 4), (5, 6, 1), (6, 7, 2), (4, 8, 1)]
+    G = _weighted_graph(9, edges, vw=[1, 1, 1, 1, 2, 2, 1, 1, 1], order={0: [2, 1]})
+    C, cmap = _coarsen(G, maxvw=3)
+    assert cmap.tolist() == [0, 0, 1, 1, 2, 3, 3, 2, 4]
+    assert C.n == 5
+    assert C.vw.tolist() == [2, 2, 3, 3, 1]
+    assert C.rowptr.tolist() == [0, 1, 3, 6, 7, 8]
+    assert C.col.tolist() == [1, 0, 2, 1, 3, 4, 2, 2]
+    assert C.wgt.tolist() == [8, 8, 4, 4, 6, 1, 6, 1]
+
+
+# Two groups: {0,1,2} tightly bound, 3 and 4 tied to each other (3) and to
+# the group by 1 each, and each tied by 2 to one of 5, 6 of the group
+# {5..9}.  From parts {0..4} | {5..9} no single move has a positive gain.
+_FM_EDGES = [(0, 1, 5), (0, 2, 5), (1, 2, 5), (0, 3, 1), (1, 4, 1), (3, 4, 3),
+             (5, 6, 5), (5, 7, 5), (6, 7, 5), (7, 8, 5), (8, 9, 5), (5, 9, 5),
+             (3, 5, 2), (4, 6, 2)]
+
+
+def test_fm_climbs_through_a_negative_move_and_rolls_back_hand_traced():
+    # Pass 1: keys 3: 2-4 = -2, 4: -2, 5: 2-15 = -13, 6: 2-10 = -8.  Vertex
+    # 3 moves first (gain -2, running sum -2); 4's key becomes 5-1 = +4 and
+    # it moves (running sum +2, the best).  0 and 1 (keys -9) would bring
+    # part 1 to 8 > W_max = 7 and are dropped.  Cut 4 -> 2, parts 3 | 7.
+    # Pass 2: 3 moves back (-4), 4 follows (+2), 6 (-8), 5 (-3): running
+    # sums -4, -2, -10, -13, never above 0; 7 and 9 would overfill part 0.
+    # All four moves are undone and refinement stops.
+    G = _weighted_graph(10, _FM_EDGES)
+    part = np.array([0] * 5 + [1] * 5, dtype=np.int64)
+    _refine_fm(G, 2, 7, 1, part)
+    assert part.tolist() == [0, 0, 0, 1, 1, 1, 1, 1, 1, 1]
+    part2 = np.array([0] * 5 + [1] * 5, dtype=np.int64)
+    _refine_fm(G, 2, 7, 5, part2)
+    assert part2.tolist() == part.tolist()
+    # the positive-gain sweeps of greedy_partition would make no move here
+    g = graph_from_dense(_dense(G))
+    assert int_cut(g, np.array([0] * 5 + [1] * 5)) == 4 and int_cut(g, part) == 2
+
+
+def test_fm_undoes_a_pass_without_gain():
+    # from the pass-1 result, a single pass tries 3, 4, 6, 5 and undoes them
+    G = _weighted_graph(10, _FM_EDGES)
+    start = [0, 0, 0, 1, 1, 1, 1, 1, 1, 1]
+    part = np.array(start, dtype=np.int64)
+    _refine_fm(G, 2, 7, 1, part)
+    assert part.tolist() == start
+
+
+def test_fm_three_parts_tie_and_undo_after_the_best_prefix_hand_traced():
+    # Parts {0,1,2} {3,4,5} {6,7,8}, W_max = 4.  Pass 1: vertex 0 gains 1
+    # towards part 1 and towards part 2; the tie goes to part 1 (best sum 1
+    # after one move).  6, 1 and 2 would overfill part 1 and are dropped; 5
+    # moves to part 0 (-4), then 4 (0); 3 would overfill part 0.  The two
+    # moves after the best prefix are undone: cut 5 -> 4.  Pass 2: 0 moves
+    # on to part 2 (gain 0 beats -1 towards part 0), 2 moves to part 1 (-4);
+    # 1 may not empty part 0.  No gain: both are undone.
+    edges = [(1, 2, 5), (0, 1, 1), (3, 4, 5), (4, 5, 5), (0, 3, 2), (6, 7, 5), (7, 8, 5),
+             (0, 6, 2), (2, 5, 1)]
+    G = _weighted_graph(9, edges)
+    want = [1, 0, 0, 1, 1, 1, 2, 2, 2]
+    for passes in (1, 2, 3):
+        part = np.array([0, 0, 0, 1, 1, 1, 2, 2, 2], dtype=np.int64)
+        _refine_fm(G, 3, 4, passes, part)
+        assert part.tolist() == want, passes
+    g = graph_from_dense(_dense(G))
+    assert int_cut(g, np.array([0, 0, 0, 1, 1, 1, 2, 2, 2])) == 5
+    assert int_cut(g, np.array(want)) == 4
+
+
+def test_fm_move_order_guards_and_stall_hand_traced():
+    # Parts {0,1} | {2..5}, W_max = 10.  Keys: 0: 4-1 = 3, 2: 5-2 = 3,
+    # 1: 3-1 = 2, 4: 2-5 = -3.  Pass 1: 0 moves (+3; tie with 2 to the lower
+    # vertex).  1's key rises to 4 but moving it would empty part 0; the
+    # entries (3, 2) and (2, 1) are stale (keys now -5 and 4).  4 moves (-3),
+    # which raises 5 to +5 (moves, best sum 5 after three moves) and 1 to 0
+    # (moves, running sum 5, not above the best, undone).  Pass 2: 1 (0) and
+    # 4 (-3) move, 5 may not empty part 0, and both moves are undone.
+    edges = [(0, 1, 1), (0, 2, 4), (1, 2, 1), (2, 3, 2), (1, 4, 2), (4, 5, 5)]
+    G = _weighted_graph(6, edges)
+    part = np.array([0, 0, 1, 1, 1, 1], dtype=np.int64)
+    trace = []
+    _refine_fm(G, 2, 10, 4, part, trace=trace)
+    assert trace == [(0, 0, 0, 1, 3), (0, 4, 1, 0, -3), (0, 5, 1, 0, 5), (0, 1, 0, 1, 0),
+                     (1, 1, 0, 1, 0), (1, 4, 0, 1, -3)]
+    assert part.tolist() == [1, 0, 1, 1, 0, 0]
+    # with a stall limit of one move, pass 1 stops after 4's move (-3) and
+    # undoes it; pass 2 moves 0 back (-3, 1 may not empty part 0), undoes it
+    # and stops
+    part = np.array([0, 0, 1, 1, 1, 1], dtype=np.int64)
+    trace = []
+    _refine_fm(G, 2, 10, 4, part, stall_limit=1, trace=trace)
+    assert trace == [(0, 0, 0, 1, 3), (0, 4, 1, 0, -3), (1, 0, 1, 0, -3)]
+    assert part.tolist() == [1, 0, 1, 1, 1, 1]
+
+
+def _dense(G):
+    W = np.zeros((G.n, G.n), dtype=np.int64)
+    for v in range(G.n):
+        for e in range(G.rowptr[v], G.rowptr[v + 1]):
+            W[v, G.col[e]] = G.wgt[e]
+    return W
+
+
+def test_multilevel_hand_traced_on_a_64_vertex_path():
+    # n = 64 > 30 K = 60 with K = 2: one coarsening level.  The matching
+    # pairs (2i, 2i+1) (cap ceil(64/40) = 2), giving a 32-vertex path of
+    # weight-2 vertices.  Growth gives part 0 the coarse vertices 0..15.
+    # FM (W_max = floor(1.1*64/2) = 35): coarse 15 moves across (gain 0),
+    # coarse 14 would bring part 1 to 36 and is dropped, the pass gains
+    # nothing and is undone.  Projected down, fine vertices 31, 30, 29 move
+    # (gain 0 each), 28 would bring part 1 to 36, and the pass is undone:
+    # the halves 0..31 | 32..63.
+    n = 64
+    g = graph_from_dense(np.eye(n, k=1, dtype=np.int64) + np.eye(n, k=-1, dtype=np.int64))
+    G = _Graph(n, np.asarray(g.rowptr, dtype=np.int64), np.asarray(g.col, dtype=np.int64),
+               np.asarray(g.wgt, dtype=np.int64), np.ones(n, dtype=np.int64))
+    C, cmap = _coarsen(G, maxvw=2)
+    assert cmap.tolist() == [v // 2 for v in range(n)]
+    assert C.n == 32 and C.vw.tolist() == [2] * 32 and C.wgt.tolist() == [1] * 62
+    assert multilevel_partition(g, 2).tolist() == [0] * 32 + [1] * 32
