@@ -339,7 +339,8 @@ bc_status rip_graph_timing(double* spgemm_ms, double* total_ms);
  * order move a vertex to the part with the largest positive gain that stays
  * within W_max, keeping its source part nonempty (ties: lower part id).
  * Host arrays: rowptr int64[n+1], col int32[nnz] (symmetric, no diagonal),
- * wgt int64[nnz] >= 1; part int32[n] output.  Errors: BC_ERR_INVALID. */
+ * wgt int64[nnz] >= 1 (col and wgt may be null when nnz = 0); part int32[n]
+ * output.  Errors: BC_ERR_INVALID. */
 bc_status bc_partition_greedy(int32_t n, const int64_t* rowptr, const int32_t* col,
                               const int64_t* wgt, int32_t K, int32_t passes, int32_t* part);
 

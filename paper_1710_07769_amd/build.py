@@ -19,7 +19,7 @@ HIP_FLAGS = [
     "-Wno-unused-result",
 ]
 HIP_SOURCES = ["outer.hip", "inner.hip", "dense.hip", "band.hip", "rip.hip", "api.hip"]
-CXX_SOURCES = ["partition.cpp", "order.cpp"]
+CXX_SOURCES = ["partition.cpp", "order.cpp", "host.cpp"]
 
 
 def _run(cmd):

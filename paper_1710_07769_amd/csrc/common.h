@@ -8,10 +8,9 @@
 #include <vector>
 
 #include "../../include/bc.h"
+#include "host.h"
 
 // ------------------------------------------------------------------ errors
-
-void bc_set_error(const std::string& msg);
 
 #define BC_HIP(call)                                                                   \
   do {                                                                                 \
@@ -31,9 +30,6 @@ struct DBuf {
 };
 
 // ------------------------------------------------------------------ layout
-// Elements per reduction tile of the vector kernels.  A tile never straddles
-// two systems of a batch, so per-system sums are sums over a tile range.
-constexpr int TILE = 1024;
 constexpr int VEC_THREADS = 256;
 static_assert(TILE % VEC_THREADS == 0, "a tile is a whole number of rows per thread");
 // Dense projection tile edge (tiles of the packed lower-triangular factor).
@@ -68,13 +64,7 @@ struct OuterState {
 };
 
 // Sliced-ELL copy of a sparse matrix for the sparse products (built when
-// its padding is modest): the rows of every tile are cut into slices of 64
-// consecutive rows, SELL_SLICES per tile (slice t * SELL_SLICES + j starts at
-// row tile_start[t] + 64 j; slices past the tile's end have width 0); entry
-// k of lane l of slice s is at ptr[s] + 64 k + l, in the row's stored order;
-// padding entries repeat the row's last column (or the tile's first index
-// for absent rows) with value 0.
-constexpr int SELL_SLICES = TILE / 64;
+// its padding is modest; layout as build_sell in host.h).
 struct SellMat {
   const long long* ptr;   // ntiles * SELL_SLICES entry offsets
   const int* wid;         // ntiles * SELL_SLICES widths
@@ -83,8 +73,6 @@ struct SellMat {
   const float* val32;     // FP32 copy for FP32 products, else null
   int il;                 // multi-vector products gather an interleaved copy
 };
-// `lanes` value that selects the sliced-ELL kernels
-constexpr int LANES_SELL = -1;
 
 // ---------------------------------------------------------- device helpers
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)

@@ -35,7 +35,8 @@ bool check_graph(int32_t n, const int64_t* rowptr, const int32_t* col, const int
 extern "C" bc_status bc_partition_greedy(int32_t n, const int64_t* rowptr, const int32_t* col,
                                          const int64_t* wgt, int32_t K, int32_t passes,
                                          int32_t* part) {
-  if (!part || K < 1 || K > n || passes < 0 || !check_graph(n, rowptr, col, wgt) || !wgt) {
+  if (!part || K < 1 || K > n || passes < 0 || !check_graph(n, rowptr, col, wgt) ||
+      (!wgt && rowptr[n] > 0)) {
     bc_set_error("bc_partition_greedy: invalid graph, K or output");
     return BC_ERR_INVALID;
   }
@@ -393,7 +394,8 @@ void refine(const Level& L, int32_t K, int64_t wmax, int32_t passes, std::vector
 extern "C" bc_status bc_partition_multilevel(int32_t n, const int64_t* rowptr, const int32_t* col,
                                              const int64_t* wgt, int32_t K, int32_t passes,
                                              int32_t* part) {
-  if (!part || K < 1 || K > n || passes < 0 || !check_graph(n, rowptr, col, wgt) || !wgt) {
+  if (!part || K < 1 || K > n || passes < 0 || !check_graph(n, rowptr, col, wgt) ||
+      (!wgt && rowptr[n] > 0)) {
     bc_set_error("bc_partition_multilevel: invalid graph, K or output");
     return BC_ERR_INVALID;
   }
