@@ -58,6 +58,12 @@ config5 = functools.lru_cache(maxsize=1)(workloads.config5)
 
 
 @functools.lru_cache(maxsize=1)
+def cfg5_rip_graph():
+    p = config5()
+    return bc.rip_graph(p.n, p.A.rowptr, p.A.col, p.A.val)
+
+
+@functools.lru_cache(maxsize=1)
 def cfg2_partition():
     p = config2()
     g = bc.rip_graph(p.n, p.A.rowptr, p.A.col, p.A.val)
@@ -106,7 +112,7 @@ def check_fp64_count_and_iterate(dev, solver, f, ref, tol=1e-10):
 def test_rip_graph_st27_100cubed_sampled_rows(dev):
     banner("rip_graph of the 27-point 100^3 matrix (120M edges): 64 sampled rows bit-exact")
     p = config5()
-    g = bc.rip_graph(p.n, p.A.rowptr, p.A.col, p.A.val)
+    g = cfg5_rip_graph()
     rows = np.sort(np.random.default_rng(5).choice(p.n, 64, replace=False))
     ref = rip_rows(p.A, rows)
     assert g.col.size > 100_000_000
@@ -154,6 +160,22 @@ def test_solve_powerlaw_500k_mixed(dev, golden):
               % (st.iterations, golden["cfg3"]["iterations"], st.rel_residual, err))
         assert st.status == bc.BC_OK and st.rel_residual <= 1e-10 * (1 + 1e-6)
         assert err <= 1e-6
+    finally:
+        solver.close()
+
+
+def test_solve_st27_100cubed_greedy_rip(dev, golden):
+    banner("greedy partition of the 27-point 100^3 row inner-product graph, K=512: "
+           "bit-exact, then the FP64 dense-projection solve on it")
+    p = config5()
+    ref = golden["cfg5_rip"]
+    g = cfg5_rip_graph()
+    assert g.col.size == ref["edges"]
+    part = bc.bc_partition_greedy(g, p.K)
+    assert partition_hash(part) == ref["partition_sha"]
+    solver = bc.BlockCimmino(p.A, part, p.K, projection=bc.BC_PROJ_DENSE_CHOL)
+    try:
+        check_fp64_count_and_iterate(dev, solver, to_dev(p.f, dev), ref)
     finally:
         solver.close()
 

@@ -56,6 +56,19 @@ def _dense_column_matrix(n, c, nz, seed):
     return Csr.from_scipy(A.tocsr())
 
 
+def _dense_columns_matrix(n, cols, nz, seed):
+    # several dense columns, values with repeated magnitudes (ties in the
+    # sparsification order)
+    rng = np.random.default_rng(seed)
+    A = sp.lil_matrix((n, n))
+    A.setdiag(rng.uniform(1.0, 2.0, n))
+    for c in cols:
+        rows = rng.choice(n, nz, replace=False)
+        A[rows, c] = rng.choice([-0.5, 0.25, 0.5, 1.0], nz)
+        A[c, c] = 3.0
+    return Csr.from_scipy(A.tocsr())
+
+
 def _int_matrix(n, seed):
     rng = np.random.default_rng(seed)
     M = sp.random(n, n, density=0.05, random_state=rng,
@@ -72,6 +85,9 @@ RIP_CASES = {
     "dense-col-25": lambda: _dense_column_matrix(25, 3, 23, 0),
     "dense-col-2000": lambda: _dense_column_matrix(2000, 17, 600, 1),
     "int-300": lambda: _int_matrix(300, 2),
+    "dense-cols-900": lambda: _dense_columns_matrix(900, [0, 5, 899, 450], 200, 3),
+    "diagonal-50": lambda: Csr.from_scipy(sp.diags(np.arange(1.0, 51.0)).tocsr()),
+    "single-1": lambda: Csr.from_scipy(sp.csr_matrix(np.array([[2.0]]))),
 }
 
 
