@@ -12,7 +12,8 @@ phases are reported beside it.
 The default workload is the batch of 256 2D convection-diffusion systems
 (sides 48..256, 8 blocks each) in plain FP64, all systems in one batched
 solve; the same run also solves the batch with FP32 projections (FP64 outer
-CG) and reports both times to tolerance and their ratio.
+CG) and reports both times to tolerance and their ratio, and times rip_graph
+end to end on the 27-point 100^3 matrix (1e6 rows, 120M edges).
 
 Usage: python bench.py [--steps K] [--warmup W]
                        [--workload cfg4|cfg1|cfg2|cfg3|cfg5|cfg5-rip|cfg5-band]
@@ -96,6 +97,8 @@ def parse():
                          "bc_solve_multi (vector 0: the workload's f, the others A times a "
                          "seeded Gaussian vector); value then counts the outer iterations of "
                          "every right-hand side.  Without it: one bc_solve")
+    ap.add_argument("--no-rip", action="store_true",
+                    help="skip the rip_graph measurement on the 27-point 100^3 matrix")
     ap.add_argument("--compare", action="store_true",
                     help="also time plain FP64 on the same matrices (per system, one after "
                          "another, for a batch) and report the time-to-tolerance ratio")
@@ -286,6 +289,50 @@ def spectrum_study(wl, f_dev, steps=60):
         finally:
             bc.bc_destroy(ctx)
         print("[bench] spectrum %s: %s" % (name, out[name]), file=sys.stderr, flush=True)
+    return out
+
+
+def rip_graph_bench(reps=3):
+    """rip_graph end to end on the 27-point 100^3 matrix (n = 1e6, 120M
+    edges): host CSR in, pinned host graph out.  Reported with the time of
+    the two sparse-product passes (HIP events), edges/s, and the passes'
+    bytes per second against two byte counts: compulsory (each pass reads A
+    and the compacted A^T once; the count pass writes the row counts, the
+    emit pass reads the row offsets and writes the graph) and gathered (each
+    product reads its column entry of A^T: index and value)."""
+    import paper_1710_07769_amd as bc
+    import workloads as W
+    q = W.config5()
+    n, nnz = q.n, q.A.nnz
+    ccount = np.bincount(q.A.col, minlength=n)
+    t = int(np.sqrt(n))
+    products = int(np.minimum(ccount, t)[q.A.col].sum())
+    wall, spg, tot = [], [], []
+    ne = 0
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        g = bc.rip_graph(n, q.A.rowptr, q.A.col, q.A.val)
+        wall.append((time.perf_counter() - t0) * 1e3)
+        tm = bc.rip_graph_timing()
+        spg.append(tm["spgemm_ms"])
+        tot.append(tm["total_ms"])
+        ne = int(g.col.size)
+        del g
+    a_bytes = (n + 1) * 4 + nnz * 12          # rowptr, col, value
+    at_bytes = (n + 1) * 4 + int(np.minimum(ccount, t).sum()) * 12
+    compulsory = 2 * (a_bytes + at_bytes) + n * 4 + (n + 1) * 8 + ne * 20
+    gathered = 2 * (a_bytes + products * 12) + n * 4 + (n + 1) * 8 + ne * 20
+    sp_s = min(spg) / 1e3
+    out = {"matrix": "27-point stencil 100^3, n=%d nnz=%d" % (n, nnz), "edges": ne,
+           "products_per_pass": products,
+           "end_to_end_ms": min(wall), "library_total_ms": min(tot), "spgemm_ms": min(spg),
+           "edges_per_s_end_to_end": ne / (min(wall) / 1e3),
+           "edges_per_s_spgemm": ne / sp_s,
+           "spgemm_gbs_compulsory": compulsory / sp_s / 1e9,
+           "spgemm_gbs_gathered": gathered / sp_s / 1e9,
+           "compulsory_bytes": compulsory, "gathered_bytes": gathered,
+           "reps": reps, "times": "best of the repetitions"}
+    print("[bench] rip_graph st27-100: %s" % out, file=sys.stderr, flush=True)
     return out
 
 
@@ -602,6 +649,8 @@ def main():
         mb["mode"] = ("bc_solve_batched with FP32 banded applies (FP64 factorization, sparse "
                       "products, outer CG scalars and true-residual replacement)")
         line["mixed_batched"] = mb
+    if not args.no_rip:
+        line["rip_graph_st27_100cubed"] = rip_graph_bench()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(

@@ -327,16 +327,32 @@ def rip_graph(n, rowptr, col, val, prescale=True, sparsify=True, alpha=1 << 20,
     g = rip_graph_t()
     _check(_lib.rip_graph(int(n), _ptr(rowptr, C.c_int32), _ptr(col, C.c_int32),
                           _ptr(val, C.c_double), C.byref(o), C.byref(g)), "rip_graph")
-    try:
-        ne = int(g.nnz)
-        out = RipGraph(int(g.n),
-                       np.ctypeslib.as_array(g.rowptr, shape=(n + 1,)).copy(),
-                       np.ctypeslib.as_array(g.col, shape=(max(ne, 1),))[:ne].copy(),
-                       np.ctypeslib.as_array(g.cost, shape=(max(ne, 1),))[:ne].copy(),
-                       np.ctypeslib.as_array(g.wgt, shape=(max(ne, 1),))[:ne].copy())
-    finally:
-        _lib.rip_graph_free(C.byref(g))
-    return out
+    # the arrays are the library's pinned host buffers, wrapped without a
+    # copy; they are released by rip_graph_free once no array refers to them
+    holder = _RipBuffers(g)
+    ne = int(g.nnz)
+
+    def wrap(ptr, ctype, dtype, count):
+        if count == 0:
+            return np.zeros(0, dtype=dtype)
+        buf = (ctype * count).from_address(C.cast(ptr, C.c_void_p).value)
+        buf._holder = holder
+        return np.frombuffer(buf, dtype=dtype)
+
+    return RipGraph(int(g.n), wrap(g.rowptr, C.c_int64, np.int64, int(g.n) + 1),
+                    wrap(g.col, C.c_int32, np.int32, ne), wrap(g.cost, C.c_double, np.float64, ne),
+                    wrap(g.wgt, C.c_int64, np.int64, ne))
+
+
+class _RipBuffers:
+    """Owner of one rip_graph_t result; frees it when the last array goes."""
+
+    def __init__(self, g):
+        self.g = g
+
+    def __del__(self):
+        if _lib is not None:
+            _lib.rip_graph_free(C.byref(self.g))
 
 
 def rip_graph_timing() -> dict:

@@ -24,14 +24,25 @@ hipError_t launch_gram(hipStream_t st, const DenseBlocks& D, const int4* tiles, 
                        const int* trow, const double* tval);
 int inner_max_resident_groups(bool mixed);
 int inner_grp_max_resident(bool mixed, int max_m);
-hipError_t rip_launch_prescale(hipStream_t st, int n, long long nnz, const int* rowptr,
-                               double* aval, const int* trow, double* tval, double* nrm,
-                               int* zero_row);
+hipError_t rip_launch_prescale(hipStream_t st, int n, const int* rowptr, double* aval,
+                               double* nrm, int* zero_row);
+size_t rip_transpose_temp_bytes(int n, long long nnz);
+size_t rip_offsets_temp_bytes(int n);
+hipError_t rip_launch_transpose(hipStream_t st, int n, long long nnz, const int* rowptr,
+                                const int* col, const double* aval, int* erow, unsigned* tkey,
+                                int* iota, int* tcnt, int* tptr, int* trow, double* tval,
+                                int* tpos, void* temp, size_t temp_bytes);
+hipError_t rip_launch_dense_cols(hipStream_t st, int n, const int* tptr, int t, int* dense,
+                                 int* ndense);
 hipError_t rip_launch_sparsify(hipStream_t st, const int* dense_cols, int ndense, int t,
-                               const int* tptr, const int* trow, double* tval,
-                               const long long* tpos, double* aval);
+                               const int* tptr, const int* trow, double* tval, const int* tpos,
+                               double* aval);
 hipError_t rip_launch_col_nonzeros(hipStream_t st, int n, const int* tptr, const double* tval,
                                    int* cnt);
+hipError_t rip_launch_scan_int(hipStream_t st, const int* cnt, int* out, int n, void* temp,
+                               size_t temp_bytes);
+hipError_t rip_launch_offsets(hipStream_t st, const int* cnt, long long* wide, long long* optr,
+                              int n, void* temp, size_t temp_bytes);
 hipError_t rip_launch_compact(hipStream_t st, int n, const int* tptr, const int* trow,
                               const double* tval, const int* cptr, int* crow, double* cval);
 hipError_t rip_launch_row_products(hipStream_t st, int n, const int* rowptr, const int* col,
@@ -2467,67 +2478,59 @@ bc_status rip_impl(int32_t n, const int32_t* rowptr, const int32_t* colidx, cons
                    const rip_opts& o, rip_graph_t* out, hipStream_t st, Arena& A) {
   const auto t0 = std::chrono::steady_clock::now();
   const long long nnz = rowptr[n];
-  // A^T on the host: per column, rows ascending, with the position in A
-  std::vector<int> tptr(n + 1, 0), trow(nnz);
-  std::vector<long long> tpos(nnz);
-  std::vector<double> tval(nnz);
-  for (long long e = 0; e < nnz; ++e) tptr[colidx[e] + 1]++;
-  for (int j = 0; j < n; ++j) tptr[j + 1] += tptr[j];
-  {
-    std::vector<int> cur(tptr.begin(), tptr.end() - 1);
-    for (int i = 0; i < n; ++i)
-      for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        const int q = cur[colidx[e]]++;
-        trow[q] = i;
-        tpos[q] = e;
-        tval[q] = vals[e];
-      }
+  // A straight from the caller's arrays; A^T, dense columns and the
+  // compacted column lists are built on the device
+  int *d_rowptr, *d_col, *d_flag;
+  double *d_aval, *d_nrm;
+  BC_TRY(A.alloc(&d_rowptr, (size_t)n + 1));
+  BC_TRY(A.alloc(&d_col, (size_t)nnz));
+  BC_TRY(A.alloc(&d_aval, (size_t)nnz));
+  BC_HIP(hipMemcpyAsync(d_rowptr, rowptr, ((size_t)n + 1) * sizeof(int), hipMemcpyHostToDevice, st));
+  if (nnz > 0) {
+    BC_HIP(hipMemcpyAsync(d_col, colidx, (size_t)nnz * sizeof(int), hipMemcpyHostToDevice, st));
+    BC_HIP(hipMemcpyAsync(d_aval, vals, (size_t)nnz * sizeof(double), hipMemcpyHostToDevice, st));
   }
-  std::vector<int> hrow(rowptr, rowptr + n + 1), hcol(colidx, colidx + nnz);
-  std::vector<double> hval(vals, vals + nnz);
-  int *d_rowptr, *d_col, *d_tptr, *d_trow, *d_flag;
-  double *d_aval, *d_tval, *d_nrm;
-  long long* d_tpos;
-  BC_TRY(A.upload(&d_rowptr, hrow, st));
-  BC_TRY(A.upload(&d_col, hcol, st));
-  BC_TRY(A.upload(&d_aval, hval, st));
-  BC_TRY(A.upload(&d_tptr, tptr, st));
-  BC_TRY(A.upload(&d_trow, trow, st));
-  BC_TRY(A.upload(&d_tval, tval, st));
-  BC_TRY(A.upload(&d_tpos, tpos, st));
-  std::vector<int> flags(2, 0);
-  BC_TRY(A.upload(&d_flag, flags, st));  // [0] zero row, [1] weight overflow
+  std::vector<int> flags(3, 0);
+  BC_TRY(A.upload(&d_flag, flags, st));  // [0] zero row, [1] weight overflow, [2] dense columns
   BC_TRY(A.alloc(&d_nrm, n));
-  if (o.prescale) {
-    BC_HIP(rip_launch_prescale(st, n, nnz, d_rowptr, d_aval, d_trow, d_tval, d_nrm, d_flag));
-  }
+  if (o.prescale) BC_HIP(rip_launch_prescale(st, n, d_rowptr, d_aval, d_nrm, d_flag));
+  int *d_erow, *d_iota, *d_tcnt, *d_tptr, *d_trow, *d_tpos;
+  unsigned* d_tkey;
+  double* d_tval;
+  void* d_temp;
+  const size_t temp_bytes = std::max(rip_transpose_temp_bytes(n, nnz), rip_offsets_temp_bytes(n));
+  BC_TRY(A.alloc(&d_erow, (size_t)nnz));
+  BC_TRY(A.alloc(&d_iota, (size_t)nnz));
+  BC_TRY(A.alloc(&d_tkey, (size_t)nnz));
+  BC_TRY(A.alloc(&d_tcnt, (size_t)n + 1));
+  BC_TRY(A.alloc(&d_tptr, (size_t)n + 1));
+  BC_TRY(A.alloc(&d_trow, (size_t)nnz));
+  BC_TRY(A.alloc(&d_tpos, (size_t)nnz));
+  BC_TRY(A.alloc(&d_tval, (size_t)nnz));
+  BC_TRY(A.alloc((char**)&d_temp, temp_bytes));
+  BC_HIP(rip_launch_transpose(st, n, nnz, d_rowptr, d_col, d_aval, d_erow, d_tkey, d_iota, d_tcnt,
+                              d_tptr, d_trow, d_tval, d_tpos, d_temp, temp_bytes));
   if (o.sparsify) {
     int t = (int)std::sqrt((double)n);
     while ((long long)(t + 1) * (t + 1) <= n) ++t;
     while ((long long)t * t > n) --t;
-    std::vector<int> dense;
-    for (int j = 0; j < n; ++j)
-      if (tptr[j + 1] - tptr[j] > t) dense.push_back(j);
-    if (!dense.empty()) {
-      int* d_dense;
-      BC_TRY(A.upload(&d_dense, dense, st));
-      BC_HIP(rip_launch_sparsify(st, d_dense, (int)dense.size(), t, d_tptr, d_trow, d_tval, d_tpos,
-                                 d_aval));
-    }
+    int* d_dense;
+    BC_TRY(A.alloc(&d_dense, n));
+    BC_HIP(rip_launch_dense_cols(st, n, d_tptr, t, d_dense, d_flag + 2));
+    int ndense = 0;
+    BC_HIP(hipMemcpyAsync(&ndense, d_flag + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    BC_HIP(hipStreamSynchronize(st));
+    BC_HIP(rip_launch_sparsify(st, d_dense, ndense, t, d_tptr, d_trow, d_tval, d_tpos, d_aval));
   }
   // compact the column lists (drop zero entries)
   int *d_ccnt, *d_cptr, *d_crow;
   double* d_cval;
-  BC_TRY(A.alloc(&d_ccnt, n));
+  BC_TRY(A.alloc(&d_ccnt, (size_t)n + 1));
+  BC_TRY(A.alloc(&d_cptr, (size_t)n + 1));
+  BC_TRY(A.alloc(&d_crow, (size_t)nnz));
+  BC_TRY(A.alloc(&d_cval, (size_t)nnz));
   BC_HIP(rip_launch_col_nonzeros(st, n, d_tptr, d_tval, d_ccnt));
-  std::vector<int> ccnt;
-  BC_TRY(d2h(ccnt, d_ccnt, n, st));
-  BC_HIP(hipStreamSynchronize(st));
-  std::vector<int> cptr(n + 1, 0);
-  for (int j = 0; j < n; ++j) cptr[j + 1] = cptr[j] + ccnt[j];
-  BC_TRY(A.upload(&d_cptr, cptr, st));
-  BC_TRY(A.alloc(&d_crow, cptr[n]));
-  BC_TRY(A.alloc(&d_cval, cptr[n]));
+  BC_HIP(rip_launch_scan_int(st, d_ccnt, d_cptr, n, d_temp, temp_bytes));
   BC_HIP(rip_launch_compact(st, n, d_tptr, d_trow, d_tval, d_cptr, d_crow, d_cval));
   // products per row -> short (LDS table) and long (global table) rows
   long long* d_ub;
@@ -2585,17 +2588,28 @@ bc_status rip_impl(int32_t n, const int32_t* rowptr, const int32_t* colidx, cons
                          d_col, d_aval, d_cptr, d_crow, d_cval, d_gkeys, d_gvals, d_cnt, nullptr,
                          nullptr, nullptr, nullptr, alpha, d_flag + 1));
   BC_HIP(hipEventRecord(e1, st));
-  std::vector<int> cnt;
-  BC_TRY(d2h(cnt, d_cnt, n, st));
+  long long *d_wide, *d_optr;
+  BC_TRY(A.alloc(&d_wide, (size_t)n + 1));
+  BC_TRY(A.alloc(&d_optr, (size_t)n + 1));
+  BC_HIP(rip_launch_offsets(st, d_cnt, d_wide, d_optr, n, d_temp, temp_bytes));
+  // the result lives in pinned host memory: the copies below go straight
+  // into it (released by rip_graph_free)
+  out->n = n;
+  if (hipHostMalloc((void**)&out->rowptr, ((size_t)n + 1) * sizeof(int64_t), hipHostMallocDefault) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    out->rowptr = nullptr;
+    bc_set_error("rip_graph: pinned host allocation failed");
+    return BC_ERR_NOMEM;
+  }
+  BC_HIP(hipMemcpyAsync(out->rowptr, d_optr, ((size_t)n + 1) * sizeof(int64_t),
+                        hipMemcpyDeviceToHost, st));
   BC_HIP(hipStreamSynchronize(st));
-  std::vector<long long> optr(n + 1, 0);
-  for (int i = 0; i < n; ++i) optr[i + 1] = optr[i] + cnt[i];
-  const long long ne = optr[n];
-  long long* d_optr;
+  const long long ne = out->rowptr[n];
+  out->nnz = ne;
   int* d_ocol;
   double* d_ocost;
   long long* d_owgt;
-  BC_TRY(A.upload(&d_optr, optr, st));
   BC_TRY(A.alloc(&d_ocol, ne));
   BC_TRY(A.alloc(&d_ocost, ne));
   BC_TRY(A.alloc(&d_owgt, ne));
@@ -2607,18 +2621,15 @@ bc_status rip_impl(int32_t n, const int32_t* rowptr, const int32_t* colidx, cons
                          d_col, d_aval, d_cptr, d_crow, d_cval, d_gkeys, d_gvals, nullptr, d_optr,
                          d_ocol, d_ocost, d_owgt, alpha, d_flag + 1));
   BC_HIP(hipEventRecord(e3, st));
-  out->n = n;
-  out->nnz = ne;
-  out->rowptr = (int64_t*)std::malloc((n + 1) * sizeof(int64_t));
-  out->col = (int32_t*)std::malloc(std::max<long long>(ne, 1) * sizeof(int32_t));
-  out->cost = (double*)std::malloc(std::max<long long>(ne, 1) * sizeof(double));
-  out->wgt = (int64_t*)std::malloc(std::max<long long>(ne, 1) * sizeof(int64_t));
-  if (!out->rowptr || !out->col || !out->cost || !out->wgt) {
+  const size_t ne1 = (size_t)std::max<long long>(ne, 1);
+  if (hipHostMalloc((void**)&out->col, ne1 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&out->cost, ne1 * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&out->wgt, ne1 * sizeof(int64_t), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
     BC_HIP(hipStreamSynchronize(st));
-    bc_set_error("rip_graph: host allocation failed");
+    bc_set_error("rip_graph: pinned host allocation failed");
     return BC_ERR_NOMEM;
   }
-  std::memcpy(out->rowptr, optr.data(), (n + 1) * sizeof(int64_t));
   if (ne) {
     BC_HIP(hipMemcpyAsync(out->col, d_ocol, ne * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     BC_HIP(hipMemcpyAsync(out->cost, d_ocost, ne * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -2647,10 +2658,10 @@ bc_status rip_impl(int32_t n, const int32_t* rowptr, const int32_t* colidx, cons
 
 extern "C" void rip_graph_free(rip_graph_t* g) {
   if (!g) return;
-  std::free(g->rowptr);
-  std::free(g->col);
-  std::free(g->cost);
-  std::free(g->wgt);
+  if (g->rowptr) (void)hipHostFree(g->rowptr);
+  if (g->col) (void)hipHostFree(g->col);
+  if (g->cost) (void)hipHostFree(g->cost);
+  if (g->wgt) (void)hipHostFree(g->wgt);
   g->rowptr = nullptr;
   g->col = nullptr;
   g->cost = nullptr;

@@ -15,6 +15,9 @@
 
 #include <cmath>
 
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
+
 namespace {
 
 constexpr int RIP_WAVES = 4;                 // wavefronts per workgroup (one row each)
@@ -49,11 +52,51 @@ __global__ void k_scale_rows(int n, const int* __restrict__ rowptr, double* __re
   for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) val[e] = val[e] / d;
 }
 
-__global__ void k_scale_cols(long long nnz, const int* __restrict__ trow, double* __restrict__ tval,
-                             const double* __restrict__ nrm) {
+// ------------------------------------------------------------- transpose
+// A^T by a stable sort of the entries by column: within a column the entries
+// keep the row-major order of A, i.e. ascending rows.
+__global__ void k_entry_rows(int n, const int* __restrict__ rowptr, int* __restrict__ erow) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) erow[e] = i;
+}
+
+__global__ void k_col_count(long long nnz, const int* __restrict__ col, int* __restrict__ cnt) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nnz) return;
-  tval[e] = tval[e] / nrm[trow[e]];
+  atomicAdd(&cnt[col[e]], 1);
+}
+
+__global__ void k_iota(long long nnz, int* __restrict__ v) {
+  const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < nnz) v[e] = (int)e;
+}
+
+// transposed entry f is A's entry tpos[f]: its row and (scaled) value
+__global__ void k_transpose_gather(long long nnz, const int* __restrict__ tpos,
+                                   const int* __restrict__ erow, const double* __restrict__ aval,
+                                   int* __restrict__ trow, double* __restrict__ tval) {
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nnz) return;
+  const int e = tpos[f];
+  trow[f] = erow[e];
+  tval[f] = aval[e];
+}
+
+// columns with more than t entries, appended in any order (each is sparsified
+// on its own)
+__global__ void k_dense_cols(int n, const int* __restrict__ tptr, int t, int* __restrict__ dense,
+                             int* __restrict__ ndense) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  if (tptr[k + 1] - tptr[k] > t) dense[atomicAdd(ndense, 1)] = k;
+}
+
+// counts widened to 64 bits with a zero appended (input of the offsets scan)
+__global__ void k_widen(int n, const int* __restrict__ c, long long* __restrict__ w) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) w[i] = c[i];
+  if (i == n) w[i] = 0;
 }
 
 // --------------------------------------------------------------- sparsify
@@ -63,7 +106,7 @@ __global__ void k_scale_cols(long long nnz, const int* __restrict__ trow, double
 // sum; the transposed lists are then compacted).
 __global__ void k_sparsify(const int* __restrict__ dense_cols, int t, const int* __restrict__ tptr,
                            const int* __restrict__ trow, double* __restrict__ tval,
-                           const long long* __restrict__ tpos, double* __restrict__ aval) {
+                           const int* __restrict__ tpos, double* __restrict__ aval) {
   const int k = dense_cols[blockIdx.x];
   const int f0 = tptr[k], f1 = tptr[k + 1];
   for (int f = f0 + threadIdx.x; f < f1; f += blockDim.x) {
@@ -81,10 +124,11 @@ __global__ void k_sparsify(const int* __restrict__ dense_cols, int t, const int*
     if (aval[tpos[f]] == 0.0) tval[f] = 0.0;
 }
 
-// count of nonzero entries per column (for compaction)
+// count of nonzero entries per column (for compaction), cnt[n] = 0
 __global__ void k_col_nonzeros(int n, const int* __restrict__ tptr, const double* __restrict__ tval,
                                int* __restrict__ cnt) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k == n) cnt[n] = 0;
   if (k >= n) return;
   int c = 0;
   for (int f = tptr[k]; f < tptr[k + 1]; ++f) c += tval[f] != 0.0;
@@ -325,29 +369,101 @@ k_rip_long(const int* __restrict__ rows, const long long* __restrict__ toff,
 
 // ------------------------------------------------------------ launchers
 
-hipError_t rip_launch_prescale(hipStream_t st, int n, long long nnz, const int* rowptr,
-                               double* aval, const int* trow, double* tval, double* nrm,
-                               int* zero_row) {
+hipError_t rip_launch_prescale(hipStream_t st, int n, const int* rowptr, double* aval,
+                               double* nrm, int* zero_row) {
   hipLaunchKernelGGL(k_rownorm, dim3((n + 255) / 256), dim3(256), 0, st, n, rowptr, aval, nrm,
                      zero_row);
   hipLaunchKernelGGL(k_scale_rows, dim3((n + 255) / 256), dim3(256), 0, st, n, rowptr, aval, nrm);
-  hipLaunchKernelGGL(k_scale_cols, dim3((unsigned)((nnz + 255) / 256)), dim3(256), 0, st, nnz,
-                     trow, tval, nrm);
+  return hipGetLastError();
+}
+
+// Temporary bytes of rip_launch_transpose's column sort and of the scans.
+size_t rip_transpose_temp_bytes(int n, long long nnz) {
+  size_t sort = 0, scan = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, sort, (const unsigned*)nullptr, (unsigned*)nullptr,
+                                  (const int*)nullptr, (int*)nullptr, (size_t)nnz, 0, 32);
+  (void)rocprim::exclusive_scan(nullptr, scan, (const int*)nullptr, (int*)nullptr, 0,
+                                (size_t)n + 1, rocprim::plus<int>());
+  return std::max<size_t>(std::max(sort, scan), 256);
+}
+
+size_t rip_offsets_temp_bytes(int n) {
+  size_t scan = 0;
+  (void)rocprim::exclusive_scan(nullptr, scan, (const long long*)nullptr, (long long*)nullptr,
+                                0LL, (size_t)n + 1, rocprim::plus<long long>());
+  return std::max<size_t>(scan, 256);
+}
+
+// A^T of the n x n CSR matrix on the device: tptr (n+1), and per transposed
+// entry its row trow, value tval and position tpos in A.  Scratch: erow,
+// tkey, iota (nnz each), tcnt (n+1, zeroed here), temp (temp_bytes).
+hipError_t rip_launch_transpose(hipStream_t st, int n, long long nnz, const int* rowptr,
+                                const int* col, const double* aval, int* erow, unsigned* tkey,
+                                int* iota, int* tcnt, int* tptr, int* trow, double* tval,
+                                int* tpos, void* temp, size_t temp_bytes) {
+  const unsigned gn = (unsigned)((nnz + 255) / 256);
+  hipError_t e = hipMemsetAsync(tcnt, 0, ((size_t)n + 1) * sizeof(int), st);
+  if (e != hipSuccess) return e;
+  if (nnz > 0) {
+    hipLaunchKernelGGL(k_entry_rows, dim3((n + 255) / 256), dim3(256), 0, st, n, rowptr, erow);
+    hipLaunchKernelGGL(k_col_count, dim3(gn), dim3(256), 0, st, nnz, col, tcnt);
+    hipLaunchKernelGGL(k_iota, dim3(gn), dim3(256), 0, st, nnz, iota);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    unsigned bits = 1;
+    while (bits < 32 && (1u << bits) < (unsigned)n) ++bits;
+    size_t tb = temp_bytes;
+    e = rocprim::radix_sort_pairs(temp, tb, (const unsigned*)col, tkey, (const int*)iota, tpos,
+                                  (size_t)nnz, 0, bits, st);
+    if (e != hipSuccess) return e;
+  }
+  size_t tb = temp_bytes;
+  e = rocprim::exclusive_scan(temp, tb, (const int*)tcnt, tptr, 0, (size_t)n + 1,
+                              rocprim::plus<int>(), st);
+  if (e != hipSuccess) return e;
+  if (nnz > 0)
+    hipLaunchKernelGGL(k_transpose_gather, dim3(gn), dim3(256), 0, st, nnz, tpos, erow, aval, trow,
+                       tval);
+  return hipGetLastError();
+}
+
+hipError_t rip_launch_dense_cols(hipStream_t st, int n, const int* tptr, int t, int* dense,
+                                 int* ndense) {
+  hipLaunchKernelGGL(k_dense_cols, dim3((n + 255) / 256), dim3(256), 0, st, n, tptr, t, dense,
+                     ndense);
   return hipGetLastError();
 }
 
 hipError_t rip_launch_sparsify(hipStream_t st, const int* dense_cols, int ndense, int t,
-                               const int* tptr, const int* trow, double* tval,
-                               const long long* tpos, double* aval) {
+                               const int* tptr, const int* trow, double* tval, const int* tpos,
+                               double* aval) {
   if (ndense == 0) return hipSuccess;
   hipLaunchKernelGGL(k_sparsify, dim3(ndense), dim3(256), 0, st, dense_cols, t, tptr, trow, tval,
                      tpos, aval);
   return hipGetLastError();
 }
 
+// cptr = exclusive scan of the n+1 counts (the last one zero)
+hipError_t rip_launch_scan_int(hipStream_t st, const int* cnt, int* out, int n, void* temp,
+                               size_t temp_bytes) {
+  size_t tb = temp_bytes;
+  return rocprim::exclusive_scan(temp, tb, cnt, out, 0, (size_t)n + 1, rocprim::plus<int>(), st);
+}
+
+// row offsets of the graph: exclusive scan of the per-row edge counts in 64 bits
+hipError_t rip_launch_offsets(hipStream_t st, const int* cnt, long long* wide, long long* optr,
+                              int n, void* temp, size_t temp_bytes) {
+  hipLaunchKernelGGL(k_widen, dim3((n + 256) / 256), dim3(256), 0, st, n, cnt, wide);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  size_t tb = temp_bytes;
+  return rocprim::exclusive_scan(temp, tb, (const long long*)wide, optr, 0LL, (size_t)n + 1,
+                                 rocprim::plus<long long>(), st);
+}
+
 hipError_t rip_launch_col_nonzeros(hipStream_t st, int n, const int* tptr, const double* tval,
                                    int* cnt) {
-  hipLaunchKernelGGL(k_col_nonzeros, dim3((n + 255) / 256), dim3(256), 0, st, n, tptr, tval, cnt);
+  hipLaunchKernelGGL(k_col_nonzeros, dim3((n + 256) / 256), dim3(256), 0, st, n, tptr, tval, cnt);
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ from oracle import (block_cimmino_cg, rip_graph, greedy_partition,  # noqa: E402
                     multilevel_partition, BlockProjections)
 
 NSAMPLE = 2000
+TAIL = 32   # iterations of residual history kept before the stop
 OUT = os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")
 
 
@@ -43,9 +44,9 @@ def run(name, A, f, part, K, tol=1e-10):
     idx = np.sort(rng.choice(A.n, size=min(NSAMPLE, A.n), replace=False))
     print("%s: iterations %d rel_res %.3e setup %.1f s solve %.1f s"
           % (name, res.iterations, res.rel_residual, t1 - t0, t2 - t1), flush=True)
-    # the relative true residuals of the last iterations (the near-tie check
-    # of a stop decided one iteration apart reads them)
-    t1_hist = max(0, res.iterations - 3)
+    # the relative true residuals of the last iterations (the checks of a
+    # stop decided at a different iteration read them)
+    t1_hist = max(0, res.iterations - TAIL + 1)
     hist = {str(t): float(res.history[t]) for t in range(t1_hist, res.iterations + 1)}
     return {"n": int(A.n), "K": int(K), "tol": tol, "iterations": int(res.iterations),
             "status": int(res.status), "rel_residual": float(res.rel_residual),
