@@ -27,7 +27,7 @@ import pytest
 import paper_1710_07769_amd as bc
 import workloads
 from oracle import rip_rows
-from _bars import counts_match_long
+from _bars import counts_match_long, residual_gap_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -96,18 +96,21 @@ def history_at(ref):
     return lambda t: tail[str(t)]
 
 
-def check_fp64_count_and_iterate(dev, solver, f, ref, tol=1e-10):
+def check_fp64_count_and_iterate(dev, solver, f, ref, A, tol=1e-10):
     x, st = solver.solve(f, tol=tol, maxit=20000)
     assert st.status == bc.BC_OK and st.rel_residual <= tol * (1 + 1e-6)
     print("iterations gpu=%d oracle=%d" % (st.iterations, ref["iterations"]))
-    # the iterate after the oracle's count of iterations
+    # the iterate after the oracle's count of iterations, compared with the oracle's
     x2, st2 = solver.solve(f, tol=0.0, maxit=ref["iterations"])
-    gpu_at = {st.iterations: st.rel_residual, ref["iterations"]: st2.rel_residual}
-    counts_match_long(st.iterations, ref["iterations"], history_at(ref), gpu_at.__getitem__, tol)
-    # iterates compared at the oracle's count
-    err = sample_err(x2.cpu().numpy(), ref)
+    x2 = x2.cpu().numpy()
+    err = sample_err(x2, ref)
     print("sampled error at equal count: %.3e" % err)
     assert err <= 1e-8
+    idx = np.asarray(ref["sample_index"])
+    gap = residual_gap_bound(A.to_scipy(), f.cpu().numpy(), x2.size,
+                             x2[idx] - np.asarray(ref["sample_x"]))
+    counts_match_long(st.iterations, ref["iterations"], history_at(ref), tol, st2.rel_residual,
+                      gap)
     return st
 
 
@@ -145,7 +148,7 @@ def test_solve_cd3d_64cubed_inner_cg(dev, golden):
     p = config2()
     solver = bc.BlockCimmino(p.A, cfg2_partition(), p.K, projection=bc.BC_PROJ_INNER_CG)
     try:
-        check_fp64_count_and_iterate(dev, solver, to_dev(p.f, dev), golden["cfg2"])
+        check_fp64_count_and_iterate(dev, solver, to_dev(p.f, dev), golden["cfg2"], p.A)
     finally:
         solver.close()
 
@@ -177,7 +180,7 @@ def test_solve_st27_100cubed_greedy_rip(dev, golden):
     assert partition_hash(part) == ref["partition_sha"]
     solver = bc.BlockCimmino(p.A, part, p.K, projection=bc.BC_PROJ_DENSE_CHOL)
     try:
-        check_fp64_count_and_iterate(dev, solver, to_dev(p.f, dev), ref)
+        check_fp64_count_and_iterate(dev, solver, to_dev(p.f, dev), ref, p.A)
     finally:
         solver.close()
 
@@ -192,7 +195,7 @@ def test_solve_st27_100cubed_dense(dev, golden, precision):
     try:
         f = to_dev(p.f, dev)
         if precision == "fp64":
-            check_fp64_count_and_iterate(dev, solver, f, golden["cfg5"])
+            check_fp64_count_and_iterate(dev, solver, f, golden["cfg5"], p.A)
         else:
             x, st = solver.solve(f, tol=1e-10)
             err = sample_err(x.cpu().numpy(), golden["cfg5"])
@@ -217,7 +220,7 @@ def test_solve_st27_100cubed_banded(dev, golden, precision):
         print("half-bandwidths %d..%d" % (bw.min(), bw.max()))
         f = to_dev(p.f, dev)
         if precision == "fp64":
-            check_fp64_count_and_iterate(dev, solver, f, golden["cfg5"])
+            check_fp64_count_and_iterate(dev, solver, f, golden["cfg5"], p.A)
         else:
             x, st = solver.solve(f, tol=1e-10)
             err = sample_err(x.cpu().numpy(), golden["cfg5"])
@@ -250,22 +253,23 @@ def test_batch256_cd2d(dev, golden, precision):
                                st)
             return at_count[t]
 
-        def gpu_at(k, t):
-            if t == sts[k].iterations:
-                return sts[k].rel_residual
-            return run_to(t)[1][k].rel_residual
-
         for k, ref in golden["cfg4"].items():
             k = int(k)
             err = sample_err(xs[k], ref)
             print("system %d (n=%d): iterations gpu=%d oracle=%d sampled err=%.2e"
                   % (k, probs[k].n, sts[k].iterations, ref["iterations"], err))
             if precision == "fp64":
-                # iterates compared at the oracle's count
-                if not counts_match_long(sts[k].iterations, ref["iterations"], history_at(ref),
-                                         lambda t, k=k: gpu_at(k, t), 1e-10, "system %d" % k):
-                    err = sample_err(run_to(ref["iterations"])[0][k], ref)
+                if sts[k].iterations != ref["iterations"]:
+                    # the iterate and residual after the oracle's count
+                    xk, stk = run_to(ref["iterations"])
+                    xk, stk = xk[k], stk[k]
+                    err = sample_err(xk, ref)
                     print("system %d: sampled err at the oracle's count %.2e" % (k, err))
+                    idx = np.asarray(ref["sample_index"])
+                    gap = residual_gap_bound(probs[k].A.to_scipy(), probs[k].f, probs[k].n,
+                                             xk[idx] - np.asarray(ref["sample_x"]))
+                    counts_match_long(sts[k].iterations, ref["iterations"], history_at(ref),
+                                      1e-10, stk.rel_residual, gap, "system %d" % k)
                 assert err <= 1e-8
             else:
                 assert err <= 1e-6
