@@ -425,6 +425,39 @@ __device__ __forceinline__ void band_sweep_run(const TF* __restrict__ F0, const 
   }
 }
 
+// The sweep bodies inside one kernel: a block whose band needs fewer slot
+// vectors per wave (nvb) than the kernel's NV runs the smallest body from
+// about NV/3, NV/2, 2NV/3 and NV that holds it, so narrow bands do not load
+// and multiply the zero slots of the widest one.  The sums are the same bits
+// either way: a slot past a block's band only adds zero products, in the same
+// wave and order.  (The chunks of several vectors keep the one body.)
+template <int NV, int K>
+constexpr int body_nv() {
+  return K == 0 ? (NV + 2) / 3 : K == 1 ? (NV + 1) / 2 : K == 2 ? (2 * NV + 2) / 3 : NV;
+}
+
+template <bool BWD, typename TF, typename TA, int NV, int NR, int K = 0>
+__device__ __forceinline__ void sweep_body(int nvb, const TF* __restrict__ F0,
+                                           const double* __restrict__ dsc,
+                                           const double* const (&src)[NR],
+                                           double* const (&dst)[NR], const bool (&act)[NR],
+                                           TA* win, TA* za, TA* p1, TA* p2, int m, int ld, int w,
+                                           int l) {
+  if constexpr (K < 3 && NR == 1) {
+    constexpr int C = body_nv<NV, K>(), Cn = body_nv<NV, K + 1>();
+    if constexpr (C < Cn) {
+      if (nvb <= C) {
+        band_sweep_run<BWD, TF, TA, C, NR>(F0, dsc, src, dst, act, win, za, p1, p2, m, ld, w, l);
+        return;
+      }
+    }
+    sweep_body<BWD, TF, TA, NV, NR, K + 1>(nvb, F0, dsc, src, dst, act, win, za, p1, p2, m, ld, w,
+                                           l);
+  } else {
+    band_sweep_run<BWD, TF, TA, NV, NR>(F0, dsc, src, dst, act, win, za, p1, p2, m, ld, w, l);
+  }
+}
+
 template <typename TF, typename TA, int NV, int NR>
 __global__ void __launch_bounds__(256, 2)
 k_band_sweep(BandBlocks B, const TF* __restrict__ FL, const TF* __restrict__ FR,
@@ -465,13 +498,15 @@ k_band_sweep(BandBlocks B, const TF* __restrict__ FL, const TF* __restrict__ FR,
   // [0 x 64 | a]: the zero half is written once
 #pragma unroll
   for (int q = 0; q < NR; ++q) za[q * 128 + l] = (TA)0;
-  band_sweep_run<false, TF, TA, NV, NR>(FL + B.soff[blk], B.dsc + row0, ub, yb, act, win, za, p1,
-                                        p2, m, ld, w, l);
+  // slot vectors per wave this block's band needs (uniform)
+  const int nvb = __builtin_amdgcn_readfirstlane((ld * (int)sizeof(TF) / 16 + 3) / 4);
+  sweep_body<false, TF, TA, NV, NR>(nvb, FL + B.soff[blk], B.dsc + row0, ub, yb, act, win, za, p1,
+                                    p2, m, ld, w, l);
   // the backward sweep starts from the forward result of every row
   __threadfence_block();
   __syncthreads();
-  band_sweep_run<true, TF, TA, NV, NR>(FR + B.soff[blk], B.dsc + row0, yb, yb, act, win, za, p1, p2,
-                                       m, ld, w, l);
+  sweep_body<true, TF, TA, NV, NR>(nvb, FR + B.soff[blk], B.dsc + row0, yb, yb, act, win, za, p1,
+                                   p2, m, ld, w, l);
 }
 
 // Register-set sizes (16-byte slot vectors per wave) the sweeps are built
