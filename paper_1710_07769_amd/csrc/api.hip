@@ -325,16 +325,24 @@ std::unordered_map<unsigned long long, LaneChoice> g_tune;
 
 unsigned long long pattern_key(const std::vector<int>& rowptr, const std::vector<int>& col, int n,
                                bool fp32) {
-  unsigned long long h = 1469598103934665603ULL;
+  // every row pointer and column index, two 32-bit entries per 64-bit mix
+  unsigned long long h = 0x243F6A8885A308D3ULL;
   auto mix = [&](unsigned long long v) {
-    h ^= v;
-    h *= 1099511628211ULL;
+    h ^= v + 0x9E3779B97F4A7C15ULL + (h << 6) + (h >> 2);
+    h *= 0xBF58476D1CE4E5B9ULL;
+    h ^= h >> 31;
   };
   mix((unsigned long long)n);
   mix((unsigned long long)col.size());
   mix(fp32 ? 1 : 0);
-  for (size_t i = 0; i < rowptr.size(); i += 7) mix((unsigned long long)rowptr[i]);
-  for (size_t i = 0; i < col.size(); i += 61) mix((unsigned long long)col[i]);
+  auto mix_all = [&](const std::vector<int>& a) {
+    size_t i = 0;
+    for (; i + 1 < a.size(); i += 2)
+      mix((unsigned long long)(unsigned)a[i] | ((unsigned long long)(unsigned)a[i + 1] << 32));
+    if (i < a.size()) mix((unsigned long long)(unsigned)a[i]);
+  };
+  mix_all(rowptr);
+  mix_all(col);
   return h;
 }
 

@@ -226,8 +226,9 @@ k_band_slots(BandBlocks B, TF* __restrict__ outL, TF* __restrict__ outR) {
 // Every wave thus holds the same z, and the only cross-wave traffic is the
 // two partial-sum exchanges.  The window keeps each value twice, 256 rows
 // apart, so that the reads of rows p - s need no wrap-around.  The slots and
-// right-hand sides of tile t+2 are loaded into registers while tile t is
-// computed (three register sets in rotation, issued in tile order).  The forward sweep (slots of L,
+// right-hand sides of the next tiles are loaded into registers while tile t
+// is computed (register sets in rotation, issued in tile order).  The
+// forward sweep (slots of L,
 // right-hand side D u) and the backward sweep (slots of R, right-hand side
 // the reversed forward result, output scaled by D) run one after the other.
 // Blocks are taken in decreasing order of work (B.order), so the long chains
@@ -274,7 +275,7 @@ __device__ __forceinline__ void band_sweep_run(const TF* __restrict__ F0, const 
                                                int m, int ld, int w, int l) {
   constexpr int VT = 16 / (int)sizeof(TF);
   constexpr int SMAX = 4 * NV * VT;  // bound of the slots a wave holds
-  constexpr int GI = NR == 1 ? 4 : 2;  // slot vectors whose LDS reads issue together
+  constexpr int GI = 4;  // one vector: slot vectors whose LDS reads issue together
   const int nt = (m + 63) >> 6;
   const int qh = band_subtile(ld), qlog = __builtin_ctz(qh), nsub = 64 >> qlog;
   using Set = SweepSet<TF, NV, NR>;
@@ -314,22 +315,37 @@ __device__ __forceinline__ void band_sweep_run(const TF* __restrict__ F0, const 
     for (int q = 0; q < NR; ++q) part[q] = (TA)0;
     // (the reads of a group of GI vectors are issued together, then
     // multiplied in slot order)
+    if constexpr (NR == 1) {
 #pragma unroll
-    for (int g = 0; g < NV; g += GI) {
-      TA wv[GI * VT][NR];
+      for (int g = 0; g < NV; g += GI) {
+        TA wv[GI * VT][NR];
 #pragma unroll
-      for (int i = g; i < g + GI && i < NV; ++i)
+        for (int i = g; i < g + GI && i < NV; ++i)
 #pragma unroll
-        for (int e = 0; e < VT; ++e)
+          for (int e = 0; e < VT; ++e)
 #pragma unroll
-          for (int q = 0; q < NR; ++q)
-            wv[(i - g) * VT + e][q] = win1[q * 512 + SMAX - ((4 * i + w) * VT + e)];
+            for (int q = 0; q < NR; ++q)
+              wv[(i - g) * VT + e][q] = win1[q * 512 + SMAX - ((4 * i + w) * VT + e)];
 #pragma unroll
-      for (int i = g; i < g + GI && i < NV; ++i)
+        for (int i = g; i < g + GI && i < NV; ++i)
 #pragma unroll
-        for (int e = 0; e < VT; ++e)
+          for (int e = 0; e < VT; ++e)
 #pragma unroll
-          for (int q = 0; q < NR; ++q) part[q] += (TA)S.cf[i * VT + e] * wv[(i - g) * VT + e][q];
+            for (int q = 0; q < NR; ++q) part[q] += (TA)S.cf[i * VT + e] * wv[(i - g) * VT + e][q];
+      }
+    } else {
+      // several vectors: the NR values of one slot at a time (NR independent sums)
+#pragma unroll
+      for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int e = 0; e < VT; ++e) {
+          TA wv[NR];
+#pragma unroll
+          for (int q = 0; q < NR; ++q) wv[q] = win1[q * 512 + SMAX - ((4 * i + w) * VT + e)];
+          const TA c = (TA)S.cf[i * VT + e];
+#pragma unroll
+          for (int q = 0; q < NR; ++q) part[q] += c * wv[q];
+        }
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) p1[(w * NR + q) * 64 + l] = part[q];
@@ -347,22 +363,36 @@ __device__ __forceinline__ void band_sweep_run(const TF* __restrict__ F0, const 
     // (vectors i < 16 / VT hold every slot below 64; a slot at or past q
     // reads a row before the sub-tile, which is 0 in [0 x 64 | a])
     constexpr int NV2 = NV < 16 / VT ? NV : 16 / VT;
+    if constexpr (NR == 1) {
 #pragma unroll
-    for (int g = 0; g < NV2; g += GI) {
-      TA wv[GI * VT][NR];
+      for (int g = 0; g < NV2; g += GI) {
+        TA wv[GI * VT][NR];
 #pragma unroll
-      for (int i = g; i < g + GI && i < NV2; ++i)
+        for (int i = g; i < g + GI && i < NV2; ++i)
 #pragma unroll
-        for (int e = 0; e < VT; ++e)
+          for (int e = 0; e < VT; ++e)
 #pragma unroll
-          for (int q = 0; q < NR; ++q)
-            wv[(i - g) * VT + e][q] = za[q * 128 + 64 + l - ((4 * i + w) * VT + e)];
+            for (int q = 0; q < NR; ++q)
+              wv[(i - g) * VT + e][q] = za[q * 128 + 64 + l - ((4 * i + w) * VT + e)];
 #pragma unroll
-      for (int i = g; i < g + GI && i < NV2; ++i)
+        for (int i = g; i < g + GI && i < NV2; ++i)
 #pragma unroll
-        for (int e = 0; e < VT; ++e)
+          for (int e = 0; e < VT; ++e)
 #pragma unroll
-          for (int q = 0; q < NR; ++q) part[q] += (TA)S.cf[i * VT + e] * wv[(i - g) * VT + e][q];
+            for (int q = 0; q < NR; ++q) part[q] += (TA)S.cf[i * VT + e] * wv[(i - g) * VT + e][q];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NV2; ++i)
+#pragma unroll
+        for (int e = 0; e < VT; ++e) {
+          TA wv[NR];
+#pragma unroll
+          for (int q = 0; q < NR; ++q) wv[q] = za[q * 128 + 64 + l - ((4 * i + w) * VT + e)];
+          const TA c = (TA)S.cf[i * VT + e];
+#pragma unroll
+          for (int q = 0; q < NR; ++q) part[q] += c * wv[q];
+        }
     }
 #pragma unroll
     for (int q = 0; q < NR; ++q) p2[(w * NR + q) * 64 + l] = part[q];
@@ -408,20 +438,33 @@ __device__ __forceinline__ void band_sweep_run(const TF* __restrict__ F0, const 
   for (int q = 0; q < NR; ++q)
 #pragma unroll
     for (int k = 0; k < 8; ++k) win[q * 512 + k * 64 + l] = (TA)0;
-  // Three register sets in rotation: tile t is computed while the sets of
-  // tiles t+1 and t+2 are in flight.
-  Set S0, S1, S2;
-  load(S0, 0);
-  load(S1, 1);
-  for (int t = 0; t < nt; t += 3) {
-    load(S2, t + 2);
-    tile(t, S0);
-    if (t + 1 >= nt) break;
-    load(S0, t + 3);
-    tile(t + 1, S1);
-    if (t + 2 >= nt) break;
-    load(S1, t + 4);
-    tile(t + 2, S2);
+  // One vector: three register sets in rotation, tile t computed while the
+  // sets of tiles t+1 and t+2 are in flight.  Several vectors (larger sets):
+  // two, so that the wide bands fit the registers without spilling.
+  if constexpr (NR == 1) {
+    Set S0, S1, S2;
+    load(S0, 0);
+    load(S1, 1);
+    for (int t = 0; t < nt; t += 3) {
+      load(S2, t + 2);
+      tile(t, S0);
+      if (t + 1 >= nt) break;
+      load(S0, t + 3);
+      tile(t + 1, S1);
+      if (t + 2 >= nt) break;
+      load(S1, t + 4);
+      tile(t + 2, S2);
+    }
+  } else {
+    Set S0, S1;
+    load(S0, 0);
+    for (int t = 0; t < nt; t += 2) {
+      load(S1, t + 1);
+      tile(t, S0);
+      if (t + 1 >= nt) break;
+      load(S0, t + 2);
+      tile(t + 1, S1);
+    }
   }
 }
 
