@@ -1082,7 +1082,36 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     }
     BC_HIP(launch_gram(st, D, ptiles, (int)gram_tiles.size(), c->d_rowptr, c->d_col, c->d_val,
                        c->d_tptr, c->d_trow, c->d_tval));
-    BC_HIP(launch_cholesky(st, D));
+    // blocked Cholesky plan: per panel step, the panel rows and trailing tiles
+    CholPlan P;
+    {
+      int maxnt = 0;
+      for (int b = 0; b < D.nblk; ++b) maxnt = std::max(maxnt, dn_nt[b]);
+      P.steps = (maxnt + CHOL_PW - 1) / CHOL_PW;
+      std::vector<int2> pl_h;
+      std::vector<int4> up_h;
+      P.panel_off.assign(1, 0);
+      P.upd_off.assign(1, 0);
+      for (int s = 0; s < P.steps; ++s) {
+        const int kb = s * CHOL_PW;
+        for (int b = 0; b < D.nblk; ++b) {
+          const int ntb = dn_nt[b], ke = std::min(ntb, kb + CHOL_PW);
+          if (kb >= ntb) continue;
+          for (int i = ke; i < ntb; ++i) pl_h.push_back(make_int2(b, i));
+          for (int i = ke; i < ntb; ++i)
+            for (int j = ke; j <= i; ++j) up_h.push_back(make_int4(b, i, j, 0));
+        }
+        P.panel_off.push_back((long long)pl_h.size());
+        P.upd_off.push_back((long long)up_h.size());
+      }
+      int2* ppl;
+      int4* pup;
+      BC_TRY(A.upload(&ppl, pl_h, st));
+      BC_TRY(A.upload(&pup, up_h, st));
+      P.panel = ppl;
+      P.upd = pup;
+    }
+    BC_HIP(launch_cholesky(st, D, P));
     BC_HIP(launch_dense_finish(st, D, c->mixed));
     BC_HIP(prepare_dense_apply());
     D.err = c->d_err;

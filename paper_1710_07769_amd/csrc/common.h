@@ -315,7 +315,17 @@ struct DenseBlocks {
                            // gave up waiting (the result is then invalid)
   unsigned long long wait_ticks;  // bound of a wait, 100 MHz wall-clock ticks (0: give up at once)
 };
-hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D);
+// Blocked Cholesky: panels of CHOL_PW tile columns; per panel step s the
+// (block, tile row) pairs of the panel solves and the (block, i, j) tiles of
+// the trailing update, concatenated over the steps (offsets on the host).
+constexpr int CHOL_PW = 4;
+struct CholPlan {
+  int steps;
+  const int2* panel;
+  const int4* upd;
+  std::vector<long long> panel_off, upd_off;  // steps + 1 each
+};
+hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D, const CholPlan& P);
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed);
 // Lets the apply kernels use the full LDS of a workgroup; call before the
 // first apply (and outside stream capture).

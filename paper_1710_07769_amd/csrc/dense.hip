@@ -121,11 +121,84 @@ __device__ __forceinline__ void store_tile(double* dst, const double* src) {
 }
 
 // ------------------------------------------------------------- Cholesky
-// Right-looking blocked Cholesky of one block per workgroup, in place on the
-// packed lower tiles: factor the diagonal tile, invert it, form the panel
-// L_ik = A_ik L_kk^{-T}, update the trailing tiles A_ij -= L_ik L_jk^T.
+// Blocked right-looking Cholesky of every block, in place on the packed lower
+// tiles, one panel of CHOL_PW tile columns (kb .. kb + kw - 1) per step:
+//   k_chol_diag   one workgroup per block: the kw x kw tiles of the diagonal
+//                 block, tile by tile (factor the diagonal tile, invert it,
+//                 form the panel tiles below it inside the diagonal block,
+//                 update the rest of the diagonal block);
+//   k_chol_panel  one workgroup per (block, tile row i below the diagonal
+//                 block): L_ik = (A_ik - sum_{kb <= c < k} L_ic L_kc^T) L_kk^{-T}
+//                 for k = kb .. kb + kw - 1;
+//   k_chol_update one workgroup per (block, i, j), kb + kw <= j <= i:
+//                 A_ij -= sum_{kb <= k < kb + kw} L_ik L_jk^T.
+// The panel and trailing products read their operand tiles straight from
+// global memory into the FP64 matrix cores (v_mfma_f64_16x16x4f64, lane
+// layout as in tile_mfma_nt: wave w owns the 32x32 quadrant at rows
+// 32 (w & 1), columns 32 (w >> 1)), and accumulate a whole panel of kw tile
+// columns in registers before the result tile is written once.
+
+// unblocked Cholesky, inverse and transposed inverse of diagonal tile k
+// (in T0, T1 = scratch); returns false (bad set) on a failed pivot
+__device__ bool chol_diag_tile(const DenseBlocks& D, int b, int k, int nt, int m, int row0,
+                               double* L, double* Dv, double* T0, double* T1, int& bad,
+                               double rel_piv) {
+  __syncthreads();
+  load_tile(T0, L + ltile(k, k));
+  __syncthreads();
+  for (int c = 0; c < DT; ++c) {
+    if (threadIdx.x == 0) {
+      const double d = T0[c * DT + c];
+      const int gr = k * DT + c;
+      const double g0 = gr < m ? D.gdiag[row0 + gr] : 1.0;
+      if (!(d > rel_piv * g0) || !isfinite(d)) {
+        bad = k * DT + c + 1;
+      } else {
+        T0[c * DT + c] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (bad) return false;
+    const double piv = T0[c * DT + c];
+    for (int rr = c + 1 + threadIdx.x; rr < DT; rr += blockDim.x) T0[c * DT + rr] /= piv;
+    __syncthreads();
+    // rank-1 update of the remaining lower part of the tile
+    const int rem = DT - c - 1;
+    for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+      const int c2 = c + 1 + e / rem, rr = c + 1 + e % rem;
+      if (rr >= c2) T0[c2 * DT + rr] -= T0[c * DT + rr] * T0[c * DT + c2];
+    }
+    __syncthreads();
+  }
+  // zero the strict upper part, write L_kk
+  for (int e = threadIdx.x; e < DT * DT; e += blockDim.x) {
+    const int c = e / DT, rr = e % DT;
+    if (rr < c) T0[e] = 0.0;
+  }
+  __syncthreads();
+  store_tile(L + ltile(k, k), T0);
+  // inverse of the lower-triangular tile: thread c solves L x = e_c
+  if (threadIdx.x < DT) {
+    const int c = threadIdx.x;
+    for (int rr = 0; rr < DT; ++rr) T1[c * DT + rr] = 0.0;
+    for (int rr = c; rr < DT; ++rr) {
+      double s = (rr == c) ? 1.0 : 0.0;
+      for (int j = c; j < rr; ++j) s -= T0[j * DT + rr] * T1[c * DT + j];
+      T1[c * DT + rr] = s / T0[rr * DT + rr];
+    }
+  }
+  __syncthreads();
+  store_tile(Dv + (long long)k * TSZ, T1);
+  // transposed inverse for the backward sweep
+  for (int e = threadIdx.x; e < DT * DT; e += blockDim.x) {
+    const int c = e / DT, rr = e % DT;
+    Dv[(long long)(nt + k) * TSZ + e] = T1[rr * DT + c];
+  }
+  return true;
+}
+
 __global__ void __launch_bounds__(GEMM_THREADS)
-k_cholesky(DenseBlocks D) {
+k_chol_diag(DenseBlocks D, int kb) {
   extern __shared__ double lds[];
   double* T0 = lds;             // diagonal tile / C tile
   double* T1 = lds + TSZ;       // inverse of the diagonal tile
@@ -134,67 +207,17 @@ k_cholesky(DenseBlocks D) {
   __shared__ int bad;
   const int b = blockIdx.x;
   const int nt = D.nt[b], m = D.m[b], row0 = D.row0[b];
+  if (kb >= nt || D.info[b] != 0) return;
+  const int ke = min(nt, kb + CHOL_PW);
   double* L = D.L + D.loff[b];
   double* Dv = D.Dinv + D.doff[b];
   // a pivot at or below m * eps * G_jj means A_i A_i^T is numerically singular
   const double rel_piv = (double)m * 2.220446049250313e-16;
   if (threadIdx.x == 0) bad = 0;
-  for (int k = 0; k < nt; ++k) {
-    __syncthreads();
-    load_tile(T0, L + ltile(k, k));
-    __syncthreads();
-    // unblocked Cholesky of the diagonal tile (column by column)
-    for (int c = 0; c < DT; ++c) {
-      if (threadIdx.x == 0) {
-        const double d = T0[c * DT + c];
-        const int gr = k * DT + c;
-        const double g0 = gr < m ? D.gdiag[row0 + gr] : 1.0;
-        if (!(d > rel_piv * g0) || !isfinite(d)) {
-          bad = k * DT + c + 1;
-        } else {
-          T0[c * DT + c] = sqrt(d);
-        }
-      }
-      __syncthreads();
-      if (bad) break;
-      const double piv = T0[c * DT + c];
-      for (int rr = c + 1 + threadIdx.x; rr < DT; rr += blockDim.x) T0[c * DT + rr] /= piv;
-      __syncthreads();
-      // rank-1 update of the remaining lower part of the tile
-      const int rem = DT - c - 1;
-      for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-        const int c2 = c + 1 + e / rem, rr = c + 1 + e % rem;
-        if (rr >= c2) T0[c2 * DT + rr] -= T0[c * DT + rr] * T0[c * DT + c2];
-      }
-      __syncthreads();
-    }
-    if (bad) break;
-    // zero the strict upper part, write L_kk
-    for (int e = threadIdx.x; e < DT * DT; e += blockDim.x) {
-      const int c = e / DT, rr = e % DT;
-      if (rr < c) T0[e] = 0.0;
-    }
-    __syncthreads();
-    store_tile(L + ltile(k, k), T0);
-    // inverse of the lower-triangular tile: thread c solves L x = e_c
-    if (threadIdx.x < DT) {
-      const int c = threadIdx.x;
-      for (int rr = 0; rr < DT; ++rr) T1[c * DT + rr] = 0.0;
-      for (int rr = c; rr < DT; ++rr) {
-        double s = (rr == c) ? 1.0 : 0.0;
-        for (int j = c; j < rr; ++j) s -= T0[j * DT + rr] * T1[c * DT + j];
-        T1[c * DT + rr] = s / T0[rr * DT + rr];
-      }
-    }
-    __syncthreads();
-    store_tile(Dv + (long long)k * TSZ, T1);
-    // transposed inverse for the backward sweep
-    for (int e = threadIdx.x; e < DT * DT; e += blockDim.x) {
-      const int c = e / DT, rr = e % DT;
-      Dv[(long long)(nt + k) * TSZ + e] = T1[rr * DT + c];
-    }
-    // panel and trailing update
-    for (int i = k + 1; i < nt; ++i) {
+  for (int k = kb; k < ke; ++k) {
+    if (!chol_diag_tile(D, b, k, nt, m, row0, L, Dv, T0, T1, bad, rel_piv)) break;
+    // panel and trailing update inside the diagonal block
+    for (int i = k + 1; i < ke; ++i) {
       __syncthreads();
       load_tile(T2, L + ltile(i, k));
       __syncthreads();
@@ -219,7 +242,93 @@ k_cholesky(DenseBlocks D) {
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) D.info[b] = bad;
+  if (threadIdx.x == 0 && bad) D.info[b] = bad;
+}
+
+// acc (this wave's quadrant, MFMA output layout) -= X Y^T for 64x64
+// column-major tiles X, Y in global memory
+__device__ __forceinline__ void quad_sub_xyt(dbl4 (&acc)[2][2], const double* __restrict__ X,
+                                             const double* __restrict__ Y, int r0, int c0, int li,
+                                             int lk) {
+#pragma unroll 4
+  for (int p0 = 0; p0 < DT; p0 += 4) {
+    const int p = p0 + lk;
+    const double a0 = -X[p * DT + r0 + li], a1 = -X[p * DT + r0 + 16 + li];
+    const double b0 = Y[p * DT + c0 + li], b1 = Y[p * DT + c0 + 16 + li];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+  }
+}
+
+// the wave's quadrant of a 64x64 column-major tile <-> MFMA output layout
+// (element (i, j) of a 16x16 result in register r of lane j + 16 g, i = 4 r + g)
+__device__ __forceinline__ void quad_load(dbl4 (&acc)[2][2], const double* C, int r0, int c0,
+                                          int li, int lk) {
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        acc[ti][tj][r] = C[(c0 + 16 * tj + li) * DT + r0 + 16 * ti + 4 * r + lk];
+}
+__device__ __forceinline__ void quad_store(double* C, const dbl4 (&acc)[2][2], int r0, int c0,
+                                           int li, int lk) {
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        C[(c0 + 16 * tj + li) * DT + r0 + 16 * ti + 4 * r + lk] = acc[ti][tj][r];
+}
+
+__global__ void __launch_bounds__(GEMM_THREADS)
+k_chol_panel(DenseBlocks D, int kb, const int2* __restrict__ list) {
+  extern __shared__ double lds[];
+  double* T0 = lds;         // the tile being formed
+  double* T1 = lds + TSZ;   // L_kk^{-1}
+  const int2 e = list[blockIdx.x];
+  const int b = e.x, i = e.y;
+  if (D.info[b] != 0) return;
+  const int nt = D.nt[b], ke = min(nt, kb + CHOL_PW);
+  double* L = D.L + D.loff[b];
+  const double* Dv = D.Dinv + D.doff[b];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w & 1), c0 = 32 * (w >> 1), li = l & 15, lk = l >> 4;
+  for (int k = kb; k < ke; ++k) {
+    dbl4 acc[2][2];
+    quad_load(acc, L + ltile(i, k), r0, c0, li, lk);
+    for (int c = kb; c < k; ++c) quad_sub_xyt(acc, L + ltile(i, c), L + ltile(k, c), r0, c0, li, lk);
+    __syncthreads();
+    quad_store(T0, acc, r0, c0, li, lk);
+    load_tile(T1, Dv + (long long)k * TSZ);
+    __syncthreads();
+    tile_mfma_nt<false>(T0, T0, T1, true);
+    __syncthreads();
+    store_tile(L + ltile(i, k), T0);
+    // the next tiles of this row read L_ik back from global memory, each
+    // wave its own quadrant's rows of all of it
+    __threadfence_block();
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(GEMM_THREADS)
+k_chol_update(DenseBlocks D, int kb, const int4* __restrict__ list) {
+  const int4 e = list[blockIdx.x];
+  const int b = e.x, i = e.y, j = e.z;
+  if (D.info[b] != 0) return;
+  const int nt = D.nt[b], ke = min(nt, kb + CHOL_PW);
+  double* L = D.L + D.loff[b];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int r0 = 32 * (w & 1), c0 = 32 * (w >> 1), li = l & 15, lk = l >> 4;
+  dbl4 acc[2][2];
+  quad_load(acc, L + ltile(i, j), r0, c0, li, lk);
+  for (int k = kb; k < ke; ++k) quad_sub_xyt(acc, L + ltile(i, k), L + ltile(j, k), r0, c0, li, lk);
+  quad_store(L + ltile(i, j), acc, r0, c0, li, lk);
 }
 
 // Transposed copy for the backward sweep and FP32 copies of everything.
@@ -644,14 +753,27 @@ hipError_t launch_gram(hipStream_t st, const DenseBlocks& D, const int4* tiles, 
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D) {
+hipError_t launch_cholesky(hipStream_t st, const DenseBlocks& D, const CholPlan& P) {
   if (D.nblk == 0) return hipSuccess;
   const size_t lds = 4 * TSZ * sizeof(double);
-  hipError_t e = hipFuncSetAttribute((const void*)k_cholesky,
+  hipError_t e = hipFuncSetAttribute((const void*)k_chol_diag,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cholesky, dim3(D.nblk), dim3(GEMM_THREADS), lds, st, D);
-  return hipGetLastError();
+  for (int s = 0; s < P.steps; ++s) {
+    const int kb = s * CHOL_PW;
+    hipLaunchKernelGGL(k_chol_diag, dim3(D.nblk), dim3(GEMM_THREADS), lds, st, D, kb);
+    const long long np = P.panel_off[s + 1] - P.panel_off[s];
+    if (np > 0)
+      hipLaunchKernelGGL(k_chol_panel, dim3((unsigned)np), dim3(GEMM_THREADS),
+                         2 * TSZ * sizeof(double), st, D, kb, P.panel + P.panel_off[s]);
+    const long long nu = P.upd_off[s + 1] - P.upd_off[s];
+    if (nu > 0)
+      hipLaunchKernelGGL(k_chol_update, dim3((unsigned)nu), dim3(GEMM_THREADS), 0, st, D, kb,
+                         P.upd + P.upd_off[s]);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t launch_dense_finish(hipStream_t st, const DenseBlocks& D, bool mixed) {
