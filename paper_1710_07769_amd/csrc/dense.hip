@@ -555,6 +555,149 @@ k_dense_apply(DenseBlocks D, const double* __restrict__ u, double* __restrict__ 
   }
 }
 
+// FP32 factors applied in FP64 arithmetic (the mixed-precision projections):
+// the same lockstep sweeps, chunks of NR = 4 or 8 vectors, with every tile product on
+// v_mfma_f64_4x4x4_4b_f64.  That instruction computes four 4x4x4 blocks;
+// block b takes A[i][k] from lane 16 k + 4 b + i and B[k][j] from lane
+// 16 k + 4 b + j, and leaves D[i][j] in lane 16 i + 4 b + j (checked on
+// gfx950 with an in-bounds one-wave probe).  Lane l loads the 4-vector of
+// rows 4 (l % 16) .. + 3 of column c0 + l / 16, as in the FP32 kernel; its
+// component g is the A operand of the instruction for the rows 4 m + g, m =
+// 4 b + i, so the four instructions of a k-step cover the 64 rows, and each
+// group of 4 of the chunk's vectors is the columns j of one instruction.  Every product and sum is FP64 (the
+// factor values are the FP32 ones, converted exactly), so the operator is the
+// fixed inverse of the rounded factor; an output element depends only on its
+// own row and vector.
+__device__ __forceinline__ int x_row(int l, int g) { return 16 * ((l & 15) >> 2) + 4 * (l >> 4) + g; }
+
+template <int NR>
+__device__ __forceinline__ void tile_prod_x(const float* __restrict__ tile, const double* z,
+                                            double (&acc)[NR / 4][4], int l) {
+  constexpr int NQ = NR / 4;  // groups of 4 vectors (the columns of one instruction)
+  const int li = l & 15, lk = l >> 4, lj = l & 3;
+  constexpr int MU = 16;  // the whole 64-column tile's loads issued together
+  flt4 a[MU];
+  double bz[MU][NQ];
+#pragma unroll
+  for (int u = 0; u < MU; ++u) a[u] = *(const flt4*)(tile + (4 * u + lk) * DT + 4 * li);
+#pragma unroll
+  for (int u = 0; u < MU; ++u)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) bz[u][q] = z[(4 * u + lk) * NR + 4 * q + lj];
+#pragma unroll
+  for (int u = 0; u < MU; ++u)
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        acc[q][g] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)a[u][g], bz[u][q], acc[q][g], 0, 0, 0);
+}
+
+template <int NR>
+__global__ void __launch_bounds__(APPLY_THREADS)
+k_dense_apply_x(DenseBlocks D, const double* __restrict__ u, double* __restrict__ y,
+                const int* __restrict__ done, int nrhs, int n1, int sys_done) {
+  constexpr int NQ = NR / 4;
+  extern __shared__ __align__(16) unsigned char dyn[];
+  constexpr int NW = APPLY_THREADS / 64;
+  static_assert(NW == 4, "one wave per row interleave");
+  const int b = blockIdx.x;
+  const int m = D.m[b], nt = D.nt[b], row0 = D.row0[b];
+  const int j0 = blockIdx.y * NR;
+  if (sys_done && done && done[D.sys[b]]) return;
+  if (sys_done) done = nullptr;
+  bool any = false;
+  for (int q = 0; q < NR; ++q) any = any || (j0 + q < nrhs && !(done && done[j0 + q]));
+  if (!any) return;
+  double* zs = (double*)dyn;                             // nt * DT rows of NR
+  double* part = zs + (size_t)nt * DT * NR;              // [NW][DT][NR]
+  double* accs = part + (size_t)NW * DT * NR;            // [DT][NR]
+  const float* L = D.L32 + D.loff[b];
+  const float* LT = D.LT32 + D.loff[b];
+  const float* Dv = D.Dinv32 + D.doff[b];
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = l & 15, lk = l >> 4, lj = l & 3;
+  if (threadIdx.x == 0) atomicAdd(&D.applies[b], 1ull);
+  // right-hand-side step: thread t handles the entries t + 256 k of the
+  // 64 x NR tile, always of vector t % NR
+  constexpr int QK = DT * NR / APPLY_THREADS;
+  const int qn = threadIdx.x % NR;
+  const bool qon = j0 + qn < nrhs && !(done && done[j0 + qn]);
+  // the vectors of this lane's outputs, and whether they are written
+  bool non[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) non[q] = j0 + 4 * q + lj < nrhs && !(done && done[j0 + 4 * q + lj]);
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool fwd = pass == 0;
+    for (int s = 0; s < nt; ++s) {
+      const int i = fwd ? s : nt - 1 - s;
+      const float* inv = Dv + (long long)(fwd ? i : nt + i) * TSZ;
+      float ainv[DT / 4];
+#pragma unroll
+      for (int c = 0; c < DT / 4; ++c) ainv[c] = inv[(4 * c + lk) * DT + 4 * li + w];
+      double upre[QK];
+      if (fwd) {
+#pragma unroll
+        for (int k = 0; k < QK; ++k) {
+          const int gi = i * DT + (threadIdx.x + APPLY_THREADS * k) / NR;
+          upre[k] = (qon && gi < m) ? u[(size_t)(j0 + qn) * n1 + row0 + gi] * D.dsc[row0 + gi] : 0.0;
+        }
+      }
+      const int orow = x_row(l, w);  // this lane's output row of the diagonal product
+      double osc = 0.0;
+      if (!fwd) {
+        const int gi = i * DT + orow;
+        osc = gi < m ? D.dsc[row0 + gi] : 0.0;
+      }
+      double acc[NQ][4];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int g = 0; g < 4; ++g) acc[q][g] = 0.0;
+      if (fwd) {
+        for (int j = w; j < i; j += NW)
+          tile_prod_x<NR>(L + ltile(i, j), zs + (size_t)j * DT * NR, acc, l);
+      } else {
+        for (int j = i + 1 + w; j < nt; j += NW)
+          tile_prod_x<NR>(LT + uttile(nt, i, j), zs + (size_t)j * DT * NR, acc, l);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+          part[((size_t)w * DT + x_row(l, g)) * NR + 4 * q + lj] = acc[q][g];
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < QK; ++k) {
+        const int e = threadIdx.x + APPLY_THREADS * k;
+        const int r = e / NR;
+        double a = fwd ? upre[k] : zs[(size_t)(i * DT + r) * NR + qn];
+        for (int ww = 0; ww < NW; ++ww) a -= part[((size_t)ww * DT + r) * NR + qn];
+        accs[e] = a;
+      }
+      __syncthreads();
+      // diagonal tile: rows 4 m + w of (L_ii^{-1} or its transpose) * accs
+      double d[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) d[q] = 0.0;
+#pragma unroll
+      for (int c = 0; c < DT / 4; ++c)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          d[q] = __builtin_amdgcn_mfma_f64_4x4x4f64((double)ainv[c],
+                                                    accs[(4 * c + lk) * NR + 4 * q + lj], d[q], 0,
+                                                    0, 0);
+      const int gi = i * DT + orow;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        zs[(size_t)gi * NR + 4 * q + lj] = d[q];
+        if (!fwd && non[q] && gi < m) y[(size_t)(j0 + 4 * q + lj) * n1 + row0 + gi] = d[q] * osc;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // The same sweeps with tile rows owned by waves, for chunks whose LDS leaves
 // room for one workgroup per CU only (where the lockstep sweep above would
 // leave the CU idle at every barrier).  Wave w computes the rows k = w mod 4
@@ -833,11 +976,9 @@ hipError_t launch_dense_multi_t(hipStream_t st, const DenseBlocks& D, const doub
 // Allows every variant of the apply the full LDS of a workgroup (once per
 // process and device, outside any stream capture).
 hipError_t prepare_dense_apply() {
-  const void* fns[] = {(const void*)k_dense_apply<float, 4>,       (const void*)k_dense_apply<float, 8>,
-                       (const void*)k_dense_apply<float, 16>,      (const void*)k_dense_apply<double, 4>,
-                       (const void*)k_dense_apply<double, 8>,      (const void*)k_dense_apply<double, 16>,
-                       (const void*)k_dense_apply_rows<float, 4>,  (const void*)k_dense_apply_rows<float, 8>,
-                       (const void*)k_dense_apply_rows<float, 16>, (const void*)k_dense_apply_rows<double, 4>,
+  const void* fns[] = {(const void*)k_dense_apply_x<4>, (const void*)k_dense_apply_x<8>,
+                       (const void*)k_dense_apply<double, 4>,      (const void*)k_dense_apply<double, 8>,
+                       (const void*)k_dense_apply<double, 16>,     (const void*)k_dense_apply_rows<double, 4>,
                        (const void*)k_dense_apply_rows<double, 8>, (const void*)k_dense_apply_rows<double, 16>};
   for (const void* fn : fns) {
     const hipError_t e =
@@ -847,19 +988,34 @@ hipError_t prepare_dense_apply() {
   return hipSuccess;
 }
 
+// FP32 factors with FP64 arithmetic: chunks of 4 vectors
+// (chunks of 8 when more than 4 vectors and their LDS fits: one read of each
+// factor per 8 vectors)
+hipError_t launch_dense_x(hipStream_t st, const DenseBlocks& D, const double* u, double* y,
+                          const int* done, int nrhs, int n1, int max_nt, int sys_done) {
+  if (nrhs > 4 && dense_multi_lds(8, max_nt, false) <= DENSE_MULTI_LDS) {
+    hipLaunchKernelGGL(k_dense_apply_x<8>, dim3(D.nblk, (nrhs + 7) / 8), dim3(APPLY_THREADS),
+                       dense_multi_lds(8, max_nt, false), st, D, u, y, done, nrhs, n1, sys_done);
+  } else {
+    hipLaunchKernelGGL(k_dense_apply_x<4>, dim3(D.nblk, (nrhs + 3) / 4), dim3(APPLY_THREADS),
+                       dense_multi_lds(4, max_nt, false), st, D, u, y, done, nrhs, n1, sys_done);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_dense_apply_multi(hipStream_t st, const DenseBlocks& D, bool mixed,
                                     const double* u, double* y, const int* done, int nrhs, int n1,
                                     int max_nt) {
   if (D.nblk == 0 || nrhs <= 0) return hipSuccess;
-  if (dense_multi_lds(4, max_nt, mixed) > DENSE_MULTI_LDS) return hipErrorInvalidValue;
-  return mixed ? launch_dense_multi_t<float>(st, D, u, y, done, nrhs, n1, max_nt, 0)
+  if (dense_multi_lds(4, max_nt, false) > DENSE_MULTI_LDS) return hipErrorInvalidValue;
+  return mixed ? launch_dense_x(st, D, u, y, done, nrhs, n1, max_nt, 0)
                : launch_dense_multi_t<double>(st, D, u, y, done, nrhs, n1, max_nt, 0);
 }
 
 hipError_t launch_dense_apply(hipStream_t st, const DenseBlocks& D, bool mixed, const double* u,
                               double* y, const int* done, int max_nt) {
   if (D.nblk == 0) return hipSuccess;
-  if (dense_multi_lds(4, max_nt, mixed) > DENSE_MULTI_LDS) return hipErrorInvalidValue;
-  return mixed ? launch_dense_multi_t<float>(st, D, u, y, done, 1, 0, max_nt, 1)
+  if (dense_multi_lds(4, max_nt, false) > DENSE_MULTI_LDS) return hipErrorInvalidValue;
+  return mixed ? launch_dense_x(st, D, u, y, done, 1, 0, max_nt, 1)
                : launch_dense_multi_t<double>(st, D, u, y, done, 1, 0, max_nt, 1);
 }
