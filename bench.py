@@ -648,8 +648,8 @@ def main():
         # the precision pattern on the same matrices, batched against batched
         mb = mixed_batched(wl, f)
         mb["speedup_vs_fp64_batched"] = line["time_to_tol_ms"] / mb["time_to_tol_ms"]
-        mb["mode"] = ("bc_solve_batched with FP32 banded applies (FP64 factorization, sparse "
-                      "products, outer CG scalars and true-residual replacement)")
+        mb["mode"] = ("bc_solve_batched with FP32 copies of the banded factors applied in FP64 "
+                      "arithmetic (FP64 factorization, sparse products and outer CG)")
         line["mixed_batched"] = mb
     if not args.no_rip:
         line["rip_graph_st27_100cubed"] = rip_graph_bench()

@@ -65,9 +65,12 @@ typedef struct {
   int32_t precision;      /* BC_FP64 (default); BC_MIXED: FP32 sparse products
                              and projections, FP64 outer CG scalars, x and
                              residuals, stop test on the FP64 true residual at
-                             each replacement; BC_MIXED_PROJ: FP64 sparse
-                             products, FP32 projections (dense factor copies /
-                             inner CG), FP64 everything else */
+                             each replacement; BC_MIXED_PROJ: FP32 copies of
+                             the projection operators (dense and banded
+                             factors, the inner-CG block matrices) applied
+                             with FP64 arithmetic, FP64 everything else (the
+                             operator is the same at every application, so no
+                             replacement is made) */
   int32_t projection;     /* How y_i = (A_i A_i^T)^{-1} u_i is computed per block.
                              BC_PROJ_DENSE_CHOL: dense FP64 Cholesky factor
                              (blocks of at most 4096 rows); BC_PROJ_INNER_CG:
@@ -235,8 +238,8 @@ bc_status bc_solve_multi(bc_ctx* ctx, int32_t nrhs, const double* f, const doubl
  * span of those before it is below 1e-5 of its norm being dropped (repeated
  * or dependent right-hand sides).  The products with H take all p
  * directions at once (as bc_solve_multi); the p x p algebra runs on the host
- * in FP64 between device reductions.  With FP32 projections (BC_MIXED,
- * BC_MIXED_PROJ) R is recomputed from the FP64 true residual every
+ * in FP64 between device reductions.  With FP32 sparse products and
+ * projections (BC_MIXED) R is recomputed from the FP64 true residual every
  * replace_every iterations, R = A^T D^{-1} (f - A x), and the directions
  * restart from it (stats.replacements counts these).  Arguments and layout as
  * bc_solve_multi; stats[j].iterations counts the block iterations until

@@ -23,7 +23,7 @@ hipError_t launch_gram(hipStream_t st, const DenseBlocks& D, const int4* tiles, 
                        const int* rowptr, const int* col, const double* val, const int* tptr,
                        const int* trow, const double* tval);
 int inner_max_resident_groups(bool mixed);
-int inner_grp_max_resident(bool mixed, int max_m);
+int inner_grp_max_resident(bool f32_vectors, int max_m);
 hipError_t rip_launch_prescale(hipStream_t st, int n, const int* rowptr, double* aval,
                                double* nrm, int* zero_row);
 size_t rip_transpose_temp_bytes(int n, long long nnz);
@@ -185,6 +185,7 @@ struct bc_ctx {
   bool timing = false;
   bool noalloc = false;  // solve without any allocation (bc_solve_noalloc): no graphs, no events
   bool mixed = false;     // FP32 projections (BC_MIXED or BC_MIXED_PROJ)
+  InnerPrec inner_prec = INNER_F64;
   bool spmv32 = false;    // FP32 sparse products (BC_MIXED)
   int nsys = 0;
   int n_total = 0;
@@ -498,6 +499,11 @@ int block_rcm(const SysIn& S, int off, const int* rows, int m, std::vector<int>&
 bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   const bc_opts& o = c->opts;
   c->mixed = o.precision == BC_MIXED || o.precision == BC_MIXED_PROJ;
+  // inner CG: FP32 throughout with FP32 sparse products; with FP64 products
+  // FP64 vectors and arithmetic on FP32 copies of the block matrices
+  c->inner_prec = o.precision == BC_MIXED        ? INNER_F32
+                  : o.precision == BC_MIXED_PROJ ? INNER_F64_V32
+                                                 : INNER_F64;
   c->spmv32 = o.precision == BC_MIXED;
   c->nsys = (int)sys.size();
   // ---- sizes
@@ -889,7 +895,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     B.btptr = pbp; B.btrow = pbr; B.btval = pbv;
     const int sup_total = (int)btptr.size() - 1;
     c->inner_sup_total = sup_total;
-    if (c->mixed) {
+    if (c->inner_prec == INNER_F32) {
       std::vector<float> b32(btval.begin(), btval.end());
       float* pb32;
       BC_TRY(A.upload(&pb32, b32, st));
@@ -1013,10 +1019,10 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     }
     G = std::min(G, 16);
     // the group kernel keeps two full block vectors in LDS
-    if ((size_t)2 * ((B.max_m + 1) / 2 * 2) * (c->mixed ? 4 : 8) > 150 * 1024) G = 1;
+    if ((size_t)2 * ((B.max_m + 1) / 2 * 2) * (c->inner_prec == INNER_F32 ? 4 : 8) > 150 * 1024) G = 1;
     if (G > 1) {
       const int per_xcd = (B.nblk + 7) / 8;
-      const int cap = inner_grp_max_resident(c->mixed, B.max_m);
+      const int cap = inner_grp_max_resident(c->inner_prec == INNER_F32, B.max_m);
       while (G > 1 && per_xcd * G * 8 > cap) --G;
     }
     B.groups = G;
@@ -1045,7 +1051,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
     BC_HIP(hipMemsetAsync(pbt, 0, B.nblk * sizeof(unsigned long long), st));
     B.blk_total = pbt;
     // FP32 inner CG cannot resolve residuals far below its unit roundoff
-    B.tol = (c->mixed && o.inner_tol < 1e-6) ? 1e-6 : o.inner_tol;
+    B.tol = (c->inner_prec == INNER_F32 && o.inner_tol < 1e-6) ? 1e-6 : o.inner_tol;
     B.maxit = o.inner_maxit;
   }
   // dense blocks
@@ -1372,17 +1378,17 @@ bc_status block_solves(bc_ctx* c, const double* u, double* y, const int* done) {
     BC_HIP(launch_band_apply_multi(st, c->band, c->mixed, u, y, done, nr, n1));
     bool taken = false;
     MultiView* mv = c->mview.get();
-    BC_HIP(launch_inner_cg_multi(st, c->inner, c->mixed, u, y, done, nr, n1, c->inner_sup_total,
+    BC_HIP(launch_inner_cg_multi(st, c->inner, c->inner_prec, u, y, done, nr, n1, c->inner_sup_total,
                                  mv ? mv->d_inner_r : nullptr, mv ? mv->d_inner_t : nullptr,
                                  &taken));
     for (int j = 0; j < nr && !taken; ++j) {
       const size_t o = (size_t)j * n1;
-      BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u + o, y + o, done ? done + j : nullptr));
+      BC_HIP(launch_inner_cg(st, c->inner, c->inner_prec, u + o, y + o, done ? done + j : nullptr));
     }
   } else {
     BC_HIP(launch_dense_apply(st, c->dense, c->mixed, u, y, done, c->dense_max_nt));
     BC_HIP(launch_band_apply(st, c->band, c->mixed, u, y, done));
-    BC_HIP(launch_inner_cg(st, c->inner, c->mixed, u, y, done));
+    BC_HIP(launch_inner_cg(st, c->inner, c->inner_prec, u, y, done));
   }
   if (c->timing) {
     BC_HIP(hipEventRecord(c->ev_proj[2 * c->ev_used + 1], st));
@@ -1449,8 +1455,10 @@ bc_status proj_bytes(bc_ctx* c, double* out) {
   if (c->inner.nblk) {
     std::vector<unsigned long long> it(c->inner.nblk);
     BC_HIP(hipMemcpy(it.data(), c->inner.blk_total, it.size() * sizeof(it[0]), hipMemcpyDeviceToHost));
+    // stored values w bytes; vectors FP32 only in the FP32 inner CG
+    const double wx = c->inner_prec == INNER_F32 ? 4.0 : 8.0;
     for (int b = 0; b < c->inner.nblk; ++b)
-      bytes += (double)it[b] * (2.0 * (w + 4.0) * (double)c->in_nnz[b] + 6.0 * w * (double)c->in_m_h[b]);
+      bytes += (double)it[b] * (2.0 * (w + 4.0) * (double)c->in_nnz[b] + 6.0 * wx * (double)c->in_m_h[b]);
   }
   if (c->dense.nblk) {
     std::vector<unsigned long long> ap(c->dense.nblk);
@@ -1675,9 +1683,12 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
   BC_HIP(launch_init_cg(st, c->d_p, c->d_r, S));
 
   // Outer iterations run in groups of G between host checks; with FP32
-  // projections G divides replace_every, so replacements fall between groups.
+  // sparse products and inner CG (BC_MIXED) G divides replace_every, so
+  // replacements fall between groups.  BC_MIXED_PROJ applies its FP32 operator
+  // copies in FP64 arithmetic: the operator is the same at every application
+  // and the FP64 recursion needs no replacement.
   int G = std::max(1, o.check_every);
-  if (c->mixed && o.replace_every > 0) G = std::gcd(G, o.replace_every);
+  if (c->spmv32 && o.replace_every > 0) G = std::gcd(G, o.replace_every);
   const bool graphs = o.use_graph && c->inner.nblk == 0 && !c->graph_off && c->mrhs.nrhs == 0 &&
                       !c->noalloc;
   std::vector<int> done(ns, 0), status(ns, 0), iters(ns, 0);
@@ -1699,7 +1710,7 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
         BC_TRY(outer_iteration(c, x, S, true));
       }
     }
-    if (c->mixed && o.replace_every > 0 && it % o.replace_every == 0) {
+    if (c->spmv32 && o.replace_every > 0 && it % o.replace_every == 0) {
       // FP64 true residual s = f - A x (and, with FP32 sparse products, the
       // stop test on it), then r = A^T D^{-1} s through the working-precision
       // projections.  With factor-based projections the FP32 operator is the
@@ -1707,9 +1718,9 @@ bc_status solve_impl(bc_ctx* c, const double* f, const double* x0, double tol, i
       // direction is kept (a reliable update), unless the new residual is
       // more than twice the recursive one (the recursion had drifted: near
       // the attainable accuracy of the FP32 operator), where CG restarts.
-      // With inner-CG projections the operator changes from one application
-      // to the next, and CG always restarts with p = r: each cycle is then a
-      // defect correction of x by replace_every CG steps.
+      // With (FP32) inner-CG projections the operator changes from one
+      // application to the next, and CG always restarts with p = r: each
+      // cycle is then a defect correction of x by replace_every CG steps.
       BC_HIP(residual_a(c, st, c->lanes, x, c->d_f, c->d_s, S, nullptr));
       if (c->spmv32) BC_HIP(launch_true_check(st, S));
       BC_TRY(block_solves(c, c->d_s, c->d_y, c->d_done));
@@ -2410,7 +2421,7 @@ bc_status block_cg_impl(bc_ctx* c, const double* f, const double* x0, double tol
       act = still;
       if (act.empty()) break;
       const int a2 = (int)act.size();
-      if (c->mixed && o.replace_every > 0 && t % o.replace_every == 0) {
+      if (c->spmv32 && o.replace_every > 0 && t % o.replace_every == 0) {
         // FP32 projections: the recursive R drifts from Xi - H X by the
         // rounding of the FP32 operator, so every replace_every iterations R
         // is recomputed from the true residual, R = A^T D^{-1} s, and the

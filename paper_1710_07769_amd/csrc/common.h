@@ -287,9 +287,13 @@ struct InnerBlocks {
   const double* t_val;
   const float* t_val32;
 };
-hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, const double* u,
+// Precision of the inner CG: FP64 throughout; FP32 throughout (vectors,
+// values, arithmetic); or FP64 vectors and arithmetic on the FP32 copies of
+// the block matrix values.
+enum InnerPrec { INNER_F64 = 0, INNER_F32 = 1, INNER_F64_V32 = 2 };
+hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, InnerPrec prec, const double* u,
                            double* y, const int* done);
-hipError_t launch_inner_cg_multi(hipStream_t st, const InnerBlocks& B, bool mixed,
+hipError_t launch_inner_cg_multi(hipStream_t st, const InnerBlocks& B, InnerPrec prec,
                                  const double* u, double* y, const int* done, int nrhs, int n1,
                                  int sup_total, void* rs, void* ts, bool* taken);
 

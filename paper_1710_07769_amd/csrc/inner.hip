@@ -57,13 +57,15 @@ __device__ __forceinline__ const double* sel_val<double>(const double* d, const 
 template <>
 __device__ __forceinline__ const float* sel_val<float>(const double*, const float* f) { return f; }
 
-template <typename T, typename IX>
-__device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const T* __restrict__ val,
+// T: vector and arithmetic type; TV: stored matrix values (float values with
+// double arithmetic are converted exactly before each product).
+template <typename T, typename TV, typename IX>
+__device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const TV* __restrict__ val,
                                       long long e, int w, const T* __restrict__ x, T acc = (T)0) {
   int k0 = 0;
   for (; k0 + 8 <= w; k0 += 8) {
     IX ix[8];
-    T vv[8];
+    TV vv[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       ix[k] = idx[e + (long long)(k0 + k) * 64];
@@ -73,19 +75,19 @@ __device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const T* __res
 #pragma unroll
     for (int k = 0; k < 8; ++k) xv[k] = x[ix[k]];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc += vv[k] * xv[k];
+    for (int k = 0; k < 8; ++k) acc += (T)vv[k] * xv[k];
   }
-  for (; k0 < w; ++k0) acc += val[e + (long long)k0 * 64] * x[idx[e + (long long)k0 * 64]];
+  for (; k0 < w; ++k0) acc += (T)val[e + (long long)k0 * 64] * x[idx[e + (long long)k0 * 64]];
   return acc;
 }
 
 // Two 8-wide slices at once: 32 independent loads per lane in flight.
-template <typename T, typename IX>
-__device__ __forceinline__ void two_slices8(const IX* __restrict__ idx, const T* __restrict__ val,
+template <typename T, typename TV, typename IX>
+__device__ __forceinline__ void two_slices8(const IX* __restrict__ idx, const TV* __restrict__ val,
                                             long long e1, long long e2, const T* __restrict__ x,
                                             T& a1, T& a2) {
   IX i1[8], i2[8];
-  T v1[8], v2[8];
+  TV v1[8], v2[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     i1[k] = idx[e1 + k * 64];
@@ -96,8 +98,8 @@ __device__ __forceinline__ void two_slices8(const IX* __restrict__ idx, const T*
   T s1 = (T)0, s2 = (T)0;
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
-    s1 += v1[k] * x[i1[k]];
-    s2 += v2[k] * x[i2[k]];
+    s1 += (T)v1[k] * x[i1[k]];
+    s2 += (T)v2[k] * x[i2[k]];
   }
   a1 = s1;
   a2 = s2;
@@ -109,7 +111,7 @@ __device__ __forceinline__ void two_slices8(const IX* __restrict__ idx, const T*
 // vector j, whose u, y and residual scratch sit at offset j * vs and whose
 // support scratch (when t is not in LDS) at j * tstr; done[sys + j] is its
 // flag.  One vector: gridDim.y = 1, vs = tstr = 0.
-template <typename T, typename IX, int RPT, bool TLDS>
+template <typename T, typename TV, typename IX, int RPT, bool TLDS>
 __global__ void __launch_bounds__(WG_THREADS)
 k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
              const int* __restrict__ done, int qcap, int tcap, int dcap, long long vs,
@@ -131,8 +133,8 @@ k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y
   const int lane = threadIdx.x & 63;
   const IX* __restrict__ aidx = reinterpret_cast<const IX*>(B.a_idx);
   const IX* __restrict__ tidx = reinterpret_cast<const IX*>(B.t_idx);
-  const T* __restrict__ aval = sel_val<T>(B.a_val, B.a_val32);
-  const T* __restrict__ tval = sel_val<T>(B.t_val, B.t_val32);
+  const TV* __restrict__ aval = sel_val<TV>(B.a_val, B.a_val32);
+  const TV* __restrict__ tval = sel_val<TV>(B.t_val, B.t_val32);
   const int nsa = (m + 63) >> 6, nst = (ns + 63) >> 6;
   constexpr int NW = WG_THREADS / 64;
   T* __restrict__ rg = Vec<T>::r(B) + (long long)j * vs + row0;   // residual of the block
@@ -177,14 +179,14 @@ k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y
         const int w1 = dw[nsa + s];
         if (s2 < nst && w1 == 8 && dw[nsa + s2] == 8) {
           T a1, a2;
-          two_slices8<T, IX>(tidx, tval, e1, dptr[nsa + s2] + lane, qs, a1, a2);
+          two_slices8<T, TV, IX>(tidx, tval, e1, dptr[nsa + s2] + lane, qs, a1, a2);
           if (s * 64 + lane < ns) ts[s * 64 + lane] = a1;
           if (s2 * 64 + lane < ns) ts[s2 * 64 + lane] = a2;
         } else {
-          const T a1 = sell_row<T, IX>(tidx, tval, e1, w1, qs);
+          const T a1 = sell_row<T, TV, IX>(tidx, tval, e1, w1, qs);
           if (s * 64 + lane < ns) ts[s * 64 + lane] = a1;
           if (s2 < nst) {
-            const T a2 = sell_row<T, IX>(tidx, tval, dptr[nsa + s2] + lane, dw[nsa + s2], qs);
+            const T a2 = sell_row<T, TV, IX>(tidx, tval, dptr[nsa + s2] + lane, dw[nsa + s2], qs);
             if (s2 * 64 + lane < ns) ts[s2 * 64 + lane] = a2;
           }
         }
@@ -198,10 +200,10 @@ k_inner_sell(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y
         if (s < nsa) {
           T a1 = (T)0, a2 = (T)0;
           if (k + 1 < RPT && s2 < nsa && dw[s] == 8 && dw[s2] == 8) {
-            two_slices8<T, IX>(aidx, aval, dptr[s] + lane, dptr[s2] + lane, ts, a1, a2);
+            two_slices8<T, TV, IX>(aidx, aval, dptr[s] + lane, dptr[s2] + lane, ts, a1, a2);
           } else {
-            a1 = sell_row<T, IX>(aidx, aval, dptr[s] + lane, dw[s], ts);
-            if (k + 1 < RPT && s2 < nsa) a2 = sell_row<T, IX>(aidx, aval, dptr[s2] + lane, dw[s2], ts);
+            a1 = sell_row<T, TV, IX>(aidx, aval, dptr[s] + lane, dw[s], ts);
+            if (k + 1 < RPT && s2 < nsa) a2 = sell_row<T, TV, IX>(aidx, aval, dptr[s2] + lane, dw[s2], ts);
           }
           const int i1 = s * 64 + lane, i2 = s2 * 64 + lane;
           if (i1 < m) {
@@ -257,25 +259,25 @@ struct VecSet {
   long long vs, tstr;
 };
 
-template <typename T, typename IX, int RPT>
+template <typename T, typename TV, typename IX, int RPT>
 hipError_t launch_sell(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
                        const int* done, int qcap, int tcap, int dcap, bool tlds, size_t lds,
                        const VecSet& V) {
-  const void* fn = tlds ? (const void*)k_inner_sell<T, IX, RPT, true>
-                        : (const void*)k_inner_sell<T, IX, RPT, false>;
+  const void* fn = tlds ? (const void*)k_inner_sell<T, TV, IX, RPT, true>
+                        : (const void*)k_inner_sell<T, TV, IX, RPT, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const dim3 grid(B.nblk, V.nv);
   if (tlds)
-    hipLaunchKernelGGL((k_inner_sell<T, IX, RPT, true>), grid, dim3(WG_THREADS), lds, st, B, u, y,
+    hipLaunchKernelGGL((k_inner_sell<T, TV, IX, RPT, true>), grid, dim3(WG_THREADS), lds, st, B, u, y,
                        done, qcap, tcap, dcap, V.vs, V.tstr);
   else
-    hipLaunchKernelGGL((k_inner_sell<T, IX, RPT, false>), grid, dim3(WG_THREADS), lds, st, B, u,
+    hipLaunchKernelGGL((k_inner_sell<T, TV, IX, RPT, false>), grid, dim3(WG_THREADS), lds, st, B, u,
                        y, done, qcap, tcap, dcap, V.vs, V.tstr);
   return hipGetLastError();
 }
 
-template <typename T, typename IX>
+template <typename T, typename TV, typename IX>
 hipError_t launch_sell_rows(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
                             const int* done, const VecSet& V = VecSet{1, 0, 0}) {
   const int rpt = (B.max_m + WG_THREADS - 1) / WG_THREADS;
@@ -287,12 +289,12 @@ hipError_t launch_sell_rows(hipStream_t st, const InnerBlocks& B, const double* 
   const size_t lds_budget = 160 * 1024 - (WG_THREADS / 64) * sizeof(double) - 256;
   const bool tlds = (size_t)(qcap + tcap) * sizeof(T) + dbytes <= lds_budget;
   const size_t lds = (size_t)(qcap + (tlds ? tcap : 0)) * sizeof(T) + dbytes;
-  if (rpt <= 4) return launch_sell<T, IX, 4>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
-  if (rpt <= 8) return launch_sell<T, IX, 8>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
-  if (rpt <= 9) return launch_sell<T, IX, 9>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
-  if (rpt <= 10) return launch_sell<T, IX, 10>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
-  if (rpt <= 12) return launch_sell<T, IX, 12>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
-  return launch_sell<T, IX, 16>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 4) return launch_sell<T, TV, IX, 4>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 8) return launch_sell<T, TV, IX, 8>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 9) return launch_sell<T, TV, IX, 9>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 10) return launch_sell<T, TV, IX, 10>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  if (rpt <= 12) return launch_sell<T, TV, IX, 12>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
+  return launch_sell<T, TV, IX, 16>(st, B, u, y, done, qcap, tcap, dcap, tlds, lds, V);
 }
 
 // ------------------------------------------------------------------------
@@ -417,7 +419,7 @@ __device__ __forceinline__ bool get_tagged2(const unsigned long long* p, bool ac
   }
 }
 
-template <typename T, typename IX, int RPT>
+template <typename T, typename TV, typename IX, int RPT>
 __global__ void __launch_bounds__(GRP_THREADS)
 k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
             const int* __restrict__ done, int rcap, int* err) {
@@ -445,8 +447,8 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   constexpr int NW = GRP_THREADS / 64;
   const IX* __restrict__ aidx = reinterpret_cast<const IX*>(B.a_idx);
   const IX* __restrict__ tidx = reinterpret_cast<const IX*>(B.t_idx);
-  const T* __restrict__ aval = sel_val<T>(B.a_val, B.a_val32);
-  const T* __restrict__ tval = sel_val<T>(B.t_val, B.t_val32);
+  const TV* __restrict__ aval = sel_val<TV>(B.a_val, B.a_val32);
+  const TV* __restrict__ tval = sel_val<TV>(B.t_val, B.t_val32);
   const long long* __restrict__ aptr = B.a_ptr + B.a_s0[b];
   const int* __restrict__ aw = B.a_w + B.a_s0[b];
   const long long* __restrict__ tptr = B.t_ptr + B.t_s0[b];
@@ -459,9 +461,9 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   // wavefront and all its own row slices
   const long long abase = aptr[0], tbase = tptr[0];
   const IX* __restrict__ aidxb = aidx + abase;
-  const T* __restrict__ avalb = aval + abase;
+  const TV* __restrict__ avalb = aval + abase;
   const IX* __restrict__ tidxb = tidx + tbase;
-  const T* __restrict__ tvalb = tval + tbase;
+  const TV* __restrict__ tvalb = tval + tbase;
   int ea[RPT], et[RPT];
   int wa[RPT], wt[RPT];
 #pragma unroll
@@ -547,12 +549,12 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
           // here rather than held across the whole loop
           int e = et[k];
           asm volatile("" : "+v"(e));
-          tacc[k] = sell_row<T, IX>(tidxb, tvalb, e, wt[k], rs);
+          tacc[k] = sell_row<T, TV, IX>(tidxb, tvalb, e, wt[k], rs);
           if (!DEFER && c * 64 + lane < ns) tg[c * 64 + lane] = tacc[k];
         }
       }
       for (int c = st0 + wave + RPT * NW; c < st1; c += NW) {
-        const T acc = sell_row<T, IX>(tidx, tval, tptr[c] + lane, tw[c], rs);
+        const T acc = sell_row<T, TV, IX>(tidx, tval, tptr[c] + lane, tw[c], rs);
         if (c * 64 + lane < ns) tg[c * 64 + lane] = acc;
       }
 #pragma unroll
@@ -578,7 +580,7 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
           int k0 = 0;
           for (; k0 + 8 <= ww; k0 += 8) {
             IX ix[8];
-            T vv[8];
+            TV vv[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
               ix[q] = aidxb[e + (k0 + q) * 64];
@@ -588,9 +590,9 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
 #pragma unroll
             for (int q = 0; q < 8; ++q) tv[q] = agent_load<T>(&tg[ix[q]]);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc += vv[q] * tv[q];
+            for (int q = 0; q < 8; ++q) acc += (T)vv[q] * tv[q];
           }
-          for (; k0 < ww; ++k0) acc += avalb[e + k0 * 64] * agent_load<T>(&tg[aidxb[e + k0 * 64]]);
+          for (; k0 < ww; ++k0) acc += (T)avalb[e + k0 * 64] * agent_load<T>(&tg[aidxb[e + k0 * 64]]);
           const int i = s * 64 + lane;
           if (DEFER)
             wacc[k] = acc;
@@ -730,12 +732,12 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
   }
 }
 
-template <typename T, typename IX, int RPT>
+template <typename T, typename TV, typename IX, int RPT>
 hipError_t launch_grp_t(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
                         const int* done, int* err) {
   const int rcap = (B.max_m + 1) / 2 * 2;
   const size_t lds = (size_t)2 * rcap * sizeof(T);
-  const void* fn = (const void*)k_inner_grp<T, IX, RPT>;
+  const void* fn = (const void*)k_inner_grp<T, TV, IX, RPT>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int per_xcd = (B.nblk + NXCD - 1) / NXCD;
@@ -746,37 +748,41 @@ hipError_t launch_grp_t(hipStream_t st, const InnerBlocks& B, const double* u, d
   return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(GRP_THREADS), args, lds, st);
 }
 
-template <typename T, typename IX>
+template <typename T, typename TV, typename IX>
 hipError_t launch_grp(hipStream_t st, const InnerBlocks& B, const double* u, double* y,
                       const int* done, int* err) {
   // own row slices per workgroup, spread over the 16 wavefronts
   const int nsa_max = (B.max_m + 63) / 64;
   const int own = (nsa_max + B.groups - 1) / B.groups;
   const int rpt = (own + 15) / 16;
-  if (rpt <= 1) return launch_grp_t<T, IX, 1>(st, B, u, y, done, err);
-  if (rpt <= 2) return launch_grp_t<T, IX, 2>(st, B, u, y, done, err);
-  if (rpt <= 4) return launch_grp_t<T, IX, 4>(st, B, u, y, done, err);
-  return launch_grp_t<T, IX, 8>(st, B, u, y, done, err);
+  if (rpt <= 1) return launch_grp_t<T, TV, IX, 1>(st, B, u, y, done, err);
+  if (rpt <= 2) return launch_grp_t<T, TV, IX, 2>(st, B, u, y, done, err);
+  if (rpt <= 4) return launch_grp_t<T, TV, IX, 4>(st, B, u, y, done, err);
+  return launch_grp_t<T, TV, IX, 8>(st, B, u, y, done, err);
 }
 
 }  // namespace
 
-hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, const double* u,
+// The kernel pair for the context's precision and index width.
+template <typename IX>
+hipError_t launch_inner_ix(hipStream_t st, const InnerBlocks& B, InnerPrec prec, const double* u,
+                           double* y, const int* done) {
+  if (B.groups > 1) {
+    int* err = B.err;
+    if (prec == INNER_F32) return launch_grp<float, float, IX>(st, B, u, y, done, err);
+    if (prec == INNER_F64_V32) return launch_grp<double, float, IX>(st, B, u, y, done, err);
+    return launch_grp<double, double, IX>(st, B, u, y, done, err);
+  }
+  if (prec == INNER_F32) return launch_sell_rows<float, float, IX>(st, B, u, y, done);
+  if (prec == INNER_F64_V32) return launch_sell_rows<double, float, IX>(st, B, u, y, done);
+  return launch_sell_rows<double, double, IX>(st, B, u, y, done);
+}
+
+hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, InnerPrec prec, const double* u,
                            double* y, const int* done) {
   if (B.nblk == 0) return hipSuccess;
-  int* err = B.err;
-  if (B.groups > 1) {
-    if (B.idx16)
-      return mixed ? launch_grp<float, uint16_t>(st, B, u, y, done, err)
-                   : launch_grp<double, uint16_t>(st, B, u, y, done, err);
-    return mixed ? launch_grp<float, int>(st, B, u, y, done, err)
-                 : launch_grp<double, int>(st, B, u, y, done, err);
-  }
-  if (B.idx16)
-    return mixed ? launch_sell_rows<float, uint16_t>(st, B, u, y, done)
-                 : launch_sell_rows<double, uint16_t>(st, B, u, y, done);
-  return mixed ? launch_sell_rows<float, int>(st, B, u, y, done)
-               : launch_sell_rows<double, int>(st, B, u, y, done);
+  return B.idx16 ? launch_inner_ix<uint16_t>(st, B, prec, u, y, done)
+                 : launch_inner_ix<int>(st, B, prec, u, y, done);
 }
 
 // nrhs vectors of a one-system context in one launch of the single-workgroup
@@ -787,7 +793,7 @@ hipError_t launch_inner_cg(hipStream_t st, const InnerBlocks& B, bool mixed, con
 // vectors reach the CUs, where concurrent single-workgroup solves beat the
 // grouped ones run one vector after another; *taken = false leaves the
 // vectors to the caller.
-hipError_t launch_inner_cg_multi(hipStream_t st, const InnerBlocks& B, bool mixed,
+hipError_t launch_inner_cg_multi(hipStream_t st, const InnerBlocks& B, InnerPrec prec,
                                  const double* u, double* y, const int* done, int nrhs, int n1,
                                  int sup_total, void* rs, void* ts, bool* taken) {
   *taken = false;
@@ -805,7 +811,7 @@ hipError_t launch_inner_cg_multi(hipStream_t st, const InnerBlocks& B, bool mixe
   if (!rs || !ts || nrhs < 1 || nrhs > 65535) return hipSuccess;
   if (B.groups > 1 && (long long)nrhs * B.nblk < ncu) return hipSuccess;
   InnerBlocks Bm = B;
-  if (mixed) {
+  if (prec == INNER_F32) {
     Bm.ri32 = static_cast<float*>(rs);
     Bm.t32 = static_cast<float*>(ts);
   } else {
@@ -814,21 +820,24 @@ hipError_t launch_inner_cg_multi(hipStream_t st, const InnerBlocks& B, bool mixe
   }
   const VecSet V{nrhs, (long long)n1, (long long)sup_total};
   *taken = true;
-  if (B.idx16)
-    return mixed ? launch_sell_rows<float, uint16_t>(st, Bm, u, y, done, V)
-                 : launch_sell_rows<double, uint16_t>(st, Bm, u, y, done, V);
-  return mixed ? launch_sell_rows<float, int>(st, Bm, u, y, done, V)
-               : launch_sell_rows<double, int>(st, Bm, u, y, done, V);
+  if (B.idx16) {
+    if (prec == INNER_F32) return launch_sell_rows<float, float, uint16_t>(st, Bm, u, y, done, V);
+    if (prec == INNER_F64_V32) return launch_sell_rows<double, float, uint16_t>(st, Bm, u, y, done, V);
+    return launch_sell_rows<double, double, uint16_t>(st, Bm, u, y, done, V);
+  }
+  if (prec == INNER_F32) return launch_sell_rows<float, float, int>(st, Bm, u, y, done, V);
+  if (prec == INNER_F64_V32) return launch_sell_rows<double, float, int>(st, Bm, u, y, done, V);
+  return launch_sell_rows<double, double, int>(st, Bm, u, y, done, V);
 }
 
-int inner_grp_max_resident(bool mixed, int max_m) {
+int inner_grp_max_resident(bool f32_vectors, int max_m) {
   int dev = 0, ncu = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
   const int rcap = (max_m + 1) / 2 * 2;
-  const size_t lds = (size_t)2 * rcap * (mixed ? sizeof(float) : sizeof(double));
-  const void* fn = mixed ? (const void*)k_inner_grp<float, uint16_t, 2>
-                         : (const void*)k_inner_grp<double, uint16_t, 2>;
+  const size_t lds = (size_t)2 * rcap * (f32_vectors ? sizeof(float) : sizeof(double));
+  const void* fn = f32_vectors ? (const void*)k_inner_grp<float, float, uint16_t, 2>
+                               : (const void*)k_inner_grp<double, double, uint16_t, 2>;
   if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, GRP_THREADS, lds) != hipSuccess)

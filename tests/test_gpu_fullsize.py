@@ -143,12 +143,28 @@ def test_multilevel_partition_cd3d_64cubed(dev, golden):
     assert partition_hash(part) == golden["cfg2"]["partition_ml_sha"]
 
 
-def test_solve_cd3d_64cubed_inner_cg(dev, golden):
-    banner("FP64 inner-CG solve, 64^3 convection-diffusion, K=32 greedy partition")
+@pytest.mark.parametrize("precision", ["fp64", "fp32-values"])
+def test_solve_cd3d_64cubed_inner_cg(dev, golden, precision):
+    banner("inner-CG solve, 64^3 convection-diffusion, K=32 greedy partition (%s)" % precision)
     p = config2()
-    solver = bc.BlockCimmino(p.A, cfg2_partition(), p.K, projection=bc.BC_PROJ_INNER_CG)
+    prec = bc.BC_FP64 if precision == "fp64" else bc.BC_MIXED_PROJ
+    solver = bc.BlockCimmino(p.A, cfg2_partition(), p.K, projection=bc.BC_PROJ_INNER_CG,
+                             precision=prec)
     try:
-        check_fp64_count_and_iterate(dev, solver, to_dev(p.f, dev), golden["cfg2"], p.A)
+        f = to_dev(p.f, dev)
+        ref = golden["cfg2"]
+        if precision == "fp64":
+            check_fp64_count_and_iterate(dev, solver, f, ref, p.A)
+        else:
+            # FP64 inner CG on the FP32 copies of the block matrices: the
+            # operator is a fixed SPD perturbation of H with the same solution
+            x, st = solver.solve(f, tol=1e-10, maxit=20000)
+            err = sample_err(x.cpu().numpy(), ref)
+            print("iterations gpu=%d oracle(FP64)=%d sampled err vs oracle=%.2e"
+                  % (st.iterations, ref["iterations"], err))
+            assert st.status == bc.BC_OK and st.rel_residual <= 1e-10 * (1 + 1e-6)
+            assert err <= 1e-6
+            assert abs(st.iterations - ref["iterations"]) <= 0.02 * ref["iterations"]
     finally:
         solver.close()
 

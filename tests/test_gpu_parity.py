@@ -412,8 +412,9 @@ MIXED_CASES = {
     "st27-10-K6-fp32-dense-applies": (lambda: workloads.small_config5(N=10, K=6), 6,
                                       {"projection": bc.BC_PROJ_DENSE_CHOL,
                                        "precision": bc.BC_MIXED_PROJ}),
-    "cd3d-12-K4-fp32-inner": (lambda: workloads.small_config2(N=12, K=4), 4,
-                              {"projection": bc.BC_PROJ_INNER_CG, "precision": bc.BC_MIXED_PROJ}),
+    "cd3d-12-K4-inner-fp32-values": (lambda: workloads.small_config2(N=12, K=4), 4,
+                                     {"projection": bc.BC_PROJ_INNER_CG,
+                                      "precision": bc.BC_MIXED_PROJ}),
     "cd2d-90-K8-fp32-band": (lambda: workloads.small_config4(nsys=1, smin=90, smax=90)[0], 8,
                              {"projection": bc.BC_PROJ_BAND_CHOL, "precision": bc.BC_MIXED}),
 }
