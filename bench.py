@@ -42,6 +42,8 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILES = {
     ("cfg4", "fp64"): "profiles/k_band_sweep_f64_cd2d_batch256_K8.md",
     ("cfg4", "mixed-proj"): "profiles/k_band_sweep_f32_cd2d_batch256_K8.md",
+    ("cfg2", "fp64"): "profiles/k_inner_grp_f64_cd3d_64cubed_K32.md",
+    ("cfg2", "mixed-proj"): "profiles/k_inner_grp_f64v32_cd3d_64cubed_K32.md",
     ("cfg5", "mixed-proj"): "profiles/k_dense_apply_f32_st27_100cubed_K512.md",
     ("cfg5-band", "mixed-proj"): "profiles/k_band_sweep_f32_st27_100cubed_K512.md",
 }
