@@ -103,6 +103,10 @@ def parse():
                          "every right-hand side.  Without it: one bc_solve")
     ap.add_argument("--no-rip", action="store_true",
                     help="skip the rip_graph measurement on the 27-point 100^3 matrix")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only measure what plain device kernels reach against the 8 TB/s "
+                         "datasheet peak (a streaming sum, a device copy, a += b) and print the "
+                         "device properties; no solve")
     ap.add_argument("--compare", action="store_true",
                     help="also time plain FP64 on the same matrices (per system, one after "
                          "another, for a batch) and report the time-to-tolerance ratio")
@@ -525,8 +529,50 @@ def fp64_comparison(wl, f_dev, t_config_ms):
             "mode": "one bc_solve per system, one after another" if wl.batched else "bc_solve"}
 
 
+def hbm_probe():
+    """Bandwidth that plain device kernels reach on this GPU: torch's
+    streaming sum (reads), device copy (read + write) and a += b (two reads,
+    one write), 1 and 4 GiB per operand, median of 10 event-timed runs."""
+    import json
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    out = {"device": p.name, "arch": getattr(p, "gcnArchName", ""),
+           "compute_units": p.multi_processor_count,
+           "memory_GiB": round(p.total_memory / 2**30, 1),
+           "l2_MiB_per_xcd": getattr(p, "L2_cache_size", 0) / 2**20,
+           "datasheet_hbm_GBs": HBM_PEAK_GBS, "rates_GBs": {}}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def med(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(10):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return sorted(ts)[5]
+
+    for gib in (1, 4):
+        n = (gib << 30) // 8
+        a = torch.empty(n, dtype=torch.float64, device="cuda")
+        b = torch.ones(n, dtype=torch.float64, device="cuda")
+        nb = gib * 2**30
+        r = out["rates_GBs"]
+        r["sum_%dGiB" % gib] = round(nb / med(lambda: b.sum()) / 1e6)
+        r["copy_%dGiB" % gib] = round(2 * nb / med(lambda: a.copy_(b)) / 1e6)
+        r["add_%dGiB" % gib] = round(3 * nb / med(lambda: a.add_(b)) / 1e6)
+        del a, b
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.hbm_probe:
+        hbm_probe()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus,
