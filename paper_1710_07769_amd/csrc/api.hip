@@ -878,28 +878,17 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
   B = InnerBlocks{};
   B.nblk = (int)in_m.size();
   if (B.nblk > 0) {
-    int *p0, *p1, *p2, *p3, *p4, *ploc, *pbp, *pbr;
-    double* pbv;
+    int *p0, *p1, *p2, *p3, *p4;
     BC_TRY(A.upload(&p0, in_row0, st));
     BC_TRY(A.upload(&p1, in_m, st));
     BC_TRY(A.upload(&p2, in_sup0, st));
     BC_TRY(A.upload(&p3, in_nsup, st));
     BC_TRY(A.upload(&p4, in_sys, st));
-    BC_TRY(A.upload(&ploc, loc, st));
-    BC_TRY(A.upload(&pbp, btptr, st));
-    BC_TRY(A.upload(&pbr, btrow, st));
-    BC_TRY(A.upload(&pbv, btval, st));
     B.row0 = p0; B.m = p1; B.sup0 = p2; B.nsup = p3; B.sys = p4;
     B.dsc = d_dsc;
-    B.rowptr = c->d_rowptr; B.loc = ploc; B.val = c->d_val; B.val32 = c->d_val32;
-    B.btptr = pbp; B.btrow = pbr; B.btval = pbv;
     const int sup_total = (int)btptr.size() - 1;
     c->inner_sup_total = sup_total;
     if (c->inner_prec == INNER_F32) {
-      std::vector<float> b32(btval.begin(), btval.end());
-      float* pb32;
-      BC_TRY(A.upload(&pb32, b32, st));
-      B.btval32 = pb32;
       BC_TRY(A.alloc(&B.q32, n));
       BC_TRY(A.alloc(&B.z32, n));
       BC_TRY(A.alloc(&B.ri32, n));
@@ -972,15 +961,17 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       }
       int *pas0, *paw, *pts0, *ptw;
       long long *pap, *ptp;
-      double *pav, *ptv;
+      double *pav = nullptr, *ptv = nullptr;
       BC_TRY(A.upload(&pas0, a_s0, st));
       BC_TRY(A.upload(&paw, a_w, st));
       BC_TRY(A.upload(&pap, a_ptr, st));
       BC_TRY(A.upload(&pts0, t_s0, st));
       BC_TRY(A.upload(&ptw, t_w, st));
       BC_TRY(A.upload(&ptp, t_ptr, st));
-      BC_TRY(A.upload(&pav, a_v, st));
-      BC_TRY(A.upload(&ptv, t_v, st));
+      if (c->inner_prec == INNER_F64) {  // (the other precisions read the FP32 copies)
+        BC_TRY(A.upload(&pav, a_v, st));
+        BC_TRY(A.upload(&ptv, t_v, st));
+      }
       if (i16) {
         std::vector<uint16_t> a16(a_ix.begin(), a_ix.end()), t16(t_ix.begin(), t_ix.end());
         uint16_t *pa16, *pt16;
@@ -995,7 +986,7 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
         B.a_idx = pa32;
         B.t_idx = pt32;
       }
-      if (c->mixed) {
+      if (c->inner_prec != INNER_F64) {
         std::vector<float> a32(a_v.begin(), a_v.end()), t32(t_v.begin(), t_v.end());
         float *pa32f, *pt32f;
         BC_TRY(A.upload(&pa32f, a32, st));
@@ -1006,7 +997,6 @@ bc_status setup_impl(bc_ctx* c, const std::vector<SysIn>& sys) {
       B.a_s0 = pas0; B.a_w = paw; B.a_ptr = pap; B.a_val = pav;
       B.t_s0 = pts0; B.t_w = ptw; B.t_ptr = ptp; B.t_val = ptv;
       B.idx16 = i16 ? 1 : 0;
-      B.sell = 1;
       BC_HIP(hipStreamSynchronize(st));  // host staging vectors go out of scope
     }
     // workgroups per block: spread the blocks over the CUs (at most 16 per

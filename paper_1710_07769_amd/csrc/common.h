@@ -243,14 +243,6 @@ struct InnerBlocks {
   const int* sup0;         // first support position
   const int* nsup;         // support size
   const int* sys;          // system of the block
-  const int* rowptr;       // CSR of the permuted A (global)
-  const int* loc;          // support position of each entry (relative to sup0)
-  const double* val;
-  const float* val32;
-  const int* btptr;        // transposed block CSR: per support position
-  const int* btrow;        // local row
-  const double* btval;
-  const float* btval32;
   double* q; double* z; double* ri; double* t;   // scratch (rows / support)
   float* q32; float* z32; float* ri32; float* t32;
   unsigned long long* xp;  // per block 2 x 16 groups x 4 words: the (r,r), (w,r) partials
@@ -264,15 +256,15 @@ struct InnerBlocks {
   int groups;              // workgroups per block
   int max_m;               // largest block
   int max_nsup;            // largest support
-  // Sliced ELL copies (slices of 64 rows / 64 support columns; entry k of
-  // lane l of slice s at ptr[s] + 64 k + l; padding has index 0, value 0)
   unsigned long long* trace; // optional phase timestamps (block 0), null when off
   int* err;                // the context's wait-error word: set to 1 when a workgroup gave up
                            // waiting for the others of its block (the result is then invalid)
   unsigned long long wait_ticks;  // bound of a wait, 100 MHz wall-clock ticks (0: give up at once)
   const double* dsc;       // per permuted row 1/||a_r||_2: the projections solve the
                            // scaled normal equations (D A_i A_i^T D) z = D u, y = D z
-  int sell;                // 1 if built
+  // Sliced ELL copies of the scaled block rows (slices of 64 rows) and of
+  // their transposes (slices of 64 support columns); entry k of lane l of
+  // slice s at ptr[s] + 64 k + l; padding has index 0, value 0
   int idx16;               // indices stored as uint16 (else int32)
   const int* a_s0;         // per block first row slice
   const long long* a_ptr;  // per row slice entry offset

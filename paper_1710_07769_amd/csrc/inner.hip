@@ -32,8 +32,6 @@ struct Vec<double> {
   static __device__ double* z(const InnerBlocks& B) { return B.z; }
   static __device__ double* r(const InnerBlocks& B) { return B.ri; }
   static __device__ double* t(const InnerBlocks& B) { return B.t; }
-  static __device__ const double* v(const InnerBlocks& B) { return B.val; }
-  static __device__ const double* bv(const InnerBlocks& B) { return B.btval; }
 };
 template <>
 struct Vec<float> {
@@ -41,8 +39,6 @@ struct Vec<float> {
   static __device__ float* z(const InnerBlocks& B) { return B.z32; }
   static __device__ float* r(const InnerBlocks& B) { return B.ri32; }
   static __device__ float* t(const InnerBlocks& B) { return B.t32; }
-  static __device__ const float* v(const InnerBlocks& B) { return B.val32; }
-  static __device__ const float* bv(const InnerBlocks& B) { return B.btval32; }
 };
 
 constexpr int WG_THREADS = 1024;
