@@ -574,8 +574,8 @@ def main():
         hbm_probe()
         return
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); got --gpus %d" % args.gpus,
+        print("bench.py runs on one GPU only: the library has no multi-GPU path; "
+              "got --gpus %d" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -1,6 +1,6 @@
 """GPU-vs-oracle parity through the C ABI (needs an MI355X).
 
-Bars (floating point from the arithmetic):
+Bars (floating point, from the arithmetic of each path):
 * rip_graph pattern, costs and weights, partitions: bit-exact.
 * bc_project, FP64 dense Cholesky: relative error <= 1e-10 against the
   oracle's QR projections (forward error ~ kappa(G_i) eps with kappa(G_i) < 1e4).
