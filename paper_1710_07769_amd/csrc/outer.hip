@@ -95,41 +95,56 @@ k_spmv(const int* __restrict__ rowptr, const int* __restrict__ col,
 // before the arithmetic; padding entries carry the value 0.
 constexpr int SELL_THREADS = 64 * SELL_SLICES;
 
+// Entries k0 .. k0 + N - 1 of a lane's slice row, N fixed: every index and
+// value load, then every gather, then the sums in stored order.
+template <int N, typename V, typename ACC>
+__device__ __forceinline__ ACC sell_chunk(const int* __restrict__ col, const V* __restrict__ val,
+                                          const double* __restrict__ x, long long e, int k0,
+                                          ACC acc) {
+  int c[N];
+  V v[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    c[q] = col[e + (long long)(k0 + q) * 64];
+    v[q] = val[e + (long long)(k0 + q) * 64];
+  }
+  ACC xv[N];
+#pragma unroll
+  for (int q = 0; q < N; ++q) xv[q] = (ACC)x[c[q]];
+#pragma unroll
+  for (int q = 0; q < N; ++q) acc += (ACC)v[q] * xv[q];
+  return acc;
+}
+
+// The last nb < 8 entries of a slice whose width is the same on every lane
+// of the wavefront: one fixed-size chunk per count.  (Loads under a per-entry
+// condition let the compiler wait for each index before the next load is
+// issued, one round trip per entry; loads repeated up to 8 entries cost
+// issue slots on the narrow slices of five-point stencils.)
+template <typename V, typename ACC>
+__device__ __forceinline__ ACC sell_tail(const int* __restrict__ col, const V* __restrict__ val,
+                                         const double* __restrict__ x, long long e, int k0, int nb,
+                                         ACC acc) {
+  switch (nb) {
+    case 1: return sell_chunk<1, V, ACC>(col, val, x, e, k0, acc);
+    case 2: return sell_chunk<2, V, ACC>(col, val, x, e, k0, acc);
+    case 3: return sell_chunk<3, V, ACC>(col, val, x, e, k0, acc);
+    case 4: return sell_chunk<4, V, ACC>(col, val, x, e, k0, acc);
+    case 5: return sell_chunk<5, V, ACC>(col, val, x, e, k0, acc);
+    case 6: return sell_chunk<6, V, ACC>(col, val, x, e, k0, acc);
+    case 7: return sell_chunk<7, V, ACC>(col, val, x, e, k0, acc);
+    default: return acc;
+  }
+}
+
 template <typename V, typename ACC>
 __device__ __forceinline__ ACC sell_row_sum(const int* __restrict__ col, const V* __restrict__ val,
                                             const double* __restrict__ x, long long e, int w) {
+  w = __builtin_amdgcn_readfirstlane(w);
   ACC acc = (ACC)0;
   int k0 = 0;
-  for (; k0 + 8 <= w; k0 += 8) {
-    int c[8];
-    V v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      c[q] = col[e + (long long)(k0 + q) * 64];
-      v[q] = val[e + (long long)(k0 + q) * 64];
-    }
-    ACC xv[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) xv[q] = (ACC)x[c[q]];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc += (ACC)v[q] * xv[q];
-  }
-  if (k0 < w) {
-    const int nb = w - k0;
-    int c[8];
-    V v[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      c[q] = q < nb ? col[e + (long long)(k0 + q) * 64] : 0;
-      v[q] = q < nb ? val[e + (long long)(k0 + q) * 64] : (V)0;
-    }
-    ACC xv[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) xv[q] = q < nb ? (ACC)x[c[q]] : (ACC)0;
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (q < nb) acc += (ACC)v[q] * xv[q];
-  }
+  for (; k0 + 8 <= w; k0 += 8) acc = sell_chunk<8, V, ACC>(col, val, x, e, k0, acc);
+  if (k0 < w) acc = sell_tail<V, ACC>(col, val, x, e, k0, w - k0, acc);
   return acc;
 }
 
@@ -140,7 +155,7 @@ k_spmv_sell(SellMat A, const double* __restrict__ x, double* __restrict__ y, Out
   const int t = tile_of_block();
   const int sys = S.tile_sys[t];
   if (skip_done && S.done[sys]) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int sl = t * SELL_SLICES + wave;
   const int i = S.tile_start[t] + wave * 64 + lane;
   const long long e = A.ptr[sl] + lane;
@@ -162,20 +177,23 @@ k_spmvT_dot_sell(SellMat AT, const double* __restrict__ y, double* __restrict__ 
   const int t = tile_of_block();
   const int sys = S.tile_sys[t];
   if (S.done[sys]) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int sl = t * SELL_SLICES + wave;
   const int j = S.tile_start[t] + wave * 64 + lane;
   const long long e = AT.ptr[sl] + lane;
   const int w = AT.wid[sl];
+  // p is loaded before the product, not after it
+  const bool own = j < S.tile_start[t + 1];
+  const double pj = own ? p[j] : 0.0;
   double acc;
   if constexpr (MIXED)
     acc = (double)sell_row_sum<float, float>(AT.col, AT.val32, y, e, w);
   else
     acc = sell_row_sum<double, double>(AT.col, AT.val, y, e, w);
   double dot = 0.0;
-  if (j < S.tile_start[t + 1]) {
+  if (own) {
     psi[j] = acc;
-    dot = p[j] * acc;
+    dot = pj * acc;
   }
   dot = block_sum(dot, sh);
   if (threadIdx.x == 0) S.part_a[t] = dot;
@@ -188,7 +206,7 @@ k_residual_sell(SellMat A, const double* __restrict__ x, const double* __restric
   const int t = tile_of_block();
   const int sys = S.tile_sys[t];
   if (mask && !mask[sys]) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int sl = t * SELL_SLICES + wave;
   const int i = S.tile_start[t] + wave * 64 + lane;
   const double acc = sell_row_sum<double, double>(A.col, A.val, x, A.ptr[sl] + lane, A.wid[sl]);
@@ -332,7 +350,7 @@ k_spmv_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x, double* _
   const int t = blockIdx.x, j0 = blockIdx.y * NR;
   bool act[NR];
   if (!chunk_active<NR>(j0, M.nrhs, skip_done ? S.done : nullptr, true, act)) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int sl = t * SELL_SLICES + wave;
   const int i = M.tile_start[t] + wave * 64 + lane;
   const long long e = A.ptr[sl] + lane;
@@ -364,7 +382,7 @@ k_spmvT_dot_sell_multi(SellMat AT, MultiRhs M, const double* __restrict__ y,
   const int t = blockIdx.x, j0 = blockIdx.y * NR;
   bool act[NR];
   if (!chunk_active<NR>(j0, M.nrhs, S.done, true, act)) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int sl = t * SELL_SLICES + wave;
   const int j = M.tile_start[t] + wave * 64 + lane;
   const long long e = AT.ptr[sl] + lane;
@@ -408,7 +426,7 @@ k_residual_sell_multi(SellMat A, MultiRhs M, const double* __restrict__ x,
   const int t = blockIdx.x, j0 = blockIdx.y * NR;
   bool act[NR];
   if (!chunk_active<NR>(j0, M.nrhs, mask, false, act)) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int sl = t * SELL_SLICES + wave;
   const int i = M.tile_start[t] + wave * 64 + lane;
   const bool row = i < M.tile_start[t + 1];
