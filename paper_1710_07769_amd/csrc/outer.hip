@@ -231,38 +231,79 @@ k_residual_sell(SellMat A, const double* __restrict__ x, const double* __restric
 // columns are scattered (SellMat::il), from a copy made first into M.il with
 // the chunk's NR values of index c side by side (sell_rows_multi_il: one
 // 64-byte gather per index).
+// N entries (fixed) from k0 of a lane's slice row for the chunk's active
+// vectors: the index and value loads, then per vector the gathers and sums.
+template <int N, typename V, typename ACC, int NR>
+__device__ __forceinline__ void multi_chunk(const int* __restrict__ col, const V* __restrict__ val,
+                                            const double* __restrict__ x, long long n1, int j0,
+                                            const bool (&act)[NR], long long e, int k0,
+                                            ACC (&acc)[NR]) {
+  int c[N];
+  V v[N];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    c[r] = col[e + (long long)(k0 + r) * 64];
+    v[r] = val[e + (long long)(k0 + r) * 64];
+  }
+#pragma unroll
+  for (int q = 0; q < NR; ++q) {
+    if (!act[q]) continue;
+    const double* xq = x + (long long)(j0 + q) * n1;
+    ACC xv[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) xv[r] = (ACC)xq[c[r]];
+#pragma unroll
+    for (int r = 0; r < N; ++r) acc[q] += (ACC)v[r] * xv[r];
+  }
+}
+
 template <typename V, typename ACC, int NR>
 __device__ __forceinline__ void sell_rows_multi(const int* __restrict__ col,
                                                 const V* __restrict__ val,
                                                 const double* __restrict__ x, long long n1,
                                                 int j0, const bool (&act)[NR], long long e, int w,
                                                 ACC (&acc)[NR]) {
+  w = __builtin_amdgcn_readfirstlane(w);
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = (ACC)0;
-  for (int k0 = 0; k0 < w; k0 += 8) {
-    const int nb = min(8, w - k0);
-    int c[8];
-    V v[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      c[r] = r < nb ? col[e + (long long)(k0 + r) * 64] : 0;
-      v[r] = r < nb ? val[e + (long long)(k0 + r) * 64] : (V)0;
-    }
-#pragma unroll
-    for (int q = 0; q < NR; ++q) {
-      if (!act[q]) continue;
-      const double* xq = x + (long long)(j0 + q) * n1;
-      ACC xv[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) xv[r] = r < nb ? (ACC)xq[c[r]] : (ACC)0;
-#pragma unroll
-      for (int r = 0; r < 8; ++r)
-        if (r < nb) acc[q] += (ACC)v[r] * xv[r];
-    }
+  int k0 = 0;
+  for (; k0 + 8 <= w; k0 += 8) multi_chunk<8, V, ACC, NR>(col, val, x, n1, j0, act, e, k0, acc);
+  // the rest as one fixed-size batch (see sell_tail)
+  switch (w - k0) {
+    case 1: multi_chunk<1, V, ACC, NR>(col, val, x, n1, j0, act, e, k0, acc); break;
+    case 2: multi_chunk<2, V, ACC, NR>(col, val, x, n1, j0, act, e, k0, acc); break;
+    case 3: multi_chunk<3, V, ACC, NR>(col, val, x, n1, j0, act, e, k0, acc); break;
+    case 4: multi_chunk<4, V, ACC, NR>(col, val, x, n1, j0, act, e, k0, acc); break;
+    case 5: multi_chunk<5, V, ACC, NR>(col, val, x, n1, j0, act, e, k0, acc); break;
+    case 6: multi_chunk<6, V, ACC, NR>(col, val, x, n1, j0, act, e, k0, acc); break;
+    case 7: multi_chunk<7, V, ACC, NR>(col, val, x, n1, j0, act, e, k0, acc); break;
+    default: break;
   }
 }
 
 typedef double dbl4m __attribute__((ext_vector_type(4)));
+// N entries (fixed) from k0, gathered from the interleaved copy: one 32-byte
+// vector per 4 right-hand sides and index.
+template <int N, typename V, typename ACC, int NR>
+__device__ __forceinline__ void multi_chunk_il(const int* __restrict__ col,
+                                               const V* __restrict__ val,
+                                               const double* __restrict__ xil, long long e, int k0,
+                                               ACC (&acc)[NR]) {
+  V v[N];
+  dbl4m xv[N][NR / 4];
+#pragma unroll
+  for (int r = 0; r < N; ++r) {
+    const int c = col[e + (long long)(k0 + r) * 64];
+    v[r] = val[e + (long long)(k0 + r) * 64];
+#pragma unroll
+    for (int h = 0; h < NR / 4; ++h) xv[r][h] = *(const dbl4m*)(xil + (long long)c * NR + 4 * h);
+  }
+#pragma unroll
+  for (int r = 0; r < N; ++r)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) acc[q] += (ACC)v[r] * (ACC)xv[r][q / 4][q % 4];
+}
+
 template <typename V, typename ACC, int NR>
 __device__ __forceinline__ void sell_rows_multi_il(const int* __restrict__ col,
                                                    const V* __restrict__ val,
@@ -270,26 +311,16 @@ __device__ __forceinline__ void sell_rows_multi_il(const int* __restrict__ col,
                                                    int w, ACC (&acc)[NR]) {
   static_assert(NR % 4 == 0, "whole 32-byte vectors per index");
   constexpr int B = 4;  // entries per batch: B * NR gathered doubles in flight
+  w = __builtin_amdgcn_readfirstlane(w);
 #pragma unroll
   for (int q = 0; q < NR; ++q) acc[q] = (ACC)0;
-  for (int k0 = 0; k0 < w; k0 += B) {
-    const int nb = min(B, w - k0);
-    V v[B];
-    dbl4m xv[B][NR / 4];
-#pragma unroll
-    for (int r = 0; r < B; ++r) {
-      const int c = r < nb ? col[e + (long long)(k0 + r) * 64] : 0;
-      v[r] = r < nb ? val[e + (long long)(k0 + r) * 64] : (V)0;
-#pragma unroll
-      for (int h = 0; h < NR / 4; ++h)
-        xv[r][h] = r < nb ? *(const dbl4m*)(xil + (long long)c * NR + 4 * h)
-                          : dbl4m{0.0, 0.0, 0.0, 0.0};
-    }
-#pragma unroll
-    for (int r = 0; r < B; ++r)
-#pragma unroll
-      for (int q = 0; q < NR; ++q)
-        if (r < nb) acc[q] += (ACC)v[r] * (ACC)xv[r][q / 4][q % 4];
+  int k0 = 0;
+  for (; k0 + B <= w; k0 += B) multi_chunk_il<B, V, ACC, NR>(col, val, xil, e, k0, acc);
+  switch (w - k0) {
+    case 1: multi_chunk_il<1, V, ACC, NR>(col, val, xil, e, k0, acc); break;
+    case 2: multi_chunk_il<2, V, ACC, NR>(col, val, xil, e, k0, acc); break;
+    case 3: multi_chunk_il<3, V, ACC, NR>(col, val, xil, e, k0, acc); break;
+    default: break;
   }
 }
 
