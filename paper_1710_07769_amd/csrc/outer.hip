@@ -36,6 +36,9 @@ __device__ __forceinline__ float group_sumf(float v) {
 // This lane's part of a row sum: entries e0 + l, e0 + l + L, ... in that
 // order (so the rounding is that of the plain loop), in batches of U whose
 // index and value loads, then gathers, are all issued before the arithmetic.
+// Past the row's end a lane loads its last entry again and does not add it:
+// loads under a per-entry condition let the compiler wait for each index
+// before the next load is issued.
 template <int L, typename V, typename ACC>
 __device__ __forceinline__ ACC lane_row_sum(const int* __restrict__ col, const V* __restrict__ val,
                                             const double* __restrict__ x, int e0, int e1, int l) {
@@ -46,13 +49,13 @@ __device__ __forceinline__ ACC lane_row_sum(const int* __restrict__ col, const V
     V v[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      const int ek = e + k * L;
-      c[k] = ek < e1 ? col[ek] : 0;
-      v[k] = ek < e1 ? val[ek] : (V)0;
+      const int ek = min(e + k * L, e1 - 1);
+      c[k] = col[ek];
+      v[k] = val[ek];
     }
     ACC xv[U];
 #pragma unroll
-    for (int k = 0; k < U; ++k) xv[k] = e + k * L < e1 ? (ACC)x[c[k]] : (ACC)0;
+    for (int k = 0; k < U; ++k) xv[k] = (ACC)x[c[k]];
 #pragma unroll
     for (int k = 0; k < U; ++k)
       if (e + k * L < e1) acc += (ACC)v[k] * xv[k];
