@@ -53,11 +53,59 @@ __device__ __forceinline__ const double* sel_val<double>(const double* d, const 
 template <>
 __device__ __forceinline__ const float* sel_val<float>(const double*, const float* f) { return f; }
 
+// N entries (fixed) from k0 of a lane's slice row, summed in stored order
+// after all their loads and gathers are issued; gx(i) reads the gathered
+// vector at i.
+template <int N, typename T, typename TV, typename IX, class Gx>
+__device__ __forceinline__ T inner_chunk(const IX* __restrict__ idx, const TV* __restrict__ val,
+                                         long long e, int k0, Gx gx, T acc) {
+  IX ix[N];
+  TV vv[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    ix[k] = idx[e + (long long)(k0 + k) * 64];
+    vv[k] = val[e + (long long)(k0 + k) * 64];
+  }
+  T xv[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) xv[k] = gx(ix[k]);
+#pragma unroll
+  for (int k = 0; k < N; ++k) acc += (T)vv[k] * xv[k];
+  return acc;
+}
+
+// The last nb < 8 entries of a slice (widths under 5 are not padded to 8):
+// one fixed-size chunk per count, instead of one round trip per entry.
+template <typename T, typename TV, typename IX, class Gx>
+__device__ __forceinline__ T inner_tail(const IX* __restrict__ idx, const TV* __restrict__ val,
+                                        long long e, int k0, int nb, Gx gx, T acc) {
+  switch (nb) {
+    case 1: return inner_chunk<1, T, TV, IX>(idx, val, e, k0, gx, acc);
+    case 2: return inner_chunk<2, T, TV, IX>(idx, val, e, k0, gx, acc);
+    case 3: return inner_chunk<3, T, TV, IX>(idx, val, e, k0, gx, acc);
+    case 4: return inner_chunk<4, T, TV, IX>(idx, val, e, k0, gx, acc);
+    case 5: return inner_chunk<5, T, TV, IX>(idx, val, e, k0, gx, acc);
+    case 6: return inner_chunk<6, T, TV, IX>(idx, val, e, k0, gx, acc);
+    case 7: return inner_chunk<7, T, TV, IX>(idx, val, e, k0, gx, acc);
+    default: return acc;
+  }
+}
+
+template <typename T>
+struct PlainGx {
+  const T* __restrict__ x;
+  template <typename IX>
+  __device__ __forceinline__ T operator()(IX i) const { return x[i]; }
+};
+
 // T: vector and arithmetic type; TV: stored matrix values (float values with
-// double arithmetic are converted exactly before each product).
-template <typename T, typename TV, typename IX>
+// double arithmetic are converted exactly before each product).  w is the
+// same on every lane of the wavefront.  BT: the rest of the slice after its
+// whole chunks of 8 as one batch (else entry by entry: fewer registers).
+template <typename T, typename TV, typename IX, bool BT = true>
 __device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const TV* __restrict__ val,
                                       long long e, int w, const T* __restrict__ x, T acc = (T)0) {
+  w = __builtin_amdgcn_readfirstlane(w);
   int k0 = 0;
   for (; k0 + 8 <= w; k0 += 8) {
     IX ix[8];
@@ -73,7 +121,11 @@ __device__ __forceinline__ T sell_row(const IX* __restrict__ idx, const TV* __re
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc += (T)vv[k] * xv[k];
   }
-  for (; k0 < w; ++k0) acc += (T)val[e + (long long)k0 * 64] * x[idx[e + (long long)k0 * 64]];
+  if constexpr (BT) {
+    if (k0 < w) acc = inner_tail<T, TV, IX>(idx, val, e, k0, w - k0, PlainGx<T>{x}, acc);
+  } else {
+    for (; k0 < w; ++k0) acc += (T)val[e + (long long)k0 * 64] * x[idx[e + (long long)k0 * 64]];
+  }
   return acc;
 }
 
@@ -545,12 +597,12 @@ k_inner_grp(InnerBlocks B, const double* __restrict__ u, double* __restrict__ y,
           // here rather than held across the whole loop
           int e = et[k];
           asm volatile("" : "+v"(e));
-          tacc[k] = sell_row<T, TV, IX>(tidxb, tvalb, e, wt[k], rs);
+          tacc[k] = sell_row<T, TV, IX, (RPT <= 4)>(tidxb, tvalb, e, wt[k], rs);
           if (!DEFER && c * 64 + lane < ns) tg[c * 64 + lane] = tacc[k];
         }
       }
       for (int c = st0 + wave + RPT * NW; c < st1; c += NW) {
-        const T acc = sell_row<T, TV, IX>(tidx, tval, tptr[c] + lane, tw[c], rs);
+        const T acc = sell_row<T, TV, IX, (RPT <= 4)>(tidx, tval, tptr[c] + lane, tw[c], rs);
         if (c * 64 + lane < ns) tg[c * 64 + lane] = acc;
       }
 #pragma unroll
