@@ -90,7 +90,17 @@ __device__ __forceinline__ double wave_sum_lane0(double v) {
 __device__ __forceinline__ double sys_sum_wave(const double* part, int t0, int t1) {
   const int lane = threadIdx.x & 63;
   double acc = 0.0;
-  for (int t = t0 + lane; t < t1; t += 64) acc += part[t];
+  // each lane adds part[t0 + lane + 64 k] for k = 0, 1, ... in that order; the
+  // loads of 8 consecutive k are issued together (past t1 a lane reloads the
+  // last partial and does not add it), not one round trip per partial
+  for (int t = t0 + lane; t < t1; t += 64 * 8) {
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = part[min(t + 64 * q, t1 - 1)];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (t + 64 * q < t1) acc += v[q];
+  }
   return wave_sum_lane0(acc);
 }
 
